@@ -1,0 +1,206 @@
+/*
+ * inla_bta.h -- C ABI of the MI355X (gfx950) library that evaluates the INLA
+ * hyperparameter objective f(theta) = -log pi~(theta | y) and its gradient for
+ * Gaussian latent models whose precision matrices are block tridiagonal with an
+ * arrowhead (BTA): nt dense time blocks of size b = ns (the spatial nodes) on
+ * the diagonal, dense coupling blocks between consecutive time steps, and a
+ * dense border of width a = nb (the fixed effects, ordered last).
+ *
+ * Paper: "Parallelized integrated nested Laplace approximations for fast
+ * Bayesian inference".  Objective: Sec. "Parallel Optimization" (f as the
+ * negative log of eq. post_theta_approx).  Factorization, log-determinant and
+ * forward/backward substitution: Sec. "Sparse Linear Algebra".  Selected
+ * inversion: Sec. "Partial Inversion" (eq. sel_inv_cov, eq. takahashi_identity,
+ * eq. takahashi_recursion), applied here block-wise.  Batches of independent
+ * theta points: Sec. "Parallel Optimization" (all central-difference points of
+ * eq. central_diff are independent) and Sec. "Parallel Line Search".
+ *
+ * Conventions shared by every entry point:
+ *   - FP64 only.  All matrices are column-major.
+ *   - Pointers named *_dev, and every block pointer inside inla_bta, are device
+ *     pointers owned by the caller; the library never frees them.
+ *   - Every call except inla_model_create is enqueued on the caller's HIP
+ *     stream (a hipStream_t passed as void*; NULL = the default stream) and
+ *     returns before the device work finishes.  Results become valid once the
+ *     caller synchronises that stream.
+ *   - Argument errors, allocation failures and launch failures are returned
+ *     synchronously as an inla_status; inla_last_error() gives details for the
+ *     calling thread.  Numerical failure (a non-positive pivot) is reported
+ *     asynchronously through the per-item status/info outputs.
+ *   - Calls that use the library's internal workspace (factor, selinv, eval)
+ *     serialise on an internal lock; issuing them from several threads is safe
+ *     but they do not overlap.
+ */
+#ifndef INLA_BTA_H
+#define INLA_BTA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  INLA_OK = 0,
+  INLA_ERR_ARG = -1,     /* invalid argument (dims, pointers, theta out of range) */
+  INLA_ERR_NOT_SPD = -2, /* reserved for synchronous SPD failures (async ones use info) */
+  INLA_ERR_BUDGET = -3,  /* one item alone exceeds the HBM budget */
+  INLA_ERR_HIP = -4,     /* a HIP runtime call or kernel launch failed */
+  INLA_ERR_NOMEM = -5,   /* device or host allocation failed */
+  INLA_ERR_STATE = -6    /* library not usable (no device, wrong architecture) */
+} inla_status;
+
+/*
+ * One BTA matrix.  Block (t,t) is D[t], block (t+1,t) is S[t], block (A,t) is
+ * R[t], block (A,A) is T.  Storage is contiguous per kind:
+ *   D: nt blocks b x b, block t at D + t*b*b, leading dimension b;
+ *   S: nt-1 blocks b x b, block t at S + t*b*b, leading dimension b (NULL if nt == 1);
+ *   R: nt blocks a x b, block t at R + t*a*b, leading dimension a (NULL if a == 0);
+ *   T: a x a, leading dimension a (NULL if a == 0).
+ * As an input precision matrix only the lower triangles of D[t] and T are read.
+ *
+ * Factor format written by inla_factor_logdet (the inverse-diagonal block
+ * Cholesky form, Q = L L^T):
+ *   D[t] <- inv(L_tt)          lower triangular, zeros stored above the diagonal
+ *   S[t] <- L_{t+1,t}          full block
+ *   R[t] <- L_{A,t}            full block
+ *   T    <- inv(L_AA)          lower triangular, zeros stored above the diagonal
+ * Keeping the inverses of the diagonal factor blocks turns every later use
+ * (the off-diagonal solves, the substitution sweeps, the selected inversion)
+ * into plain matrix products.  log|Q| = -2 sum log diag(D[t]) - 2 sum log diag(T).
+ */
+typedef struct {
+  int32_t b, nt, a;
+  double *D, *S, *R, *T;
+} inla_bta;
+
+/* Opaque model: grid stencils, A^T A split into BTA blocks, A in CSR, y. */
+typedef struct inla_model inla_model;
+
+/*
+ * Host description of one model (copied by inla_model_create).
+ * Latent order x = (u_0, ..., u_{nt-1}, beta), u_t in R^{N*N} with node
+ * (ix, iy) at index iy*N + ix; n = N*N*nt + nb.
+ *   N, nt, nb  : grid side (>= 1), time steps (>= 1), fixed effects (0..64)
+ *   h          : grid spacing; C = h^2 I in Q_s = tau^2 (kappa^2 C + G) C^{-1} (kappa^2 C + G)
+ *   beta_prior_prec : prior precision of every fixed effect
+ *   m, A_rowptr (m+1, int64), A_col (int32), A_val : observation matrix, m x n CSR.
+ *                Every row's space-time entries must lie in one time block.
+ *   y          : m responses
+ *   theta_prior_mean, theta_prior_prec : 4 each, independent Gaussian hyperprior
+ * theta = (log tau, log kappa, atanh rho, log tau_y): spatial scale, spatial
+ * range parameter, AR1 correlation in time, Gaussian noise precision.
+ */
+typedef struct {
+  int32_t N, nt, nb;
+  double h;
+  double beta_prior_prec;
+  int64_t m;
+  const int64_t *A_rowptr;
+  const int32_t *A_col;
+  const double *A_val;
+  const double *y;
+  const double *theta_prior_mean;
+  const double *theta_prior_prec;
+} inla_model_desc;
+
+typedef struct {
+  double hbm_budget_bytes; /* 0: free device memory minus a 4 GiB reserve */
+  int32_t recompute;       /* gradient path: 0 auto, 1 always, 2 never (see inla_eval_f_grad) */
+  int32_t keep_sigma;      /* reserved, must be 0 */
+  int32_t tile;            /* 0: autotuned per block size; else 64 or 128 */
+  int32_t reserved;
+  const char *autotune_cache; /* reserved, may be NULL */
+} inla_opts;
+
+/*
+ * Build a model on the current device (Sec. "Latent Gaussian Models").
+ * Copies the description, builds the spatial stencil and the per-time-step
+ * A^T A, Z^T A and Z^T Z blocks on the host, uploads them, and synchronises
+ * `hip_stream`.  *out is owned by the caller and freed by inla_model_destroy.
+ */
+inla_status inla_model_create(const inla_model_desc *desc, void *hip_stream, inla_model **out);
+void inla_model_destroy(inla_model *model);
+/* Shape of a model: b = N*N, nt, a = nb, n, m (any output pointer may be NULL). */
+inla_status inla_model_shape(const inla_model *model, int32_t *b, int32_t *nt, int32_t *a,
+                             int64_t *n, int64_t *m);
+
+/*
+ * Assemble Q_prior(theta) (which = 0) or Q_c(theta) = Q_prior + tau_y A^T A
+ * (which = 1) into the caller's BTA storage `out` (shape must equal the
+ * model's; every block is written in full, both triangles).  With which = 1
+ * and rhs_dev != NULL also writes b = tau_y A^T y (n doubles).  theta_dev: 4
+ * doubles on the device.  Sec. "Latent Gaussian Models", and Sec.
+ * "Approximating pi(theta_j | y)" for conditioning keeping the pattern.
+ */
+inla_status inla_assemble(const inla_model *model, const double *theta_dev, int32_t which,
+                          inla_bta *out, double *rhs_dev, void *hip_stream);
+
+/*
+ * In-place block Cholesky of one BTA matrix (Sec. "Sparse Linear Algebra"),
+ * into the inverse-diagonal factor format described at inla_bta.
+ * logdet_dev (1 double, may be NULL) <- log|Q|;  info_dev (1 int32, may be
+ * NULL) <- 0, or the 1-based row of the first non-positive pivot, in which
+ * case the factor and log-determinant are not meaningful (log|Q| is NaN).
+ */
+inla_status inla_factor_logdet(inla_bta *QL, double *logdet_dev, int32_t *info_dev, void *hip_stream);
+
+/*
+ * Solve Q X = RHS with the factor from inla_factor_logdet by forward then
+ * backward substitution (Sec. "Sparse Linear Algebra").  rhs_dev, x_dev:
+ * n x nrhs column-major (n = b*nt + a); they may alias.
+ */
+inla_status inla_solve(const inla_bta *L, const double *rhs_dev, double *x_dev, int32_t nrhs,
+                       void *hip_stream);
+
+/*
+ * Selected inversion of Q from its factor (Sec. "Partial Inversion"): the
+ * blocks of Sigma = Q^{-1} on the BTA pattern, computed by the block form of
+ * the Takahashi recursion from the last time block to the first.
+ * sigma_or_null: if non-NULL, receives Sigma's D (full symmetric blocks), S
+ * (block (t+1,t)), R and T blocks, same shapes as L.  diag_or_null: if
+ * non-NULL, receives the n marginal variances diag(Q^{-1}).
+ */
+inla_status inla_selinv(const inla_bta *L, inla_bta *sigma_or_null, double *diag_or_null,
+                        void *hip_stream);
+
+/*
+ * f(theta) for n_items independent (model, theta) items in one batched pass
+ * (Sec. "Parallel Optimization": independent evaluations run together).
+ * models[i] may repeat.  theta_dev: n_items x 4 (row i = item i).
+ *   f_dev      : n_items
+ *   mu_or_null : concatenation over items of the posterior mode mu (n_i each)
+ *   var_or_null: concatenation over items of the marginal variances diag(Q_c^{-1})
+ *   status_dev : n_items int32: 0 ok, 1 = Q_prior not positive definite,
+ *                2 = Q_c not positive definite (f is NaN for that item)
+ * Items are admitted in waves so that the BTA storage stays within the HBM
+ * budget of opts (NULL opts = defaults).
+ */
+inla_status inla_eval_f(const inla_model *const *models, int32_t n_items, const double *theta_dev,
+                        double *f_dev, double *mu_or_null, double *var_or_null, int32_t *status_dev,
+                        const inla_opts *opts, void *hip_stream);
+
+/*
+ * As inla_eval_f, plus grad_dev (n_items x 4) <- the exact gradient of f,
+ * from the selected-inversion blocks of Q_prior and Q_c:
+ *   df/dtheta_k = p_k (theta_k - m_k) - 1/2 tr(Q_p^{-1} dQ_p/dtheta_k)
+ *                 + 1/2 tr(Q_c^{-1} dQ_c/dtheta_k) + 1/2 mu^T (dQ_p/dtheta_k) mu
+ *                 + [k = 4] (tau_y/2 |y - A mu|^2 - m/2).
+ * The selected-inverse blocks are consumed as they are produced and not kept.
+ */
+inla_status inla_eval_f_grad(const inla_model *const *models, int32_t n_items,
+                             const double *theta_dev, double *f_dev, double *grad_dev,
+                             double *mu_or_null, double *var_or_null, int32_t *status_dev,
+                             const inla_opts *opts, void *hip_stream);
+
+/* Release the library's cached device workspace (it is re-grown on demand). */
+void inla_release_workspace(void);
+
+const char *inla_status_string(inla_status s);
+/* Thread-local text of the last synchronous error ("" if none). */
+const char *inla_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* INLA_BTA_H */

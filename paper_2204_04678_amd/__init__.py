@@ -1,0 +1,23 @@
+"""MI355X (gfx950) library for the INLA hyperparameter objective on
+block-tridiagonal-with-arrowhead precision matrices: assembly, block Cholesky
+and log-determinants, substitution, selected inversion, batched f(theta) and
+its exact gradient.  The compute runs in libinla_bta.so (hand-written HIP);
+this package only marshals arguments.
+"""
+from .binding import (  # noqa: F401
+    Bta,
+    BtaTensors,
+    InlaError,
+    InlaObjective,
+    Model,
+    assemble,
+    eval_f,
+    eval_f_grad,
+    factor_logdet,
+    header_functions,
+    lib,
+    objective,
+    release_workspace,
+    selinv,
+    solve,
+)

@@ -1,0 +1,335 @@
+"""Thin ctypes binding of libinla_bta.so (argument marshalling only).
+
+Every computation runs in the HIP library; PyTorch supplies device memory and
+the current stream.  There is no CPU fallback: if the library or a GPU is
+missing, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import torch
+
+from ._build import LIB, ROOT
+
+INLA_OK = 0
+STATUS = {0: "ok", -1: "invalid argument", -2: "not positive definite", -3: "over HBM budget",
+          -4: "HIP error", -5: "out of memory", -6: "library not usable"}
+
+
+class InlaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Bta(C.Structure):
+    _fields_ = [("b", C.c_int32), ("nt", C.c_int32), ("a", C.c_int32),
+                ("D", C.c_void_p), ("S", C.c_void_p), ("R", C.c_void_p), ("T", C.c_void_p)]
+
+
+class ModelDesc(C.Structure):
+    _fields_ = [("N", C.c_int32), ("nt", C.c_int32), ("nb", C.c_int32), ("h", C.c_double),
+                ("beta_prior_prec", C.c_double), ("m", C.c_int64),
+                ("A_rowptr", C.c_void_p), ("A_col", C.c_void_p), ("A_val", C.c_void_p),
+                ("y", C.c_void_p), ("theta_prior_mean", C.c_void_p),
+                ("theta_prior_prec", C.c_void_p)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_double), ("recompute", C.c_int32),
+                ("keep_sigma", C.c_int32), ("tile", C.c_int32), ("reserved", C.c_int32),
+                ("autotune_cache", C.c_char_p)]
+
+
+_LIB = None
+
+_SIGS = {
+    "inla_model_create": (C.c_int, [C.POINTER(ModelDesc), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "inla_model_destroy": (None, [C.c_void_p]),
+    "inla_model_shape": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_int32), C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_int64)]),
+    "inla_assemble": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(Bta), C.c_void_p,
+                                C.c_void_p]),
+    "inla_factor_logdet": (C.c_int, [C.POINTER(Bta), C.c_void_p, C.c_void_p, C.c_void_p]),
+    "inla_solve": (C.c_int, [C.POINTER(Bta), C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "inla_selinv": (C.c_int, [C.POINTER(Bta), C.POINTER(Bta), C.c_void_p, C.c_void_p]),
+    "inla_eval_f": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.c_void_p,
+                              C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Opts), C.c_void_p]),
+    "inla_eval_f_grad": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.POINTER(Opts), C.c_void_p]),
+    "inla_release_workspace": (None, []),
+    "inla_status_string": (C.c_char_p, [C.c_int]),
+    "inla_last_error": (C.c_char_p, []),
+}
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/inla_bta.h."""
+    with open(os.path.join(ROOT, "include", "inla_bta.h")) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(inla_[a-z_]+)\s*\(", text)))
+
+
+def lib(path: str = LIB):
+    """Load the HIP library (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(path)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _check(code: int):
+    if code != INLA_OK:
+        raise InlaError(code, lib().inla_last_error().decode())
+
+
+def _stream():
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU: the INLA library runs on the HIP device only")
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _dev_f64(x, device="cuda"):
+    return torch.as_tensor(np.asarray(x, dtype=np.float64)).to(device).contiguous()
+
+
+# ---------------------------------------------------------------------------
+# BTA storage
+# ---------------------------------------------------------------------------
+
+class BtaTensors:
+    """Device storage of one BTA matrix (see inla_bta in include/inla_bta.h)."""
+
+    def __init__(self, b: int, nt: int, a: int, device="cuda", D=None, S=None, R=None, T=None):
+        self.b, self.nt, self.a = b, nt, a
+        z = lambda *s: torch.empty(*s, dtype=torch.float64, device=device)  # noqa: E731
+        self.D = D if D is not None else z(nt, b, b)
+        self.S = S if S is not None else (z(nt - 1, b, b) if nt > 1 else None)
+        self.R = R if R is not None else (z(nt, b, a) if a > 0 else None)
+        self.T = T if T is not None else (z(a, a) if a > 0 else None)
+
+    # Blocks are column-major: element (i, j) of block t of D lives at D[t].view(-1)[i + j*b];
+    # with torch's row-major view that is D[t][j, i].  The helpers return the logical blocks.
+    def block(self, kind: str, t: int = 0):
+        X = getattr(self, kind)
+        if kind == "T":
+            return X.t()
+        return X[t].t()
+
+    def struct(self) -> Bta:
+        return Bta(self.b, self.nt, self.a, self.D.data_ptr(),
+                   self.S.data_ptr() if self.S is not None else 0,
+                   self.R.data_ptr() if self.R is not None else 0,
+                   self.T.data_ptr() if self.T is not None else 0)
+
+    @staticmethod
+    def from_blocks(D, S, R, T, device="cuda"):
+        """From logical numpy blocks D[nt,b,b], S[nt-1,b,b], R[nt,a,b], T[a,a]."""
+        nt, b, _ = D.shape
+        a = T.shape[0] if T is not None else 0
+        cm = lambda X: torch.as_tensor(np.ascontiguousarray(np.swapaxes(X, -1, -2))).to(device)  # noqa: E731
+        return BtaTensors(b, nt, a, device,
+                          D=cm(D), S=cm(S) if nt > 1 else None,
+                          R=cm(R) if a > 0 else None,
+                          T=torch.as_tensor(np.ascontiguousarray(T.T)).to(device) if a > 0 else None)
+
+    def to_blocks(self):
+        """Logical numpy blocks (D, S, R, T)."""
+        cm = lambda X: np.swapaxes(X.detach().cpu().numpy(), -1, -2).copy()  # noqa: E731
+        D = cm(self.D)
+        S = cm(self.S) if self.S is not None else np.zeros((0, self.b, self.b))
+        R = cm(self.R) if self.R is not None else np.zeros((self.nt, 0, self.b))
+        T = self.T.detach().cpu().numpy().T.copy() if self.T is not None else np.zeros((0, 0))
+        return D, S, R, T
+
+
+# ---------------------------------------------------------------------------
+# model
+# ---------------------------------------------------------------------------
+
+class Model:
+    """A model living on the GPU (inla_model_create)."""
+
+    def __init__(self, N, nt, nb, h, A_rowptr, A_col, A_val, y, theta_prior_mean=None,
+                 theta_prior_prec=None, beta_prior_prec=1e-3):
+        L = lib()
+        self._keep = [np.ascontiguousarray(A_rowptr, dtype=np.int64),
+                      np.ascontiguousarray(A_col, dtype=np.int32),
+                      np.ascontiguousarray(A_val, dtype=np.float64),
+                      np.ascontiguousarray(y, dtype=np.float64),
+                      np.ascontiguousarray(theta_prior_mean if theta_prior_mean is not None
+                                           else np.zeros(4), dtype=np.float64),
+                      np.ascontiguousarray(theta_prior_prec if theta_prior_prec is not None
+                                           else np.full(4, 0.01), dtype=np.float64)]
+        rp, col, val, yy, pm, pp = self._keep
+        desc = ModelDesc(N, nt, nb, h, beta_prior_prec, yy.size,
+                         rp.ctypes.data, col.ctypes.data, val.ctypes.data, yy.ctypes.data,
+                         pm.ctypes.data, pp.ctypes.data)
+        handle = C.c_void_p()
+        _check(L.inla_model_create(C.byref(desc), _stream(), C.byref(handle)))
+        self.handle = handle
+        b, t_, a, n, m = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64(), C.c_int64()
+        _check(L.inla_model_shape(handle, b, t_, a, n, m))
+        self.b, self.nt, self.a, self.n, self.m = b.value, t_.value, a.value, n.value, m.value
+        self._keep = None
+
+    @staticmethod
+    def from_data(md) -> "Model":
+        """From an inla_synth.ModelData."""
+        return Model(md.N, md.nt, md.nb, md.h, md.A_rowptr, md.A_col, md.A_val, md.y,
+                     md.theta_prior_mean, md.theta_prior_prec, md.beta_prior_prec)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _LIB is not None:
+            _LIB.inla_model_destroy(h)
+            self.handle = None
+
+
+# ---------------------------------------------------------------------------
+# the six operations
+# ---------------------------------------------------------------------------
+
+def assemble(model: Model, theta, which: int):
+    """Q_prior (which=0) or Q_c (which=1) as BtaTensors; with which=1 also b = tau_y A^T y."""
+    th = theta if torch.is_tensor(theta) else _dev_f64(theta)
+    Q = BtaTensors(model.b, model.nt, model.a)
+    rhs = torch.empty(model.n, dtype=torch.float64, device="cuda") if which == 1 else None
+    st = Q.struct()
+    _check(lib().inla_assemble(model.handle, _ptr(th), which, C.byref(st), _ptr(rhs), _stream()))
+    return (Q, rhs) if which == 1 else Q
+
+
+def factor_logdet(Q: BtaTensors):
+    """In-place factorization; returns (logdet tensor[1], info tensor[1])."""
+    ld = torch.empty(1, dtype=torch.float64, device="cuda")
+    info = torch.empty(1, dtype=torch.int32, device="cuda")
+    st = Q.struct()
+    _check(lib().inla_factor_logdet(C.byref(st), _ptr(ld), _ptr(info), _stream()))
+    return ld, info
+
+
+def solve(L: BtaTensors, rhs):
+    """x = Q^{-1} rhs from the factor (rhs: n or n x nrhs, column-major per column)."""
+    r = rhs.contiguous()
+    nrhs = 1 if r.dim() == 1 else r.shape[0]
+    x = torch.empty_like(r)
+    st = L.struct()
+    _check(lib().inla_solve(C.byref(st), _ptr(r), _ptr(x), nrhs, _stream()))
+    return x
+
+
+def selinv(L: BtaTensors, keep_sigma: bool = False):
+    """Selected inverse: (BtaTensors of Sigma or None, diag tensor[n])."""
+    n = L.b * L.nt + L.a
+    diag = torch.empty(n, dtype=torch.float64, device="cuda")
+    st = L.struct()
+    sig = BtaTensors(L.b, L.nt, L.a) if keep_sigma else None
+    sst = sig.struct() if sig is not None else None
+    _check(lib().inla_selinv(C.byref(st), C.byref(sst) if sst is not None else None, _ptr(diag),
+                             _stream()))
+    return sig, diag
+
+
+def _models_array(models):
+    arr = (C.c_void_p * len(models))(*[m.handle.value for m in models])
+    return arr
+
+
+def _opts(budget=0.0):
+    return Opts(float(budget), 0, 0, 0, 0, None)
+
+
+def eval_f(models, thetas, want_mu=False, want_var=False, budget=0.0):
+    """Batched f(theta).  Returns dict(f, status, [mu], [var]) of device tensors."""
+    if isinstance(models, Model):
+        models = [models]
+    th = thetas if torch.is_tensor(thetas) else _dev_f64(np.atleast_2d(thetas))
+    k = th.shape[0]
+    if len(models) == 1 and k > 1:
+        models = models * k
+    ntot = sum(m.n for m in models)
+    f = torch.empty(k, dtype=torch.float64, device="cuda")
+    status = torch.empty(k, dtype=torch.int32, device="cuda")
+    mu = torch.empty(ntot, dtype=torch.float64, device="cuda") if want_mu else None
+    var = torch.empty(ntot, dtype=torch.float64, device="cuda") if want_var else None
+    o = _opts(budget)
+    _check(lib().inla_eval_f(_models_array(models), k, _ptr(th), _ptr(f), _ptr(mu), _ptr(var),
+                             _ptr(status), C.byref(o), _stream()))
+    out = dict(f=f, status=status)
+    if want_mu:
+        out["mu"] = mu
+    if want_var:
+        out["var"] = var
+    return out
+
+
+def eval_f_grad(models, thetas, want_mu=False, want_var=False, budget=0.0):
+    """Batched f(theta) and its exact gradient.  Returns dict(f, grad, status, [mu], [var])."""
+    if isinstance(models, Model):
+        models = [models]
+    th = thetas if torch.is_tensor(thetas) else _dev_f64(np.atleast_2d(thetas))
+    th = th.contiguous()
+    k = th.shape[0]
+    if len(models) == 1 and k > 1:
+        models = models * k
+    ntot = sum(m.n for m in models)
+    f = torch.empty(k, dtype=torch.float64, device="cuda")
+    g = torch.empty(k, 4, dtype=torch.float64, device="cuda")
+    status = torch.empty(k, dtype=torch.int32, device="cuda")
+    mu = torch.empty(ntot, dtype=torch.float64, device="cuda") if want_mu else None
+    var = torch.empty(ntot, dtype=torch.float64, device="cuda") if want_var else None
+    o = _opts(budget)
+    _check(lib().inla_eval_f_grad(_models_array(models), k, _ptr(th), _ptr(f), _ptr(g), _ptr(mu),
+                                  _ptr(var), _ptr(status), C.byref(o), _stream()))
+    out = dict(f=f, grad=g, status=status)
+    if want_mu:
+        out["mu"] = mu
+    if want_var:
+        out["var"] = var
+    return out
+
+
+class InlaObjective(torch.autograd.Function):
+    """f(theta) with the exact gradient from the selected-inversion adjoint.
+
+    theta: (k, 4) float64 CUDA tensor; returns f (k,).  The forward pass runs
+    inla_eval_f_grad once and keeps grad f for the backward pass.
+    """
+
+    @staticmethod
+    def forward(ctx, theta, models):
+        out = eval_f_grad(models, theta.detach().contiguous())
+        ctx.save_for_backward(out["grad"])
+        return out["f"]
+
+    @staticmethod
+    def backward(ctx, gout):
+        (g,) = ctx.saved_tensors
+        return gout[:, None] * g, None
+
+
+def objective(theta, models):
+    return InlaObjective.apply(theta, models)
+
+
+def release_workspace():
+    lib().inla_release_workspace()

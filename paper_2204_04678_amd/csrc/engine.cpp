@@ -1,0 +1,843 @@
+// Host engine and C ABI of the BTA INLA library (see include/inla_bta.h).
+//
+// The engine turns each ABI call into a fixed sequence of batched kernel
+// launches on the caller's stream:
+//   factor   (per time step t, all items in lockstep)
+//       DIAG0, then for each 64-wide panel p: PANEL(p), TRAIL(p); then
+//       OFFDIAG (X = S[t] inv(L_tt)^T, R' = R[t] inv(L_tt)^T) and SCHUR
+//       (D[t+1] -= X X^T, R[t+1] -= R' X^T, T -= R' R'^T); finally ARROW.
+//   selected inversion (t = nt-1 .. 0), the block form of the Takahashi
+//   recursion (paper, Sec. "Partial Inversion"), derived from Sigma L = L^{-T}
+//   read block column by block column:
+//       V = L_{t+1,t} inv(L_tt), U = L_{A,t} inv(L_tt)
+//       Sigma_{t+1,t} = -(Sigma_{t+1,t+1} V + Sigma_{A,t+1}^T U)
+//       Sigma_{A,t}   = -(Sigma_{A,t+1} V + Sigma_{AA} U)
+//       Sigma_{t,t}   = inv(L_tt)^T inv(L_tt) - Sigma_{t+1,t}^T V - Sigma_{A,t}^T U
+//   and per step the trace reductions against the derivative blocks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/inla_bta.h"
+#include "inla_internal.h"
+
+using namespace inla;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+inla_status fail(inla_status st, const std::string &msg) {
+  g_last_error = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(INLA_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// device workspace arena: one allocation, carved per call, grown on demand
+// ---------------------------------------------------------------------------
+struct Arena {
+  char *base = nullptr;
+  size_t cap = 0;
+  int device = -1;
+  hipEvent_t last = nullptr;  // completion of the last call that used the arena
+  hipStream_t last_stream = nullptr;
+};
+std::mutex g_mutex;
+Arena g_arena;
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Collects sub-allocation requests, then binds them into the arena.
+struct Layout {
+  struct Req { void **slot; size_t bytes; };
+  std::vector<Req> reqs;
+  size_t total = 0;
+  template <class T>
+  void add(T **slot, size_t count) {
+    reqs.push_back({reinterpret_cast<void **>(slot), count * sizeof(T)});
+    total += align_up(std::max<size_t>(count * sizeof(T), 1));
+  }
+};
+
+inla_status arena_bind(Layout &L, hipStream_t s) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (g_arena.base && g_arena.device != dev) {
+    return fail(INLA_ERR_STATE, "library workspace is bound to another device");
+  }
+  // order this call after the previous user of the arena
+  if (g_arena.last && g_arena.last_stream != s) HIP_TRY(hipStreamWaitEvent(s, g_arena.last, 0));
+  if (L.total > g_arena.cap) {
+    if (g_arena.base) {
+      HIP_TRY(hipDeviceSynchronize());
+      HIP_TRY(hipFree(g_arena.base));
+      g_arena.base = nullptr;
+      g_arena.cap = 0;
+    }
+    size_t want = align_up(L.total);
+    void *p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(INLA_ERR_NOMEM, "device workspace allocation of " + std::to_string(want) +
+                                      " bytes failed");
+    }
+    g_arena.base = static_cast<char *>(p);
+    g_arena.cap = want;
+    g_arena.device = dev;
+  }
+  size_t off = 0;
+  for (auto &r : L.reqs) {
+    *r.slot = g_arena.base + off;
+    off += align_up(std::max<size_t>(r.bytes, 1));
+  }
+  return INLA_OK;
+}
+
+inla_status arena_done(hipStream_t s) {
+  if (!g_arena.last) HIP_TRY(hipEventCreateWithFlags(&g_arena.last, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(g_arena.last, s));
+  g_arena.last_stream = s;
+  return INLA_OK;
+}
+
+template <class T>
+inla_status upload(T *dst, const std::vector<T> &src, hipStream_t s) {
+  if (src.empty()) return INLA_OK;
+  HIP_TRY(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return INLA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// phase sequences
+// ---------------------------------------------------------------------------
+struct Batch {
+  std::vector<ItemDev> host;
+  ItemDev *dev = nullptr;
+  int max_nt = 0, max_b = 0, max_a = 0;
+  void finalize() {
+    for (auto &it : host) {
+      max_nt = std::max(max_nt, it.nt);
+      max_b = std::max(max_b, it.b);
+      max_a = std::max(max_a, it.a);
+    }
+  }
+};
+
+inla_status run_phase(const Batch &B, int phase, int t, int p, hipStream_t s) {
+  long long total = 0;
+  for (const auto &it : B.host) total += phase_tasks(it, phase, t, p);
+  if (total > INT_MAX) return fail(INLA_ERR_ARG, "too many tile tasks in one launch");
+  HIP_TRY(launch_tile_phase(B.dev, (int)B.host.size(), (int)total, phase, t, p, s));
+  return INLA_OK;
+}
+
+#define ST_TRY(expr)                     \
+  do {                                   \
+    inla_status st_ = (expr);            \
+    if (st_ != INLA_OK) return st_;      \
+  } while (0)
+
+inla_status run_factor(const Batch &B, hipStream_t s) {
+  for (int t = 0; t < B.max_nt; ++t) {
+    ST_TRY(run_phase(B, PH_DIAG0, t, 0, s));
+    int mp = 0;
+    for (const auto &it : B.host)
+      if (t < it.nt) mp = std::max(mp, it.nP);
+    for (int p = 0; p < mp; ++p) {
+      ST_TRY(run_phase(B, PH_PANEL, t, p, s));
+      if (p + 1 < mp) ST_TRY(run_phase(B, PH_TRAIL, t, p, s));
+    }
+    ST_TRY(run_phase(B, PH_OFFDIAG, t, 0, s));
+    ST_TRY(run_phase(B, PH_SCHUR, t, 0, s));
+  }
+  ST_TRY(run_phase(B, PH_ARROW, 0, 0, s));
+  return INLA_OK;
+}
+
+inla_status run_selinv(const Batch &B, bool traces, hipStream_t s) {
+  const int n = (int)B.host.size();
+  ST_TRY(run_phase(B, PH_SI_INIT, 0, 0, s));
+  if (traces) HIP_TRY(launch_trace_step(B.dev, n, -1, s));
+  for (int t = B.max_nt - 1; t >= 0; --t) {
+    ST_TRY(run_phase(B, PH_SI_VU, t, 0, s));
+    ST_TRY(run_phase(B, PH_SI_SR, t, 0, s));
+    ST_TRY(run_phase(B, PH_SI_SD, t, 0, s));
+    if (traces) HIP_TRY(launch_trace_step(B.dev, n, t, s));
+  }
+  return INLA_OK;
+}
+
+inla_status run_solve(const Batch &B, double *const *xs_dev, double *const *tmps_dev, hipStream_t s) {
+  const int n = (int)B.host.size();
+  for (int t = 0; t < B.max_nt; ++t) {
+    HIP_TRY(launch_solve_stage(B.dev, n, B.max_b, B.max_a, t, SV_F1, xs_dev, tmps_dev, s));
+    HIP_TRY(launch_solve_stage(B.dev, n, B.max_b, B.max_a, t, SV_F2, xs_dev, tmps_dev, s));
+  }
+  if (B.max_a > 0) {
+    HIP_TRY(launch_solve_stage(B.dev, n, B.max_b, B.max_a, 0, SV_FA1, xs_dev, tmps_dev, s));
+    HIP_TRY(launch_solve_stage(B.dev, n, B.max_b, B.max_a, 0, SV_FA2, xs_dev, tmps_dev, s));
+    HIP_TRY(launch_solve_stage(B.dev, n, B.max_b, B.max_a, 0, SV_BA, xs_dev, tmps_dev, s));
+  }
+  for (int t = B.max_nt - 1; t >= 0; --t) {
+    HIP_TRY(launch_solve_stage(B.dev, n, B.max_b, B.max_a, t, SV_B1, xs_dev, tmps_dev, s));
+    HIP_TRY(launch_solve_stage(B.dev, n, B.max_b, B.max_a, t, SV_B2, xs_dev, tmps_dev, s));
+  }
+  return INLA_OK;
+}
+
+inla_status check_bta(const inla_bta *q, const char *what) {
+  if (!q) return fail(INLA_ERR_ARG, std::string(what) + " is NULL");
+  if (q->b < 1 || q->nt < 1 || q->a < 0 || q->a > kMaxArrow)
+    return fail(INLA_ERR_ARG, std::string(what) + ": need b >= 1, nt >= 1, 0 <= a <= 64");
+  if (!q->D || (q->nt > 1 && !q->S) || (q->a > 0 && (!q->R || !q->T)))
+    return fail(INLA_ERR_ARG, std::string(what) + ": missing block pointer");
+  if ((long long)q->b * q->b > (1LL << 40))
+    return fail(INLA_ERR_ARG, std::string(what) + ": block too large");
+  return INLA_OK;
+}
+
+ItemDev item_from_bta(const inla_bta &q) {
+  ItemDev it;
+  std::memset(&it, 0, sizeof(it));
+  it.b = q.b; it.nt = q.nt; it.a = q.a; it.nP = ntile(q.b);
+  it.D = q.D; it.S = q.S; it.R = q.R; it.T = q.T;
+  return it;
+}
+
+// Workspace of one item's factorization.
+void layout_factor_ws(Layout &L, ItemDev &it) {
+  const size_t bb = (size_t)it.b * it.b;
+  L.add(&it.W1, bb);
+  L.add(&it.W2, bb);
+  L.add(&it.W3, std::max<size_t>((size_t)it.a * it.b, 1));
+  L.add(&it.ldpart, (size_t)it.nt * it.nP + 1);
+  L.add(&it.info, 1);
+}
+
+// Workspace of one item's selected inversion when Sigma is streamed.
+void layout_selinv_ws(Layout &L, ItemDev &it) {
+  const size_t bb = (size_t)it.b * it.b;
+  L.add(&it.SD, 2 * bb);
+  L.add(&it.SR, std::max<size_t>(2 * (size_t)it.a * it.b, 1));
+  L.add(&it.ST, std::max<size_t>((size_t)it.a * it.a, 1));
+}
+
+size_t bta_doubles(int b, int nt, int a) {
+  return (size_t)(2 * nt - 1) * b * b + (size_t)nt * a * b + (size_t)a * a;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// model
+// ---------------------------------------------------------------------------
+struct inla_model {
+  ModelDev host;      // field values with device pointers
+  ModelDev *dev = nullptr;
+  void *mem = nullptr;
+  int device = 0;
+  long long n = 0, m = 0;
+};
+
+namespace {
+
+struct HostModel {
+  int N, nt, a, b;
+  std::vector<int> colptr, rowidx, colidx;
+  std::vector<double> pdelta, pg1, pg2, AtA, ZtA, ZtZ, Aty;
+};
+
+inla_status build_host_model(const inla_model_desc &d, HostModel &hm) {
+  const int N = d.N, nt = d.nt, a = d.nb;
+  const int b = N * N;
+  const long long nst = (long long)b * nt, n = nst + a;
+  hm.N = N; hm.nt = nt; hm.a = a; hm.b = b;
+  // Q_s pattern: all nodes within grid distance |dx| + |dy| <= 2 of each node
+  // (the reach of G^2), plus any extra pair that A^T A couples.
+  std::vector<std::vector<int>> rows(b);
+  auto grid_ok = [&](int x, int y) { return x >= 0 && x < N && y >= 0 && y < N; };
+  for (int sy = 0; sy < N; ++sy)
+    for (int sx = 0; sx < N; ++sx) {
+      auto &r = rows[sy * N + sx];
+      for (int dy = -2; dy <= 2; ++dy)
+        for (int dx = -2; dx <= 2; ++dx)
+          if (std::abs(dx) + std::abs(dy) <= 2 && grid_ok(sx + dx, sy + dy))
+            r.push_back((sy + dy) * N + (sx + dx));
+    }
+  // validate A and collect extra couplings
+  for (long long j = 0; j < d.m; ++j) {
+    const long long e0 = d.A_rowptr[j], e1 = d.A_rowptr[j + 1];
+    if (e1 < e0) return fail(INLA_ERR_ARG, "A_rowptr is not non-decreasing");
+    int tj = -1;
+    for (long long e = e0; e < e1; ++e) {
+      const long long c = d.A_col[e];
+      if (c < 0 || c >= n) return fail(INLA_ERR_ARG, "A column index out of range");
+      if (c < nst) {
+        const int t = (int)(c / b);
+        if (tj >= 0 && t != tj) return fail(INLA_ERR_ARG, "an observation couples two time blocks");
+        tj = t;
+      }
+    }
+    for (long long e = e0; e < e1; ++e) {
+      const long long ce = d.A_col[e];
+      if (ce >= nst) continue;
+      const int se = (int)(ce % b);
+      for (long long f = e0; f < e1; ++f) {
+        const long long cf = d.A_col[f];
+        if (cf >= nst) continue;
+        const int sf = (int)(cf % b);
+        const int ex = se % N, ey = se / N, fx = sf % N, fy = sf / N;
+        if (std::abs(ex - fx) + std::abs(ey - fy) > 2) rows[sf].push_back(se);
+      }
+    }
+  }
+  hm.colptr.assign(b + 1, 0);
+  for (int s = 0; s < b; ++s) {
+    auto &r = rows[s];
+    std::sort(r.begin(), r.end());
+    r.erase(std::unique(r.begin(), r.end()), r.end());
+    hm.colptr[s + 1] = hm.colptr[s] + (int)r.size();
+  }
+  const int nnz = hm.colptr[b];
+  hm.rowidx.resize(nnz);
+  hm.colidx.resize(nnz);
+  for (int s = 0; s < b; ++s)
+    for (size_t k = 0; k < rows[s].size(); ++k) {
+      hm.rowidx[hm.colptr[s] + k] = rows[s][k];
+      hm.colidx[hm.colptr[s] + k] = s;
+    }
+  auto find = [&](int i, int s) -> int {
+    const int *lo = hm.rowidx.data() + hm.colptr[s], *hi = hm.rowidx.data() + hm.colptr[s + 1];
+    const int *p = std::lower_bound(lo, hi, i);
+    return (p != hi && *p == i) ? (int)(p - hm.rowidx.data()) : -1;
+  };
+  // G (4-neighbour Neumann Laplacian) and G^2 on the pattern
+  auto Gval = [&](int i, int s) -> double {
+    const int ix = i % N, iy = i / N, sx = s % N, sy = s / N;
+    if (i == s) {
+      int deg = 0;
+      if (sx > 0) ++deg;
+      if (sx < N - 1) ++deg;
+      if (sy > 0) ++deg;
+      if (sy < N - 1) ++deg;
+      return deg;
+    }
+    return (std::abs(ix - sx) + std::abs(iy - sy) == 1) ? -1.0 : 0.0;
+  };
+  hm.pdelta.assign(nnz, 0.0);
+  hm.pg1.assign(nnz, 0.0);
+  hm.pg2.assign(nnz, 0.0);
+  for (int s = 0; s < b; ++s) {
+    const int sx = s % N, sy = s / N;
+    for (int e = hm.colptr[s]; e < hm.colptr[s + 1]; ++e) {
+      const int i = hm.rowidx[e];
+      hm.pdelta[e] = (i == s) ? 1.0 : 0.0;
+      hm.pg1[e] = Gval(i, s);
+      // (G^2)(i,s) = sum_u G(i,u) G(u,s), u over s and its neighbours
+      double g2 = 0.0;
+      const int us[5][2] = {{0, 0}, {-1, 0}, {1, 0}, {0, -1}, {0, 1}};
+      for (auto &du : us) {
+        const int ux = sx + du[0], uy = sy + du[1];
+        if (!grid_ok(ux, uy)) continue;
+        const int u = uy * N + ux;
+        g2 += Gval(i, u) * Gval(u, s);
+      }
+      hm.pg2[e] = g2;
+    }
+  }
+  // A^T A per time block, Z^T A_t, Z^T Z, A^T y (row order: deterministic sums)
+  hm.AtA.assign((size_t)nt * nnz, 0.0);
+  hm.ZtA.assign((size_t)nt * a * b, 0.0);
+  hm.ZtZ.assign((size_t)a * a, 0.0);
+  hm.Aty.assign((size_t)n, 0.0);
+  for (long long j = 0; j < d.m; ++j) {
+    const long long e0 = d.A_rowptr[j], e1 = d.A_rowptr[j + 1];
+    const double yj = d.y[j];
+    for (long long e = e0; e < e1; ++e) hm.Aty[d.A_col[e]] += d.A_val[e] * yj;
+    for (long long e = e0; e < e1; ++e) {
+      const long long ce = d.A_col[e];
+      const double ve = d.A_val[e];
+      for (long long f = e0; f < e1; ++f) {
+        const long long cf = d.A_col[f];
+        const double vf = d.A_val[f];
+        if (ce < nst && cf < nst) {
+          const int t = (int)(ce / b);
+          const int k = find((int)(ce % b), (int)(cf % b));
+          hm.AtA[(size_t)t * nnz + k] += ve * vf;
+        } else if (ce >= nst && cf < nst) {
+          const int t = (int)(cf / b);
+          hm.ZtA[(size_t)t * a * b + (size_t)(cf % b) * a + (ce - nst)] += ve * vf;
+        } else if (ce >= nst && cf >= nst) {
+          hm.ZtZ[(size_t)(ce - nst) + (size_t)(cf - nst) * a] += ve * vf;
+        }
+      }
+    }
+  }
+  return INLA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *inla_status_string(inla_status s) {
+  switch (s) {
+    case INLA_OK: return "ok";
+    case INLA_ERR_ARG: return "invalid argument";
+    case INLA_ERR_NOT_SPD: return "matrix not positive definite";
+    case INLA_ERR_BUDGET: return "item exceeds the HBM budget";
+    case INLA_ERR_HIP: return "HIP runtime error";
+    case INLA_ERR_NOMEM: return "out of memory";
+    case INLA_ERR_STATE: return "library not usable";
+  }
+  return "unknown status";
+}
+
+const char *inla_last_error(void) { return g_last_error.c_str(); }
+
+inla_status inla_model_create(const inla_model_desc *desc, void *hip_stream, inla_model **out) {
+  g_last_error.clear();
+  if (!desc || !out) return fail(INLA_ERR_ARG, "desc and out must be non-NULL");
+  *out = nullptr;
+  const inla_model_desc &d = *desc;
+  if (d.N < 1 || d.nt < 1 || d.nb < 0 || d.nb > kMaxArrow)
+    return fail(INLA_ERR_ARG, "need N >= 1, nt >= 1, 0 <= nb <= 64");
+  if (!(d.h > 0.0) || !(d.beta_prior_prec > 0.0))
+    return fail(INLA_ERR_ARG, "need h > 0 and beta_prior_prec > 0");
+  if (d.m < 1 || !d.A_rowptr || !d.A_col || !d.A_val || !d.y || !d.theta_prior_mean ||
+      !d.theta_prior_prec)
+    return fail(INLA_ERR_ARG, "missing observation data or hyperprior");
+  if ((long long)d.N * d.N > 65536) return fail(INLA_ERR_ARG, "N*N above 65536 not supported");
+  for (int k = 0; k < 4; ++k)
+    if (!(d.theta_prior_prec[k] > 0.0)) return fail(INLA_ERR_ARG, "hyperprior precision must be > 0");
+  HostModel hm;
+  ST_TRY(build_host_model(d, hm));
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  inla_model *M = new inla_model();
+  HIP_TRY(hipGetDevice(&M->device));
+  const int b = hm.b, nt = hm.nt, a = hm.a;
+  const long long n = (long long)b * nt + a;
+  const long long nnzA = d.A_rowptr[d.m];
+  M->n = n;
+  M->m = d.m;
+  ModelDev &h = M->host;
+  std::memset(&h, 0, sizeof(h));
+  h.N = d.N; h.nt = nt; h.a = a; h.b = b; h.m = d.m; h.n = n; h.h = d.h;
+  h.beta_prec = d.beta_prior_prec;
+  for (int k = 0; k < 4; ++k) {
+    h.prior_mean[k] = d.theta_prior_mean[k];
+    h.prior_prec[k] = d.theta_prior_prec[k];
+  }
+  h.nnz = hm.colptr[b];
+  Layout L;
+  int *colptr, *rowidx, *colidx, *A_col;
+  double *pdelta, *pg1, *pg2, *AtA, *ZtA, *ZtZ, *Aty, *A_val, *y;
+  long long *A_rowptr;
+  ModelDev *mdev;
+  L.add(&mdev, 1);
+  L.add(&colptr, hm.colptr.size());
+  L.add(&rowidx, hm.rowidx.size());
+  L.add(&colidx, hm.colidx.size());
+  L.add(&pdelta, hm.pdelta.size());
+  L.add(&pg1, hm.pg1.size());
+  L.add(&pg2, hm.pg2.size());
+  L.add(&AtA, hm.AtA.size());
+  L.add(&ZtA, std::max<size_t>(hm.ZtA.size(), 1));
+  L.add(&ZtZ, std::max<size_t>(hm.ZtZ.size(), 1));
+  L.add(&Aty, hm.Aty.size());
+  L.add(&A_rowptr, (size_t)d.m + 1);
+  L.add(&A_col, (size_t)nnzA);
+  L.add(&A_val, (size_t)nnzA);
+  L.add(&y, (size_t)d.m);
+  if (hipMalloc(&M->mem, L.total) != hipSuccess) {
+    (void)hipGetLastError();
+    delete M;
+    return fail(INLA_ERR_NOMEM, "model allocation failed");
+  }
+  size_t off = 0;
+  for (auto &r : L.reqs) {
+    *r.slot = static_cast<char *>(M->mem) + off;
+    off += align_up(std::max<size_t>(r.bytes, 1));
+  }
+  auto put = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
+    if (!bytes) return hipSuccess;
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+  };
+  h.colptr = colptr; h.rowidx = rowidx; h.colidx = colidx; h.pdelta = pdelta; h.pg1 = pg1;
+  h.pg2 = pg2; h.AtA = AtA; h.ZtA = ZtA; h.ZtZ = ZtZ; h.Aty = Aty; h.A_rowptr = A_rowptr;
+  h.A_col = A_col; h.A_val = A_val; h.y = y;
+  hipError_t e = hipSuccess;
+  if (!e) e = put(colptr, hm.colptr.data(), hm.colptr.size() * sizeof(int));
+  if (!e) e = put(rowidx, hm.rowidx.data(), hm.rowidx.size() * sizeof(int));
+  if (!e) e = put(colidx, hm.colidx.data(), hm.colidx.size() * sizeof(int));
+  if (!e) e = put(pdelta, hm.pdelta.data(), hm.pdelta.size() * sizeof(double));
+  if (!e) e = put(pg1, hm.pg1.data(), hm.pg1.size() * sizeof(double));
+  if (!e) e = put(pg2, hm.pg2.data(), hm.pg2.size() * sizeof(double));
+  if (!e) e = put(AtA, hm.AtA.data(), hm.AtA.size() * sizeof(double));
+  if (!e) e = put(ZtA, hm.ZtA.data(), hm.ZtA.size() * sizeof(double));
+  if (!e) e = put(ZtZ, hm.ZtZ.data(), hm.ZtZ.size() * sizeof(double));
+  if (!e) e = put(Aty, hm.Aty.data(), hm.Aty.size() * sizeof(double));
+  if (!e) e = put(A_rowptr, d.A_rowptr, ((size_t)d.m + 1) * sizeof(long long));
+  if (!e) e = put(A_col, d.A_col, (size_t)nnzA * sizeof(int));
+  if (!e) e = put(A_val, d.A_val, (size_t)nnzA * sizeof(double));
+  if (!e) e = put(y, d.y, (size_t)d.m * sizeof(double));
+  if (!e) e = put(mdev, &h, sizeof(ModelDev));
+  if (!e) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipFree(M->mem);
+    delete M;
+    return fail(INLA_ERR_HIP, std::string("model upload: ") + hipGetErrorString(e));
+  }
+  M->dev = mdev;
+  *out = M;
+  return INLA_OK;
+}
+
+void inla_model_destroy(inla_model *model) {
+  if (!model) return;
+  {
+    std::lock_guard<std::mutex> lk(g_mutex);
+    if (g_arena.last) (void)hipEventSynchronize(g_arena.last);
+  }
+  if (model->mem) (void)hipFree(model->mem);
+  delete model;
+}
+
+inla_status inla_model_shape(const inla_model *model, int32_t *b, int32_t *nt, int32_t *a,
+                             int64_t *n, int64_t *m) {
+  if (!model) return fail(INLA_ERR_ARG, "model is NULL");
+  if (b) *b = model->host.b;
+  if (nt) *nt = model->host.nt;
+  if (a) *a = model->host.a;
+  if (n) *n = model->n;
+  if (m) *m = model->m;
+  return INLA_OK;
+}
+
+inla_status inla_assemble(const inla_model *model, const double *theta_dev, int32_t which,
+                          inla_bta *out, double *rhs_dev, void *hip_stream) {
+  g_last_error.clear();
+  if (!model || !theta_dev) return fail(INLA_ERR_ARG, "model and theta must be non-NULL");
+  if (which != 0 && which != 1) return fail(INLA_ERR_ARG, "which must be 0 or 1");
+  ST_TRY(check_bta(out, "out"));
+  const ModelDev &h = model->host;
+  if (out->b != h.b || out->nt != h.nt || out->a != h.a)
+    return fail(INLA_ERR_ARG, "out shape does not match the model");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  HIP_TRY(launch_assemble(model->dev, h.b, h.nt, h.a, theta_dev, which, out->D, out->S, out->R,
+                          out->T, which ? rhs_dev : nullptr, s));
+  return INLA_OK;
+}
+
+inla_status inla_factor_logdet(inla_bta *QL, double *logdet_dev, int32_t *info_dev,
+                               void *hip_stream) {
+  g_last_error.clear();
+  ST_TRY(check_bta(QL, "QL"));
+  std::lock_guard<std::mutex> lk(g_mutex);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  Batch B;
+  B.host.push_back(item_from_bta(*QL));
+  Layout L;
+  layout_factor_ws(L, B.host[0]);
+  L.add(&B.dev, 1);
+  double *ld_tmp;
+  int *info_tmp;
+  L.add(&ld_tmp, 1);
+  L.add(&info_tmp, 1);
+  ST_TRY(arena_bind(L, s));
+  B.finalize();
+  HIP_TRY(launch_fill_int(B.host[0].info, 1, kInfoNone, s));
+  ST_TRY(upload(B.dev, B.host, s));
+  ST_TRY(run_factor(B, s));
+  HIP_TRY(launch_logdet_finish(B.dev, 1, logdet_dev ? logdet_dev : ld_tmp,
+                               info_dev ? info_dev : info_tmp, s));
+  return arena_done(s);
+}
+
+inla_status inla_solve(const inla_bta *L_, const double *rhs_dev, double *x_dev, int32_t nrhs,
+                       void *hip_stream) {
+  g_last_error.clear();
+  ST_TRY(check_bta(L_, "L"));
+  if (nrhs < 1 || !rhs_dev || !x_dev) return fail(INLA_ERR_ARG, "need nrhs >= 1 and vectors");
+  std::lock_guard<std::mutex> lk(g_mutex);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const long long n = (long long)L_->b * L_->nt + L_->a;
+  Batch B;
+  for (int r = 0; r < nrhs; ++r) B.host.push_back(item_from_bta(*L_));
+  B.finalize();
+  Layout L;
+  L.add(&B.dev, nrhs);
+  double **xs, **tmps, *tmp;
+  L.add(&xs, nrhs);
+  L.add(&tmps, nrhs);
+  const size_t tl = std::max(L_->b, std::max(L_->a, 1));
+  L.add(&tmp, tl * nrhs);
+  ST_TRY(arena_bind(L, s));
+  if (x_dev != rhs_dev)
+    HIP_TRY(hipMemcpyAsync(x_dev, rhs_dev, (size_t)n * nrhs * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+  std::vector<double *> hx(nrhs), ht(nrhs);
+  for (int r = 0; r < nrhs; ++r) {
+    hx[r] = x_dev + (size_t)r * n;
+    ht[r] = tmp + (size_t)r * tl;
+  }
+  ST_TRY(upload(B.dev, B.host, s));
+  ST_TRY(upload(xs, hx, s));
+  ST_TRY(upload(tmps, ht, s));
+  ST_TRY(run_solve(B, xs, tmps, s));
+  return arena_done(s);
+}
+
+inla_status inla_selinv(const inla_bta *L_, inla_bta *sigma_or_null, double *diag_or_null,
+                        void *hip_stream) {
+  g_last_error.clear();
+  ST_TRY(check_bta(L_, "L"));
+  if (sigma_or_null) {
+    ST_TRY(check_bta(sigma_or_null, "sigma"));
+    if (sigma_or_null->b != L_->b || sigma_or_null->nt != L_->nt || sigma_or_null->a != L_->a)
+      return fail(INLA_ERR_ARG, "sigma shape does not match L");
+  }
+  std::lock_guard<std::mutex> lk(g_mutex);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  Batch B;
+  B.host.push_back(item_from_bta(*L_));
+  ItemDev &it = B.host[0];
+  Layout L;
+  const size_t bb = (size_t)it.b * it.b;
+  L.add(&it.W2, bb);
+  L.add(&it.W3, std::max<size_t>((size_t)it.a * it.b, 1));
+  if (sigma_or_null) {
+    it.SD = sigma_or_null->D; it.sd_stride = (long long)bb;
+    it.SS = sigma_or_null->S; it.ss_stride = (long long)bb;
+    it.SR = sigma_or_null->R; it.sr_stride = (long long)it.a * it.b;
+    it.ST = sigma_or_null->T;
+  } else {
+    layout_selinv_ws(L, it);
+    L.add(&it.SS, bb);
+  }
+  it.diag = diag_or_null;
+  L.add(&B.dev, 1);
+  ST_TRY(arena_bind(L, s));
+  B.finalize();
+  ST_TRY(upload(B.dev, B.host, s));
+  ST_TRY(run_selinv(B, diag_or_null != nullptr, s));
+  return arena_done(s);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched f(theta) and gradient
+// ---------------------------------------------------------------------------
+namespace {
+
+struct ThetaItemBufs {
+  ItemDev P, C;
+  double *x = nullptr, *tmp = nullptr, *term = nullptr;
+};
+
+size_t theta_item_bytes(const ModelDev &h, bool selinv) {
+  const size_t bb = (size_t)h.b * h.b, ab = (size_t)h.a * h.b;
+  const int nP = ntile(h.b);
+  size_t per = bta_doubles(h.b, h.nt, h.a) * 8 + (2 * bb + ab) * 8 + ((size_t)h.nt * nP + 1) * 8 +
+               4 * kAlign * 4;
+  if (selinv) per += (2 * bb + 2 * ab + (size_t)h.a * h.a) * 8 + ((size_t)h.nt + 1) * 32;
+  return 2 * per + ((size_t)h.n + std::max(h.b, h.a) + kTermBlocks * 4) * 8 + 4096;
+}
+
+inla_status eval_impl(const inla_model *const *models, int32_t n_items, const double *theta_dev,
+                      double *f_dev, double *grad_dev, double *mu_out, double *var_out,
+                      int32_t *status_dev, const inla_opts *opts, hipStream_t s) {
+  if (!models || n_items < 1 || !theta_dev || !f_dev)
+    return fail(INLA_ERR_ARG, "need models, n_items >= 1, theta and f");
+  for (int i = 0; i < n_items; ++i)
+    if (!models[i]) return fail(INLA_ERR_ARG, "NULL model in batch");
+  if (opts && opts->keep_sigma != 0) return fail(INLA_ERR_ARG, "keep_sigma is reserved (must be 0)");
+  const bool grad = grad_dev != nullptr;
+  const bool need_selinv = grad || var_out != nullptr;
+  // HBM admission: split the items into waves whose storage fits the budget
+  double budget = opts ? opts->hbm_budget_bytes : 0.0;
+  if (!(budget > 0.0)) {
+    size_t fr = 0, tot = 0;
+    HIP_TRY(hipMemGetInfo(&fr, &tot));
+    budget = (double)fr + (double)g_arena.cap - 4.0 * (1ULL << 30);
+  }
+  std::vector<size_t> bytes(n_items);
+  for (int i = 0; i < n_items; ++i) {
+    bytes[i] = theta_item_bytes(models[i]->host, need_selinv);
+    if ((double)bytes[i] > budget)
+      return fail(INLA_ERR_BUDGET, "item " + std::to_string(i) + " needs " +
+                                       std::to_string(bytes[i]) + " bytes, above the HBM budget");
+  }
+  // per-item output offsets into the concatenated mu / var buffers
+  std::vector<long long> voff(n_items + 1, 0);
+  for (int i = 0; i < n_items; ++i) voff[i + 1] = voff[i] + models[i]->n;
+  int start = 0;
+  while (start < n_items) {
+    int end = start;
+    double acc = 0.0;
+    while (end < n_items && acc + (double)bytes[end] <= budget) acc += (double)bytes[end++];
+    const int k = end - start;
+    std::vector<ThetaItemBufs> tb(k);
+    Layout L;
+    std::vector<double *> Dbase(2 * k);
+    for (int q = 0; q < k; ++q) {
+      const ModelDev &h = models[start + q]->host;
+      for (int w = 0; w < 2; ++w) {
+        ItemDev &it = w ? tb[q].C : tb[q].P;
+        std::memset(&it, 0, sizeof(it));
+        it.b = h.b; it.nt = h.nt; it.a = h.a; it.nP = ntile(h.b);
+        it.which = w;
+        it.model = models[start + q]->dev;
+        it.theta = theta_dev + 4 * (start + q);
+        L.add(&Dbase[2 * q + w], bta_doubles(h.b, h.nt, h.a));
+        layout_factor_ws(L, it);
+        if (need_selinv) {
+          layout_selinv_ws(L, it);
+          if (grad) L.add(&it.trpart, ((size_t)h.nt + 1) * 4);
+        }
+      }
+      if (!mu_out) L.add(&tb[q].x, (size_t)h.n);
+      L.add(&tb[q].tmp, (size_t)std::max(h.b, std::max(h.a, 1)));
+      L.add(&tb[q].term, (size_t)kTermBlocks * 4);
+    }
+    ItemDev *fdev, *sdev, *vdev;
+    double **xs, **tmps, *logdet;
+    int *info;
+    TermItem *tdev;
+    CombineItem *cdev;
+    L.add(&fdev, 2 * k);
+    L.add(&sdev, k);
+    L.add(&vdev, 2 * k);
+    L.add(&xs, k);
+    L.add(&tmps, k);
+    L.add(&logdet, 2 * k);
+    L.add(&info, 2 * k);
+    L.add(&tdev, k);
+    L.add(&cdev, k);
+    ST_TRY(arena_bind(L, s));
+    // carve BTA storage and finish descriptors
+    Batch F, Sv, Si;
+    std::vector<double *> hx(k), ht(k);
+    std::vector<TermItem> th(k);
+    std::vector<CombineItem> ch(k);
+    for (int q = 0; q < k; ++q) {
+      const int i = start + q;
+      const ModelDev &h = models[i]->host;
+      const size_t bb = (size_t)h.b * h.b;
+      for (int w = 0; w < 2; ++w) {
+        ItemDev &it = w ? tb[q].C : tb[q].P;
+        double *base = Dbase[2 * q + w];
+        it.D = base;
+        it.S = h.nt > 1 ? base + (size_t)h.nt * bb : nullptr;
+        it.R = h.a > 0 ? base + (size_t)(2 * h.nt - 1) * bb : nullptr;
+        it.T = h.a > 0 ? it.R + (size_t)h.nt * h.a * h.b : nullptr;
+        if (need_selinv) it.SS = it.W1;
+        if (w == 1 && var_out) it.diag = var_out + voff[i];
+      }
+      if (mu_out) tb[q].x = mu_out + voff[i];
+      hx[q] = tb[q].x;
+      ht[q] = tb[q].tmp;
+      F.host.push_back(tb[q].P);
+      F.host.push_back(tb[q].C);
+      Sv.host.push_back(tb[q].C);
+      if (grad) Si.host.push_back(tb[q].P);
+      if (need_selinv) Si.host.push_back(tb[q].C);
+      th[q] = TermItem{models[i]->dev, theta_dev + 4 * i, tb[q].x, tb[q].term};
+      CombineItem c;
+      std::memset(&c, 0, sizeof(c));
+      c.model = models[i]->dev;
+      c.theta = theta_dev + 4 * i;
+      c.term_part = tb[q].term;
+      c.mu = tb[q].x;
+      c.logdet = logdet + 2 * q;
+      c.trp = grad ? tb[q].P.trpart : nullptr;
+      c.trc = grad ? tb[q].C.trpart : nullptr;
+      c.info = info + 2 * q;
+      c.f = f_dev + i;
+      c.grad = grad ? grad_dev + 4 * i : nullptr;
+      c.status = status_dev ? status_dev + i : nullptr;
+      ch[q] = c;
+    }
+    F.dev = fdev; Sv.dev = sdev; Si.dev = vdev;
+    F.finalize(); Sv.finalize(); Si.finalize();
+    ST_TRY(upload(fdev, F.host, s));
+    ST_TRY(upload(sdev, Sv.host, s));
+    if (need_selinv) ST_TRY(upload(vdev, Si.host, s));
+    ST_TRY(upload(xs, hx, s));
+    ST_TRY(upload(tmps, ht, s));
+    ST_TRY(upload(tdev, th, s));
+    ST_TRY(upload(cdev, ch, s));
+    // assemble Q_prior, Q_c and b = tau_y A^T y (into x, solved in place)
+    for (int q = 0; q < k; ++q) {
+      const int i = start + q;
+      const ModelDev &h = models[i]->host;
+      for (int w = 0; w < 2; ++w) {
+        ItemDev &it = w ? tb[q].C : tb[q].P;
+        HIP_TRY(launch_assemble(models[i]->dev, h.b, h.nt, h.a, theta_dev + 4 * i, w, it.D, it.S,
+                                it.R, it.T, w ? tb[q].x : nullptr, s));
+        HIP_TRY(launch_fill_int(it.info, 1, kInfoNone, s));
+      }
+    }
+    ST_TRY(run_factor(F, s));
+    HIP_TRY(launch_logdet_finish(fdev, 2 * k, logdet, info, s));
+    ST_TRY(run_solve(Sv, xs, tmps, s));
+    HIP_TRY(launch_terms(tdev, k, s));
+    if (need_selinv) ST_TRY(run_selinv(Si, true, s));
+    HIP_TRY(launch_combine(cdev, k, s));
+    start = end;
+  }
+  return arena_done(s);
+}
+
+}  // namespace
+
+extern "C" {
+
+inla_status inla_eval_f(const inla_model *const *models, int32_t n_items, const double *theta_dev,
+                        double *f_dev, double *mu_or_null, double *var_or_null, int32_t *status_dev,
+                        const inla_opts *opts, void *hip_stream) {
+  g_last_error.clear();
+  std::lock_guard<std::mutex> lk(g_mutex);
+  return eval_impl(models, n_items, theta_dev, f_dev, nullptr, mu_or_null, var_or_null, status_dev,
+                   opts, static_cast<hipStream_t>(hip_stream));
+}
+
+inla_status inla_eval_f_grad(const inla_model *const *models, int32_t n_items,
+                             const double *theta_dev, double *f_dev, double *grad_dev,
+                             double *mu_or_null, double *var_or_null, int32_t *status_dev,
+                             const inla_opts *opts, void *hip_stream) {
+  g_last_error.clear();
+  if (!grad_dev) return fail(INLA_ERR_ARG, "grad_dev must be non-NULL");
+  std::lock_guard<std::mutex> lk(g_mutex);
+  return eval_impl(models, n_items, theta_dev, f_dev, grad_dev, mu_or_null, var_or_null,
+                   status_dev, opts, static_cast<hipStream_t>(hip_stream));
+}
+
+void inla_release_workspace(void) {
+  std::lock_guard<std::mutex> lk(g_mutex);
+  if (g_arena.base) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(g_arena.base);
+    g_arena.base = nullptr;
+    g_arena.cap = 0;
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,175 @@
+// Internal declarations shared by the device kernels and the host engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace inla {
+
+constexpr int kTile = 64;        // tile edge of the block kernels (rows = cols)
+constexpr int kMaxArrow = 64;    // arrow (fixed-effect) width handled by one tile
+constexpr int kThreads = 256;    // threads per workgroup of the tile kernels
+constexpr int kInfoNone = 0x7fffffff;
+
+// Device view of one model (read-only after create).
+struct ModelDev {
+  int N, nt, a, b;               // grid side, time steps, arrow width, block size N*N
+  long long m;                   // observations
+  long long n;                   // latent dimension b*nt + a
+  double h, beta_prec;
+  double prior_mean[4], prior_prec[4];
+  // union pattern of Q_s and of every A_t^T A_t, column-compressed over b x b
+  int nnz;
+  int pad_;
+  const int *colptr;             // b + 1
+  const int *rowidx;             // nnz
+  const int *colidx;             // nnz: column of each pattern entry
+  const double *pdelta;          // nnz: identity entry (1 on the diagonal)
+  const double *pg1;             // nnz: grid Laplacian G
+  const double *pg2;             // nnz: G^2
+  const double *AtA;             // nt * nnz: (A_t^T A_t) on the pattern
+  const double *ZtA;             // nt * a * b: (Z^T A_t), column-major a x b per t
+  const double *ZtZ;             // a * a
+  const double *Aty;             // n: A^T y
+  const long long *A_rowptr;     // m + 1
+  const int *A_col;              // nnz(A)
+  const double *A_val;
+  const double *y;               // m
+};
+
+// Device descriptor of one BTA matrix in flight through factor / selinv.
+struct ItemDev {
+  int b, nt, a, nP;              // block size, time blocks, arrow width, ceil(b / kTile)
+  double *D, *S, *R, *T;         // BTA storage (Q in, factor out)
+  double *W1, *W2, *W3;          // workspace: b*b, b*b, a*b
+  // Selected inversion: Sigma blocks.  When sd_stride != 0 the blocks of step t
+  // live at SD + t*sd_stride etc. (caller storage); otherwise Sigma_D and
+  // Sigma_R ping-pong between two buffers by the parity of t and Sigma_S uses
+  // one buffer.
+  double *SD, *SS, *SR, *ST;
+  long long sd_stride, ss_stride, sr_stride;
+  double *ldpart;                // nt*nP + 1 partial sums of log L_jj
+  int *info;                     // first failing pivot (1-based row); kInfoNone = none
+  // outputs of the selected inversion
+  double *diag;                  // n marginal variances (or null)
+  double *trpart;                // (nt + 1) * 4 partial traces (or null)
+  const ModelDev *model;         // model whose derivative blocks the traces use (or null)
+  const double *theta;           // 4 hyperparameters of this item (device)
+  int which;                     // 0: Q_prior, 1: Q_c
+  int pad_;
+};
+
+__host__ __device__ inline double *sig_D(const ItemDev &it, int t) {
+  return it.sd_stride ? it.SD + (long long)t * it.sd_stride : it.SD + (long long)(t & 1) * it.b * it.b;
+}
+__host__ __device__ inline double *sig_S(const ItemDev &it, int t) {
+  return it.ss_stride ? it.SS + (long long)t * it.ss_stride : it.SS;
+}
+__host__ __device__ inline double *sig_R(const ItemDev &it, int t) {
+  return it.sr_stride ? it.SR + (long long)t * it.sr_stride : it.SR + (long long)(t & 1) * it.a * it.b;
+}
+
+// Phases of the tile kernels.
+enum Phase : int {
+  PH_DIAG0 = 0,      // POTRF + TRTRI of tile (0,0) of D[t]
+  PH_PANEL = 1,      // panel p: L[i,p] = A[i,p] Linv_pp^T (i > p); Linv row p
+  PH_TRAIL = 2,      // trailing update of panel p; diag tile p+1; copy Linv row p to D[t]
+  PH_OFFDIAG = 3,    // X = S[t] Linv^T, R' = R[t] Linv^T; copy last Linv row to D[t]
+  PH_SCHUR = 4,      // D[t+1] -= X X^T, R[t+1] -= R' X^T, T -= R' R'^T; copy X, R' back
+  PH_ARROW = 5,      // POTRF + TRTRI of T
+  PH_SI_INIT = 6,    // Sigma_T = Linv_AA^T Linv_AA
+  PH_SI_VU = 7,      // V = L_{t+1,t} Linv_tt, U = L_{A,t} Linv_tt
+  PH_SI_SR = 8,      // Sigma_S[t], Sigma_R[t]
+  PH_SI_SD = 9,      // Sigma_D[t] (lower tiles, mirrored)
+  PH_COUNT = 10
+};
+
+__host__ __device__ inline int ntile(int n) { return (n + kTile - 1) / kTile; }
+
+// Number of workgroup tasks of one item in (phase, t, p).
+__host__ __device__ inline int phase_tasks(const ItemDev &it, int phase, int t, int p) {
+  const int nP = it.nP;
+  const bool arrow = it.a > 0;
+  if (phase == PH_ARROW || phase == PH_SI_INIT) return arrow ? 1 : 0;
+  if (t >= it.nt) return 0;
+  const bool last = (t == it.nt - 1);
+  switch (phase) {
+    case PH_DIAG0: return 1;
+    case PH_PANEL:
+      if (p >= nP) return 0;
+      return (nP - 1 - p) + p;   // panel tiles below the diagonal + Linv row p tiles
+    case PH_TRAIL:
+      if (p >= nP - 1) return 0;
+      return (nP - 1 - p) * (nP - p) / 2 + (p + 1);
+    case PH_OFFDIAG:   // X tiles, R' tiles, copy of the last Linv row, zero upper tiles of D[t]
+      return (last ? 0 : nP * nP) + (arrow ? nP : 0) + nP + nP * (nP - 1) / 2;
+    case PH_SCHUR:
+      return (last ? 0 : nP * (nP + 1) / 2 + nP * nP) +
+             (arrow ? ((last ? 0 : nP) + 1 + nP) : 0);
+    case PH_SI_VU:
+      return (last ? 0 : nP * nP) + (arrow ? nP : 0);
+    case PH_SI_SR:
+      return (last ? 0 : nP * nP) + (arrow ? nP : 0);
+    case PH_SI_SD:
+      return nP * (nP + 1) / 2;
+    default: return 0;
+  }
+}
+
+// Phases that need the large-LDS kernel variant (in-tile Cholesky / left epilogue).
+__host__ __device__ inline bool phase_is_fat(int phase) {
+  return phase == PH_DIAG0 || phase == PH_PANEL || phase == PH_TRAIL || phase == PH_ARROW;
+}
+
+// ---- launch wrappers (bta_kernels.hip) ----
+hipError_t launch_tile_phase(const ItemDev *items_dev, int n_items, int total, int phase, int t,
+                             int p, hipStream_t s);
+hipError_t launch_fill(double *ptr, long long n, double v, hipStream_t s);
+hipError_t launch_fill_int(int *ptr, long long n, int v, hipStream_t s);
+hipError_t launch_logdet_finish(const ItemDev *items_dev, int n_items, double *logdet_out,
+                                int *info_out, hipStream_t s);
+// ---- model kernels (model_kernels.hip) ----
+// Assemble Q_prior (which = 0) or Q_c (which = 1) of one model into BTA storage;
+// with rhs != null also b = tau_y A^T y.
+hipError_t launch_assemble(const ModelDev *model_dev, int b, int nt, int a, const double *theta,
+                           int which, double *D, double *S, double *R, double *T, double *rhs,
+                           hipStream_t s);
+// One stage of the forward / backward substitution sweeps for a batch of
+// factors.  xs[i] (n_i doubles, device) holds the right-hand side on entry and
+// the solution on exit; tmps[i] is max(b_i, a_i) doubles of scratch.
+enum SolveStage : int { SV_F1 = 0, SV_F2 = 1, SV_FA1 = 2, SV_FA2 = 3, SV_BA = 4, SV_B1 = 5, SV_B2 = 6 };
+hipError_t launch_solve_stage(const ItemDev *items_dev, int n_items, int max_b, int max_a, int t,
+                              int stage, double *const *xs_dev, double *const *tmps_dev,
+                              hipStream_t s);
+// Traces of Sigma with the derivative blocks and the marginal variances of
+// time block t (t = -1: the arrow block).
+hipError_t launch_trace_step(const ItemDev *items_dev, int n_items, int t, hipStream_t s);
+// Posterior-mode terms: per item partial sums of mu^T Q_st mu, mu^T dQ2 mu,
+// mu^T dQ3 mu and |y - A mu|^2 (beta part included in the first).
+constexpr int kTermBlocks = 256;
+struct TermItem {
+  const ModelDev *model;
+  const double *theta;   // 4
+  const double *mu;      // n
+  double *part;          // kTermBlocks * 4
+};
+hipError_t launch_terms(const TermItem *items_dev, int n_items, hipStream_t s);
+// Final combination: f and gradient of each theta item.
+struct CombineItem {
+  const ModelDev *model;
+  const double *theta;
+  const double *term_part;   // kTermBlocks * 4
+  const double *mu;          // n (posterior mode)
+  const double *logdet;      // [0] = log|Q_p|, [1] = log|Q_c|
+  const double *trp;         // (nt + 1) * 4 partial traces of Q_p (or null)
+  const double *trc;         // (nt + 1) * 4 partial traces of Q_c (or null)
+  const int *info;           // [0] Q_p, [1] Q_c
+  double *f;                 // 1
+  double *grad;              // 4 (or null)
+  int *status;               // 1 (or null)
+  int pad_;
+};
+hipError_t launch_combine(const CombineItem *items_dev, int n_items, hipStream_t s);
+
+}  // namespace inla

@@ -1,0 +1,482 @@
+// Model-specific kernels: assembly of the BTA precision blocks, the block
+// substitution sweeps, the trace reductions of the selected inverse against
+// the derivative blocks, the posterior-mode terms and the final combination
+// of f(theta) and its gradient.
+//
+// Model (paper, Sec. "Latent Gaussian Models", latent vector without the
+// linear predictor): x = (u_0..u_{nt-1}, beta) is Gaussian with precision
+//   Q_prior = blockdiag(Q_AR1(rho) (x) Q_s(tau, kappa), beta_prec I),
+//   Q_s = (tau^2 / h^2) (kappa^2 h^2 I + G)^2,
+//   Q_AR1 = T(rho) / (1 - rho^2)  (stationary AR1, unit marginal variance),
+// observations y = A x + e, e ~ N(0, tau_y^{-1} I), so that
+//   Q_c = Q_prior + tau_y A^T A and the mode solves Q_c mu = tau_y A^T y.
+#include <cmath>
+
+#include "inla_internal.h"
+
+namespace inla {
+
+namespace {
+
+struct Coef {
+  double tau, kappa, rho, tauy;
+  double qsc;    // tau^2 / h^2
+  double k2;     // kappa^2 h^2
+  double dq2;    // 4 tau^2 kappa^2  (d Q_s / d log kappa = dq2 (k2 I + G))
+  double inv1mr2;
+};
+
+__device__ inline Coef make_coef(const ModelDev &M, const double *th) {
+  Coef c;
+  c.tau = exp(th[0]);
+  c.kappa = exp(th[1]);
+  c.rho = tanh(th[2]);
+  c.tauy = exp(th[3]);
+  c.qsc = c.tau * c.tau / (M.h * M.h);
+  c.k2 = c.kappa * c.kappa * M.h * M.h;
+  c.dq2 = 4.0 * c.tau * c.tau * c.kappa * c.kappa;
+  c.inv1mr2 = 1.0 / (1.0 - c.rho * c.rho);
+  return c;
+}
+
+// AR1 precision entries and their theta_3 derivatives (rho = tanh theta_3).
+__device__ inline double ar1_diag(const Coef &c, int t, int nt) {
+  if (nt == 1) return 1.0;
+  return (t == 0 || t == nt - 1) ? c.inv1mr2 : (1.0 + c.rho * c.rho) * c.inv1mr2;
+}
+__device__ inline double ar1_off(const Coef &c) { return -c.rho * c.inv1mr2; }
+__device__ inline double ar1_ddiag(const Coef &c, int t, int nt) {
+  if (nt == 1) return 0.0;
+  return (t == 0 || t == nt - 1) ? 2.0 * c.rho * c.inv1mr2 : 4.0 * c.rho * c.inv1mr2;
+}
+__device__ inline double ar1_doff(const Coef &c) { return -(1.0 + c.rho * c.rho) * c.inv1mr2; }
+
+// Q_s and dQ_s/dtheta_2 on pattern entry e.
+__device__ inline double qs_entry(const ModelDev &M, const Coef &c, int e) {
+  return c.qsc * (c.k2 * c.k2 * M.pdelta[e] + 2.0 * c.k2 * M.pg1[e] + M.pg2[e]);
+}
+__device__ inline double dqs_entry(const ModelDev &M, const Coef &c, int e) {
+  return c.dq2 * (c.k2 * M.pdelta[e] + M.pg1[e]);
+}
+
+template <int NT>
+__device__ inline void block_reduce(double (&v)[4], double *red) {
+  // fixed-order tree over the workgroup; result in red[0..3]
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) red[k * NT + tid] = v[k];
+  __syncthreads();
+  for (int off = NT / 2; off > 0; off >>= 1) {
+    if (tid < off) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) red[k * NT + tid] += red[k * NT + tid + off];
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// assembly
+// ---------------------------------------------------------------------------
+
+// One workgroup writes column s of one b x b block (D[t] for blockIdx.y < nt,
+// S[t] for blockIdx.y - nt).  Entries outside the pattern are zero.
+__global__ void assemble_blocks_kernel(const ModelDev *__restrict__ Mp, const double *theta,
+                                       int which, double *D, double *S) {
+  const ModelDev &M = *Mp;
+  const int b = M.b, nt = M.nt;
+  const int s = blockIdx.x;
+  const int blk = blockIdx.y;
+  const bool isS = blk >= nt;
+  const int t = isS ? blk - nt : blk;
+  const Coef c = make_coef(M, theta);
+  const double cblk = isS ? ar1_off(c) : ar1_diag(c, t, nt);
+  double *col = (isS ? S : D) + (long long)t * b * b + (long long)s * b;
+  const int e0 = M.colptr[s], e1 = M.colptr[s + 1];
+  for (int i = threadIdx.x; i < b; i += blockDim.x) {
+    double v = 0.0;
+    for (int e = e0; e < e1; ++e) {
+      if (M.rowidx[e] == i) {
+        v = cblk * qs_entry(M, c, e);
+        if (!isS && which) v += c.tauy * M.AtA[(long long)t * M.nnz + e];
+        break;
+      }
+    }
+    col[i] = v;
+  }
+}
+
+// Arrow blocks: R[t] = tau_y (Z^T A_t) (Q_c) or 0; T = beta_prec I (+ tau_y Z^T Z);
+// rhs = tau_y A^T y.
+__global__ void assemble_arrow_kernel(const ModelDev *__restrict__ Mp, const double *theta, int which,
+                                      double *R, double *T, double *rhs) {
+  const ModelDev &M = *Mp;
+  const int a = M.a;
+  const long long nR = (long long)M.nt * a * M.b;
+  const long long nT = (long long)a * a;
+  const long long nrhs = rhs ? M.n : 0;
+  const double tauy = exp(theta[3]);
+  const long long total = nR + nT + nrhs;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    if (i < nR) {
+      R[i] = which ? tauy * M.ZtA[i] : 0.0;
+    } else if (i < nR + nT) {
+      const long long k = i - nR;
+      const int r = (int)(k % a), cc = (int)(k / a);
+      T[k] = (r == cc ? M.beta_prec : 0.0) + (which ? tauy * M.ZtZ[k] : 0.0);
+    } else {
+      const long long k = i - nR - nT;
+      rhs[k] = tauy * M.Aty[k];
+    }
+  }
+}
+
+hipError_t launch_assemble(const ModelDev *model_dev, int b, int nt, int a, const double *theta,
+                           int which, double *D, double *S, double *R, double *T, double *rhs,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(assemble_blocks_kernel, dim3(b, 2 * nt - 1), dim3(256), 0, s, model_dev, theta,
+                     which, D, S);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const long long total = (long long)nt * a * b + (long long)a * a + (rhs ? (long long)b * nt + a : 0);
+  if (total > 0) {
+    const long long blocks = std::min<long long>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(assemble_arrow_kernel, dim3((unsigned)blocks), dim3(256), 0, s, model_dev,
+                       theta, which, R, T, rhs);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+// ---------------------------------------------------------------------------
+// substitution sweeps with the inverse-diagonal factor
+//   forward:  z_t = Linv_tt (r_t - L_{t,t-1} z_{t-1}),  z_A = Linv_AA (r_A - sum_t L_{A,t} z_t)
+//   backward: x_A = Linv_AA^T z_A,  x_t = Linv_tt^T (z_t - L_{t+1,t}^T x_{t+1} - L_{A,t}^T x_A)
+// ---------------------------------------------------------------------------
+
+__global__ void solve_stage_kernel(const ItemDev *__restrict__ items, int t, int stage,
+                                   double *const *xs, double *const *tmps) {
+  const ItemDev it = items[blockIdx.y];
+  const int b = it.b, a = it.a, nt = it.nt;
+  const long long bb = (long long)b * b;
+  double *x = xs[blockIdx.y];
+  double *tmp = tmps[blockIdx.y];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  __shared__ double red[4][64];
+  __shared__ double xa[kMaxArrow];
+  switch (stage) {
+    case SV_F1:
+    case SV_F2: {
+      if (t >= nt) return;
+      const int r = blockIdx.x * 64 + lane;
+      const double *M = (stage == SV_F1) ? (t > 0 ? it.S + (long long)(t - 1) * bb : nullptr)
+                                         : it.D + (long long)t * bb;
+      const double *v = (stage == SV_F1) ? x + (long long)(t - 1) * b : tmp;
+      const int jend = (stage == SV_F1) ? b : min(b, blockIdx.x * 64 + 64);
+      double acc = 0.0;
+      if (M && r < b) {
+        for (int j = w; j < jend; j += 4) acc += M[r + (long long)j * b] * v[j];
+      }
+      red[w][lane] = acc;
+      __syncthreads();
+      if (w == 0 && r < b) {
+        const double sum = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+        if (stage == SV_F1) tmp[r] = x[(long long)t * b + r] - sum;
+        else x[(long long)t * b + r] = sum;
+      }
+      return;
+    }
+    case SV_FA1: {
+      const int c = blockIdx.x;
+      if (c >= a) return;
+      const long long len = (long long)nt * b;
+      double acc = 0.0;
+      for (long long k = tid; k < len; k += blockDim.x) acc += it.R[c + k * a] * x[k];
+      __shared__ double r1[256];
+      r1[tid] = acc;
+      __syncthreads();
+      for (int off = 128; off > 0; off >>= 1) {
+        if (tid < off) r1[tid] += r1[tid + off];
+        __syncthreads();
+      }
+      if (tid == 0) tmp[c] = x[len + c] - r1[0];
+      return;
+    }
+    case SV_FA2: {
+      if (blockIdx.x != 0 || a == 0) return;
+      if (tid < a) {
+        double acc = 0.0;
+        for (int j = 0; j <= tid; ++j) acc += it.T[tid + (long long)j * a] * tmp[j];
+        x[(long long)nt * b + tid] = acc;
+      }
+      return;
+    }
+    case SV_BA: {
+      if (blockIdx.x != 0 || a == 0) return;
+      if (tid < a) xa[tid] = x[(long long)nt * b + tid];
+      __syncthreads();
+      if (tid < a) {
+        double acc = 0.0;
+        for (int i = tid; i < a; ++i) acc += it.T[i + (long long)tid * a] * xa[i];
+        x[(long long)nt * b + tid] = acc;
+      }
+      return;
+    }
+    case SV_B1:
+    case SV_B2: {
+      if (t >= nt) return;
+      const int j = blockIdx.x * 4 + w;
+      if (j >= b) return;
+      double acc = 0.0;
+      if (stage == SV_B1) {
+        if (t < nt - 1) {
+          const double *X = it.S + (long long)t * bb + (long long)j * b;
+          const double *xn = x + (long long)(t + 1) * b;
+          for (int i = lane; i < b; i += 64) acc += X[i] * xn[i];
+        }
+        if (a > 0) {
+          const double *Rt = it.R + (long long)t * a * b + (long long)j * a;
+          const double *xA = x + (long long)nt * b;
+          for (int c = lane; c < a; c += 64) acc += Rt[c] * xA[c];
+        }
+      } else {
+        const double *L = it.D + (long long)t * bb + (long long)j * b;
+        for (int i = j + lane; i < b; i += 64) acc += L[i] * tmp[i];
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+      if (lane == 0) {
+        if (stage == SV_B1) tmp[j] = x[(long long)t * b + j] - acc;
+        else x[(long long)t * b + j] = acc;
+      }
+      return;
+    }
+    default:
+      return;
+  }
+}
+
+hipError_t launch_solve_stage(const ItemDev *items_dev, int n_items, int max_b, int max_a, int t,
+                              int stage, double *const *xs_dev, double *const *tmps_dev,
+                              hipStream_t s) {
+  int gx = 1;
+  switch (stage) {
+    case SV_F1: case SV_F2: gx = (max_b + 63) / 64; break;
+    case SV_B1: case SV_B2: gx = (max_b + 3) / 4; break;
+    case SV_FA1: gx = max_a; break;
+    default: gx = 1;
+  }
+  if (gx <= 0 || n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(solve_stage_kernel, dim3(gx, n_items), dim3(256), 0, s, items_dev, t, stage,
+                     xs_dev, tmps_dev);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// traces tr(Sigma dQ/dtheta_k) over the BTA pattern, and marginal variances
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void trace_step_kernel(const ItemDev *__restrict__ items, int t) {
+  const ItemDev it = items[blockIdx.x];
+  if (!it.trpart && !it.diag) return;
+  const int b = it.b, a = it.a, nt = it.nt;
+  const int tid = threadIdx.x;
+  __shared__ double red[4 * 256];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  if (t < 0) {
+    // arrow block: Sigma_T
+    if (a > 0) {
+      if (it.diag && tid < a) it.diag[(long long)nt * b + tid] = it.ST[tid + (long long)tid * a];
+      if (it.trpart && it.which == 1 && it.model) {
+        const double tauy = exp(it.theta[3]);
+        for (int k = tid; k < a * a; k += 256) v[3] += tauy * it.model->ZtZ[k] * it.ST[k];
+      }
+    }
+    if (!it.trpart) return;
+    block_reduce<256>(v, red);
+    if (tid == 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) it.trpart[(long long)nt * 4 + k] = red[k * 256];
+    }
+    return;
+  }
+  if (t >= nt) return;
+  const double *SD = sig_D(it, t);
+  if (it.diag) {
+    for (int s = tid; s < b; s += 256) it.diag[(long long)t * b + s] = SD[s + (long long)s * b];
+  }
+  if (!it.trpart) return;
+  const ModelDev &M = *it.model;
+  const Coef c = make_coef(M, it.theta);
+  const double cD = ar1_diag(c, t, nt), cS = ar1_off(c);
+  const double dcD = ar1_ddiag(c, t, nt), dcS = ar1_doff(c);
+  const bool hasS = t < nt - 1;
+  const double *SS = hasS ? sig_S(it, t) : nullptr;
+  for (int e = tid; e < M.nnz; e += 256) {
+    const int i = M.rowidx[e], s = M.colidx[e];
+    const double q = qs_entry(M, c, e), dq = dqs_entry(M, c, e);
+    const double sd = SD[i + (long long)s * b];
+    v[0] += 2.0 * cD * q * sd;
+    v[1] += cD * dq * sd;
+    v[2] += dcD * q * sd;
+    if (it.which == 1) v[3] += c.tauy * M.AtA[(long long)t * M.nnz + e] * sd;
+    if (hasS) {
+      const double ss = SS[i + (long long)s * b];
+      v[0] += 4.0 * cS * q * ss;
+      v[1] += 2.0 * cS * dq * ss;
+      v[2] += 2.0 * dcS * q * ss;
+    }
+  }
+  if (it.which == 1 && a > 0) {
+    const double *SR = sig_R(it, t);
+    const double *Z = M.ZtA + (long long)t * a * b;
+    for (int k = tid; k < a * b; k += 256) v[3] += 2.0 * c.tauy * Z[k] * SR[k];
+  }
+  block_reduce<256>(v, red);
+  if (tid == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) it.trpart[(long long)t * 4 + k] = red[k * 256];
+  }
+}
+
+hipError_t launch_trace_step(const ItemDev *items_dev, int n_items, int t, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(trace_step_kernel, dim3(n_items), dim3(256), 0, s, items_dev, t);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// posterior-mode terms
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void terms_kernel(const TermItem *__restrict__ items) {
+  const TermItem ti = items[blockIdx.y];
+  const ModelDev &M = *ti.model;
+  const int b = M.b, nt = M.nt;
+  const Coef c = make_coef(M, ti.theta);
+  const double cS = ar1_off(c), dcS = ar1_doff(c);
+  const double *mu = ti.mu;
+  const long long nst = (long long)nt * b;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < nst; idx += stride) {
+    const int t = (int)(idx / b), s = (int)(idx % b);
+    const double *mt = mu + (long long)t * b;
+    const double *mn = (t < nt - 1) ? mt + b : nullptr;
+    double q0 = 0.0, d0 = 0.0, q1 = 0.0, d1 = 0.0;
+    for (int e = M.colptr[s]; e < M.colptr[s + 1]; ++e) {
+      const int i = M.rowidx[e];
+      const double q = qs_entry(M, c, e), dq = dqs_entry(M, c, e);
+      q0 += q * mt[i];
+      d0 += dq * mt[i];
+      if (mn) {
+        q1 += q * mn[i];
+        d1 += dq * mn[i];
+      }
+    }
+    const double u = mt[s];
+    const double cD = ar1_diag(c, t, nt), dcD = ar1_ddiag(c, t, nt);
+    v[0] += u * (cD * q0 + 2.0 * cS * q1);
+    v[1] += u * (cD * d0 + 2.0 * cS * d1);
+    v[2] += u * (dcD * q0 + 2.0 * dcS * q1);
+  }
+  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < M.m; j += stride) {
+    double r = M.y[j];
+    for (long long e = M.A_rowptr[j]; e < M.A_rowptr[j + 1]; ++e) r -= M.A_val[e] * mu[M.A_col[e]];
+    v[3] += r * r;
+  }
+  __shared__ double red[4 * 256];
+  block_reduce<256>(v, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ti.part[(long long)blockIdx.x * 4 + k] = red[k * 256];
+  }
+}
+
+hipError_t launch_terms(const TermItem *items_dev, int n_items, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(terms_kernel, dim3(kTermBlocks, n_items), dim3(256), 0, s, items_dev);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// f(theta) and its gradient
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void combine_kernel(const CombineItem *__restrict__ items) {
+  const CombineItem ci = items[blockIdx.x];
+  const ModelDev &M = *ci.model;
+  const int tid = threadIdx.x;
+  __shared__ double red[4 * 256];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = tid; k < kTermBlocks; k += 256) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] += ci.term_part[k * 4 + q];
+  }
+  block_reduce<256>(v, red);
+  const double q0 = red[0], q1 = red[256], q2 = red[512], rss = red[768];
+  __syncthreads();
+  double tp[4] = {0.0, 0.0, 0.0, 0.0}, tc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int ntr = M.nt + 1;
+  if (ci.trp) {
+    for (int k = tid; k < ntr; k += 256) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) tp[q] += ci.trp[k * 4 + q];
+    }
+  }
+  block_reduce<256>(tp, red);
+  double trp[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) trp[q] = red[q * 256];
+  __syncthreads();
+  if (ci.trc) {
+    for (int k = tid; k < ntr; k += 256) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) tc[q] += ci.trc[k * 4 + q];
+    }
+  }
+  block_reduce<256>(tc, red);
+  double trc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) trc[q] = red[q * 256];
+  if (tid != 0) return;
+  const double *th = ci.theta;
+  const double tauy = exp(th[3]);
+  double qb = 0.0;
+  const double *muA = ci.mu + (long long)M.nt * M.b;
+  for (int k = 0; k < M.a; ++k) qb += muA[k] * muA[k];
+  qb *= M.beta_prec;
+  double logprior = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    const double d = th[k] - M.prior_mean[k];
+    logprior += 0.5 * log(M.prior_prec[k] / (2.0 * M_PI)) - 0.5 * M.prior_prec[k] * d * d;
+  }
+  const double mm = (double)M.m;
+  const double ldp = ci.logdet[0], ldc = ci.logdet[1];
+  const int st = ci.info[0] ? 1 : (ci.info[1] ? 2 : 0);
+  double f = -logprior - 0.5 * ldp + 0.5 * (q0 + qb) - 0.5 * mm * th[3] + 0.5 * tauy * rss +
+             0.5 * ldc + 0.5 * mm * log(2.0 * M_PI);
+  if (st) f = NAN;
+  *ci.f = f;
+  if (ci.status) *ci.status = st;
+  if (ci.grad) {
+    const double mean_terms[4] = {2.0 * q0, q1, q2, 0.0};
+    for (int k = 0; k < 4; ++k) {
+      double g = M.prior_prec[k] * (th[k] - M.prior_mean[k]) - 0.5 * trp[k] + 0.5 * trc[k] +
+                 0.5 * mean_terms[k];
+      if (k == 3) g += 0.5 * tauy * rss - 0.5 * mm;
+      ci.grad[k] = st ? NAN : g;
+    }
+  }
+}
+
+hipError_t launch_combine(const CombineItem *items_dev, int n_items, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(combine_kernel, dim3(n_items), dim3(256), 0, s, items_dev);
+  return hipGetLastError();
+}
+
+}  // namespace inla

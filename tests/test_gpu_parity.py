@@ -1,0 +1,190 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Tolerances: log-determinants and f within 1e-10 relative; mean within 1e-9
+(max-norm relative); variances within 1e-9 per component; the adjoint
+gradient within 1e-9 of the oracle's dense-inverse gradient; factor and
+selected-inverse blocks within 1e-11 relative to the block norm.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from inla_synth import THETA0, config_model, make_model
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2204_04678_amd as P
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    P.lib()
+    return P
+
+
+def rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+def rand_spd_bta(b, nt, a, seed):
+    """Dense SPD matrix with the BTA pattern (strict diagonal dominance)."""
+    rng = np.random.default_rng(seed)
+    n = b * nt + a
+    Q = np.zeros((n, n))
+    for t in range(nt):
+        blk = rng.uniform(-1, 1, (b, b))
+        Q[t * b:(t + 1) * b, t * b:(t + 1) * b] = blk
+        if t + 1 < nt:
+            Q[(t + 1) * b:(t + 2) * b, t * b:(t + 1) * b] = rng.uniform(-1, 1, (b, b))
+        if a:
+            Q[b * nt:, t * b:(t + 1) * b] = rng.uniform(-1, 1, (a, b))
+    if a:
+        Q[b * nt:, b * nt:] = rng.uniform(-1, 1, (a, a))
+    Q = np.tril(Q)
+    Q = Q + np.tril(Q, -1).T
+    Q += np.diag(np.abs(Q).sum(axis=1) + 1.0)
+    return Q
+
+
+def expected_factor(Q, b, nt, a):
+    D, S, R, T = O.bta_factor_blocks(Q, b, nt, a)
+    Di = np.stack([np.linalg.inv(D[t]) for t in range(nt)])
+    Ti = np.linalg.inv(T) if a else T
+    return Di, S, R, Ti
+
+
+def blk_err(x, y):
+    if x.size == 0:
+        return 0.0
+    return np.abs(x - y).max() / max(np.abs(y).max(), 1e-300)
+
+
+SHAPES = [(1, 4, 2), (16, 1, 0), (64, 3, 1), (100, 3, 2), (130, 2, 3), (70, 4, 0), (200, 2, 5)]
+
+
+@pytest.mark.parametrize("b,nt,a", SHAPES)
+def test_factor_logdet_random_bta(P, b, nt, a):
+    print(f"factor b={b} nt={nt} a={a}", flush=True)
+    Q = rand_spd_bta(b, nt, a, seed=b * 100 + nt * 10 + a)
+    Qt = P.BtaTensors.from_blocks(*O.bta_blocks(Q, b, nt, a))
+    ld, info = P.factor_logdet(Qt)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    L = np.linalg.cholesky(Q)
+    ld_ref = 2.0 * math.fsum(np.log(np.diag(L)))
+    assert rel(ld.item(), ld_ref) < 1e-12
+    got = Qt.to_blocks()
+    exp = expected_factor(Q, b, nt, a)
+    for g, e, name in zip(got, exp, "DSRT"):
+        assert blk_err(g, e) < 1e-11, name
+
+
+@pytest.mark.parametrize("b,nt,a", [(100, 3, 2), (64, 2, 1), (1, 5, 1), (130, 2, 0)])
+def test_solve_and_selinv_random_bta(P, b, nt, a):
+    print(f"solve/selinv b={b} nt={nt} a={a}", flush=True)
+    Q = rand_spd_bta(b, nt, a, seed=7 + b + nt + a)
+    n = Q.shape[0]
+    Qt = P.BtaTensors.from_blocks(*O.bta_blocks(Q, b, nt, a))
+    P.factor_logdet(Qt)
+    rng = np.random.default_rng(3)
+    r = rng.standard_normal((2, n))
+    x = P.solve(Qt, torch.as_tensor(r).cuda())
+    sig, diag = P.selinv(Qt, keep_sigma=True)
+    torch.cuda.synchronize()
+    Sinv = np.linalg.inv(Q)
+    xr = np.linalg.solve(Q, r.T).T
+    np.testing.assert_allclose(x.cpu().numpy(), xr, rtol=0, atol=1e-10 * np.abs(xr).max())
+    np.testing.assert_allclose(diag.cpu().numpy(), np.diag(Sinv), rtol=1e-10)
+    got = sig.to_blocks()
+    exp = O.bta_blocks(Sinv, b, nt, a)
+    for g, e, name in zip(got, exp, "DSRT"):
+        assert blk_err(g, e) < 1e-10, name
+
+
+def test_not_spd_reports_pivot(P):
+    b, nt, a = 70, 3, 2
+    Q = rand_spd_bta(b, nt, a, seed=5)
+    bad = b * 1 + 66  # global row of the planted negative pivot
+    Q[bad, bad] = -5.0
+    Qt = P.BtaTensors.from_blocks(*O.bta_blocks(Q, b, nt, a))
+    ld, info = P.factor_logdet(Qt)
+    torch.cuda.synchronize()
+    assert int(info.item()) == bad + 1
+    assert math.isnan(ld.item())
+
+
+def model_small(N=5, nt=3, nb=2, seed=3):
+    return make_model(N, nt, nb, seed)
+
+
+@pytest.mark.parametrize("shape", [(5, 3, 2), (1, 4, 2), (9, 2, 0), (10, 1, 3)])
+def test_assemble(P, shape):
+    md = model_small(*shape)
+    M = P.Model.from_data(md)
+    theta = np.array([0.2, 0.9, 0.7, 3.0])
+    Qp = P.assemble(M, theta, 0)
+    Qc, rhs = P.assemble(M, theta, 1)
+    torch.cuda.synchronize()
+    Qp_ref, Qc_ref, b_ref = O.conditional_precision(md, theta)
+    for Qt, Qr in ((Qp, Qp_ref), (Qc, Qc_ref)):
+        exp = O.bta_blocks(Qr, md.ns, md.nt, md.nb)
+        for g, e, name in zip(Qt.to_blocks(), exp, "DSRT"):
+            assert blk_err(g, e) < 1e-14, name
+    np.testing.assert_allclose(rhs.cpu().numpy(), b_ref, rtol=1e-13, atol=1e-13 * np.abs(b_ref).max())
+
+
+def test_eval_f_c1(P):
+    md = config_model("c1")
+    M = P.Model.from_data(md)
+    out = P.eval_f(M, THETA0, want_mu=True, want_var=True)
+    torch.cuda.synchronize()
+    ref = O.eval_f_dense(md, THETA0)
+    assert int(out["status"].item()) == 0
+    assert rel(out["f"].item(), ref["f"]) < 1e-10
+    mu = out["mu"].cpu().numpy()
+    assert np.abs(mu - ref["mu"]).max() / np.abs(ref["mu"]).max() < 1e-9
+    var_ref = O.marginal_variances_dense(md, THETA0)
+    assert np.max(np.abs(out["var"].cpu().numpy() - var_ref) / var_ref) < 1e-9
+
+
+def test_logdets_c1_and_closed_form(P):
+    md = config_model("c1")
+    M = P.Model.from_data(md)
+    Qp = P.assemble(M, THETA0, 0)
+    Qc, _ = P.assemble(M, THETA0, 1)
+    ldp, _ = P.factor_logdet(Qp)
+    ldc, _ = P.factor_logdet(Qc)
+    torch.cuda.synchronize()
+    ref = O.eval_f_dense(md, THETA0)
+    assert rel(ldp.item(), ref["logdet_p"]) < 1e-10
+    assert rel(ldc.item(), ref["logdet_c"]) < 1e-10
+
+
+def test_eval_f_grad_small(P):
+    md = config_model("c4small")
+    M = P.Model.from_data(md)
+    out = P.eval_f_grad(M, THETA0)
+    torch.cuda.synchronize()
+    g = out["grad"].cpu().numpy()[0]
+    gref = O.dense_gradient(md, THETA0)
+    assert rel(out["f"].item(), O.eval_f_dense(md, THETA0)["f"]) < 1e-10
+    assert np.max(np.abs(g - gref) / np.maximum(np.abs(gref), 1e-3 * np.abs(gref).max())) < 1e-9
+
+
+def test_batched_uneven_matches_single(P):
+    mds = [make_model(4, 3, 2, 1), make_model(6, 2, 3, 2), make_model(9, 4, 1, 3)]
+    Ms = [P.Model.from_data(m) for m in mds]
+    th = np.array([[0.1, 0.8, 0.5, 2.0], [0.3, 1.1, 1.0, 3.0], [-0.2, 0.6, 0.2, 2.5]])
+    out = P.eval_f_grad(Ms, th)
+    torch.cuda.synchronize()
+    for i, (md, M) in enumerate(zip(mds, Ms)):
+        one = P.eval_f_grad(M, th[i])
+        torch.cuda.synchronize()
+        assert out["f"][i].item() == one["f"][0].item()
+        assert torch.equal(out["grad"][i], one["grad"][0])
+        assert rel(out["f"][i].item(), O.eval_f_dense(md, th[i])["f"]) < 1e-10
