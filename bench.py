@@ -1,0 +1,203 @@
+"""Benchmark: f(theta) + grad f evaluations per second on one MI355X.
+
+Workload (default): the 32x32-grid, 50-time-step, 4-fixed-effect model
+(n = 51204, block size b = 1024), FP64.  One step = one evaluation of f(theta)
+and its exact gradient at theta0 through the selected-inversion adjoint:
+assembly of Q_prior and Q_c, both block Cholesky factorizations and
+log-determinants, the mode solve, both selected inversions with the trace
+reductions, and the combination into f and grad f.  Inputs are resident in HBM
+before the timed region.
+
+Also measured in the same run (reported beside the headline, not as it):
+  * the plain finite-difference baseline on the same GPU: 2*dim(theta)+1 = 9
+    f-only evaluations one after another per gradient;
+  * the same 9 points as one batched call;
+  * the CPU oracle on the host (bounded sample), as the cpu_baseline.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6  # MI355X, dense FP64 matrix (and vector) peak, published
+
+
+def flops_chol(b, nt, a):
+    """Dense-block BTA Cholesky: POTRF per block, TRSM/SYRK/GEMM couplings, arrow."""
+    return (nt * b ** 3 / 3 + (nt - 1) * (2 * b ** 3 + 2 * a * b * b) + nt * (a * b * b + a * a * b)
+            + a ** 3 / 3)
+
+
+def flops_selinv(b, nt, a):
+    """Block selected inversion: per step POTRI (2/3 b^3), V (b^3), Sigma_S (2 b^3), Sigma_D (b^3)."""
+    return nt * (2.0 / 3.0) * b ** 3 + (nt - 1) * 4 * b ** 3 + nt * (4 * a * b * b + 2 * a * a * b)
+
+
+def cpu_baseline(md, theta, budget_s=20.0):
+    """Oracle f(theta) on the host; the oracle's gradient is 2d+1 = 9 f evaluations."""
+    import numpy as np
+
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        oracle.eval_f_banded(md, np.asarray(theta))
+        n += 1
+        if time.perf_counter() - t0 > budget_s / 2 or n >= 3:
+            break
+    dt = (time.perf_counter() - t0) / n
+    return {"value": 1.0 / (9.0 * dt), "unit": "f+grad evals/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"{n} oracle f evaluation(s) (bordered-banded LAPACK Cholesky of Q_p and Q_c + "
+                      f"solve) at the workload size, {dt:.2f} s each; f+grad by central "
+                      f"differences = 9 f evaluations"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c4", "c5"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fd", action="store_true", help="skip the finite-difference baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
+              f"batched items would shard across GPUs by theta point, which is not built.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2204_04678_amd as P
+    from inla_synth import THETA0, config_model, fd_stencil
+
+    if not os.path.exists(P.binding.LIB):
+        from paper_2204_04678_amd import _build
+        _build.build()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    md = config_model(args.config)
+    model = P.Model.from_data(md)
+    b, nt, a = md.ns, md.nt, md.nb
+    theta = torch.tensor(THETA0[None, :], dtype=torch.float64, device="cuda")
+    F_alg = 2 * flops_chol(b, nt, a) + 2 * flops_selinv(b, nt, a)
+
+    for _ in range(args.warmup):
+        P.eval_f_grad(model, theta)
+    torch.cuda.synchronize()
+
+    P.profile_begin()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = P.eval_f_grad(model, theta)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = P.profile_end()
+    step_s = (t1 - t0) / args.steps
+    value = 1.0 / step_s
+    f_val = float(out["f"][0].item())
+    grad = out["grad"][0].cpu().numpy().tolist()
+
+    # dominant tile kernel by time
+    kinds = {"product_x": ("tile_big_kernel" if os.environ.get("INLA_TILE", "") != "64"
+                           else "tile_phase_kernel<false>") + " (b x b products)",
+             "product": "tile_phase_kernel<false>", "chol": "tile_phase_kernel<true>"}
+    slots = prof.pop("slots")
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    pk = prof[dom]
+    achieved = pk["flops"] / (pk["ms"] * 1e-3) / 1e12 if pk["ms"] > 0 else 0.0
+    roofline = {"bound": "mfma", "kernel": kinds[dom],
+                "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                "launches_per_step": pk["launches"] / args.steps,
+                "avg_launch_us": round(pk["ms"] * 1e3 / max(pk["launches"], 1), 3),
+                "kernel_share_of_step": round(pk["ms"] * 1e-3 / (t1 - t0), 4),
+                "other_kernel": {k: {"ms_per_step": round(v["ms"] / args.steps, 3),
+                                     "tflops": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 3)}
+                                 for k, v in prof.items() if k != dom},
+                "per_phase_ms_per_step": {k: round(v["ms"] / args.steps, 3)
+                                          for k, v in slots.items() if v["launches"]},
+                "per_phase_launches_per_step": {k: v["launches"] / args.steps
+                                                for k, v in slots.items() if v["launches"]}}
+
+    extra = {}
+    if not args.no_fd:
+        pts = torch.tensor(fd_stencil(THETA0, 1e-3), dtype=torch.float64, device="cuda")
+        reps = max(1, args.steps // 3)
+        P.eval_f(model, pts[0:1])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for i in range(pts.shape[0]):
+                P.eval_f(model, pts[i:i + 1])
+        torch.cuda.synchronize()
+        fd_seq = (time.perf_counter() - t0) / reps
+        P.eval_f(model, pts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fdb = P.eval_f(model, pts)
+        torch.cuda.synchronize()
+        fd_bat = (time.perf_counter() - t0) / reps
+        fv = fdb["f"].cpu().numpy()
+        g_fd = [(fv[1 + 2 * k] - fv[2 + 2 * k]) / 2e-3 for k in range(4)]
+        extra["fd_baseline"] = {
+            "grad_evals_per_s_sequential": round(1.0 / fd_seq, 4),
+            "grad_evals_per_s_batched9": round(1.0 / fd_bat, 4),
+            "adjoint_speedup_vs_sequential_fd": round(value * fd_seq, 3),
+            "adjoint_speedup_vs_batched_fd": round(value * fd_bat, 3),
+            "fd_grad_h1e-3": g_fd,
+        }
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(md, THETA0)
+
+    rec = {
+        "metric": "f(theta)+grad f evaluations/s (BTA Cholesky + selected-inversion adjoint, FP64)",
+        "value": round(value, 4),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(step_s * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded grid model; no dataset)",
+        "config": {"workload": f"{args.config}: N={md.N} (b={b}), nt={nt}, nb={a}, n={md.n}, "
+                               f"m={md.m}, one theta, f+grad via adjoint",
+                   "b": b, "nt": nt, "a": a, "n": md.n, "items": 1},
+        "pct_fp64_peak_whole_step": round(100 * F_alg * value / (PEAK_FP64_TFLOPS * 1e12), 3),
+        "alg_flops_per_step": F_alg,
+        "f": f_val,
+        "grad": grad,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        **extra,
+    }
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

@@ -193,6 +193,24 @@ inla_status inla_eval_f_grad(const inla_model *const *models, int32_t n_items,
                              double *mu_or_null, double *var_or_null, int32_t *status_dev,
                              const inla_opts *opts, void *hip_stream);
 
+/*
+ * Instrumentation for benchmarks.  Between inla_profile_begin() and
+ * inla_profile_end() every kernel launch of the library is bracketed by HIP
+ * events on the stream it runs on.  inla_profile_end waits for those events
+ * and writes, per profiling slot k < nslots, out[3k+0] = launches,
+ * out[3k+1] = summed kernel time in milliseconds, out[3k+2] = algorithmic
+ * FP64 flops of those launches (the dense-block operation counts of the
+ * method, not the flops of padded tiles).  Slots 0..10 are the phases of the
+ * tile kernels (Cholesky of the first diagonal tile, panel solve, trailing
+ * update with the next diagonal tile, inverse of the diagonal factor block,
+ * off-diagonal solve, Schur update, arrow Cholesky, and the four steps of the
+ * selected inversion, in that order); then substitution sweeps, trace
+ * reductions, assembly, and the rest.  inla_profile_slots() returns the count.
+ */
+inla_status inla_profile_begin(void);
+inla_status inla_profile_end(double *out, int32_t nslots);
+int32_t inla_profile_slots(void);
+
 /* Release the library's cached device workspace (it is re-grown on demand). */
 void inla_release_workspace(void);
 

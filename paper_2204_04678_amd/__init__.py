@@ -17,6 +17,8 @@ from .binding import (  # noqa: F401
     header_functions,
     lib,
     objective,
+    profile_begin,
+    profile_end,
     release_workspace,
     selinv,
     solve,

@@ -64,6 +64,9 @@ _SIGS = {
                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.POINTER(Opts), C.c_void_p]),
     "inla_release_workspace": (None, []),
+    "inla_profile_begin": (C.c_int, []),
+    "inla_profile_end": (C.c_int, [C.POINTER(C.c_double), C.c_int32]),
+    "inla_profile_slots": (C.c_int32, []),
     "inla_status_string": (C.c_char_p, [C.c_int]),
     "inla_last_error": (C.c_char_p, []),
 }
@@ -333,3 +336,33 @@ def objective(theta, models):
 
 def release_workspace():
     lib().inla_release_workspace()
+
+
+def profile_begin():
+    _check(lib().inla_profile_begin())
+
+
+PROFILE_SLOTS = ["diag0", "panel", "trail", "trtri", "offdiag_x", "offdiag", "schur_x", "schur",
+                 "arrow", "si_init", "si_vu_x", "si_vu", "si_sr_x", "si_sr", "si_sd_x", "solve",
+                 "trace", "assemble", "misc"]
+PRODUCT_X = ("offdiag_x", "schur_x", "si_vu_x", "si_sr_x", "si_sd_x")   # b x b products
+FAT_PHASES = ("diag0", "trail", "arrow")   # run by the Cholesky-capable tile kernel
+
+
+def profile_end():
+    """Per slot: dict(launches, ms, flops); plus per tile-kernel kind aggregates."""
+    n = lib().inla_profile_slots()
+    out = (C.c_double * (3 * n))()
+    _check(lib().inla_profile_end(out, n))
+    slots = {PROFILE_SLOTS[k]: dict(launches=out[3 * k], ms=out[3 * k + 1], flops=out[3 * k + 2])
+             for k in range(n)}
+    kinds = {"product_x": dict(launches=0.0, ms=0.0, flops=0.0),
+             "product": dict(launches=0.0, ms=0.0, flops=0.0),
+             "chol": dict(launches=0.0, ms=0.0, flops=0.0)}
+    for k in range(15):
+        name = PROFILE_SLOTS[k]
+        dst = kinds["chol" if name in FAT_PHASES else
+                    ("product_x" if name in PRODUCT_X else "product")]
+        for f in ("launches", "ms", "flops"):
+            dst[f] += slots[name][f]
+    return {"slots": slots, **kinds}

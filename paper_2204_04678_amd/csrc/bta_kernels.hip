@@ -15,17 +15,21 @@ namespace inla {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int KC = 16;            // k-chunk staged through LDS
 constexpr int LDP = kTile + 2;    // LDS row length of a [k][row] operand panel
 constexpr int TLD = kTile + 1;    // LDS row length of a full 64 x 64 tile
-constexpr int kLeanLds = 2 * KC * LDP;
-constexpr int kFatLds = 2 * kTile * TLD + kTile + 64;
+constexpr int kLeanKC = 32;       // k-chunk of the product kernel
+constexpr int kFatKC = 32;        // k-chunk of the Cholesky-capable kernel
+constexpr int kLeanLds = 2 * 2 * kLeanKC * LDP;                      // double-buffered panels
+constexpr int kFatLds = 2 * kTile * TLD + 2 * kTile;                 // tile + inverse + logs
+static_assert(kFatLds >= 2 * 2 * kFatKC * LDP, "fat LDS must hold the product panels too");
+constexpr int kBigKC = 16;                                            // k-chunk, big tiles
+constexpr int kBigLds = 2 * 2 * kBigKC * (kBig + 2);
 
 struct Seg {
   const double *A;
-  long long ars, aks;             // op(A)(r, k) = A[r*ars + k*aks]
   const double *B;
-  long long brs, bks;             // op(B)(c, k) = B[c*brs + k*bks];  product = op(A) op(B)^T
+  int ars, aks;                   // op(A)(r, k) = A[r*ars + k*aks]
+  int brs, bks;                   // op(B)(c, k) = B[c*brs + k*bks];  product = op(A) op(B)^T
   int k0, k1;
   double alpha;
 };
@@ -48,11 +52,16 @@ struct Task {
   long long ldl;
   double *ldsum;
   int row_off;
-  int left;                       // C = -E P with E a lower-triangular tile
-  const double *E;
-  long long lde;
   const double *src;              // copy source (ld = ldc)
 };
+
+// Loads and stores through the global address space (global_load / global_store
+// instead of flat ones, whose completion counter is shared with LDS traffic).
+typedef __attribute__((address_space(1))) double gdouble;
+__device__ __forceinline__ double gld(const double *p) {
+  return *(const gdouble *)p;
+}
+__device__ __forceinline__ void gst(double *p, double v) { *(gdouble *)p = v; }
 
 __device__ inline int tdim(int n, int i) { return min(kTile, n - i * kTile); }
 __device__ inline long long toff(int b, int i, int j) {
@@ -65,21 +74,21 @@ __device__ inline void tri_decode(int q, int &i, int &j) {
   i = r;
   j = q - r * (r + 1) / 2;
 }
-__device__ inline void set_seg(Seg &g, const double *A, long long ars, long long aks, const double *B,
-                               long long brs, long long bks, int k0, int k1, double alpha) {
+__device__ inline void set_seg(Seg &g, const double *A, int ars, int aks, const double *B, int brs,
+                               int bks, int k0, int k1, double alpha) {
   g.A = A; g.ars = ars; g.aks = aks; g.B = B; g.brs = brs; g.bks = bks;
   g.k0 = k0; g.k1 = k1; g.alpha = alpha;
 }
 
 // Map (item, phase, t, p, local task q) to the work of one workgroup.
-__device__ void decode(const ItemDev &it, int phase, int t, int p, int q, Task &tk) {
+__device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int p, int q, Task &tk) {
   const int b = it.b, a = it.a, nP = it.nP;
   const long long bb = (long long)b * b;
   const bool arrow = a > 0;
   const bool last = (t == it.nt - 1);
   tk.kind = TK_PRODUCT; tk.nseg = 0; tk.beta = 0.0; tk.mirror = 0; tk.diagtile = 0; tk.chol = 0;
-  tk.left = 0; tk.Cm = nullptr; tk.Lout = nullptr; tk.ldsum = nullptr; tk.E = nullptr;
-  tk.src = nullptr; tk.ldl = 0; tk.lde = 0; tk.row_off = 0;
+  tk.Cm = nullptr; tk.Lout = nullptr; tk.ldsum = nullptr; tk.src = nullptr; tk.ldl = 0;
+  tk.row_off = 0;
   double *Dt = it.D + (long long)t * bb;
   double *St = it.S ? it.S + (long long)t * bb : nullptr;
   double *Rt = arrow ? it.R + (long long)t * a * b : nullptr;
@@ -92,60 +101,66 @@ __device__ void decode(const ItemDev &it, int phase, int t, int p, int q, Task &
       return;
     }
     case PH_PANEL: {
-      if (q < nP - 1 - p) {
-        const int i = p + 1 + q;
-        tk.m = tdim(b, i); tk.n = tdim(b, p);
-        tk.C = Dt + toff(b, i, p); tk.ldc = b;
-        set_seg(tk.seg[0], Dt + toff(b, i, p), 1, b, it.W1 + toff(b, p, p), 1, b, 0, tdim(b, p), 1.0);
-        tk.nseg = 1;
-      } else {
-        const int j = q - (nP - 1 - p);
-        tk.m = tdim(b, p); tk.n = tdim(b, j);
-        tk.C = it.W1 + toff(b, p, j); tk.ldc = b;
-        set_seg(tk.seg[0], Dt + (long long)p * kTile, 1, b, it.W1 + (long long)j * kTile * b, b, 1,
-                j * kTile, p * kTile, 1.0);
-        tk.nseg = 1;
-        tk.left = 1; tk.E = it.W1 + toff(b, p, p); tk.lde = b;
-      }
+      const int i = p + 1 + q;
+      tk.m = tdim(b, i); tk.n = tdim(b, p);
+      tk.C = Dt + toff(b, i, p); tk.ldc = b;
+      set_seg(tk.seg[0], Dt + toff(b, i, p), 1, b, it.W1 + toff(b, p, p), 1, b, 0, tdim(b, p), 1.0);
+      tk.nseg = 1;
       return;
     }
     case PH_TRAIL: {
-      const int n2 = nP - 1 - p;
-      const int cnt = n2 * (n2 + 1) / 2;
-      if (q < cnt) {
-        int ii, jj;
-        tri_decode(q, ii, jj);
-        const int i = p + 1 + ii, j = p + 1 + jj;
-        tk.m = tdim(b, i); tk.n = tdim(b, j);
-        tk.C = Dt + toff(b, i, j); tk.ldc = b; tk.beta = 1.0;
-        set_seg(tk.seg[0], Dt + toff(b, i, p), 1, b, Dt + toff(b, j, p), 1, b, 0, tdim(b, p), -1.0);
-        tk.nseg = 1;
-        if (i == p + 1 && j == p + 1) {
-          tk.chol = 1; tk.Lout = it.W1 + toff(b, i, i); tk.ldl = b;
-          tk.ldsum = it.ldpart + (long long)t * nP + i; tk.row_off = t * b + i * kTile;
-        }
-      } else {
-        const int j = q - cnt;
-        tk.kind = TK_COPY;
-        tk.m = tdim(b, p); tk.n = tdim(b, j);
-        tk.src = it.W1 + toff(b, p, j); tk.C = Dt + toff(b, p, j); tk.ldc = b;
+      int ii, jj;
+      tri_decode(q, ii, jj);
+      const int i = p + 1 + ii, j = p + 1 + jj;
+      tk.m = tdim(b, i); tk.n = tdim(b, j);
+      tk.C = Dt + toff(b, i, j); tk.ldc = b; tk.beta = 1.0;
+      set_seg(tk.seg[0], Dt + toff(b, i, p), 1, b, Dt + toff(b, j, p), 1, b, 0, tdim(b, p), -1.0);
+      tk.nseg = 1;
+      if (i == p + 1 && j == p + 1) {
+        tk.chol = 1; tk.Lout = it.W1 + toff(b, i, i); tk.ldl = b;
+        tk.ldsum = it.ldpart + (long long)t * nP + i; tk.row_off = t * b + i * kTile;
       }
+      return;
+    }
+    case PH_TRTRI: {
+      const int level = p >> 1, stage = p & 1;
+      const int s = 1 << (level - 1);
+      int idx = q, i = 0, j = 0, v0 = 0, uend = 0;
+      for (int u0 = 0; u0 + s < nP; u0 += 2 * s) {
+        const int vs = min(s, nP - (u0 + s));
+        if (idx < s * vs) {
+          i = u0 + s + idx / s;
+          j = u0 + idx % s;
+          v0 = u0 + s;
+          uend = u0 + s;
+          break;
+        }
+        idx -= s * vs;
+      }
+      tk.m = tdim(b, i); tk.n = tdim(b, j);
+      if (stage == 0) {   // T = L_VU X_UU
+        tk.C = it.W2 + toff(b, i, j); tk.ldc = b;
+        set_seg(tk.seg[0], Dt + (long long)i * kTile, 1, b, it.W1 + (long long)j * kTile * b, b, 1,
+                j * kTile, uend * kTile, 1.0);
+      } else {            // X_VU = -X_VV T
+        tk.C = it.W1 + toff(b, i, j); tk.ldc = b;
+        set_seg(tk.seg[0], it.W1 + (long long)i * kTile, 1, b, it.W2 + (long long)j * kTile * b, b,
+                1, v0 * kTile, min(b, (i + 1) * kTile), -1.0);
+      }
+      tk.nseg = 1;
+      return;
+    }
+    case PH_OFFDIAG_X: {
+      const int i = q / nP, j = q % nP;
+      tk.m = tdim(b, i); tk.n = tdim(b, j);
+      tk.C = it.W2 + toff(b, i, j); tk.ldc = b;
+      set_seg(tk.seg[0], St + (long long)i * kTile, 1, b, it.W1 + (long long)j * kTile, 1, b, 0,
+              min(b, (j + 1) * kTile), 1.0);
+      tk.nseg = 1;
       return;
     }
     case PH_OFFDIAG: {
       int idx = q;
-      if (!last) {
-        if (idx < nP * nP) {
-          const int i = idx / nP, j = idx % nP;
-          tk.m = tdim(b, i); tk.n = tdim(b, j);
-          tk.C = it.W2 + toff(b, i, j); tk.ldc = b;
-          set_seg(tk.seg[0], St + (long long)i * kTile, 1, b, it.W1 + (long long)j * kTile, 1, b, 0,
-                  min(b, (j + 1) * kTile), 1.0);
-          tk.nseg = 1;
-          return;
-        }
-        idx -= nP * nP;
-      }
       if (arrow) {
         if (idx < nP) {
           const int j = idx;
@@ -158,40 +173,28 @@ __device__ void decode(const ItemDev &it, int phase, int t, int p, int q, Task &
         }
         idx -= nP;
       }
-      if (idx < nP) {
-        const int j = idx;
-        tk.kind = TK_COPY;
-        tk.m = tdim(b, nP - 1); tk.n = tdim(b, j);
-        tk.src = it.W1 + toff(b, nP - 1, j); tk.C = Dt + toff(b, nP - 1, j); tk.ldc = b;
-        return;
-      }
-      idx -= nP;
       {
-        // strictly upper tile (i, j), j > i, of the factor block: stored as zeros
-        int jj, ii;
-        tri_decode(idx, jj, ii);   // jj > ii enumerates pairs with j in 1..nP-1, i < j
-        const int j = jj + 1, i = ii;
-        tk.kind = TK_ZERO;
+        // D[t] <- inv(L_tt): lower tiles copied from the workspace, upper tiles zero
+        const int i = idx / nP, j = idx % nP;
+        tk.kind = (i >= j) ? TK_COPY : TK_ZERO;
         tk.m = tdim(b, i); tk.n = tdim(b, j);
-        tk.C = Dt + toff(b, i, j); tk.ldc = b;
+        tk.src = it.W1 + toff(b, i, j); tk.C = Dt + toff(b, i, j); tk.ldc = b;
       }
+      return;
+    }
+    case PH_SCHUR_X: {
+      int i, j;
+      tri_decode(q, i, j);
+      tk.m = tdim(b, i); tk.n = tdim(b, j);
+      tk.C = it.D + (long long)(t + 1) * bb + toff(b, i, j); tk.ldc = b; tk.beta = 1.0;
+      set_seg(tk.seg[0], it.W2 + (long long)i * kTile, 1, b, it.W2 + (long long)j * kTile, 1, b, 0, b,
+              -1.0);
+      tk.nseg = 1;
       return;
     }
     case PH_SCHUR: {
       int idx = q;
       if (!last) {
-        const int c1 = nP * (nP + 1) / 2;
-        if (idx < c1) {
-          int i, j;
-          tri_decode(idx, i, j);
-          tk.m = tdim(b, i); tk.n = tdim(b, j);
-          tk.C = it.D + (long long)(t + 1) * bb + toff(b, i, j); tk.ldc = b; tk.beta = 1.0;
-          set_seg(tk.seg[0], it.W2 + (long long)i * kTile, 1, b, it.W2 + (long long)j * kTile, 1, b, 0,
-                  b, -1.0);
-          tk.nseg = 1;
-          return;
-        }
-        idx -= c1;
         if (idx < nP * nP) {
           const int i = idx / nP, j = idx % nP;
           tk.kind = TK_COPY;
@@ -245,53 +248,44 @@ __device__ void decode(const ItemDev &it, int phase, int t, int p, int q, Task &
       tk.nseg = 1;
       return;
     }
+    case PH_SI_VU_X: {
+      const int i = q / nP, j = q % nP;
+      tk.m = tdim(b, i); tk.n = tdim(b, j);
+      tk.C = it.W2 + toff(b, i, j); tk.ldc = b;
+      set_seg(tk.seg[0], St + (long long)i * kTile, 1, b, Dt + (long long)j * kTile * b, b, 1,
+              j * kTile, b, 1.0);
+      tk.nseg = 1;
+      return;
+    }
     case PH_SI_VU: {
-      int idx = q;
-      if (!last) {
-        if (idx < nP * nP) {
-          const int i = idx / nP, j = idx % nP;
-          tk.m = tdim(b, i); tk.n = tdim(b, j);
-          tk.C = it.W2 + toff(b, i, j); tk.ldc = b;
-          set_seg(tk.seg[0], St + (long long)i * kTile, 1, b, Dt + (long long)j * kTile * b, b, 1,
-                  j * kTile, b, 1.0);
-          tk.nseg = 1;
-          return;
-        }
-        idx -= nP * nP;
-      }
-      const int j = idx;
+      const int j = q;
       tk.m = a; tk.n = tdim(b, j);
       tk.C = it.W3 + (long long)j * kTile * a; tk.ldc = a;
       set_seg(tk.seg[0], Rt, 1, a, Dt + (long long)j * kTile * b, b, 1, j * kTile, b, 1.0);
       tk.nseg = 1;
       return;
     }
-    case PH_SI_SR: {
-      int idx = q;
-      double *SDn = last ? nullptr : sig_D(it, t + 1);
-      double *SRn = (last || !arrow) ? nullptr : sig_R(it, t + 1);
-      if (!last) {
-        if (idx < nP * nP) {
-          const int i = idx / nP, j = idx % nP;
-          tk.m = tdim(b, i); tk.n = tdim(b, j);
-          tk.C = sig_S(it, t) + toff(b, i, j); tk.ldc = b;
-          set_seg(tk.seg[0], SDn + (long long)i * kTile, 1, b, it.W2 + (long long)j * kTile * b, b, 1,
-                  0, b, -1.0);
-          tk.nseg = 1;
-          if (arrow) {
-            set_seg(tk.seg[1], SRn + (long long)i * kTile * a, a, 1, it.W3 + (long long)j * kTile * a,
-                    a, 1, 0, a, -1.0);
-            tk.nseg = 2;
-          }
-          return;
-        }
-        idx -= nP * nP;
+    case PH_SI_SR_X: {
+      const int i = q / nP, j = q % nP;
+      double *SDn = sig_D(it, t + 1);
+      tk.m = tdim(b, i); tk.n = tdim(b, j);
+      tk.C = sig_S(it, t) + toff(b, i, j); tk.ldc = b;
+      set_seg(tk.seg[0], SDn + (long long)i * kTile, 1, b, it.W2 + (long long)j * kTile * b, b, 1, 0,
+              b, -1.0);
+      tk.nseg = 1;
+      if (arrow) {
+        set_seg(tk.seg[1], sig_R(it, t + 1) + (long long)i * kTile * a, a, 1,
+                it.W3 + (long long)j * kTile * a, a, 1, 0, a, -1.0);
+        tk.nseg = 2;
       }
-      const int j = idx;
+      return;
+    }
+    case PH_SI_SR: {
+      const int j = q;
       tk.m = a; tk.n = tdim(b, j);
       tk.C = sig_R(it, t) + (long long)j * kTile * a; tk.ldc = a;
       if (!last) {
-        set_seg(tk.seg[0], SRn, 1, a, it.W2 + (long long)j * kTile * b, b, 1, 0, b, -1.0);
+        set_seg(tk.seg[0], sig_R(it, t + 1), 1, a, it.W2 + (long long)j * kTile * b, b, 1, 0, b, -1.0);
         set_seg(tk.seg[1], it.ST, 1, a, it.W3 + (long long)j * kTile * a, a, 1, 0, a, -1.0);
         tk.nseg = 2;
       } else {
@@ -300,7 +294,7 @@ __device__ void decode(const ItemDev &it, int phase, int t, int p, int q, Task &
       }
       return;
     }
-    case PH_SI_SD: {
+    case PH_SI_SD_X: {
       int i, j;
       tri_decode(q, i, j);
       double *SDt = sig_D(it, t);
@@ -332,61 +326,228 @@ __device__ void decode(const ItemDev &it, int phase, int t, int p, int q, Task &
   }
 }
 
-// Stage rows [0, rows) x k in [kc, min(kc+KC, k1)) of op(X) into P[k][row] (zero-filled).
-__device__ inline void load_panel(double *P, const double *X, long long rs, long long ks, int rows,
-                                  int kc, int k1, double alpha) {
+// Map (item, product phase, t, local task q) to one 128 x 128 output tile.  The
+// k ranges are those of the 64-tile form widened to the big tile; the extra
+// range only meets entries that are stored as zeros (the workspace holding
+// inv(L_tt) is cleared before the factorization, and the factor blocks keep
+// zeros above their diagonal).
+__device__ __forceinline__ long long boff(int b, int I, int J) {
+  return (long long)I * kBig + (long long)J * kBig * b;
+}
+__device__ __forceinline__ int bdim(int n, int I) { return min(kBig, n - I * kBig); }
+
+__device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, int q, Task &tk) {
+  const int b = it.b, a = it.a, nQ = nbig(it.b);
+  const long long bb = (long long)b * b;
+  const bool arrow = a > 0;
+  const bool last = (t == it.nt - 1);
+  tk.kind = TK_PRODUCT; tk.nseg = 0; tk.beta = 0.0; tk.mirror = 0; tk.diagtile = 0; tk.chol = 0;
+  tk.Cm = nullptr; tk.Lout = nullptr; tk.ldsum = nullptr; tk.src = nullptr; tk.ldl = 0;
+  tk.row_off = 0;
+  double *Dt = it.D + (long long)t * bb;
+  double *St = it.S ? it.S + (long long)t * bb : nullptr;
+  int I, J;
+  switch (phase) {
+    case PH_OFFDIAG_X:
+      I = q / nQ; J = q % nQ;
+      tk.m = bdim(b, I); tk.n = bdim(b, J);
+      tk.C = it.W2 + boff(b, I, J); tk.ldc = b;
+      set_seg(tk.seg[0], St + (long long)I * kBig, 1, b, it.W1 + (long long)J * kBig, 1, b, 0,
+              min(b, (J + 1) * kBig), 1.0);
+      tk.nseg = 1;
+      return;
+    case PH_SCHUR_X:
+      tri_decode(q, I, J);
+      tk.m = bdim(b, I); tk.n = bdim(b, J);
+      tk.C = it.D + (long long)(t + 1) * bb + boff(b, I, J); tk.ldc = b; tk.beta = 1.0;
+      set_seg(tk.seg[0], it.W2 + (long long)I * kBig, 1, b, it.W2 + (long long)J * kBig, 1, b, 0, b,
+              -1.0);
+      tk.nseg = 1;
+      return;
+    case PH_SI_VU_X:
+      I = q / nQ; J = q % nQ;
+      tk.m = bdim(b, I); tk.n = bdim(b, J);
+      tk.C = it.W2 + boff(b, I, J); tk.ldc = b;
+      set_seg(tk.seg[0], St + (long long)I * kBig, 1, b, Dt + (long long)J * kBig * b, b, 1,
+              J * kBig, b, 1.0);
+      tk.nseg = 1;
+      return;
+    case PH_SI_SR_X:
+      I = q / nQ; J = q % nQ;
+      tk.m = bdim(b, I); tk.n = bdim(b, J);
+      tk.C = sig_S(it, t) + boff(b, I, J); tk.ldc = b;
+      set_seg(tk.seg[0], sig_D(it, t + 1) + (long long)I * kBig, 1, b,
+              it.W2 + (long long)J * kBig * b, b, 1, 0, b, -1.0);
+      tk.nseg = 1;
+      if (arrow) {
+        set_seg(tk.seg[1], sig_R(it, t + 1) + (long long)I * kBig * a, a, 1,
+                it.W3 + (long long)J * kBig * a, a, 1, 0, a, -1.0);
+        tk.nseg = 2;
+      }
+      return;
+    case PH_SI_SD_X: {
+      tri_decode(q, I, J);
+      double *SDt = sig_D(it, t);
+      tk.m = bdim(b, I); tk.n = bdim(b, J);
+      tk.C = SDt + boff(b, I, J); tk.ldc = b;
+      tk.mirror = 1; tk.Cm = SDt + boff(b, J, I); tk.diagtile = (I == J);
+      set_seg(tk.seg[0], Dt + (long long)I * kBig * b, b, 1, Dt + (long long)J * kBig * b, b, 1,
+              I * kBig, b, 1.0);
+      tk.nseg = 1;
+      if (!last) {
+        set_seg(tk.seg[1], sig_S(it, t) + (long long)I * kBig * b, b, 1,
+                it.W2 + (long long)J * kBig * b, b, 1, 0, b, -1.0);
+        tk.nseg = 2;
+        if (arrow) {
+          set_seg(tk.seg[2], sig_R(it, t) + (long long)I * kBig * a, a, 1,
+                  it.W3 + (long long)J * kBig * a, a, 1, 0, a, -1.0);
+          tk.nseg = 3;
+        }
+      } else if (arrow) {
+        set_seg(tk.seg[1], sig_R(it, t) + (long long)I * kBig * a, a, 1,
+                it.W3 + (long long)J * kBig * a, a, 1, 0, a, -1.0);
+        tk.nseg = 2;
+      }
+      return;
+    }
+    default:
+      tk.kind = TK_NONE;
+      return;
+  }
+}
+
+// Global -> register staging of rows [0, rows) x k in [kc, min(kc+KC, k1)) of op(X)
+// for a panel of ROWS rows, NT threads.  Addresses are clamped into range so
+// that every load is unconditional and all of them stay in flight together;
+// masking and scaling happen at the LDS store.
+template <int KC, int ROWS, int NT>
+__device__ __forceinline__ void gload(double (&r)[KC * ROWS / NT], const double *X, int rs, int ks,
+                                      int rows, int kc, int k1) {
   const int tid = threadIdx.x;
+  constexpr int NE = KC * ROWS / NT;
+  const int rmax = rows - 1, kmax = k1 - 1;
   if (rs == 1) {
 #pragma unroll
-    for (int q = 0; q < (KC * kTile) / kThreads; ++q) {
-      const int e = tid + q * kThreads;
-      const int r = e & (kTile - 1), k = e / kTile;
-      const int kk = kc + k;
-      double v = 0.0;
-      if (r < rows && kk < k1) v = alpha * X[(long long)r + (long long)kk * ks];
-      P[k * LDP + r] = v;
+    for (int q = 0; q < NE; ++q) {
+      const int e = tid + q * NT;
+      const int rr = e % ROWS, kk = kc + e / ROWS;
+      r[q] = gld(X + (long long)min(rr, rmax) + (long long)min(kk, kmax) * ks);
     }
   } else {
 #pragma unroll
-    for (int q = 0; q < (KC * kTile) / kThreads; ++q) {
-      const int e = tid + q * kThreads;
-      const int k = e & (KC - 1), r = e / KC;
-      const int kk = kc + k;
-      double v = 0.0;
-      if (r < rows && kk < k1) v = alpha * X[(long long)r * rs + (long long)kk * ks];
-      P[k * LDP + r] = v;
+    for (int q = 0; q < NE; ++q) {
+      const int e = tid + q * NT;
+      const int kk = kc + e % KC, rr = e / KC;
+      r[q] = gld(X + (long long)min(rr, rmax) * rs + (long long)min(kk, kmax) * ks);
     }
   }
 }
 
-// acc += op(A) op(B)^T over all segments of the task.
-__device__ void run_product(const Task &tk, double *smem, d4 (&acc)[2][2]) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wr = w >> 1, wc = w & 1;
-  double *As = smem;
-  double *Bs = smem + KC * LDP;
+// Register -> LDS panel P[k][row] (row length ROWS + 2), zeroing out-of-range
+// entries and applying alpha.
+template <int KC, int ROWS, int NT>
+__device__ __forceinline__ void sstore(double *P, const double (&r)[KC * ROWS / NT], bool rows_contig,
+                                       int rows, int kc, int k1, double alpha) {
+  const int tid = threadIdx.x;
+  constexpr int NE = KC * ROWS / NT;
+  constexpr int LD = ROWS + 2;
+  if (rows_contig) {
 #pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    if (s >= tk.nseg) break;
-    const Seg g = tk.seg[s];
-    for (int kc = g.k0; kc < g.k1; kc += KC) {
-      load_panel(As, g.A, g.ars, g.aks, tk.m, kc, g.k1, g.alpha);
-      load_panel(Bs, g.B, g.brs, g.bks, tk.n, kc, g.k1, 1.0);
-      __syncthreads();
-#pragma unroll
-      for (int kk = 0; kk < KC; kk += 4) {
-        const int kr = (kk + (lane >> 4)) * LDP;
-        const double a0 = As[kr + wr * 32 + (lane & 15)];
-        const double a1 = As[kr + wr * 32 + 16 + (lane & 15)];
-        const double b0 = Bs[kr + wc * 32 + (lane & 15)];
-        const double b1 = Bs[kr + wc * 32 + 16 + (lane & 15)];
-        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-      }
-      __syncthreads();
+    for (int q = 0; q < NE; ++q) {
+      const int e = tid + q * NT;
+      const int rr = e % ROWS, k = e / ROWS;
+      P[k * LD + rr] = (rr < rows && kc + k < k1) ? alpha * r[q] : 0.0;
     }
+  } else {
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      const int e = tid + q * NT;
+      const int k = e % KC, rr = e / KC;
+      P[k * LD + rr] = (rr < rows && kc + k < k1) ? alpha * r[q] : 0.0;
+    }
+  }
+}
+
+// Geometry of the chunk held in the staging registers.
+struct ChunkInfo {
+  bool fa, fb;
+  int kc, k1;
+  double alpha;
+};
+
+template <int KC, int ROWS, int NT>
+__device__ __forceinline__ void load_seg_chunk(const Seg &g, int m, int n, int kc,
+                                               double (&ra)[KC * ROWS / NT],
+                                               double (&rb)[KC * ROWS / NT], ChunkInfo &ci) {
+  gload<KC, ROWS, NT>(ra, g.A, g.ars, g.aks, m, kc, g.k1);
+  gload<KC, ROWS, NT>(rb, g.B, g.brs, g.bks, n, kc, g.k1);
+  ci.fa = g.ars == 1;
+  ci.fb = g.brs == 1;
+  ci.kc = kc;
+  ci.k1 = g.k1;
+  ci.alpha = g.alpha;
+}
+
+// acc += sum over segments of op(A) op(B)^T for an output tile of ROWS x ROWS
+// computed by WR x WC waves; wave (wr, wc) owns rows wr*ROWS/WR .. and columns
+// wc*ROWS/WC .., i.e. MR x MC MFMA blocks of 16 x 16.  LDS panels are
+// double-buffered: the next chunk is fetched into registers while the current
+// one feeds the matrix cores, so there is one barrier per chunk.  Chunks are
+// numbered across the segments; segment fields are only indexed by constants
+// so the task stays in registers.
+template <int KC, int ROWS, int WR, int WC>
+__device__ __forceinline__ void run_product(const Task &tk, double *smem,
+                                            d4 (&acc)[ROWS / WR / 16][ROWS / WC / 16]) {
+  constexpr int NT = 64 * WR * WC;
+  constexpr int NE = KC * ROWS / NT;
+  constexpr int LD = ROWS + 2;
+  constexpr int MR = ROWS / WR / 16, MC = ROWS / WC / 16;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = w / WC, wc = w % WC;
+  const int n0 = (tk.nseg > 0 && tk.seg[0].k1 > tk.seg[0].k0) ? (tk.seg[0].k1 - tk.seg[0].k0 + KC - 1) / KC : 0;
+  const int n1 = (tk.nseg > 1 && tk.seg[1].k1 > tk.seg[1].k0) ? (tk.seg[1].k1 - tk.seg[1].k0 + KC - 1) / KC : 0;
+  const int n2 = (tk.nseg > 2 && tk.seg[2].k1 > tk.seg[2].k0) ? (tk.seg[2].k1 - tk.seg[2].k0 + KC - 1) / KC : 0;
+  const int total = n0 + n1 + n2;
+  if (total == 0) return;
+  double ra[NE], rb[NE];
+  ChunkInfo ci;
+  auto fetch = [&](int c) {
+    if (c < n0) load_seg_chunk<KC, ROWS, NT>(tk.seg[0], tk.m, tk.n, tk.seg[0].k0 + c * KC, ra, rb, ci);
+    else if (c < n0 + n1)
+      load_seg_chunk<KC, ROWS, NT>(tk.seg[1], tk.m, tk.n, tk.seg[1].k0 + (c - n0) * KC, ra, rb, ci);
+    else
+      load_seg_chunk<KC, ROWS, NT>(tk.seg[2], tk.m, tk.n, tk.seg[2].k0 + (c - n0 - n1) * KC, ra, rb,
+                                   ci);
+  };
+  auto stage = [&](double *dst) {
+    sstore<KC, ROWS, NT>(dst, ra, ci.fa, tk.m, ci.kc, ci.k1, ci.alpha);
+    sstore<KC, ROWS, NT>(dst + KC * LD, rb, ci.fb, tk.n, ci.kc, ci.k1, 1.0);
+  };
+  fetch(0);
+  stage(smem);
+  __syncthreads();
+  for (int c = 0; c < total; ++c) {
+    const int cur = c & 1;
+    const bool has_next = c + 1 < total;
+    if (has_next) fetch(c + 1);
+    const double *As = smem + cur * (2 * KC * LD);
+    const double *Bs = As + KC * LD;
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      const int kr = (kk + (lane >> 4)) * LD;
+      double av[MR], bv[MC];
+#pragma unroll
+      for (int x = 0; x < MR; ++x) av[x] = As[kr + wr * (ROWS / WR) + x * 16 + (lane & 15)];
+#pragma unroll
+      for (int x = 0; x < MC; ++x) bv[x] = Bs[kr + wc * (ROWS / WC) + x * 16 + (lane & 15)];
+#pragma unroll
+      for (int mi = 0; mi < MR; ++mi)
+#pragma unroll
+        for (int nj = 0; nj < MC; ++nj)
+          acc[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mi], bv[nj], acc[mi][nj], 0, 0, 0);
+    }
+    if (has_next) stage(smem + (cur ^ 1) * (2 * KC * LD));
+    __syncthreads();
   }
 }
 
@@ -396,64 +557,151 @@ __device__ inline int acc_row(int wr, int mi, int lane, int r) {
 }
 __device__ inline int acc_col(int wc, int nj, int lane) { return wc * 32 + nj * 16 + (lane & 15); }
 
-// Cholesky of the lower triangle of the w x w tile A (LDS, row-major, ld TLD)
-// followed by the inverse of the factor.  Columns are kept unscaled during the
-// elimination (A_j[i][k] -= A_j[i][j] A_j[k][j] / A_j[j][j]), so one barrier
-// per column suffices; then V = unit-lower factor, Y = V^{-1} by forward
-// substitution, and inv(L) = diag(1/l) Y with l_j = sqrt(pivot_j).
-__device__ void chol_inv_tile(double *A, double *X, double *dl, int w, double *Lout, long long ldl,
-                              double *ldsum, int row_off, int *info) {
-  const int tid = threadIdx.x;
-  const int ntri = w * (w + 1) / 2;
-  int ei[9], ek[9];
+__device__ inline double rdlane(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// Cholesky + inverse of one 64 x 64 tile held in LDS (A, row-major, ld TLD;
+// rows/cols >= w padded with the identity).  16 x 16 diagonal blocks are
+// factored and inverted by one wave in registers (rows in lanes, pivots and
+// rows broadcast with readlane); the panel solves, trailing updates and the
+// block inverse X = L^{-1} (X_ij = -X_ii sum_m L_im X_mj) run on the matrix
+// cores.  Writes inv(L) (zeros above the diagonal) to Lout and sum log L_jj.
+__device__ void chol_inv_tile(double *A, double *X, double *dlog, int w, double *Lout,
+                              long long ldl, double *ldsum, int row_off, int *info) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nb = (w + 15) / 16;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int k = 0; k < nb; ++k) {
+    // (a) factor and invert the diagonal block (k,k) in wave 0: lane i holds row
+    //     i; every update is a select, so the wave never branches.
+    if (wv == 0) {
+      const int r0 = 16 * k;
+      double a[16], x[16], rinv[16];
 #pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    const int e = tid + q * kThreads;
-    if (e < ntri) {
-      int i, k;
-      tri_decode(e, i, k);
-      ei[q] = i; ek[q] = k;
-    } else {
-      ei[q] = -1; ek[q] = 0;
+      for (int c = 0; c < 16; ++c)
+        a[c] = (lane < 16 && c <= lane) ? A[(r0 + lane) * TLD + r0 + c] : 0.0;
+      int bad = -1;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const double piv = rdlane(a[j], j);
+        if (bad < 0 && !(piv > 0.0) && r0 + j < w) bad = j;
+        const double dj = sqrt(piv);
+        const double inv = 1.0 / dj;
+        rinv[j] = inv;
+        a[j] = (lane > j) ? a[j] * inv : ((lane == j) ? dj : a[j]);
+#pragma unroll
+        for (int m = j + 1; m < 16; ++m) {
+          const double lm = rdlane(a[j], m);
+          a[m] = (lane >= m) ? fma(-a[j], lm, a[m]) : a[m];
+        }
+      }
+      if (bad >= 0 && lane == 0) atomicMin(info, row_off + r0 + bad + 1);
+#pragma unroll
+      for (int c = 0; c < 16; ++c) x[c] = (c == lane) ? 1.0 : 0.0;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+#pragma unroll
+        for (int c = 0; c <= m; ++c) x[c] = (lane == m) ? x[c] * rinv[m] : x[c];
+#pragma unroll
+        for (int c = 0; c <= m; ++c) {
+          const double xm = rdlane(x[c], m);
+          x[c] = (lane > m) ? fma(-a[m], xm, x[c]) : x[c];
+        }
+      }
+      if (lane < 16) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) X[(r0 + lane) * TLD + r0 + c] = (c <= lane) ? x[c] : 0.0;
+        double dg = a[0];
+#pragma unroll
+        for (int c = 1; c < 16; ++c) dg = (c == lane) ? a[c] : dg;
+        dlog[r0 + lane] = (r0 + lane < w) ? log(dg) : 0.0;
+      }
     }
-  }
-  for (int j = 0; j < w; ++j) {
-    const double piv = A[j * TLD + j];
-    if (tid == 0 && !(piv > 0.0)) atomicMin(info, row_off + j + 1);
-    const double inv = 1.0 / piv;
+    __syncthreads();
+    if (k + 1 >= nb) break;
+    // (b) panel blocks L_ik = A_ik Linv_kk^T, i > k
+    {
+      const int i = k + 1 + wv;
+      if (i < nb) {
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      if (ek[q] > j) A[ei[q] * TLD + ek[q]] -= A[ei[q] * TLD + j] * A[ek[q] * TLD + j] * inv;
+        for (int q = 0; q < 4; ++q) {
+          const double av = A[(16 * i + lr) * TLD + 16 * k + 4 * q + lk];
+          const double bv = X[(16 * k + lr) * TLD + 16 * k + 4 * q + lk];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) A[(16 * i + lk + 4 * r) * TLD + 16 * k + lr] = acc[r];
+      }
+    }
+    __syncthreads();
+    // (c) trailing blocks A_ij -= L_ik L_jk^T, k < j <= i < nb
+    {
+      const int nrem = nb - 1 - k;
+      const int nblk = nrem * (nrem + 1) / 2;
+      for (int e = wv; e < nblk; e += 4) {
+        int ii, jj;
+        tri_decode(e, ii, jj);
+        const int i = k + 1 + ii, j = k + 1 + jj;
+        d4 acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = A[(16 * i + lk + 4 * r) * TLD + 16 * j + lr];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double av = A[(16 * i + lr) * TLD + 16 * k + 4 * q + lk];
+          const double bv = A[(16 * j + lr) * TLD + 16 * k + 4 * q + lk];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-av, bv, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) A[(16 * i + lk + 4 * r) * TLD + 16 * j + lr] = acc[r];
+      }
     }
     __syncthreads();
   }
-  // unit-lower V (in place below the diagonal) and Y = I
+  // block inverse below the diagonal, one block diagonal d at a time
+  for (int d = 1; d < nb; ++d) {
+    const int j = wv, i = wv + d;
+    double *P = A + 16 * (wv + 1);   // scratch: upper block (0, wv+1) of A is unused
+    const bool act = i < nb;
+    if (act) {
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int m = j; m < i; ++m) {
 #pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    if (ei[q] >= 0) {
-      if (ei[q] > ek[q]) A[ei[q] * TLD + ek[q]] /= A[ek[q] * TLD + ek[q]];
-      X[ei[q] * TLD + ek[q]] = (ei[q] == ek[q]) ? 1.0 : 0.0;
+        for (int q = 0; q < 4; ++q) {
+          const double av = A[(16 * i + lr) * TLD + 16 * m + 4 * q + lk];
+          const double bv = X[(16 * m + 4 * q + lk) * TLD + 16 * j + lr];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) P[(lk + 4 * r) * TLD + lr] = acc[r];
     }
-  }
-  if (tid < w) dl[tid] = sqrt(A[tid * TLD + tid]);
-  __syncthreads();
-  for (int k = 0; k + 1 < w; ++k) {
+    __syncthreads();
+    if (act) {
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      if (ei[q] > k && ek[q] <= k) X[ei[q] * TLD + ek[q]] -= A[ei[q] * TLD + k] * X[k * TLD + ek[q]];
+      for (int q = 0; q < 4; ++q) {
+        const double av = X[(16 * i + lr) * TLD + 16 * i + 4 * q + lk];
+        const double bv = P[(4 * q + lk) * TLD + lr];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) X[(16 * i + lk + 4 * r) * TLD + 16 * j + lr] = -acc[r];
     }
     __syncthreads();
   }
-  // inv(L) = diag(1/l) Y, stored as a full tile with zeros above the diagonal
   for (int e = tid; e < kTile * kTile; e += kThreads) {
     const int r = e & (kTile - 1), c = e / kTile;
-    if (r < w && c < w) Lout[r + (long long)c * ldl] = (c <= r) ? X[r * TLD + c] / dl[r] : 0.0;
+    if (r < w && c < w) gst(Lout + r + (long long)c * ldl, (c <= r) ? X[r * TLD + c] : 0.0);
   }
-  if (tid < 64) {
-    double v = (tid < w) ? log(dl[tid]) : 0.0;
+  if (wv == 0) {
+    double v = (lane < w) ? dlog[lane] : 0.0;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (tid == 0) *ldsum = v;
+    if (lane == 0) *ldsum = v;
   }
 }
 
@@ -476,10 +724,19 @@ __global__ __launch_bounds__(kThreads) void tile_phase_kernel(const ItemDev *__r
   const int wr = w >> 1, wc = w & 1;
   if (tk.kind == TK_NONE) return;
   if (tk.kind == TK_COPY || tk.kind == TK_ZERO) {
-    for (int e = tid; e < kTile * kTile; e += kThreads) {
-      const int r = e & (kTile - 1), c = e / kTile;
-      if (r < tk.m && c < tk.n)
-        tk.C[r + c * tk.ldc] = (tk.kind == TK_COPY) ? tk.src[r + c * tk.ldc] : 0.0;
+    // out-of-range lanes rewrite the clamped edge element with its own value
+    double v[kTile * kTile / kThreads];
+#pragma unroll
+    for (int q = 0; q < kTile * kTile / kThreads; ++q) {
+      const int e = tid + q * kThreads;
+      const int r = min(e & (kTile - 1), tk.m - 1), c = min(e / kTile, tk.n - 1);
+      v[q] = (tk.kind == TK_COPY) ? gld(tk.src + r + c * tk.ldc) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kTile * kTile / kThreads; ++q) {
+      const int e = tid + q * kThreads;
+      const int r = min(e & (kTile - 1), tk.m - 1), c = min(e / kTile, tk.n - 1);
+      gst(tk.C + r + c * tk.ldc, v[q]);
     }
     return;
   }
@@ -488,15 +745,15 @@ __global__ __launch_bounds__(kThreads) void tile_phase_kernel(const ItemDev *__r
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
     for (int nj = 0; nj < 2; ++nj) acc[mi][nj] = d4{0.0, 0.0, 0.0, 0.0};
-  run_product(tk, smem, acc);
+  run_product<FAT ? kFatKC : kLeanKC, kTile, 2, 2>(tk, smem, acc);
 
   if constexpr (FAT) {
     if (tk.chol) {
       double *A = smem;
       double *X = smem + kTile * TLD;
-      double *dl = smem + 2 * kTile * TLD;
-      for (int e = tid; e < kTile * kTile; e += kThreads) A[(e / kTile) * TLD + (e % kTile)] = 0.0;
-      __syncthreads();
+      double *dlog = smem + 2 * kTile * TLD;
+      // the tile (identity padding beyond w) is written in full, without branches
+      double cold[2][2][4];
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
@@ -504,26 +761,8 @@ __global__ __launch_bounds__(kThreads) void tile_phase_kernel(const ItemDev *__r
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int row = acc_row(wr, mi, lane, r), col = acc_col(wc, nj, lane);
-            if (row < tk.m && col < tk.n) {
-              double v = acc[mi][nj][r];
-              if (tk.beta != 0.0) v += tk.beta * tk.C[row + col * tk.ldc];
-              A[row * TLD + col] = v;
-            }
+            cold[mi][nj][r] = gld(tk.C + min(row, tk.m - 1) + min(col, tk.n - 1) * tk.ldc);
           }
-      __syncthreads();
-      chol_inv_tile(A, X, dl, tk.m, tk.Lout, tk.ldl, tk.ldsum, tk.row_off, it.info);
-      return;
-    }
-    if (tk.left) {
-      // P (m x n) -> LDS as [k = row of P][col]; E (m x m lower) -> LDS as [k][row]
-      double *Pl = smem;
-      double *El = smem + kTile * TLD;
-      for (int e = tid; e < kTile * kTile; e += kThreads) {
-        const int r = e & (kTile - 1), c = e / kTile;
-        Pl[c * TLD + r] = 0.0;
-        El[c * TLD + r] = (r < tk.m && c < tk.m) ? tk.E[r + c * tk.lde] : 0.0;  // El[k=c][row=r]
-      }
-      __syncthreads();
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
@@ -531,38 +770,42 @@ __global__ __launch_bounds__(kThreads) void tile_phase_kernel(const ItemDev *__r
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int row = acc_row(wr, mi, lane, r), col = acc_col(wc, nj, lane);
-            if (row < tk.m && col < tk.n) Pl[row * TLD + col] = acc[mi][nj][r];
+            const double v = acc[mi][nj][r] + tk.beta * cold[mi][nj][r];
+            const double pad = (row == col) ? 1.0 : 0.0;
+            A[row * TLD + col] = (row < tk.m && col < tk.n) ? v : pad;
           }
       __syncthreads();
-      d4 out[2][2];
-#pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-        for (int nj = 0; nj < 2; ++nj) out[mi][nj] = d4{0.0, 0.0, 0.0, 0.0};
-      for (int kk = 0; kk < kTile; kk += 4) {
-        const int k = kk + (lane >> 4);
-        const double a0 = El[k * TLD + wr * 32 + (lane & 15)];
-        const double a1 = El[k * TLD + wr * 32 + 16 + (lane & 15)];
-        const double b0 = Pl[k * TLD + wc * 32 + (lane & 15)];
-        const double b1 = Pl[k * TLD + wc * 32 + 16 + (lane & 15)];
-        out[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, out[0][0], 0, 0, 0);
-        out[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, out[0][1], 0, 0, 0);
-        out[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, out[1][0], 0, 0, 0);
-        out[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, out[1][1], 0, 0, 0);
-      }
-#pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-        for (int nj = 0; nj < 2; ++nj)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = acc_row(wr, mi, lane, r), col = acc_col(wc, nj, lane);
-            if (row < tk.m && col < tk.n) tk.C[row + col * tk.ldc] = -out[mi][nj][r];
-          }
+      chol_inv_tile(A, X, dlog, tk.m, tk.Lout, tk.ldl, tk.ldsum, tk.row_off, it.info);
       return;
     }
   }
-  // plain (and mirrored) store
+  // plain (and mirrored) store; C is read first (clamped, unconditional) when beta != 0
+  double cold[2][2][4];
+  if (tk.beta != 0.0) {
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = min(acc_row(wr, mi, lane, r), tk.m - 1);
+          const int col = min(acc_col(wc, nj, lane), tk.n - 1);
+          cold[mi][nj][r] = tk.beta * gld(tk.C + row + col * tk.ldc);
+        }
+  } else {
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cold[mi][nj][r] = 0.0;
+  }
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[mi][nj][r] += cold[mi][nj][r];
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
@@ -571,26 +814,97 @@ __global__ __launch_bounds__(kThreads) void tile_phase_kernel(const ItemDev *__r
       for (int r = 0; r < 4; ++r) {
         const int row = acc_row(wr, mi, lane, r), col = acc_col(wc, nj, lane);
         if (row < tk.m && col < tk.n) {
-          double v = acc[mi][nj][r];
+          const double v = acc[mi][nj][r];
           double *cp = tk.C + row + col * tk.ldc;
-          if (tk.beta != 0.0) v += tk.beta * (*cp);
           if (tk.mirror && tk.diagtile) {
             if (row >= col) {
-              *cp = v;
-              tk.Cm[col + row * tk.ldc] = v;
+              gst(cp, v);
+              gst(tk.Cm + col + row * tk.ldc, v);
             }
           } else {
-            *cp = v;
-            if (tk.mirror) tk.Cm[col + row * tk.ldc] = v;
+            gst(cp, v);
+            if (tk.mirror) gst(tk.Cm + col + row * tk.ldc, v);
+          }
+        }
+      }
+}
+
+// 128 x 128 output tiles for the b x b products: 8 waves in a 2 x 4
+// arrangement, 64 x 32 outputs (4 x 2 MFMA blocks) per wave.
+constexpr int kBigThreads = 512;
+__global__ __launch_bounds__(kBigThreads, 1) void tile_big_kernel(const ItemDev *__restrict__ items,
+                                                                  int n_items, int phase, int t) {
+  __shared__ double smem[kBigLds];
+  int q = blockIdx.x;
+  int ii = 0;
+  for (; ii < n_items; ++ii) {
+    const int c = phase_tasks(items[ii], phase, t, 0, true);
+    if (q < c) break;
+    q -= c;
+  }
+  if (ii >= n_items) return;
+  const ItemDev it = items[ii];
+  Task tk;
+  decode_big(it, phase, t, q, tk);
+  if (tk.kind != TK_PRODUCT) return;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = w / 4, wc = w % 4;
+  d4 acc[4][2];
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int nj = 0; nj < 2; ++nj) acc[mi][nj] = d4{0.0, 0.0, 0.0, 0.0};
+  run_product<kBigKC, kBig, 2, 4>(tk, smem, acc);
+  if (tk.beta != 0.0) {
+    double cold[4][2][4];
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+      for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = min(wr * 64 + mi * 16 + (lane >> 4) + 4 * r, tk.m - 1);
+          const int col = min(wc * 32 + nj * 16 + (lane & 15), tk.n - 1);
+          cold[mi][nj][r] = gld(tk.C + row + col * tk.ldc);
+        }
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+      for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[mi][nj][r] += tk.beta * cold[mi][nj][r];
+  }
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wr * 64 + mi * 16 + (lane >> 4) + 4 * r;
+        const int col = wc * 32 + nj * 16 + (lane & 15);
+        if (row < tk.m && col < tk.n) {
+          const double v = acc[mi][nj][r];
+          double *cp = tk.C + row + col * tk.ldc;
+          if (tk.mirror && tk.diagtile) {
+            if (row >= col) {
+              gst(cp, v);
+              gst(tk.Cm + col + row * tk.ldc, v);
+            }
+          } else {
+            gst(cp, v);
+            if (tk.mirror) gst(tk.Cm + col + row * tk.ldc, v);
           }
         }
       }
 }
 
 hipError_t launch_tile_phase(const ItemDev *items_dev, int n_items, int total, int phase, int t,
-                             int p, hipStream_t s) {
+                             int p, bool big, hipStream_t s) {
   if (total <= 0) return hipSuccess;
-  if (phase_is_fat(phase)) {
+  if (big && phase_is_product_x(phase)) {
+    hipLaunchKernelGGL(tile_big_kernel, dim3(total), dim3(kBigThreads), 0, s, items_dev, n_items,
+                       phase, t);
+  } else if (phase_is_fat(phase)) {
     hipLaunchKernelGGL(tile_phase_kernel<true>, dim3(total), dim3(kThreads), 0, s, items_dev, n_items,
                        phase, t, p);
   } else {

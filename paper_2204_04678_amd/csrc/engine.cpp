@@ -20,6 +20,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -126,11 +127,15 @@ inla_status upload(T *dst, const std::vector<T> &src, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // phase sequences
 // ---------------------------------------------------------------------------
+bool use_big_tiles(const std::vector<ItemDev> &items);
+
 struct Batch {
   std::vector<ItemDev> host;
   ItemDev *dev = nullptr;
   int max_nt = 0, max_b = 0, max_a = 0;
+  bool big = false;
   void finalize() {
+    big = use_big_tiles(host);
     for (auto &it : host) {
       max_nt = std::max(max_nt, it.nt);
       max_b = std::max(max_b, it.b);
@@ -139,11 +144,97 @@ struct Batch {
   }
 };
 
+// Algorithmic FP64 flops of one item in one phase (dense-block counts:
+// POTRF(b) = b^3/3, TRTRI(b) = b^3/3, TRSM/TRMM(m x b) = m b^2, SYRK(n, k) = n^2 k,
+// GEMM(m, n, k) = 2 m n k, LAUUM(b) = b^3/3).
+double phase_flops(const ItemDev &it, int phase, int t, int p) {
+  if (phase_tasks(it, phase, t, p) == 0) return 0.0;
+  const double b = it.b, a = it.a, b3 = b * b * b;
+  const bool last = (t == it.nt - 1);
+  switch (phase) {
+    case PH_DIAG0: return b3 / 3.0;                  // POTRF of the block, all panels
+    case PH_TRTRI: return (p & 1) ? 0.0 : b3 / (3.0 * trtri_levels(it.nP));  // TRTRI, spread
+    case PH_OFFDIAG_X: return last ? 0.0 : b3;
+    case PH_OFFDIAG: return a * b * b;
+    case PH_SCHUR_X: return last ? 0.0 : b3;
+    case PH_SCHUR: return (last ? 0.0 : 2.0 * a * b * b) + a * a * b;
+    case PH_ARROW: return 2.0 * a * a * a / 3.0;
+    case PH_SI_INIT: return a * a * a / 3.0;
+    case PH_SI_VU_X: return last ? 0.0 : b3;
+    case PH_SI_VU: return a * b * b;
+    case PH_SI_SR_X: return last ? 0.0 : 2.0 * b3 + 2.0 * a * b * b;
+    case PH_SI_SR: return (last ? 0.0 : 2.0 * a * b * b) + 2.0 * a * a * b;
+    case PH_SI_SD_X: return b3 / 3.0 + (last ? 0.0 : b3) + a * b * b;
+    default: return 0.0;
+  }
+}
+
+// Tile size of the b x b product phases: 128-wide tiles when a launch has
+// enough of them to fill the chip, else 64-wide ones.  INLA_TILE=64|128 forces one.
+bool use_big_tiles(const std::vector<ItemDev> &items) {
+  const char *e = getenv("INLA_TILE");
+  const int force = e ? atoi(e) : 0;
+  if (force == 64) return false;
+  if (force == 128) return true;
+  long long big = 0;
+  for (const auto &it : items) big += (long long)nbig(it.b) * nbig(it.b);
+  return big >= 256;
+}
+
+// Profiling slots: the tile phases, then the other kernel families.
+enum ProfSlot : int { PS_SOLVE = PH_COUNT, PS_TRACE, PS_ASSEMBLE, PS_MISC, PS_COUNT };
+
+struct ProfRec {
+  hipEvent_t e0, e1;
+  int slot;
+  double flops;
+};
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<ProfRec> recs;
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+};
+Profiler g_prof;
+
+// Brackets one launch with events when profiling is on.
+struct ProfScope {
+  ProfRec rec{nullptr, nullptr, 0, 0.0};
+  hipStream_t s;
+  ProfScope(int slot, double flops, hipStream_t st) : s(st) {
+    if (!g_prof.on) return;
+    rec.slot = slot;
+    rec.flops = flops;
+    rec.e0 = g_prof.get();
+    rec.e1 = g_prof.get();
+    if (rec.e0 && rec.e1) (void)hipEventRecord(rec.e0, s);
+  }
+  ~ProfScope() {
+    if (!g_prof.on || !rec.e0 || !rec.e1) return;
+    (void)hipEventRecord(rec.e1, s);
+    g_prof.recs.push_back(rec);
+  }
+};
+
 inla_status run_phase(const Batch &B, int phase, int t, int p, hipStream_t s) {
+  const bool big = B.big && phase_is_product_x(phase);
   long long total = 0;
-  for (const auto &it : B.host) total += phase_tasks(it, phase, t, p);
+  for (const auto &it : B.host) total += phase_tasks(it, phase, t, p, big);
   if (total > INT_MAX) return fail(INLA_ERR_ARG, "too many tile tasks in one launch");
-  HIP_TRY(launch_tile_phase(B.dev, (int)B.host.size(), (int)total, phase, t, p, s));
+  if (total == 0) return INLA_OK;
+  double flops = 0.0;
+  if (g_prof.on)
+    for (const auto &it : B.host) flops += phase_flops(it, phase, t, p);
+  ProfScope ps(phase, flops, s);
+  HIP_TRY(launch_tile_phase(B.dev, (int)B.host.size(), (int)total, phase, t, p, big, s));
   return INLA_OK;
 }
 
@@ -154,16 +245,25 @@ inla_status run_phase(const Batch &B, int phase, int t, int p, hipStream_t s) {
   } while (0)
 
 inla_status run_factor(const Batch &B, hipStream_t s) {
+  // the workspace that receives inv(L_tt) starts as zeros: its tiles above the
+  // diagonal are never written and the big-tile products read them as zeros
+  for (const auto &it : B.host) HIP_TRY(launch_fill(it.W1, (long long)it.b * it.b, 0.0, s));
   for (int t = 0; t < B.max_nt; ++t) {
     ST_TRY(run_phase(B, PH_DIAG0, t, 0, s));
     int mp = 0;
     for (const auto &it : B.host)
       if (t < it.nt) mp = std::max(mp, it.nP);
-    for (int p = 0; p < mp; ++p) {
+    for (int p = 0; p + 1 < mp; ++p) {
       ST_TRY(run_phase(B, PH_PANEL, t, p, s));
-      if (p + 1 < mp) ST_TRY(run_phase(B, PH_TRAIL, t, p, s));
+      ST_TRY(run_phase(B, PH_TRAIL, t, p, s));
     }
+    for (int level = 1; level <= trtri_levels(mp); ++level) {
+      ST_TRY(run_phase(B, PH_TRTRI, t, 2 * level, s));
+      ST_TRY(run_phase(B, PH_TRTRI, t, 2 * level + 1, s));
+    }
+    ST_TRY(run_phase(B, PH_OFFDIAG_X, t, 0, s));
     ST_TRY(run_phase(B, PH_OFFDIAG, t, 0, s));
+    ST_TRY(run_phase(B, PH_SCHUR_X, t, 0, s));
     ST_TRY(run_phase(B, PH_SCHUR, t, 0, s));
   }
   ST_TRY(run_phase(B, PH_ARROW, 0, 0, s));
@@ -175,10 +275,15 @@ inla_status run_selinv(const Batch &B, bool traces, hipStream_t s) {
   ST_TRY(run_phase(B, PH_SI_INIT, 0, 0, s));
   if (traces) HIP_TRY(launch_trace_step(B.dev, n, -1, s));
   for (int t = B.max_nt - 1; t >= 0; --t) {
+    ST_TRY(run_phase(B, PH_SI_VU_X, t, 0, s));
     ST_TRY(run_phase(B, PH_SI_VU, t, 0, s));
+    ST_TRY(run_phase(B, PH_SI_SR_X, t, 0, s));
     ST_TRY(run_phase(B, PH_SI_SR, t, 0, s));
-    ST_TRY(run_phase(B, PH_SI_SD, t, 0, s));
-    if (traces) HIP_TRY(launch_trace_step(B.dev, n, t, s));
+    ST_TRY(run_phase(B, PH_SI_SD_X, t, 0, s));
+    if (traces) {
+      ProfScope ps(PS_TRACE, 0.0, s);
+      HIP_TRY(launch_trace_step(B.dev, n, t, s));
+    }
   }
   return INLA_OK;
 }
@@ -186,8 +291,14 @@ inla_status run_selinv(const Batch &B, bool traces, hipStream_t s) {
 inla_status run_solve(const Batch &B, double *const *xs_dev, double *const *tmps_dev, hipStream_t s) {
   const int n = (int)B.host.size();
   for (int t = 0; t < B.max_nt; ++t) {
-    HIP_TRY(launch_solve_stage(B.dev, n, B.max_b, B.max_a, t, SV_F1, xs_dev, tmps_dev, s));
-    HIP_TRY(launch_solve_stage(B.dev, n, B.max_b, B.max_a, t, SV_F2, xs_dev, tmps_dev, s));
+    {
+      ProfScope ps(PS_SOLVE, 0.0, s);
+      HIP_TRY(launch_solve_stage(B.dev, n, B.max_b, B.max_a, t, SV_F1, xs_dev, tmps_dev, s));
+    }
+    {
+      ProfScope ps(PS_SOLVE, 0.0, s);
+      HIP_TRY(launch_solve_stage(B.dev, n, B.max_b, B.max_a, t, SV_F2, xs_dev, tmps_dev, s));
+    }
   }
   if (B.max_a > 0) {
     HIP_TRY(launch_solve_stage(B.dev, n, B.max_b, B.max_a, 0, SV_FA1, xs_dev, tmps_dev, s));
@@ -195,8 +306,14 @@ inla_status run_solve(const Batch &B, double *const *xs_dev, double *const *tmps
     HIP_TRY(launch_solve_stage(B.dev, n, B.max_b, B.max_a, 0, SV_BA, xs_dev, tmps_dev, s));
   }
   for (int t = B.max_nt - 1; t >= 0; --t) {
-    HIP_TRY(launch_solve_stage(B.dev, n, B.max_b, B.max_a, t, SV_B1, xs_dev, tmps_dev, s));
-    HIP_TRY(launch_solve_stage(B.dev, n, B.max_b, B.max_a, t, SV_B2, xs_dev, tmps_dev, s));
+    {
+      ProfScope ps(PS_SOLVE, 0.0, s);
+      HIP_TRY(launch_solve_stage(B.dev, n, B.max_b, B.max_a, t, SV_B1, xs_dev, tmps_dev, s));
+    }
+    {
+      ProfScope ps(PS_SOLVE, 0.0, s);
+      HIP_TRY(launch_solve_stage(B.dev, n, B.max_b, B.max_a, t, SV_B2, xs_dev, tmps_dev, s));
+    }
   }
   return INLA_OK;
 }
@@ -790,8 +907,11 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
       const ModelDev &h = models[i]->host;
       for (int w = 0; w < 2; ++w) {
         ItemDev &it = w ? tb[q].C : tb[q].P;
-        HIP_TRY(launch_assemble(models[i]->dev, h.b, h.nt, h.a, theta_dev + 4 * i, w, it.D, it.S,
-                                it.R, it.T, w ? tb[q].x : nullptr, s));
+        {
+          ProfScope ps(PS_ASSEMBLE, 0.0, s);
+          HIP_TRY(launch_assemble(models[i]->dev, h.b, h.nt, h.a, theta_dev + 4 * i, w, it.D, it.S,
+                                  it.R, it.T, w ? tb[q].x : nullptr, s));
+        }
         HIP_TRY(launch_fill_int(it.info, 1, kInfoNone, s));
       }
     }
@@ -829,6 +949,35 @@ inla_status inla_eval_f_grad(const inla_model *const *models, int32_t n_items,
   return eval_impl(models, n_items, theta_dev, f_dev, grad_dev, mu_or_null, var_or_null,
                    status_dev, opts, static_cast<hipStream_t>(hip_stream));
 }
+
+inla_status inla_profile_begin(void) {
+  std::lock_guard<std::mutex> lk(g_mutex);
+  g_prof.recs.clear();
+  g_prof.used = 0;
+  g_prof.on = true;
+  return INLA_OK;
+}
+
+inla_status inla_profile_end(double *out, int32_t nslots) {
+  std::lock_guard<std::mutex> lk(g_mutex);
+  g_prof.on = false;
+  std::vector<double> acc(3 * PS_COUNT, 0.0);
+  for (auto &r : g_prof.recs) {
+    HIP_TRY(hipEventSynchronize(r.e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, r.e0, r.e1));
+    acc[3 * r.slot + 0] += 1.0;
+    acc[3 * r.slot + 1] += ms;
+    acc[3 * r.slot + 2] += r.flops;
+  }
+  g_prof.recs.clear();
+  g_prof.used = 0;
+  if (out)
+    for (int k = 0; k < std::min<int>(nslots, PS_COUNT) * 3; ++k) out[k] = acc[k];
+  return INLA_OK;
+}
+
+int32_t inla_profile_slots(void) { return PS_COUNT; }
 
 void inla_release_workspace(void) {
   std::lock_guard<std::mutex> lk(g_mutex);

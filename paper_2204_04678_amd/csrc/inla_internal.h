@@ -70,26 +70,61 @@ __host__ __device__ inline double *sig_R(const ItemDev &it, int t) {
   return it.sr_stride ? it.SR + (long long)t * it.sr_stride : it.SR + (long long)(t & 1) * it.a * it.b;
 }
 
-// Phases of the tile kernels.
+// Phases of the tile kernels.  Phases ending in _X are the b x b products; they
+// run either on 64 x 64 tiles or on 128 x 128 "big" tiles (big = true).
 enum Phase : int {
-  PH_DIAG0 = 0,      // POTRF + TRTRI of tile (0,0) of D[t]
-  PH_PANEL = 1,      // panel p: L[i,p] = A[i,p] Linv_pp^T (i > p); Linv row p
-  PH_TRAIL = 2,      // trailing update of panel p; diag tile p+1; copy Linv row p to D[t]
-  PH_OFFDIAG = 3,    // X = S[t] Linv^T, R' = R[t] Linv^T; copy last Linv row to D[t]
-  PH_SCHUR = 4,      // D[t+1] -= X X^T, R[t+1] -= R' X^T, T -= R' R'^T; copy X, R' back
-  PH_ARROW = 5,      // POTRF + TRTRI of T
-  PH_SI_INIT = 6,    // Sigma_T = Linv_AA^T Linv_AA
-  PH_SI_VU = 7,      // V = L_{t+1,t} Linv_tt, U = L_{A,t} Linv_tt
-  PH_SI_SR = 8,      // Sigma_S[t], Sigma_R[t]
-  PH_SI_SD = 9,      // Sigma_D[t] (lower tiles, mirrored)
-  PH_COUNT = 10
+  PH_DIAG0 = 0,      // Cholesky + inverse of tile (0,0) of D[t]
+  PH_PANEL = 1,      // panel p: L[i,p] = A[i,p] Linv_pp^T (i > p)
+  PH_TRAIL = 2,      // trailing update by panel p; Cholesky + inverse of tile (p+1,p+1)
+  PH_TRTRI = 3,      // inverse of L_tt by recursive doubling; p = 2*level + stage
+  PH_OFFDIAG_X = 4,  // X = S[t] Linv^T
+  PH_OFFDIAG = 5,    // R' = R[t] Linv^T; D[t] <- Linv (zeros above)
+  PH_SCHUR_X = 6,    // D[t+1] -= X X^T
+  PH_SCHUR = 7,      // R[t+1] -= R' X^T, T -= R' R'^T; copy X, R' back
+  PH_ARROW = 8,      // Cholesky + inverse of T
+  PH_SI_INIT = 9,    // Sigma_T = Linv_AA^T Linv_AA
+  PH_SI_VU_X = 10,   // V = L_{t+1,t} Linv_tt
+  PH_SI_VU = 11,     // U = L_{A,t} Linv_tt
+  PH_SI_SR_X = 12,   // Sigma_S[t]
+  PH_SI_SR = 13,     // Sigma_R[t]
+  PH_SI_SD_X = 14,   // Sigma_D[t] (lower tiles, mirrored)
+  PH_COUNT = 15
 };
+
+constexpr int kBig = 128;        // edge of a big tile
+__host__ __device__ inline int nbig(int n) { return (n + kBig - 1) / kBig; }
+__host__ __device__ inline bool phase_is_product_x(int phase) {
+  return phase == PH_OFFDIAG_X || phase == PH_SCHUR_X || phase == PH_SI_VU_X ||
+         phase == PH_SI_SR_X || phase == PH_SI_SD_X;
+}
 
 __host__ __device__ inline int ntile(int n) { return (n + kTile - 1) / kTile; }
 
-// Number of workgroup tasks of one item in (phase, t, p).
-__host__ __device__ inline int phase_tasks(const ItemDev &it, int phase, int t, int p) {
+// Recursive-doubling inverse of a block lower-triangular matrix with nP tiles:
+// at level L (block size s = 2^(L-1) tiles) each pair of adjacent diagonal
+// blocks U = [u0, u0+s), V = [u0+s, min(u0+2s, nP)) gets
+//   X_VU = -X_VV (L_VU X_UU)   (stage 0: T = L_VU X_UU; stage 1: X_VU = -X_VV T).
+__host__ __device__ inline int trtri_levels(int nP) {
+  int L = 0;
+  while ((1 << L) < nP) ++L;
+  return L;
+}
+__host__ __device__ inline int trtri_tasks(int nP, int level) {
+  const int s = 1 << (level - 1);
+  int cnt = 0;
+  for (int u0 = 0; u0 + s < nP; u0 += 2 * s) {
+    const int vs = (nP - (u0 + s) < s) ? nP - (u0 + s) : s;
+    cnt += s * vs;
+  }
+  return cnt;
+}
+
+// Number of workgroup tasks of one item in (phase, t, p); big selects 128-tiles
+// for the _X phases.
+__host__ __device__ inline int phase_tasks(const ItemDev &it, int phase, int t, int p,
+                                           bool big = false) {
   const int nP = it.nP;
+  const int nQ = big ? nbig(it.b) : nP;
   const bool arrow = it.a > 0;
   if (phase == PH_ARROW || phase == PH_SI_INIT) return arrow ? 1 : 0;
   if (t >= it.nt) return 0;
@@ -97,34 +132,35 @@ __host__ __device__ inline int phase_tasks(const ItemDev &it, int phase, int t, 
   switch (phase) {
     case PH_DIAG0: return 1;
     case PH_PANEL:
-      if (p >= nP) return 0;
-      return (nP - 1 - p) + p;   // panel tiles below the diagonal + Linv row p tiles
+      return (p < nP - 1) ? (nP - 1 - p) : 0;
     case PH_TRAIL:
-      if (p >= nP - 1) return 0;
-      return (nP - 1 - p) * (nP - p) / 2 + (p + 1);
-    case PH_OFFDIAG:   // X tiles, R' tiles, copy of the last Linv row, zero upper tiles of D[t]
-      return (last ? 0 : nP * nP) + (arrow ? nP : 0) + nP + nP * (nP - 1) / 2;
+      return (p < nP - 1) ? (nP - 1 - p) * (nP - p) / 2 : 0;
+    case PH_TRTRI: {
+      const int level = p >> 1;
+      return (level >= 1 && level <= trtri_levels(nP)) ? trtri_tasks(nP, level) : 0;
+    }
+    case PH_OFFDIAG_X: return last ? 0 : nQ * nQ;
+    case PH_OFFDIAG: return (arrow ? nP : 0) + nP * nP;
+    case PH_SCHUR_X: return last ? 0 : nQ * (nQ + 1) / 2;
     case PH_SCHUR:
-      return (last ? 0 : nP * (nP + 1) / 2 + nP * nP) +
-             (arrow ? ((last ? 0 : nP) + 1 + nP) : 0);
-    case PH_SI_VU:
-      return (last ? 0 : nP * nP) + (arrow ? nP : 0);
-    case PH_SI_SR:
-      return (last ? 0 : nP * nP) + (arrow ? nP : 0);
-    case PH_SI_SD:
-      return nP * (nP + 1) / 2;
+      return (last ? 0 : nP * nP) + (arrow ? ((last ? 0 : nP) + 1 + nP) : 0);
+    case PH_SI_VU_X: return last ? 0 : nQ * nQ;
+    case PH_SI_VU: return arrow ? nP : 0;
+    case PH_SI_SR_X: return last ? 0 : nQ * nQ;
+    case PH_SI_SR: return arrow ? nP : 0;
+    case PH_SI_SD_X: return nQ * (nQ + 1) / 2;
     default: return 0;
   }
 }
 
-// Phases that need the large-LDS kernel variant (in-tile Cholesky / left epilogue).
+// Phases whose workgroups may run the in-tile Cholesky (large-LDS variant).
 __host__ __device__ inline bool phase_is_fat(int phase) {
-  return phase == PH_DIAG0 || phase == PH_PANEL || phase == PH_TRAIL || phase == PH_ARROW;
+  return phase == PH_DIAG0 || phase == PH_TRAIL || phase == PH_ARROW;
 }
 
 // ---- launch wrappers (bta_kernels.hip) ----
 hipError_t launch_tile_phase(const ItemDev *items_dev, int n_items, int total, int phase, int t,
-                             int p, hipStream_t s);
+                             int p, bool big, hipStream_t s);
 hipError_t launch_fill(double *ptr, long long n, double v, hipStream_t s);
 hipError_t launch_fill_int(int *ptr, long long n, int v, hipStream_t s);
 hipError_t launch_logdet_finish(const ItemDev *items_dev, int n_items, double *logdet_out,

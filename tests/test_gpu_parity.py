@@ -18,6 +18,13 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
+@pytest.fixture(params=["64", "128"], ids=["tile64", "tile128"])
+def tile(request, monkeypatch):
+    """Run the b x b product phases on 64- or 128-wide tiles."""
+    monkeypatch.setenv("INLA_TILE", request.param)
+    return request.param
+
+
 @pytest.fixture(scope="module")
 def P():
     import paper_2204_04678_amd as P
@@ -64,12 +71,13 @@ def blk_err(x, y):
     return np.abs(x - y).max() / max(np.abs(y).max(), 1e-300)
 
 
-SHAPES = [(1, 4, 2), (16, 1, 0), (64, 3, 1), (100, 3, 2), (130, 2, 3), (70, 4, 0), (200, 2, 5)]
+SHAPES = [(1, 4, 2), (16, 1, 0), (64, 3, 1), (100, 3, 2), (130, 2, 3), (70, 4, 0), (200, 2, 5),
+          (300, 2, 3), (257, 2, 1), (17, 3, 1), (520, 2, 2)]
 
 
 @pytest.mark.parametrize("b,nt,a", SHAPES)
-def test_factor_logdet_random_bta(P, b, nt, a):
-    print(f"factor b={b} nt={nt} a={a}", flush=True)
+def test_factor_logdet_random_bta(P, tile, b, nt, a):
+    print(f"factor b={b} nt={nt} a={a} tile={tile}", flush=True)
     Q = rand_spd_bta(b, nt, a, seed=b * 100 + nt * 10 + a)
     Qt = P.BtaTensors.from_blocks(*O.bta_blocks(Q, b, nt, a))
     ld, info = P.factor_logdet(Qt)
@@ -84,9 +92,10 @@ def test_factor_logdet_random_bta(P, b, nt, a):
         assert blk_err(g, e) < 1e-11, name
 
 
-@pytest.mark.parametrize("b,nt,a", [(100, 3, 2), (64, 2, 1), (1, 5, 1), (130, 2, 0)])
-def test_solve_and_selinv_random_bta(P, b, nt, a):
-    print(f"solve/selinv b={b} nt={nt} a={a}", flush=True)
+@pytest.mark.parametrize("b,nt,a", [(100, 3, 2), (64, 2, 1), (1, 5, 1), (130, 2, 0), (300, 3, 3),
+                                   (257, 2, 1)])
+def test_solve_and_selinv_random_bta(P, tile, b, nt, a):
+    print(f"solve/selinv b={b} nt={nt} a={a} tile={tile}", flush=True)
     Q = rand_spd_bta(b, nt, a, seed=7 + b + nt + a)
     n = Q.shape[0]
     Qt = P.BtaTensors.from_blocks(*O.bta_blocks(Q, b, nt, a))
@@ -138,7 +147,7 @@ def test_assemble(P, shape):
     np.testing.assert_allclose(rhs.cpu().numpy(), b_ref, rtol=1e-13, atol=1e-13 * np.abs(b_ref).max())
 
 
-def test_eval_f_c1(P):
+def test_eval_f_c1(P, tile):
     md = config_model("c1")
     M = P.Model.from_data(md)
     out = P.eval_f(M, THETA0, want_mu=True, want_var=True)
@@ -165,7 +174,7 @@ def test_logdets_c1_and_closed_form(P):
     assert rel(ldc.item(), ref["logdet_c"]) < 1e-10
 
 
-def test_eval_f_grad_small(P):
+def test_eval_f_grad_small(P, tile):
     md = config_model("c4small")
     M = P.Model.from_data(md)
     out = P.eval_f_grad(M, THETA0)
