@@ -203,9 +203,16 @@ inla_status inla_eval_f_grad(const inla_model *const *models, int32_t n_items,
  * method, not the flops of padded tiles).  Slots 0..10 are the phases of the
  * tile kernels (Cholesky of the first diagonal tile, panel solve, trailing
  * update with the next diagonal tile, inverse of the diagonal factor block,
- * off-diagonal solve, Schur update, arrow Cholesky, and the four steps of the
- * selected inversion, in that order); then substitution sweeps, trace
- * reductions, assembly, and the rest.  inla_profile_slots() returns the count.
+ * the b x b off-diagonal solve and its arrow/copy remainder, the b x b Schur
+ * update and its remainder, arrow Cholesky, and the selected-inversion steps
+ * with their remainders, in that order); then substitution sweeps, trace
+ * reductions, assembly, the rest, and a last slot whose out[0] is the number
+ * of evaluations the records cover (a replayed graph re-records its events,
+ * so it counts once) and out[1] the number of unreadable records, then four
+ * slots per kernel: the 64-tile product kernel, the in-tile Cholesky kernel,
+ * the 128-tile product kernel, and all other kernels.
+ * inla_profile_slots() returns the slot count.  Profiling drops any captured
+ * graph of inla_eval_f / inla_eval_f_grad when it starts and ends.
  */
 inla_status inla_profile_begin(void);
 inla_status inla_profile_end(double *out, int32_t nslots);

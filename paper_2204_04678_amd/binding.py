@@ -344,25 +344,23 @@ def profile_begin():
 
 PROFILE_SLOTS = ["diag0", "panel", "trail", "trtri", "offdiag_x", "offdiag", "schur_x", "schur",
                  "arrow", "si_init", "si_vu_x", "si_vu", "si_sr_x", "si_sr", "si_sd_x", "solve",
-                 "trace", "assemble", "misc"]
+                 "trace", "assemble", "misc", "calls"]
 PRODUCT_X = ("offdiag_x", "schur_x", "si_vu_x", "si_sr_x", "si_sd_x")   # b x b products
 FAT_PHASES = ("diag0", "trail", "arrow")   # run by the Cholesky-capable tile kernel
 
 
+KERNEL_KINDS = ["tile_phase_kernel<false>", "tile_phase_kernel<true>", "tile_big_kernel", "other"]
+
+
 def profile_end():
-    """Per slot: dict(launches, ms, flops); plus per tile-kernel kind aggregates."""
+    """Per phase slot and per kernel: dict(launches, ms, flops)."""
     n = lib().inla_profile_slots()
     out = (C.c_double * (3 * n))()
     _check(lib().inla_profile_end(out, n))
-    slots = {PROFILE_SLOTS[k]: dict(launches=out[3 * k], ms=out[3 * k + 1], flops=out[3 * k + 2])
-             for k in range(n)}
-    kinds = {"product_x": dict(launches=0.0, ms=0.0, flops=0.0),
-             "product": dict(launches=0.0, ms=0.0, flops=0.0),
-             "chol": dict(launches=0.0, ms=0.0, flops=0.0)}
-    for k in range(15):
-        name = PROFILE_SLOTS[k]
-        dst = kinds["chol" if name in FAT_PHASES else
-                    ("product_x" if name in PRODUCT_X else "product")]
-        for f in ("launches", "ms", "flops"):
-            dst[f] += slots[name][f]
-    return {"slots": slots, **kinds}
+    rows = [dict(launches=out[3 * k], ms=out[3 * k + 1], flops=out[3 * k + 2]) for k in range(n)]
+    nph = len(PROFILE_SLOTS) - 1
+    slots = {PROFILE_SLOTS[k]: rows[k] for k in range(nph)}
+    calls = rows[nph]
+    kernels = {KERNEL_KINDS[k]: rows[nph + 1 + k] for k in range(len(KERNEL_KINDS))}
+    return {"slots": slots, "kernels": kernels, "calls": int(calls["launches"]),
+            "bad": int(calls["ms"])}

@@ -705,21 +705,32 @@ __device__ void chol_inv_tile(double *A, double *X, double *dlog, int w, double 
   }
 }
 
+// One launch covers the tasks of `phase` and, if phase2 >= 0, of `phase2` as
+// well (two independent phases of the same step), item by item.
 template <bool FAT>
 __global__ __launch_bounds__(kThreads) void tile_phase_kernel(const ItemDev *__restrict__ items,
-                                                              int n_items, int phase, int t, int p) {
+                                                              int n_items, int phase, int phase2,
+                                                              int t, int p) {
   __shared__ double smem[FAT ? kFatLds : kLeanLds];
   int q = blockIdx.x;
-  int ii = 0;
+  int ii = 0, ph = phase;
   for (; ii < n_items; ++ii) {
     const int c = phase_tasks(items[ii], phase, t, p);
     if (q < c) break;
     q -= c;
+    if (phase2 >= 0) {
+      const int c2 = phase_tasks(items[ii], phase2, t, p);
+      if (q < c2) {
+        ph = phase2;
+        break;
+      }
+      q -= c2;
+    }
   }
   if (ii >= n_items) return;
   const ItemDev it = items[ii];
   Task tk;
-  decode(it, phase, t, p, q, tk);
+  decode(it, ph, t, p, q, tk);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = w >> 1, wc = w & 1;
   if (tk.kind == TK_NONE) return;
@@ -898,18 +909,18 @@ __global__ __launch_bounds__(kBigThreads, 1) void tile_big_kernel(const ItemDev 
       }
 }
 
-hipError_t launch_tile_phase(const ItemDev *items_dev, int n_items, int total, int phase, int t,
-                             int p, bool big, hipStream_t s) {
+hipError_t launch_tile_phase(const ItemDev *items_dev, int n_items, int total, int phase,
+                             int phase2, int t, int p, bool big, hipStream_t s) {
   if (total <= 0) return hipSuccess;
-  if (big && phase_is_product_x(phase)) {
+  if (big && phase_is_product_x(phase) && phase2 < 0) {
     hipLaunchKernelGGL(tile_big_kernel, dim3(total), dim3(kBigThreads), 0, s, items_dev, n_items,
                        phase, t);
-  } else if (phase_is_fat(phase)) {
+  } else if (phase_is_fat(phase) || (phase2 >= 0 && phase_is_fat(phase2))) {
     hipLaunchKernelGGL(tile_phase_kernel<true>, dim3(total), dim3(kThreads), 0, s, items_dev, n_items,
-                       phase, t, p);
+                       phase, phase2, t, p);
   } else {
     hipLaunchKernelGGL(tile_phase_kernel<false>, dim3(total), dim3(kThreads), 0, s, items_dev,
-                       n_items, phase, t, p);
+                       n_items, phase, phase2, t, p);
   }
   return hipGetLastError();
 }

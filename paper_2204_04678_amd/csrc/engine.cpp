@@ -57,6 +57,7 @@ struct Arena {
   int device = -1;
   hipEvent_t last = nullptr;  // completion of the last call that used the arena
   hipStream_t last_stream = nullptr;
+  unsigned long long gen = 0; // bumped whenever a call lays out the arena afresh
 };
 std::mutex g_mutex;
 Arena g_arena;
@@ -107,6 +108,7 @@ inla_status arena_bind(Layout &L, hipStream_t s) {
     *r.slot = g_arena.base + off;
     off += align_up(std::max<size_t>(r.bytes, 1));
   }
+  ++g_arena.gen;
   return INLA_OK;
 }
 
@@ -181,16 +183,27 @@ bool use_big_tiles(const std::vector<ItemDev> &items) {
   return big >= 256;
 }
 
+#define ST_TRY_INNER(expr)               \
+  do {                                   \
+    inla_status st_ = (expr);            \
+    if (st_ != INLA_OK) return st_;      \
+  } while (0)
+
 // Profiling slots: the tile phases, then the other kernel families.
 enum ProfSlot : int { PS_SOLVE = PH_COUNT, PS_TRACE, PS_ASSEMBLE, PS_MISC, PS_COUNT };
 
+// Kernel behind a record: 0 tile_phase_kernel<false>, 1 tile_phase_kernel<true>,
+// 2 tile_big_kernel, 3 any other kernel.
+enum ProfKind : int { PK_LEAN = 0, PK_FAT = 1, PK_BIG = 2, PK_OTHER = 3, PK_COUNT = 4 };
 struct ProfRec {
   hipEvent_t e0, e1;
   int slot;
+  int kind;
   double flops;
 };
 struct Profiler {
   bool on = false;
+  int calls = 0;   // evaluations whose launches are in recs (a graph counts once)
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   std::vector<ProfRec> recs;
@@ -206,20 +219,23 @@ struct Profiler {
 Profiler g_prof;
 
 // Brackets one launch with events when profiling is on.
+inline void prof_record(hipEvent_t e, hipStream_t s) { (void)hipEventRecord(e, s); }
+
 struct ProfScope {
-  ProfRec rec{nullptr, nullptr, 0, 0.0};
+  ProfRec rec{nullptr, nullptr, 0, PK_OTHER, 0.0};
   hipStream_t s;
-  ProfScope(int slot, double flops, hipStream_t st) : s(st) {
+  ProfScope(int slot, double flops, hipStream_t st, int kind = PK_OTHER) : s(st) {
     if (!g_prof.on) return;
     rec.slot = slot;
+    rec.kind = kind;
     rec.flops = flops;
     rec.e0 = g_prof.get();
     rec.e1 = g_prof.get();
-    if (rec.e0 && rec.e1) (void)hipEventRecord(rec.e0, s);
+    if (rec.e0 && rec.e1) prof_record(rec.e0, s);
   }
   ~ProfScope() {
     if (!g_prof.on || !rec.e0 || !rec.e1) return;
-    (void)hipEventRecord(rec.e1, s);
+    prof_record(rec.e1, s);
     g_prof.recs.push_back(rec);
   }
 };
@@ -233,8 +249,46 @@ inla_status run_phase(const Batch &B, int phase, int t, int p, hipStream_t s) {
   double flops = 0.0;
   if (g_prof.on)
     for (const auto &it : B.host) flops += phase_flops(it, phase, t, p);
-  ProfScope ps(phase, flops, s);
-  HIP_TRY(launch_tile_phase(B.dev, (int)B.host.size(), (int)total, phase, t, p, big, s));
+  ProfScope ps(phase, flops, s, big ? PK_BIG : (phase_is_fat(phase) ? PK_FAT : PK_LEAN));
+  HIP_TRY(launch_tile_phase(B.dev, (int)B.host.size(), (int)total, phase, -1, t, p, big, s));
+  return INLA_OK;
+}
+
+// Side stream (default priority) for phases that run beside a big-tile launch.
+hipStream_t g_side = nullptr;
+hipEvent_t g_fork = nullptr, g_join = nullptr;
+
+// Runs the b x b product phase px together with the independent phase pr of
+// the same step: in one 64-tile launch, or, with big tiles, px on s and pr on
+// a side stream joined back into s.
+inla_status run_pair(const Batch &B, int px, int pr, int t, hipStream_t s) {
+  if (!B.big) {
+    long long total = 0;
+    double flops = 0.0;
+    for (const auto &it : B.host) {
+      total += phase_tasks(it, px, t, 0) + phase_tasks(it, pr, t, 0);
+      if (g_prof.on) flops += phase_flops(it, px, t, 0) + phase_flops(it, pr, t, 0);
+    }
+    if (total > INT_MAX) return fail(INLA_ERR_ARG, "too many tile tasks in one launch");
+    if (total == 0) return INLA_OK;
+    ProfScope ps(px, flops, s, PK_LEAN);
+    HIP_TRY(launch_tile_phase(B.dev, (int)B.host.size(), (int)total, px, pr, t, 0, false, s));
+    return INLA_OK;
+  }
+  long long rem = 0;
+  for (const auto &it : B.host) rem += phase_tasks(it, pr, t, 0);
+  if (rem == 0) return run_phase(B, px, t, 0, s);
+  if (!g_side) {
+    HIP_TRY(hipStreamCreateWithFlags(&g_side, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&g_fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&g_join, hipEventDisableTiming));
+  }
+  HIP_TRY(hipEventRecord(g_fork, s));
+  HIP_TRY(hipStreamWaitEvent(g_side, g_fork, 0));
+  ST_TRY_INNER(run_phase(B, pr, t, 0, g_side));
+  HIP_TRY(hipEventRecord(g_join, g_side));
+  ST_TRY_INNER(run_phase(B, px, t, 0, s));
+  HIP_TRY(hipStreamWaitEvent(s, g_join, 0));
   return INLA_OK;
 }
 
@@ -261,10 +315,8 @@ inla_status run_factor(const Batch &B, hipStream_t s) {
       ST_TRY(run_phase(B, PH_TRTRI, t, 2 * level, s));
       ST_TRY(run_phase(B, PH_TRTRI, t, 2 * level + 1, s));
     }
-    ST_TRY(run_phase(B, PH_OFFDIAG_X, t, 0, s));
-    ST_TRY(run_phase(B, PH_OFFDIAG, t, 0, s));
-    ST_TRY(run_phase(B, PH_SCHUR_X, t, 0, s));
-    ST_TRY(run_phase(B, PH_SCHUR, t, 0, s));
+    ST_TRY(run_pair(B, PH_OFFDIAG_X, PH_OFFDIAG, t, s));
+    ST_TRY(run_pair(B, PH_SCHUR_X, PH_SCHUR, t, s));
   }
   ST_TRY(run_phase(B, PH_ARROW, 0, 0, s));
   return INLA_OK;
@@ -275,10 +327,8 @@ inla_status run_selinv(const Batch &B, bool traces, hipStream_t s) {
   ST_TRY(run_phase(B, PH_SI_INIT, 0, 0, s));
   if (traces) HIP_TRY(launch_trace_step(B.dev, n, -1, s));
   for (int t = B.max_nt - 1; t >= 0; --t) {
-    ST_TRY(run_phase(B, PH_SI_VU_X, t, 0, s));
-    ST_TRY(run_phase(B, PH_SI_VU, t, 0, s));
-    ST_TRY(run_phase(B, PH_SI_SR_X, t, 0, s));
-    ST_TRY(run_phase(B, PH_SI_SR, t, 0, s));
+    ST_TRY(run_pair(B, PH_SI_VU_X, PH_SI_VU, t, s));
+    ST_TRY(run_pair(B, PH_SI_SR_X, PH_SI_SR, t, s));
     ST_TRY(run_phase(B, PH_SI_SD_X, t, 0, s));
     if (traces) {
       ProfScope ps(PS_TRACE, 0.0, s);
@@ -778,6 +828,54 @@ size_t theta_item_bytes(const ModelDev &h, bool selinv) {
   return 2 * per + ((size_t)h.n + std::max(h.b, h.a) + kTermBlocks * 4) * 8 + 4096;
 }
 
+// The launch sequence of one batched evaluation, captured once per call
+// signature and replayed.  Inputs and outputs pass through library buffers so
+// the captured graph only ever touches library memory.
+struct EvalGraph {
+  bool valid = false;
+  std::vector<const inla_model *> models;
+  bool grad = false, var = false, mu = false, prof = false;
+  unsigned long long gen = 0;
+  char *base = nullptr;
+  hipGraphExec_t exec = nullptr;
+  double *th = nullptr, *f = nullptr, *g = nullptr, *mu_buf = nullptr, *var_buf = nullptr;
+  int *st = nullptr;
+  long long ntot = 0;
+};
+EvalGraph g_graph;
+hipStream_t g_cap = nullptr;
+
+bool graphs_enabled() {
+  const char *e = getenv("INLA_GRAPH");
+  return !(e && e[0] == '0');
+}
+
+void drop_graph() {
+  if (g_graph.exec) (void)hipGraphExecDestroy(g_graph.exec);
+  g_graph = EvalGraph();
+}
+
+inla_status ensure_streams() {
+  if (!g_side) {
+    HIP_TRY(hipStreamCreateWithFlags(&g_side, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&g_fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&g_join, hipEventDisableTiming));
+  }
+  if (!g_cap) HIP_TRY(hipStreamCreateWithFlags(&g_cap, hipStreamNonBlocking));
+  return INLA_OK;
+}
+
+inla_status copy_outputs(const EvalGraph &G, int n, double *f_dev, double *grad_dev, double *mu_out,
+                         double *var_out, int32_t *status_dev, hipStream_t s) {
+  const auto D2D = hipMemcpyDeviceToDevice;
+  HIP_TRY(hipMemcpyAsync(f_dev, G.f, (size_t)n * 8, D2D, s));
+  if (grad_dev) HIP_TRY(hipMemcpyAsync(grad_dev, G.g, (size_t)n * 32, D2D, s));
+  if (status_dev) HIP_TRY(hipMemcpyAsync(status_dev, G.st, (size_t)n * 4, D2D, s));
+  if (mu_out) HIP_TRY(hipMemcpyAsync(mu_out, G.mu_buf, (size_t)G.ntot * 8, D2D, s));
+  if (var_out) HIP_TRY(hipMemcpyAsync(var_out, G.var_buf, (size_t)G.ntot * 8, D2D, s));
+  return INLA_OK;
+}
+
 inla_status eval_impl(const inla_model *const *models, int32_t n_items, const double *theta_dev,
                       double *f_dev, double *grad_dev, double *mu_out, double *var_out,
                       int32_t *status_dev, const inla_opts *opts, hipStream_t s) {
@@ -786,6 +884,7 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
   for (int i = 0; i < n_items; ++i)
     if (!models[i]) return fail(INLA_ERR_ARG, "NULL model in batch");
   if (opts && opts->keep_sigma != 0) return fail(INLA_ERR_ARG, "keep_sigma is reserved (must be 0)");
+  ST_TRY(ensure_streams());
   const bool grad = grad_dev != nullptr;
   const bool need_selinv = grad || var_out != nullptr;
   // HBM admission: split the items into waves whose storage fits the budget
@@ -796,8 +895,10 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
     budget = (double)fr + (double)g_arena.cap - 4.0 * (1ULL << 30);
   }
   std::vector<size_t> bytes(n_items);
+  double all = 0.0;
   for (int i = 0; i < n_items; ++i) {
     bytes[i] = theta_item_bytes(models[i]->host, need_selinv);
+    all += (double)bytes[i];
     if ((double)bytes[i] > budget)
       return fail(INLA_ERR_BUDGET, "item " + std::to_string(i) + " needs " +
                                        std::to_string(bytes[i]) + " bytes, above the HBM budget");
@@ -805,6 +906,24 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
   // per-item output offsets into the concatenated mu / var buffers
   std::vector<long long> voff(n_items + 1, 0);
   for (int i = 0; i < n_items; ++i) voff[i + 1] = voff[i] + models[i]->n;
+  const long long ntot = voff[n_items];
+
+  // replay a captured graph when the call matches it and nothing else has
+  // laid out the workspace since
+  // (events recorded during capture cannot be timed, so profiling runs eagerly)
+  const bool graphable = graphs_enabled() && !g_prof.on && all <= budget;
+  std::vector<const inla_model *> key(models, models + n_items);
+  if (graphable && g_graph.valid && g_graph.models == key && g_graph.grad == grad &&
+      g_graph.var == (var_out != nullptr) && g_graph.mu == (mu_out != nullptr) &&
+      g_graph.prof == g_prof.on && g_graph.gen == g_arena.gen && g_graph.base == g_arena.base) {
+    if (g_arena.last && g_arena.last_stream != s) HIP_TRY(hipStreamWaitEvent(s, g_arena.last, 0));
+    HIP_TRY(hipMemcpyAsync(g_graph.th, theta_dev, (size_t)n_items * 32, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipGraphLaunch(g_graph.exec, s));
+    ST_TRY(copy_outputs(g_graph, n_items, f_dev, grad_dev, mu_out, var_out, status_dev, s));
+    return arena_done(s);
+  }
+  if (graphable) drop_graph();
+
   int start = 0;
   while (start < n_items) {
     int end = start;
@@ -814,6 +933,15 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
     std::vector<ThetaItemBufs> tb(k);
     Layout L;
     std::vector<double *> Dbase(2 * k);
+    EvalGraph G;
+    if (graphable) {
+      L.add(&G.th, (size_t)4 * k);
+      L.add(&G.f, (size_t)k);
+      L.add(&G.g, (size_t)4 * k);
+      L.add(&G.st, (size_t)k);
+      L.add(&G.mu_buf, (size_t)ntot);
+      if (var_out) L.add(&G.var_buf, (size_t)ntot);
+    }
     for (int q = 0; q < k; ++q) {
       const ModelDev &h = models[start + q]->host;
       for (int w = 0; w < 2; ++w) {
@@ -822,7 +950,6 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
         it.b = h.b; it.nt = h.nt; it.a = h.a; it.nP = ntile(h.b);
         it.which = w;
         it.model = models[start + q]->dev;
-        it.theta = theta_dev + 4 * (start + q);
         L.add(&Dbase[2 * q + w], bta_doubles(h.b, h.nt, h.a));
         layout_factor_ws(L, it);
         if (need_selinv) {
@@ -830,7 +957,7 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
           if (grad) L.add(&it.trpart, ((size_t)h.nt + 1) * 4);
         }
       }
-      if (!mu_out) L.add(&tb[q].x, (size_t)h.n);
+      if (!mu_out && !graphable) L.add(&tb[q].x, (size_t)h.n);
       L.add(&tb[q].tmp, (size_t)std::max(h.b, std::max(h.a, 1)));
       L.add(&tb[q].term, (size_t)kTermBlocks * 4);
     }
@@ -849,15 +976,23 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
     L.add(&tdev, k);
     L.add(&cdev, k);
     ST_TRY(arena_bind(L, s));
+    // where this wave reads theta and writes its outputs
+    const double *th = graphable ? G.th : theta_dev + 4 * start;
+    double *fo = graphable ? G.f : f_dev + start;
+    double *go = graphable ? G.g : (grad ? grad_dev + 4 * start : nullptr);
+    int *so = graphable ? G.st : (status_dev ? status_dev + start : nullptr);
+    double *muo = graphable ? G.mu_buf : (mu_out ? mu_out + voff[start] : nullptr);
+    double *vo = graphable ? G.var_buf : (var_out ? var_out + voff[start] : nullptr);
     // carve BTA storage and finish descriptors
     Batch F, Sv, Si;
     std::vector<double *> hx(k), ht(k);
-    std::vector<TermItem> th(k);
+    std::vector<TermItem> thv(k);
     std::vector<CombineItem> ch(k);
     for (int q = 0; q < k; ++q) {
       const int i = start + q;
       const ModelDev &h = models[i]->host;
       const size_t bb = (size_t)h.b * h.b;
+      const long long off = voff[i] - voff[start];
       for (int w = 0; w < 2; ++w) {
         ItemDev &it = w ? tb[q].C : tb[q].P;
         double *base = Dbase[2 * q + w];
@@ -865,10 +1000,11 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
         it.S = h.nt > 1 ? base + (size_t)h.nt * bb : nullptr;
         it.R = h.a > 0 ? base + (size_t)(2 * h.nt - 1) * bb : nullptr;
         it.T = h.a > 0 ? it.R + (size_t)h.nt * h.a * h.b : nullptr;
+        it.theta = th + 4 * q;
         if (need_selinv) it.SS = it.W1;
-        if (w == 1 && var_out) it.diag = var_out + voff[i];
+        if (w == 1 && vo) it.diag = vo + off;
       }
-      if (mu_out) tb[q].x = mu_out + voff[i];
+      if (muo) tb[q].x = muo + off;
       hx[q] = tb[q].x;
       ht[q] = tb[q].tmp;
       F.host.push_back(tb[q].P);
@@ -876,20 +1012,20 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
       Sv.host.push_back(tb[q].C);
       if (grad) Si.host.push_back(tb[q].P);
       if (need_selinv) Si.host.push_back(tb[q].C);
-      th[q] = TermItem{models[i]->dev, theta_dev + 4 * i, tb[q].x, tb[q].term};
+      thv[q] = TermItem{models[i]->dev, th + 4 * q, tb[q].x, tb[q].term};
       CombineItem c;
       std::memset(&c, 0, sizeof(c));
       c.model = models[i]->dev;
-      c.theta = theta_dev + 4 * i;
+      c.theta = th + 4 * q;
       c.term_part = tb[q].term;
       c.mu = tb[q].x;
       c.logdet = logdet + 2 * q;
       c.trp = grad ? tb[q].P.trpart : nullptr;
       c.trc = grad ? tb[q].C.trpart : nullptr;
       c.info = info + 2 * q;
-      c.f = f_dev + i;
-      c.grad = grad ? grad_dev + 4 * i : nullptr;
-      c.status = status_dev ? status_dev + i : nullptr;
+      c.f = fo + q;
+      c.grad = go ? go + 4 * q : nullptr;
+      c.status = so ? so + q : nullptr;
       ch[q] = c;
     }
     F.dev = fdev; Sv.dev = sdev; Si.dev = vdev;
@@ -899,28 +1035,68 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
     if (need_selinv) ST_TRY(upload(vdev, Si.host, s));
     ST_TRY(upload(xs, hx, s));
     ST_TRY(upload(tmps, ht, s));
-    ST_TRY(upload(tdev, th, s));
+    ST_TRY(upload(tdev, thv, s));
     ST_TRY(upload(cdev, ch, s));
-    // assemble Q_prior, Q_c and b = tau_y A^T y (into x, solved in place)
-    for (int q = 0; q < k; ++q) {
-      const int i = start + q;
-      const ModelDev &h = models[i]->host;
-      for (int w = 0; w < 2; ++w) {
-        ItemDev &it = w ? tb[q].C : tb[q].P;
-        {
-          ProfScope ps(PS_ASSEMBLE, 0.0, s);
-          HIP_TRY(launch_assemble(models[i]->dev, h.b, h.nt, h.a, theta_dev + 4 * i, w, it.D, it.S,
-                                  it.R, it.T, w ? tb[q].x : nullptr, s));
-        }
-        HIP_TRY(launch_fill_int(it.info, 1, kInfoNone, s));
-      }
+    if (graphable)
+      HIP_TRY(hipMemcpyAsync(G.th, theta_dev, (size_t)k * 32, hipMemcpyDeviceToDevice, s));
+    hipStream_t ls = s;
+    if (graphable) {
+      ls = g_cap;
+      HIP_TRY(hipStreamBeginCapture(ls, hipStreamCaptureModeThreadLocal));
     }
-    ST_TRY(run_factor(F, s));
-    HIP_TRY(launch_logdet_finish(fdev, 2 * k, logdet, info, s));
-    ST_TRY(run_solve(Sv, xs, tmps, s));
-    HIP_TRY(launch_terms(tdev, k, s));
-    if (need_selinv) ST_TRY(run_selinv(Si, true, s));
-    HIP_TRY(launch_combine(cdev, k, s));
+    auto body = [&]() -> inla_status {
+      // assemble Q_prior, Q_c and b = tau_y A^T y (into x, solved in place)
+      for (int q = 0; q < k; ++q) {
+        const int i = start + q;
+        const ModelDev &h = models[i]->host;
+        for (int w = 0; w < 2; ++w) {
+          ItemDev &it = w ? tb[q].C : tb[q].P;
+          {
+            ProfScope ps(PS_ASSEMBLE, 0.0, ls);
+            HIP_TRY(launch_assemble(models[i]->dev, h.b, h.nt, h.a, th + 4 * q, w, it.D, it.S, it.R,
+                                    it.T, w ? tb[q].x : nullptr, ls));
+          }
+          HIP_TRY(launch_fill_int(it.info, 1, kInfoNone, ls));
+        }
+      }
+      ST_TRY(run_factor(F, ls));
+      HIP_TRY(launch_logdet_finish(fdev, 2 * k, logdet, info, ls));
+      ST_TRY(run_solve(Sv, xs, tmps, ls));
+      HIP_TRY(launch_terms(tdev, k, ls));
+      if (need_selinv) ST_TRY(run_selinv(Si, true, ls));
+      HIP_TRY(launch_combine(cdev, k, ls));
+      return INLA_OK;
+    };
+    if (g_prof.on) ++g_prof.calls;
+    inla_status st = body();
+    if (graphable) {
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamEndCapture(ls, &graph);
+      if (st != INLA_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+      }
+      if (e != hipSuccess) return fail(INLA_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+      hipGraphExec_t exec = nullptr;
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) return fail(INLA_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+      G.valid = true;
+      G.models = key;
+      G.grad = grad;
+      G.var = var_out != nullptr;
+      G.mu = mu_out != nullptr;
+      G.prof = g_prof.on;
+      G.gen = g_arena.gen;
+      G.base = g_arena.base;
+      G.exec = exec;
+      G.ntot = ntot;
+      g_graph = G;
+      HIP_TRY(hipGraphLaunch(g_graph.exec, s));
+      ST_TRY(copy_outputs(g_graph, n_items, f_dev, grad_dev, mu_out, var_out, status_dev, s));
+    } else if (st != INLA_OK) {
+      return st;
+    }
     start = end;
   }
   return arena_done(s);
@@ -952,8 +1128,10 @@ inla_status inla_eval_f_grad(const inla_model *const *models, int32_t n_items,
 
 inla_status inla_profile_begin(void) {
   std::lock_guard<std::mutex> lk(g_mutex);
+  drop_graph();   // a captured graph may hold events of the pool
   g_prof.recs.clear();
   g_prof.used = 0;
+  g_prof.calls = 0;
   g_prof.on = true;
   return INLA_OK;
 }
@@ -961,26 +1139,38 @@ inla_status inla_profile_begin(void) {
 inla_status inla_profile_end(double *out, int32_t nslots) {
   std::lock_guard<std::mutex> lk(g_mutex);
   g_prof.on = false;
-  std::vector<double> acc(3 * PS_COUNT, 0.0);
+  const int nall = PS_COUNT + 1 + PK_COUNT;
+  std::vector<double> acc(3 * nall, 0.0);
+  int bad = 0;
   for (auto &r : g_prof.recs) {
-    HIP_TRY(hipEventSynchronize(r.e1));
     float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, r.e0, r.e1));
-    acc[3 * r.slot + 0] += 1.0;
-    acc[3 * r.slot + 1] += ms;
-    acc[3 * r.slot + 2] += r.flops;
+    if (hipEventSynchronize(r.e1) != hipSuccess || hipEventElapsedTime(&ms, r.e0, r.e1) != hipSuccess) {
+      (void)hipGetLastError();
+      ++bad;
+      continue;
+    }
+    for (int slot : {r.slot, PS_COUNT + 1 + r.kind}) {
+      acc[3 * slot + 0] += 1.0;
+      acc[3 * slot + 1] += ms;
+      acc[3 * slot + 2] += r.flops;
+    }
   }
+  // slot PS_COUNT: evaluations represented, unreadable records
+  acc[3 * PS_COUNT + 0] = g_prof.calls;
+  acc[3 * PS_COUNT + 1] = bad;
   g_prof.recs.clear();
   g_prof.used = 0;
+  drop_graph();
   if (out)
-    for (int k = 0; k < std::min<int>(nslots, PS_COUNT) * 3; ++k) out[k] = acc[k];
+    for (int k = 0; k < std::min<int>(nslots, nall) * 3; ++k) out[k] = acc[k];
   return INLA_OK;
 }
 
-int32_t inla_profile_slots(void) { return PS_COUNT; }
+int32_t inla_profile_slots(void) { return PS_COUNT + 1 + PK_COUNT; }
 
 void inla_release_workspace(void) {
   std::lock_guard<std::mutex> lk(g_mutex);
+  drop_graph();
   if (g_arena.base) {
     (void)hipDeviceSynchronize();
     (void)hipFree(g_arena.base);

@@ -159,8 +159,8 @@ __host__ __device__ inline bool phase_is_fat(int phase) {
 }
 
 // ---- launch wrappers (bta_kernels.hip) ----
-hipError_t launch_tile_phase(const ItemDev *items_dev, int n_items, int total, int phase, int t,
-                             int p, bool big, hipStream_t s);
+hipError_t launch_tile_phase(const ItemDev *items_dev, int n_items, int total, int phase,
+                             int phase2, int t, int p, bool big, hipStream_t s);
 hipError_t launch_fill(double *ptr, long long n, double v, hipStream_t s);
 hipError_t launch_fill_int(int *ptr, long long n, int v, hipStream_t s);
 hipError_t launch_logdet_finish(const ItemDev *items_dev, int n_items, double *logdet_out,

@@ -197,3 +197,38 @@ def test_batched_uneven_matches_single(P):
         assert out["f"][i].item() == one["f"][0].item()
         assert torch.equal(out["grad"][i], one["grad"][0])
         assert rel(out["f"][i].item(), O.eval_f_dense(md, th[i])["f"]) < 1e-10
+
+
+def test_graph_replay_matches_eager(P, monkeypatch):
+    """A replayed graph (same call signature, new theta) equals the eager path bitwise."""
+    md = config_model("c4small")
+    M = P.Model.from_data(md)
+    th1 = np.array([0.1, 0.7, 1.2, 4.0])
+    th2 = np.array([-0.2, 1.1, 0.8, 4.4])
+    monkeypatch.setenv("INLA_GRAPH", "1")
+    P.eval_f_grad(M, th1, want_var=True)            # captures
+    rep = P.eval_f_grad(M, th2, want_var=True)      # replays with the new theta
+    rep2 = P.eval_f_grad(M, th2, want_var=True)     # replays again
+    torch.cuda.synchronize()
+    monkeypatch.setenv("INLA_GRAPH", "0")
+    eag = P.eval_f_grad(M, th2, want_var=True)
+    torch.cuda.synchronize()
+    for key in ("f", "grad", "var"):
+        assert torch.equal(rep[key], eag[key]), key
+        assert torch.equal(rep2[key], eag[key]), key
+    assert rel(rep["f"].item(), O.eval_f_dense(md, th2)["f"]) < 1e-10
+
+
+def test_hbm_admission_waves_match_single_wave(P, monkeypatch):
+    """A budget that admits one item at a time gives the same results as one wave."""
+    monkeypatch.setenv("INLA_GRAPH", "0")
+    mds = [make_model(5, 3, 2, 11), make_model(4, 4, 3, 12), make_model(6, 2, 1, 13)]
+    Ms = [P.Model.from_data(m) for m in mds]
+    th = np.array([[0.1, 0.8, 0.5, 2.0], [0.3, 1.1, 1.0, 3.0], [-0.2, 0.6, 0.2, 2.5]])
+    one = P.eval_f_grad(Ms, th)
+    torch.cuda.synchronize()
+    waves = P.eval_f_grad(Ms, th, budget=1.8e5)
+    torch.cuda.synchronize()
+    assert torch.equal(one["f"], waves["f"]) and torch.equal(one["grad"], waves["grad"])
+    with pytest.raises(P.InlaError):
+        P.eval_f_grad(Ms, th, budget=1.0e3)
