@@ -172,7 +172,10 @@ inla_status inla_selinv(const inla_bta *L, inla_bta *sigma_or_null, double *diag
  *   mu_or_null : concatenation over items of the posterior mode mu (n_i each)
  *   var_or_null: concatenation over items of the marginal variances diag(Q_c^{-1})
  *   status_dev : n_items int32: 0 ok, 1 = Q_prior not positive definite,
- *                2 = Q_c not positive definite (f is NaN for that item)
+ *                2 = Q_c not positive definite, 3 = theta outside the parameter
+ *                space (a non-finite entry, or tanh(theta_3) = +-1 in FP64);
+ *                f (and the gradient) are NaN for such an item, the other
+ *                items of the batch are unaffected
  * Items are admitted in waves so that the BTA storage stays within the HBM
  * budget of opts (NULL opts = defaults).
  */

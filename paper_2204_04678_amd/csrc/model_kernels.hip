@@ -456,7 +456,12 @@ __global__ __launch_bounds__(256) void combine_kernel(const CombineItem *__restr
   }
   const double mm = (double)M.m;
   const double ldp = ci.logdet[0], ldc = ci.logdet[1];
-  const int st = ci.info[0] ? 1 : (ci.info[1] ? 2 : 0);
+  // status: 3 = theta outside the parameter space (non-finite, or |rho| = 1 in
+  // floating point), 1 / 2 = Q_prior / Q_c not positive definite
+  bool bad_theta = false;
+  for (int k = 0; k < 4; ++k) bad_theta = bad_theta || !isfinite(th[k]);
+  bad_theta = bad_theta || !(fabs(tanh(th[2])) < 1.0);
+  const int st = bad_theta ? 3 : (ci.info[0] ? 1 : (ci.info[1] ? 2 : 0));
   double f = -logprior - 0.5 * ldp + 0.5 * (q0 + qb) - 0.5 * mm * th[3] + 0.5 * tauy * rss +
              0.5 * ldc + 0.5 * mm * log(2.0 * M_PI);
   if (st) f = NAN;

@@ -1,0 +1,131 @@
+"""GPU parity at the full workload sizes, against stored oracle values.
+
+The stored values (tests/golden/<workload>.json) were written by
+tests/golden/make_golden.py, which calls only the CPU oracle.  Each test also
+checks a property that holds at any size: the prior log-determinant against
+its closed form from the spectrum of the grid Laplacian.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from inla_synth import THETA0, config_model, fd_stencil, uneven_batch
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2204_04678_amd as P
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    P.lib()
+    return P
+
+
+def rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+def golden(name):
+    with open(os.path.join(GOLDEN, f"{name}.json")) as fh:
+        return json.load(fh)
+
+
+def closed_logdet_prior(md, theta):
+    """log|Q_p| = ns log|Q_AR1| + nt log|Q_s| + nb log(beta_prec), Q_s from its spectrum."""
+    N, h, nt, nb = md.N, md.h, md.nt, md.nb
+    ns = N * N
+    kappa2h2 = math.exp(2 * theta[1]) * h * h
+    rho = math.tanh(theta[2])
+    lam = 4.0 * np.sin(np.pi * np.arange(N) / (2.0 * N)) ** 2
+    ld_s = ns * (2 * theta[0] - 2 * math.log(h)) + 2 * math.fsum(
+        np.log(kappa2h2 + lam[:, None] + lam[None, :]).ravel())
+    ld_ar = -(nt - 1) * math.log(1 - rho * rho)
+    return ns * ld_ar + nt * ld_s + nb * math.log(md.beta_prior_prec)
+
+
+def check_against_golden(P, name, tol_f=1e-10):
+    g = golden(name)
+    md = config_model(name)
+    print(f"{name}: n={md.n}", flush=True)
+    M = P.Model.from_data(md)
+    out = P.eval_f(M, THETA0, want_mu=True, want_var=True)
+    Qp = P.assemble(M, THETA0, 0)
+    ldp, _ = P.factor_logdet(Qp)
+    del Qp
+    Qc, _ = P.assemble(M, THETA0, 1)
+    ldc, _ = P.factor_logdet(Qc)
+    del Qc
+    torch.cuda.synchronize()
+    assert int(out["status"].item()) == 0
+    assert rel(out["f"].item(), g["f"]) < tol_f
+    assert rel(ldp.item(), g["logdet_p"]) < 1e-10
+    assert rel(ldc.item(), g["logdet_c"]) < 1e-10
+    assert rel(ldp.item(), closed_logdet_prior(md, THETA0)) < 1e-10
+    idx = np.array(g["idx"])
+    mu = out["mu"].cpu().numpy()[idx]
+    assert np.max(np.abs(mu - np.array(g["mu"]))) / g["mu_absmax"] < 1e-9
+    if "var" in g:
+        var = out["var"].cpu().numpy()[idx]
+        vr = np.array(g["var"])
+        assert np.max(np.abs(var - vr) / vr) < 1e-9
+    return M, md
+
+
+def test_workload_32x32x50_against_oracle(P):
+    check_against_golden(P, "c2")
+
+
+def test_workload_40x40x100_against_oracle_and_fd(P):
+    M, md = check_against_golden(P, "c4")
+    # adjoint gradient against central differences of the GPU's own f (h = 1e-4)
+    pts = torch.tensor(fd_stencil(THETA0, 1e-4), dtype=torch.float64, device="cuda")
+    fv = P.eval_f(M, pts)["f"].cpu().numpy()
+    fd = np.array([(fv[1 + 2 * k] - fv[2 + 2 * k]) / 2e-4 for k in range(4)])
+    g = P.eval_f_grad(M, THETA0)["grad"].cpu().numpy()[0]
+    scale = np.abs(fd).max()
+    assert np.all(np.abs(g - fd) <= 1e-5 * np.maximum(np.abs(fd), 1e-3 * scale)), (g, fd)
+
+
+def test_workload_45x45x200_against_oracle(P):
+    if not os.path.exists(os.path.join(GOLDEN, "c5.json")):
+        pytest.skip("stored oracle values for the 45x45x200 workload not generated")
+    check_against_golden(P, "c5")
+
+
+def test_uneven_batch_of_64_models(P):
+    """All 64 models in one batched call; every eighth against the oracle."""
+    g = golden("c3")
+    items = uneven_batch(64)
+    Ms = [P.Model.from_data(md) for md, _ in items]
+    th = np.stack([t for _, t in items])
+    out = P.eval_f_grad(Ms, th)
+    torch.cuda.synchronize()
+    assert int(out["status"].max().item()) == 0
+    f = out["f"].cpu().numpy()
+    for rec in g["items"]:
+        assert rel(f[rec["item"]], rec["f"]) < 1e-10, rec["item"]
+    # a model alone gives the same f and gradient (tile choice may differ: 1e-12)
+    for j in (3, 40):
+        one = P.eval_f_grad(Ms[j], th[j])
+        assert rel(one["f"][0].item(), f[j]) < 1e-12
+        gj = out["grad"][j].cpu().numpy()
+        assert np.max(np.abs(one["grad"][0].cpu().numpy() - gj) / np.abs(gj)) < 1e-10
+
+
+def test_invalid_theta_is_reported_per_item(P):
+    md = config_model("c4small")
+    M = P.Model.from_data(md)
+    th = np.stack([THETA0, np.array([0.0, 1.0, 30.0, 4.6]), THETA0])   # tanh(30) == 1.0
+    out = P.eval_f_grad([M, M, M], th)
+    torch.cuda.synchronize()
+    st = out["status"].cpu().numpy()
+    assert list(st) == [0, 3, 0]
+    f = out["f"].cpu().numpy()
+    assert math.isnan(f[1]) and f[0] == f[2]
