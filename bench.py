@@ -72,7 +72,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c4", "c5"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
+                    help="c2 (default, the headline): 32x32x50, one theta; c3: 64 uneven models, "
+                         "one batched call; c4: 40x40x100, one theta; c5: 45x45x200, the 8 "
+                         "line-search points in one batched call")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fd", action="store_true", help="skip the finite-difference baseline")
     args = ap.parse_args()
@@ -86,7 +89,7 @@ def main():
     import torch
 
     import paper_2204_04678_amd as P
-    from inla_synth import THETA0, config_model, fd_stencil
+    from inla_synth import THETA0, config_model, config_theta_batch, fd_stencil, uneven_batch
 
     if not os.path.exists(P.binding.LIB):
         from paper_2204_04678_amd import _build
@@ -94,11 +97,26 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
 
-    md = config_model(args.config)
-    model = P.Model.from_data(md)
+    if args.config == "c3":
+        items = uneven_batch(64)
+        mds = [m for m, _ in items]
+        model = [P.Model.from_data(m) for m in mds]
+        theta = torch.tensor(np.stack([t for _, t in items]), dtype=torch.float64, device="cuda")
+        md = mds[0]
+        workload = "64 models of uneven (N in {16,24,32}, nt in [20,100], nb in [2,6]), each " \
+                   "with its own theta, f+grad via adjoint, one batched call"
+    else:
+        md = config_model(args.config)
+        mds = [md]
+        model = P.Model.from_data(md)
+        th = config_theta_batch(args.config) if args.config == "c5" else THETA0[None, :]
+        theta = torch.tensor(th, dtype=torch.float64, device="cuda")
+        mds = mds * theta.shape[0]
+        workload = (f"N={md.N} (b={md.ns}), nt={md.nt}, nb={md.nb}, n={md.n}, m={md.m}, "
+                    f"{theta.shape[0]} theta point(s), f+grad via adjoint")
+    n_items = theta.shape[0]
     b, nt, a = md.ns, md.nt, md.nb
-    theta = torch.tensor(THETA0[None, :], dtype=torch.float64, device="cuda")
-    F_alg = 2 * flops_chol(b, nt, a) + 2 * flops_selinv(b, nt, a)
+    F_alg = sum(2 * flops_chol(m.ns, m.nt, m.nb) + 2 * flops_selinv(m.ns, m.nt, m.nb) for m in mds)
 
     # Timed region: the evaluation replays its captured hipGraph (one launch of
     # the whole ~2.5k-kernel sequence per step).
@@ -111,7 +129,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     step_s = (t1 - t0) / args.steps
-    value = 1.0 / step_s
+    value = n_items / step_s
 
     # Kernel timing pass: the same steps launched eagerly with HIP events around
     # every kernel on its stream (events recorded inside a captured graph cannot
@@ -131,8 +149,12 @@ def main():
     else:
         os.environ["INLA_GRAPH"] = prev_graph
     eager_step_s = (tp1 - tp0) / args.steps
-    f_val = float(out["f"][0].item())
-    grad = out["grad"][0].cpu().numpy().tolist()
+    f_val = out["f"].cpu().numpy().tolist()
+    grad = out["grad"].cpu().numpy().tolist()
+    if n_items == 1:
+        f_val, grad = f_val[0], grad[0]
+    elif n_items > 8:
+        f_val, grad = f_val[:8], grad[:8]
 
     calls = max(prof["calls"], 1)
     slots, kernels = prof["slots"], prof["kernels"]
@@ -160,7 +182,7 @@ def main():
                                           for k, v in slots.items() if v["launches"]}}
 
     extra = {}
-    if not args.no_fd:
+    if not args.no_fd and args.config in ("c2", "c4"):
         pts = torch.tensor(fd_stencil(THETA0, 1e-3), dtype=torch.float64, device="cuda")
         reps = max(1, args.steps // 3)
         P.eval_f(model, pts[0:1])
@@ -190,7 +212,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(md, THETA0)
+        cpu = cpu_baseline(md, theta[0].cpu().numpy())
 
     rec = {
         "metric": "f(theta)+grad f evaluations/s (BTA Cholesky + selected-inversion adjoint, FP64)",
@@ -205,9 +227,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded grid model; no dataset)",
-        "config": {"workload": f"{args.config}: N={md.N} (b={b}), nt={nt}, nb={a}, n={md.n}, "
-                               f"m={md.m}, one theta, f+grad via adjoint",
-                   "b": b, "nt": nt, "a": a, "n": md.n, "items": 1},
+        "config": {"workload": workload, "b": b, "nt": nt, "a": a, "n": md.n, "items": n_items},
         "pct_fp64_peak_whole_step": round(100 * F_alg * value / (PEAK_FP64_TFLOPS * 1e12), 3),
         "alg_flops_per_step": F_alg,
         "f": f_val,

@@ -22,8 +22,17 @@ constexpr int kFatKC = 32;        // k-chunk of the Cholesky-capable kernel
 constexpr int kLeanLds = 2 * 2 * kLeanKC * LDP;                      // double-buffered panels
 constexpr int kFatLds = 2 * kTile * TLD + 2 * kTile;                 // tile + inverse + logs
 static_assert(kFatLds >= 2 * 2 * kFatKC * LDP, "fat LDS must hold the product panels too");
-constexpr int kBigKC = 16;                                            // k-chunk, big tiles
-constexpr int kBigLds = 2 * 2 * kBigKC * (kBig + 2);
+// Big-tile kernel layouts: WR x WC waves over a 128 x 128 tile, k-chunk KC,
+// register prefetch depth DEPTH, and the waves per SIMD it is built for.
+template <int V> struct BigCfg;
+template <> struct BigCfg<0> {   // 8 waves of 64 x 32, two waves per SIMD
+  static constexpr int WR = 2, WC = 4, KC = 16, DEPTH = 2, OCC = 1;
+};
+template <> struct BigCfg<1> {   // 4 waves of 64 x 64, one wave per SIMD
+  static constexpr int WR = 2, WC = 2, KC = 16, DEPTH = 2, OCC = 1;
+};
+template <int V> constexpr int big_threads() { return 64 * BigCfg<V>::WR * BigCfg<V>::WC; }
+template <int V> constexpr int big_lds() { return 2 * 2 * BigCfg<V>::KC * (kBig + 2); }
 
 struct Seg {
   const double *A;
@@ -284,14 +293,12 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       const int j = q;
       tk.m = a; tk.n = tdim(b, j);
       tk.C = sig_R(it, t) + (long long)j * kTile * a; tk.ldc = a;
-      if (!last) {
-        set_seg(tk.seg[0], sig_R(it, t + 1), 1, a, it.W2 + (long long)j * kTile * b, b, 1, 0, b, -1.0);
-        set_seg(tk.seg[1], it.ST, 1, a, it.W3 + (long long)j * kTile * a, a, 1, 0, a, -1.0);
-        tk.nseg = 2;
-      } else {
-        set_seg(tk.seg[0], it.ST, 1, a, it.W3 + (long long)j * kTile * a, a, 1, 0, a, -1.0);
-        tk.nseg = 1;
-      }
+      // every segment has a fixed slot (an empty one when absent), so that the
+      // task never needs an indexed segment
+      set_seg(tk.seg[0], it.ST, 1, a, it.W3 + (long long)j * kTile * a, a, 1, 0, a, -1.0);
+      set_seg(tk.seg[1], sig_R(it, t + 1), 1, a, it.W2 + (long long)j * kTile * b, b, 1, 0,
+              last ? 0 : b, -1.0);
+      tk.nseg = 2;
       return;
     }
     case PH_SI_SD_X: {
@@ -301,23 +308,14 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       tk.m = tdim(b, i); tk.n = tdim(b, j);
       tk.C = SDt + toff(b, i, j); tk.ldc = b;
       tk.mirror = 1; tk.Cm = SDt + toff(b, j, i); tk.diagtile = (i == j);
+      // fixed slots: LinvT Linv, then - Sigma_S^T V, then - Sigma_R^T U (empty when absent)
       set_seg(tk.seg[0], Dt + (long long)i * kTile * b, b, 1, Dt + (long long)j * kTile * b, b, 1,
               i * kTile, b, 1.0);
-      tk.nseg = 1;
-      if (!last) {
-        set_seg(tk.seg[1], sig_S(it, t) + (long long)i * kTile * b, b, 1,
-                it.W2 + (long long)j * kTile * b, b, 1, 0, b, -1.0);
-        tk.nseg = 2;
-        if (arrow) {
-          set_seg(tk.seg[2], sig_R(it, t) + (long long)i * kTile * a, a, 1,
-                  it.W3 + (long long)j * kTile * a, a, 1, 0, a, -1.0);
-          tk.nseg = 3;
-        }
-      } else if (arrow) {
-        set_seg(tk.seg[1], sig_R(it, t) + (long long)i * kTile * a, a, 1,
-                it.W3 + (long long)j * kTile * a, a, 1, 0, a, -1.0);
-        tk.nseg = 2;
-      }
+      set_seg(tk.seg[1], sig_S(it, t) + (long long)i * kTile * b, b, 1,
+              it.W2 + (long long)j * kTile * b, b, 1, 0, last ? 0 : b, -1.0);
+      set_seg(tk.seg[2], sig_R(it, t) + (long long)i * kTile * a, a, 1,
+              it.W3 + (long long)j * kTile * a, a, 1, 0, a, -1.0);
+      tk.nseg = 3;
       return;
     }
     default:
@@ -393,21 +391,11 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
       tk.mirror = 1; tk.Cm = SDt + boff(b, J, I); tk.diagtile = (I == J);
       set_seg(tk.seg[0], Dt + (long long)I * kBig * b, b, 1, Dt + (long long)J * kBig * b, b, 1,
               I * kBig, b, 1.0);
-      tk.nseg = 1;
-      if (!last) {
-        set_seg(tk.seg[1], sig_S(it, t) + (long long)I * kBig * b, b, 1,
-                it.W2 + (long long)J * kBig * b, b, 1, 0, b, -1.0);
-        tk.nseg = 2;
-        if (arrow) {
-          set_seg(tk.seg[2], sig_R(it, t) + (long long)I * kBig * a, a, 1,
-                  it.W3 + (long long)J * kBig * a, a, 1, 0, a, -1.0);
-          tk.nseg = 3;
-        }
-      } else if (arrow) {
-        set_seg(tk.seg[1], sig_R(it, t) + (long long)I * kBig * a, a, 1,
-                it.W3 + (long long)J * kBig * a, a, 1, 0, a, -1.0);
-        tk.nseg = 2;
-      }
+      set_seg(tk.seg[1], sig_S(it, t) + (long long)I * kBig * b, b, 1,
+              it.W2 + (long long)J * kBig * b, b, 1, 0, last ? 0 : b, -1.0);
+      set_seg(tk.seg[2], sig_R(it, t) + (long long)I * kBig * a, a, 1,
+              it.W3 + (long long)J * kBig * a, a, 1, 0, a, -1.0);
+      tk.nseg = 3;
       return;
     }
     default:
@@ -420,26 +408,36 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
 // for a panel of ROWS rows, NT threads.  Addresses are clamped into range so
 // that every load is unconditional and all of them stay in flight together;
 // masking and scaling happen at the LDS store.
+// Element q of a thread's share of a KC x ROWS chunk: row r0 + q*dr, k k0 + q*dk.
+// Row-contiguous operands give each thread one row and a run of k (coalesced
+// along rows); k-contiguous ones give each thread one k and a run of rows.
+template <int KC, int ROWS, int NT>
+struct ChunkMap {
+  int r0, dr, k0, dk;
+  __device__ __forceinline__ ChunkMap(bool rows_contig) {
+    static_assert(NT % ROWS == 0 && NT % KC == 0, "chunk map needs NT to be a multiple");
+    const int tid = threadIdx.x;
+    r0 = rows_contig ? tid % ROWS : tid / KC;
+    dr = rows_contig ? 0 : NT / KC;
+    k0 = rows_contig ? tid / ROWS : tid % KC;
+    dk = rows_contig ? NT / ROWS : 0;
+  }
+};
+
+// Raw loads of one KC x ROWS chunk of op(X)(r, k) = X[r*rs + k*ks] into
+// registers.  Addresses are clamped into range so that every load is
+// unconditional and all of them stay in flight together; masking and scaling
+// happen at the LDS store.
 template <int KC, int ROWS, int NT>
 __device__ __forceinline__ void gload(double (&r)[KC * ROWS / NT], const double *X, int rs, int ks,
                                       int rows, int kc, int k1) {
-  const int tid = threadIdx.x;
   constexpr int NE = KC * ROWS / NT;
+  const ChunkMap<KC, ROWS, NT> cm(rs == 1);
   const int rmax = rows - 1, kmax = k1 - 1;
-  if (rs == 1) {
 #pragma unroll
-    for (int q = 0; q < NE; ++q) {
-      const int e = tid + q * NT;
-      const int rr = e % ROWS, kk = kc + e / ROWS;
-      r[q] = gld(X + (long long)min(rr, rmax) + (long long)min(kk, kmax) * ks);
-    }
-  } else {
-#pragma unroll
-    for (int q = 0; q < NE; ++q) {
-      const int e = tid + q * NT;
-      const int kk = kc + e % KC, rr = e / KC;
-      r[q] = gld(X + (long long)min(rr, rmax) * rs + (long long)min(kk, kmax) * ks);
-    }
+  for (int q = 0; q < NE; ++q) {
+    const int rr = min(cm.r0 + q * cm.dr, rmax), kk = min(kc + cm.k0 + q * cm.dk, kmax);
+    r[q] = gld(X + (long long)rr * rs + (long long)kk * ks);
   }
 }
 
@@ -448,24 +446,21 @@ __device__ __forceinline__ void gload(double (&r)[KC * ROWS / NT], const double 
 template <int KC, int ROWS, int NT>
 __device__ __forceinline__ void sstore(double *P, const double (&r)[KC * ROWS / NT], bool rows_contig,
                                        int rows, int kc, int k1, double alpha) {
-  const int tid = threadIdx.x;
   constexpr int NE = KC * ROWS / NT;
   constexpr int LD = ROWS + 2;
-  if (rows_contig) {
+  const ChunkMap<KC, ROWS, NT> cm(rows_contig);
 #pragma unroll
-    for (int q = 0; q < NE; ++q) {
-      const int e = tid + q * NT;
-      const int rr = e % ROWS, k = e / ROWS;
-      P[k * LD + rr] = (rr < rows && kc + k < k1) ? alpha * r[q] : 0.0;
-    }
-  } else {
-#pragma unroll
-    for (int q = 0; q < NE; ++q) {
-      const int e = tid + q * NT;
-      const int k = e % KC, rr = e / KC;
-      P[k * LD + rr] = (rr < rows && kc + k < k1) ? alpha * r[q] : 0.0;
-    }
+  for (int q = 0; q < NE; ++q) {
+    const int rr = cm.r0 + q * cm.dr, k = cm.k0 + q * cm.dk;
+    P[k * LD + rr] = (rr < rows && kc + k < k1) ? alpha * r[q] : 0.0;
   }
+}
+
+// Value of segment 0, 1 or 2 (arguments by value, so the choice is a select of
+// registers and never an indexed access into the task).
+template <class T>
+__device__ __forceinline__ T pick3(bool s1, bool s2, T v0, T v1, T v2) {
+  return s2 ? v2 : (s1 ? v1 : v0);
 }
 
 // Geometry of the chunk held in the staging registers.
@@ -475,27 +470,16 @@ struct ChunkInfo {
   double alpha;
 };
 
-template <int KC, int ROWS, int NT>
-__device__ __forceinline__ void load_seg_chunk(const Seg &g, int m, int n, int kc,
-                                               double (&ra)[KC * ROWS / NT],
-                                               double (&rb)[KC * ROWS / NT], ChunkInfo &ci) {
-  gload<KC, ROWS, NT>(ra, g.A, g.ars, g.aks, m, kc, g.k1);
-  gload<KC, ROWS, NT>(rb, g.B, g.brs, g.bks, n, kc, g.k1);
-  ci.fa = g.ars == 1;
-  ci.fb = g.brs == 1;
-  ci.kc = kc;
-  ci.k1 = g.k1;
-  ci.alpha = g.alpha;
-}
-
 // acc += sum over segments of op(A) op(B)^T for an output tile of ROWS x ROWS
 // computed by WR x WC waves; wave (wr, wc) owns rows wr*ROWS/WR .. and columns
 // wc*ROWS/WC .., i.e. MR x MC MFMA blocks of 16 x 16.  LDS panels are
-// double-buffered: the next chunk is fetched into registers while the current
-// one feeds the matrix cores, so there is one barrier per chunk.  Chunks are
-// numbered across the segments; segment fields are only indexed by constants
-// so the task stays in registers.
-template <int KC, int ROWS, int WR, int WC>
+// double-buffered with one barrier per chunk.  With DEPTH = 1 the next chunk
+// is fetched into registers while the current one feeds the matrix cores; with
+// DEPTH = 2 two register sets alternate so that the loads of chunk c + 2 are
+// issued while chunk c is multiplied and have two chunk-times to arrive.
+// Chunks are numbered across the segments; segment fields are only indexed by
+// constants so the task stays in registers.
+template <int KC, int ROWS, int WR, int WC, int DEPTH = 1>
 __device__ __forceinline__ void run_product(const Task &tk, double *smem,
                                             d4 (&acc)[ROWS / WR / 16][ROWS / WC / 16]) {
   constexpr int NT = 64 * WR * WC;
@@ -509,28 +493,33 @@ __device__ __forceinline__ void run_product(const Task &tk, double *smem,
   const int n2 = (tk.nseg > 2 && tk.seg[2].k1 > tk.seg[2].k0) ? (tk.seg[2].k1 - tk.seg[2].k0 + KC - 1) / KC : 0;
   const int total = n0 + n1 + n2;
   if (total == 0) return;
-  double ra[NE], rb[NE];
-  ChunkInfo ci;
-  auto fetch = [&](int c) {
-    if (c < n0) load_seg_chunk<KC, ROWS, NT>(tk.seg[0], tk.m, tk.n, tk.seg[0].k0 + c * KC, ra, rb, ci);
-    else if (c < n0 + n1)
-      load_seg_chunk<KC, ROWS, NT>(tk.seg[1], tk.m, tk.n, tk.seg[1].k0 + (c - n0) * KC, ra, rb, ci);
-    else
-      load_seg_chunk<KC, ROWS, NT>(tk.seg[2], tk.m, tk.n, tk.seg[2].k0 + (c - n0 - n1) * KC, ra, rb,
-                                   ci);
+  // chunk c of the concatenated segments; the segment's fields are picked
+  // with uniform selects so that a single copy of the load code exists
+  auto fetch = [&](int c, double (&ra)[NE], double (&rb)[NE], ChunkInfo &ci) {
+    const bool s1 = c >= n0, s2 = c >= n0 + n1;
+    const double *A = pick3(s1, s2, tk.seg[0].A, tk.seg[1].A, tk.seg[2].A);
+    const double *B = pick3(s1, s2, tk.seg[0].B, tk.seg[1].B, tk.seg[2].B);
+    const int ars = pick3(s1, s2, tk.seg[0].ars, tk.seg[1].ars, tk.seg[2].ars);
+    const int aks = pick3(s1, s2, tk.seg[0].aks, tk.seg[1].aks, tk.seg[2].aks);
+    const int brs = pick3(s1, s2, tk.seg[0].brs, tk.seg[1].brs, tk.seg[2].brs);
+    const int bks = pick3(s1, s2, tk.seg[0].bks, tk.seg[1].bks, tk.seg[2].bks);
+    const int k0 = pick3(s1, s2, tk.seg[0].k0, tk.seg[1].k0, tk.seg[2].k0);
+    const int k1 = pick3(s1, s2, tk.seg[0].k1, tk.seg[1].k1, tk.seg[2].k1);
+    const int cs = c - (s2 ? n0 + n1 : (s1 ? n0 : 0));
+    const int kc = k0 + cs * KC;
+    gload<KC, ROWS, NT>(ra, A, ars, aks, tk.m, kc, k1);
+    gload<KC, ROWS, NT>(rb, B, brs, bks, tk.n, kc, k1);
+    ci.fa = ars == 1;
+    ci.fb = brs == 1;
+    ci.kc = kc;
+    ci.k1 = k1;
+    ci.alpha = pick3(s1, s2, tk.seg[0].alpha, tk.seg[1].alpha, tk.seg[2].alpha);
   };
-  auto stage = [&](double *dst) {
+  auto stage = [&](double *dst, const double (&ra)[NE], const double (&rb)[NE], const ChunkInfo &ci) {
     sstore<KC, ROWS, NT>(dst, ra, ci.fa, tk.m, ci.kc, ci.k1, ci.alpha);
     sstore<KC, ROWS, NT>(dst + KC * LD, rb, ci.fb, tk.n, ci.kc, ci.k1, 1.0);
   };
-  fetch(0);
-  stage(smem);
-  __syncthreads();
-  for (int c = 0; c < total; ++c) {
-    const int cur = c & 1;
-    const bool has_next = c + 1 < total;
-    if (has_next) fetch(c + 1);
-    const double *As = smem + cur * (2 * KC * LD);
+  auto compute = [&](const double *As) {
     const double *Bs = As + KC * LD;
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
@@ -546,8 +535,45 @@ __device__ __forceinline__ void run_product(const Task &tk, double *smem,
         for (int nj = 0; nj < MC; ++nj)
           acc[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mi], bv[nj], acc[mi][nj], 0, 0, 0);
     }
-    if (has_next) stage(smem + (cur ^ 1) * (2 * KC * LD));
+  };
+  double *buf0 = smem, *buf1 = smem + 2 * KC * LD;
+  double ra0[NE], rb0[NE];
+  ChunkInfo ci0;
+  if constexpr (DEPTH == 1) {
+    fetch(0, ra0, rb0, ci0);
+    stage(buf0, ra0, rb0, ci0);
     __syncthreads();
+    for (int c = 0; c < total; ++c) {
+      const int cur = c & 1;
+      const bool has_next = c + 1 < total;
+      fetch(min(c + 1, total - 1), ra0, rb0, ci0);
+      compute(cur ? buf1 : buf0);
+      if (has_next) stage(cur ? buf0 : buf1, ra0, rb0, ci0);
+      __syncthreads();
+    }
+  } else {
+    // The loads are issued unconditionally (past the end they re-read the last
+    // chunk, which stays unused) so that every wait on a register set counts
+    // exactly the loads issued after it and leaves them in flight.
+    double ra1[NE], rb1[NE];
+    ChunkInfo ci1;
+    const int last = total - 1;
+    fetch(0, ra0, rb0, ci0);
+    fetch(min(1, last), ra1, rb1, ci1);
+    stage(buf0, ra0, rb0, ci0);
+    __syncthreads();
+    // invariant at the top: buf0 holds chunk c, set 1 holds (or awaits) chunk c + 1
+    for (int c = 0; c < total; c += 2) {
+      fetch(min(c + 2, last), ra0, rb0, ci0);
+      compute(buf0);
+      if (c + 1 < total) stage(buf1, ra1, rb1, ci1);
+      __syncthreads();
+      if (c + 1 >= total) break;
+      fetch(min(c + 3, last), ra1, rb1, ci1);
+      compute(buf1);
+      if (c + 2 < total) stage(buf0, ra0, rb0, ci0);
+      __syncthreads();
+    }
   }
 }
 
@@ -707,28 +733,57 @@ __device__ void chol_inv_tile(double *A, double *X, double *dlog, int w, double 
 
 // One launch covers the tasks of `phase` and, if phase2 >= 0, of `phase2` as
 // well (two independent phases of the same step), item by item.
+// Owner of workgroup task q in a launch over n_items items whose task counts
+// are count(item): the lanes of each wave evaluate 64 items at a time, an
+// inclusive prefix sum over the wave finds the item, and q becomes the index of
+// the task within it.  Returns n_items when q is past the last task.
+template <class Count>
+__device__ __forceinline__ int find_item(const ItemDev *items, int n_items, int &q, Count count) {
+  const int lane = threadIdx.x & 63;
+  int base = 0;
+  for (int i0 = 0; i0 < n_items; i0 += 64) {
+    const int i = i0 + lane;
+    const int c = (i < n_items) ? count(items[i]) : 0;
+    int incl = c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(incl, off);
+      incl += (lane >= off) ? v : 0;
+    }
+    const int tot = __builtin_amdgcn_readfirstlane(__shfl(incl, 63));
+    if (q < base + tot) {
+      const unsigned long long m = __ballot(base + incl > q);
+      const int l = __ffsll((unsigned long long)m) - 1;
+      // the results are wave-uniform; say so, so that the item's fields are
+      // read with scalar loads
+      q = __builtin_amdgcn_readfirstlane(q - base - __shfl(incl - c, l));
+      return __builtin_amdgcn_readfirstlane(i0 + l);
+    }
+    base += tot;
+  }
+  return n_items;
+}
+
 template <bool FAT>
 __global__ __launch_bounds__(kThreads) void tile_phase_kernel(const ItemDev *__restrict__ items,
                                                               int n_items, int phase, int phase2,
                                                               int t, int p) {
   __shared__ double smem[FAT ? kFatLds : kLeanLds];
+  // tasks are ordered item by item, the item's `phase` tasks before its `phase2` ones
   int q = blockIdx.x;
-  int ii = 0, ph = phase;
-  for (; ii < n_items; ++ii) {
-    const int c = phase_tasks(items[ii], phase, t, p);
-    if (q < c) break;
-    q -= c;
-    if (phase2 >= 0) {
-      const int c2 = phase_tasks(items[ii], phase2, t, p);
-      if (q < c2) {
-        ph = phase2;
-        break;
-      }
-      q -= c2;
-    }
-  }
+  const int ii = find_item(items, n_items, q, [&](const ItemDev &x) {
+    return phase_tasks(x, phase, t, p) + (phase2 >= 0 ? phase_tasks(x, phase2, t, p) : 0);
+  });
   if (ii >= n_items) return;
   const ItemDev it = items[ii];
+  int ph = phase;
+  {
+    const int c1 = phase_tasks(it, phase, t, p);
+    if (q >= c1) {
+      q -= c1;
+      ph = phase2;
+    }
+  }
   Task tk;
   decode(it, ph, t, p, q, tk);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -756,7 +811,7 @@ __global__ __launch_bounds__(kThreads) void tile_phase_kernel(const ItemDev *__r
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
     for (int nj = 0; nj < 2; ++nj) acc[mi][nj] = d4{0.0, 0.0, 0.0, 0.0};
-  run_product<FAT ? kFatKC : kLeanKC, kTile, 2, 2>(tk, smem, acc);
+  run_product<FAT ? kFatKC : kLeanKC, kTile, 2, 2, 2>(tk, smem, acc);
 
   if constexpr (FAT) {
     if (tk.chol) {
@@ -842,57 +897,57 @@ __global__ __launch_bounds__(kThreads) void tile_phase_kernel(const ItemDev *__r
 
 // 128 x 128 output tiles for the b x b products: 8 waves in a 2 x 4
 // arrangement, 64 x 32 outputs (4 x 2 MFMA blocks) per wave.
-constexpr int kBigThreads = 512;
-__global__ __launch_bounds__(kBigThreads, 1) void tile_big_kernel(const ItemDev *__restrict__ items,
-                                                                  int n_items, int phase, int t) {
-  __shared__ double smem[kBigLds];
-  int q = blockIdx.x;
-  int ii = 0;
-  for (; ii < n_items; ++ii) {
-    const int c = phase_tasks(items[ii], phase, t, 0, true);
-    if (q < c) break;
-    q -= c;
-  }
+// The dispatcher deals workgroups round-robin to the 8 XCDs (workgroup id
+// mod 8), each with its own L2.  Renumbering so that XCD x receives one
+// contiguous range of tiles keeps tiles that share operand panels on one L2
+// and gives every XCD the same mix of short and long tiles.
+__device__ __forceinline__ int xcd_contiguous(int bid, int n) {
+  const int x = bid & 7, j = bid >> 3;
+  const int per = n >> 3, rem = n & 7;
+  return x * per + min(x, rem) + j;
+}
+
+template <int V>
+__global__ __launch_bounds__(big_threads<V>(), BigCfg<V>::OCC) void tile_big_kernel(
+    const ItemDev *__restrict__ items, int n_items, int phase, int t) {
+  using C = BigCfg<V>;
+  constexpr int MR = kBig / C::WR / 16, MC = kBig / C::WC / 16;
+  __shared__ double smem[big_lds<V>()];
+  int q = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int ii = find_item(items, n_items, q,
+                           [&](const ItemDev &x) { return phase_tasks(x, phase, t, 0, true); });
   if (ii >= n_items) return;
   const ItemDev it = items[ii];
   Task tk;
   decode_big(it, phase, t, q, tk);
   if (tk.kind != TK_PRODUCT) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wr = w / 4, wc = w % 4;
-  d4 acc[4][2];
+  const int wr = w / C::WC, wc = w % C::WC;
+  d4 acc[MR][MC];
 #pragma unroll
-  for (int mi = 0; mi < 4; ++mi)
+  for (int mi = 0; mi < MR; ++mi)
 #pragma unroll
-    for (int nj = 0; nj < 2; ++nj) acc[mi][nj] = d4{0.0, 0.0, 0.0, 0.0};
-  run_product<kBigKC, kBig, 2, 4>(tk, smem, acc);
-  if (tk.beta != 0.0) {
-    double cold[4][2][4];
+    for (int nj = 0; nj < MC; ++nj) acc[mi][nj] = d4{0.0, 0.0, 0.0, 0.0};
+  run_product<C::KC, kBig, C::WR, C::WC, C::DEPTH>(tk, smem, acc);
 #pragma unroll
-    for (int mi = 0; mi < 4; ++mi)
+  for (int mi = 0; mi < MR; ++mi)
 #pragma unroll
-      for (int nj = 0; nj < 2; ++nj)
+    for (int nj = 0; nj < MC; ++nj) {
+      double cold[4];
+      if (tk.beta != 0.0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = min(wr * 64 + mi * 16 + (lane >> 4) + 4 * r, tk.m - 1);
-          const int col = min(wc * 32 + nj * 16 + (lane & 15), tk.n - 1);
-          cold[mi][nj][r] = gld(tk.C + row + col * tk.ldc);
+          const int row = min(wr * (kBig / C::WR) + mi * 16 + (lane >> 4) + 4 * r, tk.m - 1);
+          const int col = min(wc * (kBig / C::WC) + nj * 16 + (lane & 15), tk.n - 1);
+          cold[r] = gld(tk.C + row + col * tk.ldc);
         }
 #pragma unroll
-    for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-      for (int nj = 0; nj < 2; ++nj)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[mi][nj][r] += tk.beta * cold[mi][nj][r];
-  }
-#pragma unroll
-  for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-    for (int nj = 0; nj < 2; ++nj)
+        for (int r = 0; r < 4; ++r) acc[mi][nj][r] += tk.beta * cold[r];
+      }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = wr * 64 + mi * 16 + (lane >> 4) + 4 * r;
-        const int col = wc * 32 + nj * 16 + (lane & 15);
+        const int row = wr * (kBig / C::WR) + mi * 16 + (lane >> 4) + 4 * r;
+        const int col = wc * (kBig / C::WC) + nj * 16 + (lane & 15);
         if (row < tk.m && col < tk.n) {
           const double v = acc[mi][nj][r];
           double *cp = tk.C + row + col * tk.ldc;
@@ -907,14 +962,25 @@ __global__ __launch_bounds__(kBigThreads, 1) void tile_big_kernel(const ItemDev 
           }
         }
       }
+    }
+}
+
+// Layout of the big-tile kernel: INLA_BIG_VARIANT=0|1 (default 0).
+int big_variant() {
+  const char *e = getenv("INLA_BIG_VARIANT");
+  return (e && e[0] == '1') ? 1 : 0;
 }
 
 hipError_t launch_tile_phase(const ItemDev *items_dev, int n_items, int total, int phase,
                              int phase2, int t, int p, bool big, hipStream_t s) {
   if (total <= 0) return hipSuccess;
   if (big && phase_is_product_x(phase) && phase2 < 0) {
-    hipLaunchKernelGGL(tile_big_kernel, dim3(total), dim3(kBigThreads), 0, s, items_dev, n_items,
-                       phase, t);
+    if (big_variant() == 0)
+      hipLaunchKernelGGL(tile_big_kernel<0>, dim3(total), dim3(big_threads<0>()), 0, s, items_dev,
+                         n_items, phase, t);
+    else
+      hipLaunchKernelGGL(tile_big_kernel<1>, dim3(total), dim3(big_threads<1>()), 0, s, items_dev,
+                         n_items, phase, t);
   } else if (phase_is_fat(phase) || (phase2 >= 0 && phase_is_fat(phase2))) {
     hipLaunchKernelGGL(tile_phase_kernel<true>, dim3(total), dim3(kThreads), 0, s, items_dev, n_items,
                        phase, phase2, t, p);
