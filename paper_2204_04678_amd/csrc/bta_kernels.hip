@@ -583,6 +583,23 @@ __device__ inline int acc_row(int wr, int mi, int lane, int r) {
 }
 __device__ inline int acc_col(int wc, int nj, int lane) { return wc * 32 + nj * 16 + (lane & 15); }
 
+// 1/x and 1/sqrt(x) from the hardware estimates, each refined by two Newton
+// steps (r <- r + r(1 - x r) and y <- y + y(1 - x y^2)/2), which take the
+// estimate to full double precision for the positive pivots of a Cholesky
+// factorization.
+__device__ __forceinline__ double recip_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return y;
+}
+
 __device__ inline double rdlane(double v, int l) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
@@ -600,50 +617,88 @@ __device__ void chol_inv_tile(double *A, double *X, double *dlog, int w, double 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nb = (w + 15) / 16;
   const int lr = lane & 15, lk = lane >> 4;
+  double *col = dlog + kTile;   // 16-entry column broadcast buffer
   for (int k = 0; k < nb; ++k) {
-    // (a) factor and invert the diagonal block (k,k) in wave 0: lane i holds row
-    //     i; every update is a select, so the wave never branches.
+    // (a) factor and invert the diagonal block (k,k) in wave 0.  Cholesky,
+    //     right-looking: lane i holds row i; at pivot j the lanes publish
+    //     column j in LDS and read it back whole (broadcast reads), so the
+    //     update needs no cross-lane moves.  Then the inverse by forward
+    //     substitution, lane c computing column c from the rows of L in LDS.
+    //     Reads follow writes of the same wave in order; the wave barriers
+    //     keep the compiler from moving LDS accesses across them.
     if (wv == 0) {
       const int r0 = 16 * k;
-      double a[16], x[16], rinv[16];
+      double a[16], rinv[16];
+      // Lane i computes row i of the factor; its entries above the diagonal
+      // are scratch (they only ever feed other entries above the diagonal),
+      // so the updates run on every lane without per-column lane masks.
+      const int lr16 = lane & 15;
 #pragma unroll
-      for (int c = 0; c < 16; ++c)
-        a[c] = (lane < 16 && c <= lane) ? A[(r0 + lane) * TLD + r0 + c] : 0.0;
-      int bad = -1;
+      for (int c = 0; c < 16; ++c) a[c] = A[(r0 + lr16) * TLD + r0 + c];
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const double piv = rdlane(a[j], j);
-        if (bad < 0 && !(piv > 0.0) && r0 + j < w) bad = j;
-        const double dj = sqrt(piv);
-        const double inv = 1.0 / dj;
-        rinv[j] = inv;
-        a[j] = (lane > j) ? a[j] * inv : ((lane == j) ? dj : a[j]);
+        if (lane < 16) col[lane] = a[j];
+        __builtin_amdgcn_wave_barrier();
+        double cv[16];
 #pragma unroll
-        for (int m = j + 1; m < 16; ++m) {
-          const double lm = rdlane(a[j], m);
-          a[m] = (lane >= m) ? fma(-a[j], lm, a[m]) : a[m];
-        }
-      }
-      if (bad >= 0 && lane == 0) atomicMin(info, row_off + r0 + bad + 1);
+        for (int m = j; m < 16; ++m) cv[m] = col[m];
+        __builtin_amdgcn_wave_barrier();
+        const double piv = cv[j];
+        const double ip = recip_nr(piv);
+        const double rs = rsqrt_nr(piv);
+        rinv[j] = rs;
+        // A_im -= L_ij L_mj = A_ij A_mj / piv for m > j; then L_ij = A_ij / sqrt(piv)
+        const double wj = a[j] * ip;
 #pragma unroll
-      for (int c = 0; c < 16; ++c) x[c] = (c == lane) ? 1.0 : 0.0;
+        for (int m = j + 1; m < 16; ++m) a[m] = fma(-wj, cv[m], a[m]);
+        a[j] *= rs;
+        // one pivot at a time: the empty asm statements make this step's
+        // updates happen here (deferring them would keep every step's column
+        // live at once)
 #pragma unroll
-      for (int m = 0; m < 16; ++m) {
-#pragma unroll
-        for (int c = 0; c <= m; ++c) x[c] = (lane == m) ? x[c] * rinv[m] : x[c];
-#pragma unroll
-        for (int c = 0; c <= m; ++c) {
-          const double xm = rdlane(x[c], m);
-          x[c] = (lane > m) ? fma(-a[m], xm, x[c]) : x[c];
-        }
+        for (int m = j; m < 16; ++m) asm volatile("" : "+v"(a[m]));
       }
       if (lane < 16) {
 #pragma unroll
-        for (int c = 0; c < 16; ++c) X[(r0 + lane) * TLD + r0 + c] = (c <= lane) ? x[c] : 0.0;
-        double dg = a[0];
+        for (int c = 0; c < 16; ++c) A[(r0 + lane) * TLD + r0 + c] = a[c];
+      }
+      __builtin_amdgcn_wave_barrier();
+      // L_jj = piv_j / sqrt(piv_j) is NaN exactly when the pivot is not
+      // positive (or not a number): the first such row is the failure
+      const double dg = A[(r0 + lr16) * TLD + r0 + lr16];
+      const bool ok = (dg > 0.0) || lane >= 16 || r0 + lane >= w;
+      const unsigned long long badm = __ballot(!ok);
+      if (badm && lane == 0) atomicMin(info, row_off + r0 + __ffsll(badm));
+      if (lane < 16) dlog[r0 + lane] = (r0 + lane < w) ? log(dg) : 0.0;
+      __builtin_amdgcn_wave_barrier();
+      // X = L^{-1}: X_ic = (delta_ic - sum_{m<i} L_im X_mc) / L_ii; entries
+      // above the diagonal come out zero because the right-hand side is e_c
+      // (row i + 1 of L is read while row i is computed; the scheduling
+      // barrier keeps the reads from running further ahead)
+      double x[16], lc[16];
 #pragma unroll
-        for (int c = 1; c < 16; ++c) dg = (c == lane) ? a[c] : dg;
-        dlog[r0 + lane] = (r0 + lane < w) ? log(dg) : 0.0;
+      for (int i = 0; i < 16; ++i) {
+        double ln[16];
+        if (i + 1 < 16) {
+#pragma unroll
+          for (int m = 0; m <= i; ++m) ln[m] = A[(r0 + i + 1) * TLD + r0 + m];
+        }
+        double s0 = (i == lane) ? 1.0 : 0.0, s1 = 0.0;
+#pragma unroll
+        for (int m = 0; m < i; ++m) {
+          if (m & 1) s1 = fma(-lc[m], x[m], s1);
+          else s0 = fma(-lc[m], x[m], s0);
+        }
+        x[i] = (s0 + s1) * rinv[i];
+        if (i + 1 < 16) {
+#pragma unroll
+          for (int m = 0; m <= i; ++m) lc[m] = ln[m];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (lane < 16) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) X[(r0 + i) * TLD + r0 + lane] = x[i];
       }
     }
     __syncthreads();
@@ -731,8 +786,6 @@ __device__ void chol_inv_tile(double *A, double *X, double *dlog, int w, double 
   }
 }
 
-// One launch covers the tasks of `phase` and, if phase2 >= 0, of `phase2` as
-// well (two independent phases of the same step), item by item.
 // Owner of workgroup task q in a launch over n_items items whose task counts
 // are count(item): the lanes of each wave evaluate 64 items at a time, an
 // inclusive prefix sum over the wave finds the item, and q becomes the index of
@@ -764,6 +817,8 @@ __device__ __forceinline__ int find_item(const ItemDev *items, int n_items, int 
   return n_items;
 }
 
+// One launch covers the tasks of `phase` and, if phase2 >= 0, of `phase2` as
+// well (two independent phases of the same step), item by item.
 template <bool FAT>
 __global__ __launch_bounds__(kThreads) void tile_phase_kernel(const ItemDev *__restrict__ items,
                                                               int n_items, int phase, int phase2,
