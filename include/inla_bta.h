@@ -104,13 +104,36 @@ typedef struct {
   const double *theta_prior_prec;
 } inla_model_desc;
 
+/*
+ * Options of inla_eval_f / inla_eval_f_grad (NULL = all zero).
+ *   hbm_budget_bytes : device bytes the batch may occupy; items are admitted
+ *                      in waves that fit (0: free memory minus a 4 GiB reserve)
+ *   recompute        : 1 = Q_prior and Q_c of an item share one BTA storage
+ *                      and workspace and are processed one after the other
+ *                      (about half the memory per item, two dependent chains
+ *                      instead of one batched chain); 2 = never; 0 = when it
+ *                      needs fewer admission waves.  Selected-inverse blocks
+ *                      are never stored in either mode: each is recomputed
+ *                      from the stored factor and consumed as it is produced.
+ *   keep_sigma       : reserved, must be 0
+ *   tile             : 64 or 128 forces the tile of the b x b products;
+ *                      0 = the autotuner's entry for this call signature if
+ *                      autotune_cache is set, else a built-in rule
+ *   autotune_cache   : path of a JSON file (or NULL).  On the first call with
+ *                      a new signature (the multiset of item shapes and the
+ *                      outputs asked for) every tile layout is timed once on
+ *                      the caller's stream, synchronously, and the fastest is
+ *                      stored; later calls and processes read it back.
+ * Results with different tile layouts agree to rounding (about 1e-15
+ * relative), not bitwise.
+ */
 typedef struct {
-  double hbm_budget_bytes; /* 0: free device memory minus a 4 GiB reserve */
-  int32_t recompute;       /* gradient path: 0 auto, 1 always, 2 never (see inla_eval_f_grad) */
-  int32_t keep_sigma;      /* reserved, must be 0 */
-  int32_t tile;            /* 0: autotuned per block size; else 64 or 128 */
+  double hbm_budget_bytes;
+  int32_t recompute;
+  int32_t keep_sigma;
+  int32_t tile;
   int32_t reserved;
-  const char *autotune_cache; /* reserved, may be NULL */
+  const char *autotune_cache;
 } inla_opts;
 
 /*

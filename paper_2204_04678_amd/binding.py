@@ -257,11 +257,17 @@ def _models_array(models):
     return arr
 
 
-def _opts(budget=0.0):
-    return Opts(float(budget), 0, 0, 0, 0, None)
+def _opts(budget=0.0, recompute=0, tile=0, autotune_cache=None):
+    """inla_opts: HBM budget in bytes (0 = free memory minus a reserve);
+    recompute 0 auto / 1 always / 2 never share one matrix's storage between
+    Q_prior and Q_c; tile 0 (built-in rule or autotuner), 64 or 128;
+    autotune_cache: JSON file the autotuner reads and extends (None: off)."""
+    path = None if autotune_cache is None else os.fsencode(os.fspath(autotune_cache))
+    return Opts(float(budget), int(recompute), 0, int(tile), 0, path)
 
 
-def eval_f(models, thetas, want_mu=False, want_var=False, budget=0.0):
+def eval_f(models, thetas, want_mu=False, want_var=False, budget=0.0, recompute=0, tile=0,
+           autotune_cache=None):
     """Batched f(theta).  Returns dict(f, status, [mu], [var]) of device tensors."""
     if isinstance(models, Model):
         models = [models]
@@ -274,7 +280,7 @@ def eval_f(models, thetas, want_mu=False, want_var=False, budget=0.0):
     status = torch.empty(k, dtype=torch.int32, device="cuda")
     mu = torch.empty(ntot, dtype=torch.float64, device="cuda") if want_mu else None
     var = torch.empty(ntot, dtype=torch.float64, device="cuda") if want_var else None
-    o = _opts(budget)
+    o = _opts(budget, recompute, tile, autotune_cache)
     _check(lib().inla_eval_f(_models_array(models), k, _ptr(th), _ptr(f), _ptr(mu), _ptr(var),
                              _ptr(status), C.byref(o), _stream()))
     out = dict(f=f, status=status)
@@ -285,7 +291,8 @@ def eval_f(models, thetas, want_mu=False, want_var=False, budget=0.0):
     return out
 
 
-def eval_f_grad(models, thetas, want_mu=False, want_var=False, budget=0.0):
+def eval_f_grad(models, thetas, want_mu=False, want_var=False, budget=0.0, recompute=0, tile=0,
+                autotune_cache=None):
     """Batched f(theta) and its exact gradient.  Returns dict(f, grad, status, [mu], [var])."""
     if isinstance(models, Model):
         models = [models]
@@ -300,7 +307,7 @@ def eval_f_grad(models, thetas, want_mu=False, want_var=False, budget=0.0):
     status = torch.empty(k, dtype=torch.int32, device="cuda")
     mu = torch.empty(ntot, dtype=torch.float64, device="cuda") if want_mu else None
     var = torch.empty(ntot, dtype=torch.float64, device="cuda") if want_var else None
-    o = _opts(budget)
+    o = _opts(budget, recompute, tile, autotune_cache)
     _check(lib().inla_eval_f_grad(_models_array(models), k, _ptr(th), _ptr(f), _ptr(g), _ptr(mu),
                                   _ptr(var), _ptr(status), C.byref(o), _stream()))
     out = dict(f=f, grad=g, status=status)
@@ -314,24 +321,30 @@ def eval_f_grad(models, thetas, want_mu=False, want_var=False, budget=0.0):
 class InlaObjective(torch.autograd.Function):
     """f(theta) with the exact gradient from the selected-inversion adjoint.
 
-    theta: (k, 4) float64 CUDA tensor; returns f (k,).  The forward pass runs
-    inla_eval_f_grad once and keeps grad f for the backward pass.
+    theta: (k, 4) float64 CUDA tensor; returns f (k,).  When theta requires a
+    gradient the forward pass runs inla_eval_f_grad once and keeps grad f for
+    the backward pass; otherwise it runs inla_eval_f.
     """
 
     @staticmethod
-    def forward(ctx, theta, models):
-        out = eval_f_grad(models, theta.detach().contiguous())
-        ctx.save_for_backward(out["grad"])
+    def forward(ctx, theta, models, opts):
+        th = theta.detach().contiguous()
+        if ctx.needs_input_grad[0]:
+            out = eval_f_grad(models, th, **opts)
+            ctx.save_for_backward(out["grad"])
+        else:
+            out = eval_f(models, th, **opts)
         return out["f"]
 
     @staticmethod
     def backward(ctx, gout):
         (g,) = ctx.saved_tensors
-        return gout[:, None] * g, None
+        return gout[:, None] * g, None, None
 
 
-def objective(theta, models):
-    return InlaObjective.apply(theta, models)
+def objective(theta, models, **opts):
+    """f(theta) as a differentiable function of theta (k x 4); opts as eval_f."""
+    return InlaObjective.apply(theta, models, opts)
 
 
 def release_workspace():

@@ -600,18 +600,14 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   return y;
 }
 
-__device__ inline double rdlane(double v, int l) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-  return __hiloint2double(hi, lo);
-}
-
 // Cholesky + inverse of one 64 x 64 tile held in LDS (A, row-major, ld TLD;
 // rows/cols >= w padded with the identity).  16 x 16 diagonal blocks are
-// factored and inverted by one wave in registers (rows in lanes, pivots and
-// rows broadcast with readlane); the panel solves, trailing updates and the
-// block inverse X = L^{-1} (X_ij = -X_ii sum_m L_im X_mj) run on the matrix
-// cores.  Writes inv(L) (zeros above the diagonal) to Lout and sum log L_jj.
+// factored and inverted by one wave (rows in lanes, columns broadcast through
+// LDS); the panel solves, trailing updates and the block inverse X = L^{-1}
+// (X_ij = -X_ii sum_m L_im X_mj) run on the matrix cores.  Writes inv(L)
+// (zeros above the diagonal) to Lout and sum log L_jj; a pivot that is not
+// positive sets *info to its 1-based row (row_off + local row) if smaller.
+// dlog holds 64 logs followed by a 16-entry column buffer (2 * kTile doubles).
 __device__ void chol_inv_tile(double *A, double *X, double *dlog, int w, double *Lout,
                               long long ldl, double *ldsum, int row_off, int *info) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1020,10 +1016,14 @@ __global__ __launch_bounds__(big_threads<V>(), BigCfg<V>::OCC) void tile_big_ker
     }
 }
 
-// Layout of the big-tile kernel: INLA_BIG_VARIANT=0|1 (default 0).
+// Layout of the big-tile kernel: the engine's choice (the autotuner's, else
+// 0); INLA_BIG_VARIANT=0|1 in the environment overrides it.
+static int g_big_variant = 0;
+void set_big_variant(int v) { g_big_variant = (v == 1) ? 1 : 0; }
 int big_variant() {
   const char *e = getenv("INLA_BIG_VARIANT");
-  return (e && e[0] == '1') ? 1 : 0;
+  if (e && (e[0] == '0' || e[0] == '1')) return e[0] - '0';
+  return g_big_variant;
 }
 
 hipError_t launch_tile_phase(const ItemDev *items_dev, int n_items, int total, int phase,
@@ -1075,7 +1075,9 @@ hipError_t launch_fill_int(int *ptr, long long n, int v, hipStream_t s) {
 }
 
 // log|Q| = 2 sum of the per-tile partial sums of log L_jj, in a fixed tree order.
-__global__ void logdet_finish_kernel(const ItemDev *items, double *logdet_out, int *info_out) {
+// Item i writes logdet_out[i * stride] and info_out[i * stride].
+__global__ void logdet_finish_kernel(const ItemDev *items, double *logdet_out, int *info_out,
+                                     int stride) {
   const ItemDev it = items[blockIdx.x];
   const int cnt = it.nt * it.nP + (it.a > 0 ? 1 : 0);
   __shared__ double red[256];
@@ -1089,16 +1091,16 @@ __global__ void logdet_finish_kernel(const ItemDev *items, double *logdet_out, i
   }
   if (threadIdx.x == 0) {
     const int inf = *it.info;
-    if (info_out) info_out[blockIdx.x] = (inf == kInfoNone) ? 0 : inf;
-    if (logdet_out) logdet_out[blockIdx.x] = (inf == kInfoNone) ? 2.0 * red[0] : NAN;
+    if (info_out) info_out[blockIdx.x * stride] = (inf == kInfoNone) ? 0 : inf;
+    if (logdet_out) logdet_out[blockIdx.x * stride] = (inf == kInfoNone) ? 2.0 * red[0] : NAN;
   }
 }
 
 hipError_t launch_logdet_finish(const ItemDev *items_dev, int n_items, double *logdet_out,
-                                int *info_out, hipStream_t s) {
+                                int *info_out, hipStream_t s, int stride) {
   if (n_items <= 0) return hipSuccess;
   hipLaunchKernelGGL(logdet_finish_kernel, dim3(n_items), dim3(256), 0, s, items_dev, logdet_out,
-                     info_out);
+                     info_out, stride);
   return hipGetLastError();
 }
 

@@ -171,11 +171,14 @@ double phase_flops(const ItemDev &it, int phase, int t, int p) {
   }
 }
 
-// Tile size of the b x b product phases: 128-wide tiles when a launch has
-// enough of them to fill the chip, else 64-wide ones.  INLA_TILE=64|128 forces one.
+// Tile size of the b x b product phases: the caller's or the autotuner's
+// choice (g_tile_pref), else 128-wide tiles when a launch has enough of them
+// to fill the chip and 64-wide ones otherwise.  INLA_TILE=64|128 in the
+// environment overrides both.
+int g_tile_pref = 0;
 bool use_big_tiles(const std::vector<ItemDev> &items) {
   const char *e = getenv("INLA_TILE");
-  const int force = e ? atoi(e) : 0;
+  const int force = e ? atoi(e) : g_tile_pref;
   if (force == 64) return false;
   if (force == 128) return true;
   long long big = 0;
@@ -819,13 +822,16 @@ struct ThetaItemBufs {
   double *x = nullptr, *tmp = nullptr, *term = nullptr;
 };
 
-size_t theta_item_bytes(const ModelDev &h, bool selinv) {
+// Device bytes one (model, theta) item needs: two BTA matrices with their
+// workspaces, or one shared by Q_prior and Q_c when `seq` (the two are then
+// processed one after the other).
+size_t theta_item_bytes(const ModelDev &h, bool selinv, bool seq) {
   const size_t bb = (size_t)h.b * h.b, ab = (size_t)h.a * h.b;
   const int nP = ntile(h.b);
   size_t per = bta_doubles(h.b, h.nt, h.a) * 8 + (2 * bb + ab) * 8 + ((size_t)h.nt * nP + 1) * 8 +
                4 * kAlign * 4;
   if (selinv) per += (2 * bb + 2 * ab + (size_t)h.a * h.a) * 8 + ((size_t)h.nt + 1) * 32;
-  return 2 * per + ((size_t)h.n + std::max(h.b, h.a) + kTermBlocks * 4) * 8 + 4096;
+  return (seq ? 1 : 2) * per + ((size_t)h.n + std::max(h.b, h.a) + kTermBlocks * 4) * 8 + 4096;
 }
 
 // The launch sequence of one batched evaluation, captured once per call
@@ -834,7 +840,8 @@ size_t theta_item_bytes(const ModelDev &h, bool selinv) {
 struct EvalGraph {
   bool valid = false;
   std::vector<const inla_model *> models;
-  bool grad = false, var = false, mu = false, prof = false;
+  bool grad = false, var = false, mu = false, prof = false, seq = false;
+  int tile = 0, variant = 0;
   unsigned long long gen = 0;
   char *base = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -876,46 +883,71 @@ inla_status copy_outputs(const EvalGraph &G, int n, double *f_dev, double *grad_
   return INLA_OK;
 }
 
-inla_status eval_impl(const inla_model *const *models, int32_t n_items, const double *theta_dev,
-                      double *f_dev, double *grad_dev, double *mu_out, double *var_out,
-                      int32_t *status_dev, const inla_opts *opts, hipStream_t s) {
-  if (!models || n_items < 1 || !theta_dev || !f_dev)
-    return fail(INLA_ERR_ARG, "need models, n_items >= 1, theta and f");
-  for (int i = 0; i < n_items; ++i)
-    if (!models[i]) return fail(INLA_ERR_ARG, "NULL model in batch");
-  if (opts && opts->keep_sigma != 0) return fail(INLA_ERR_ARG, "keep_sigma is reserved (must be 0)");
-  ST_TRY(ensure_streams());
+// One batched evaluation with a fixed tile choice.  `seq_mode`: 2 never,
+// 1 always, 0 when the two-matrix layout needs more admission waves than the
+// one-matrix layout.
+inla_status eval_run(const inla_model *const *models, int32_t n_items, const double *theta_dev,
+                     double *f_dev, double *grad_dev, double *mu_out, double *var_out,
+                     int32_t *status_dev, double budget, int seq_mode, bool allow_graph,
+                     hipStream_t s) {
   const bool grad = grad_dev != nullptr;
   const bool need_selinv = grad || var_out != nullptr;
   // HBM admission: split the items into waves whose storage fits the budget
-  double budget = opts ? opts->hbm_budget_bytes : 0.0;
-  if (!(budget > 0.0)) {
-    size_t fr = 0, tot = 0;
-    HIP_TRY(hipMemGetInfo(&fr, &tot));
-    budget = (double)fr + (double)g_arena.cap - 4.0 * (1ULL << 30);
-  }
-  std::vector<size_t> bytes(n_items);
+  auto waves_for = [&](bool seq, std::vector<size_t> &bytes, double &all) -> int {
+    bytes.assign(n_items, 0);
+    all = 0.0;
+    int waves = 0;
+    double acc = budget + 1.0;
+    for (int i = 0; i < n_items; ++i) {
+      bytes[i] = theta_item_bytes(models[i]->host, need_selinv, seq);
+      all += (double)bytes[i];
+      if ((double)bytes[i] > budget) return INT_MAX;
+      if (acc + (double)bytes[i] > budget) {
+        ++waves;
+        acc = 0.0;
+      }
+      acc += (double)bytes[i];
+    }
+    return waves;
+  };
+  std::vector<size_t> bytes;
   double all = 0.0;
-  for (int i = 0; i < n_items; ++i) {
-    bytes[i] = theta_item_bytes(models[i]->host, need_selinv);
-    all += (double)bytes[i];
-    if ((double)bytes[i] > budget)
-      return fail(INLA_ERR_BUDGET, "item " + std::to_string(i) + " needs " +
-                                       std::to_string(bytes[i]) + " bytes, above the HBM budget");
+  bool seq = seq_mode == 1;
+  int waves = waves_for(seq, bytes, all);
+  if (seq_mode == 0) {
+    std::vector<size_t> b1;
+    double a1 = 0.0;
+    const int w1 = waves_for(true, b1, a1);
+    if (w1 < waves) {
+      seq = true;
+      waves = w1;
+      bytes.swap(b1);
+      all = a1;
+    }
+  }
+  if (waves == INT_MAX) {
+    for (int i = 0; i < n_items; ++i)
+      if ((double)bytes[i] > budget || bytes[i] == 0)
+        return fail(INLA_ERR_BUDGET, "item " + std::to_string(i) + " needs " +
+                                         std::to_string(theta_item_bytes(models[i]->host,
+                                                                         need_selinv, seq)) +
+                                         " bytes, above the HBM budget");
   }
   // per-item output offsets into the concatenated mu / var buffers
   std::vector<long long> voff(n_items + 1, 0);
   for (int i = 0; i < n_items; ++i) voff[i + 1] = voff[i] + models[i]->n;
   const long long ntot = voff[n_items];
+  const int tile = g_tile_pref, variant = big_variant();
 
   // replay a captured graph when the call matches it and nothing else has
   // laid out the workspace since
   // (events recorded during capture cannot be timed, so profiling runs eagerly)
-  const bool graphable = graphs_enabled() && !g_prof.on && all <= budget;
+  const bool graphable = allow_graph && graphs_enabled() && !g_prof.on && all <= budget;
   std::vector<const inla_model *> key(models, models + n_items);
   if (graphable && g_graph.valid && g_graph.models == key && g_graph.grad == grad &&
       g_graph.var == (var_out != nullptr) && g_graph.mu == (mu_out != nullptr) &&
-      g_graph.prof == g_prof.on && g_graph.gen == g_arena.gen && g_graph.base == g_arena.base) {
+      g_graph.prof == g_prof.on && g_graph.seq == seq && g_graph.tile == tile &&
+      g_graph.variant == variant && g_graph.gen == g_arena.gen && g_graph.base == g_arena.base) {
     if (g_arena.last && g_arena.last_stream != s) HIP_TRY(hipStreamWaitEvent(s, g_arena.last, 0));
     HIP_TRY(hipMemcpyAsync(g_graph.th, theta_dev, (size_t)n_items * 32, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipGraphLaunch(g_graph.exec, s));
@@ -950,6 +982,12 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
         it.b = h.b; it.nt = h.nt; it.a = h.a; it.nP = ntile(h.b);
         it.which = w;
         it.model = models[start + q]->dev;
+        if (w == 1 && seq) {
+          // Q_c reuses the storage and workspaces of Q_prior (aliased below,
+          // once the arena has placed them); only its trace partials are its own
+          if (grad) L.add(&it.trpart, ((size_t)h.nt + 1) * 4);
+          continue;
+        }
         L.add(&Dbase[2 * q + w], bta_doubles(h.b, h.nt, h.a));
         layout_factor_ws(L, it);
         if (need_selinv) {
@@ -976,6 +1014,15 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
     L.add(&tdev, k);
     L.add(&cdev, k);
     ST_TRY(arena_bind(L, s));
+    if (seq) {
+      for (int q = 0; q < k; ++q) {
+        const ItemDev &pv = tb[q].P;
+        ItemDev &cv = tb[q].C;
+        cv.W1 = pv.W1; cv.W2 = pv.W2; cv.W3 = pv.W3; cv.ldpart = pv.ldpart; cv.info = pv.info;
+        cv.SD = pv.SD; cv.SR = pv.SR; cv.ST = pv.ST;
+        Dbase[2 * q + 1] = Dbase[2 * q];
+      }
+    }
     // where this wave reads theta and writes its outputs
     const double *th = graphable ? G.th : theta_dev + 4 * start;
     double *fo = graphable ? G.f : f_dev + start;
@@ -983,8 +1030,10 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
     int *so = graphable ? G.st : (status_dev ? status_dev + start : nullptr);
     double *muo = graphable ? G.mu_buf : (mu_out ? mu_out + voff[start] : nullptr);
     double *vo = graphable ? G.var_buf : (var_out ? var_out + voff[start] : nullptr);
-    // carve BTA storage and finish descriptors
-    Batch F, Sv, Si;
+    // carve BTA storage and finish descriptors.  Two-matrix layout: one
+    // factor batch over (P_0, C_0, P_1, ...), one selinv batch likewise.
+    // Sequential layout: a P batch and a C batch of each kind.
+    Batch F, Sv, Si, Fc, Sic;
     std::vector<double *> hx(k), ht(k);
     std::vector<TermItem> thv(k);
     std::vector<CombineItem> ch(k);
@@ -1007,11 +1056,18 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
       if (muo) tb[q].x = muo + off;
       hx[q] = tb[q].x;
       ht[q] = tb[q].tmp;
-      F.host.push_back(tb[q].P);
-      F.host.push_back(tb[q].C);
+      if (seq) {
+        F.host.push_back(tb[q].P);
+        Fc.host.push_back(tb[q].C);
+        if (grad) Si.host.push_back(tb[q].P);
+        if (need_selinv) Sic.host.push_back(tb[q].C);
+      } else {
+        F.host.push_back(tb[q].P);
+        F.host.push_back(tb[q].C);
+        if (grad) Si.host.push_back(tb[q].P);
+        if (need_selinv) Si.host.push_back(tb[q].C);
+      }
       Sv.host.push_back(tb[q].C);
-      if (grad) Si.host.push_back(tb[q].P);
-      if (need_selinv) Si.host.push_back(tb[q].C);
       thv[q] = TermItem{models[i]->dev, th + 4 * q, tb[q].x, tb[q].term};
       CombineItem c;
       std::memset(&c, 0, sizeof(c));
@@ -1028,11 +1084,25 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
       c.status = so ? so + q : nullptr;
       ch[q] = c;
     }
+    // every descriptor must point into the arena before anything is launched
+    for (int q = 0; q < k; ++q)
+      for (const ItemDev *it : {&tb[q].P, &tb[q].C}) {
+        const bool ok = it->D && it->W1 && it->W2 && it->W3 && it->ldpart && it->info &&
+                        (!need_selinv || (it->SD && it->SR && it->ST)) &&
+                        (!grad || it->trpart) && tb[q].x && tb[q].tmp && tb[q].term;
+        if (!ok) return fail(INLA_ERR_STATE, "internal: workspace of item " +
+                                                 std::to_string(start + q) + " not placed");
+      }
+    // descriptor arrays: the sequential layout splits fdev / vdev in halves
     F.dev = fdev; Sv.dev = sdev; Si.dev = vdev;
+    Fc.dev = fdev + k; Sic.dev = vdev + k;
     F.finalize(); Sv.finalize(); Si.finalize();
+    if (seq) { Fc.finalize(); Sic.finalize(); }
     ST_TRY(upload(fdev, F.host, s));
+    if (seq) ST_TRY(upload(Fc.dev, Fc.host, s));
     ST_TRY(upload(sdev, Sv.host, s));
-    if (need_selinv) ST_TRY(upload(vdev, Si.host, s));
+    if (need_selinv && !Si.host.empty()) ST_TRY(upload(vdev, Si.host, s));
+    if (seq && need_selinv) ST_TRY(upload(Sic.dev, Sic.host, s));
     ST_TRY(upload(xs, hx, s));
     ST_TRY(upload(tmps, ht, s));
     ST_TRY(upload(tdev, thv, s));
@@ -1044,26 +1114,44 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
       ls = g_cap;
       HIP_TRY(hipStreamBeginCapture(ls, hipStreamCaptureModeThreadLocal));
     }
-    auto body = [&]() -> inla_status {
-      // assemble Q_prior, Q_c and b = tau_y A^T y (into x, solved in place)
+    auto assemble = [&](int w) -> inla_status {
       for (int q = 0; q < k; ++q) {
         const int i = start + q;
         const ModelDev &h = models[i]->host;
-        for (int w = 0; w < 2; ++w) {
-          ItemDev &it = w ? tb[q].C : tb[q].P;
-          {
-            ProfScope ps(PS_ASSEMBLE, 0.0, ls);
-            HIP_TRY(launch_assemble(models[i]->dev, h.b, h.nt, h.a, th + 4 * q, w, it.D, it.S, it.R,
-                                    it.T, w ? tb[q].x : nullptr, ls));
-          }
-          HIP_TRY(launch_fill_int(it.info, 1, kInfoNone, ls));
+        ItemDev &it = w ? tb[q].C : tb[q].P;
+        {
+          ProfScope ps(PS_ASSEMBLE, 0.0, ls);
+          HIP_TRY(launch_assemble(models[i]->dev, h.b, h.nt, h.a, th + 4 * q, w, it.D, it.S, it.R,
+                                  it.T, w ? tb[q].x : nullptr, ls));
         }
+        HIP_TRY(launch_fill_int(it.info, 1, kInfoNone, ls));
       }
-      ST_TRY(run_factor(F, ls));
-      HIP_TRY(launch_logdet_finish(fdev, 2 * k, logdet, info, ls));
-      ST_TRY(run_solve(Sv, xs, tmps, ls));
-      HIP_TRY(launch_terms(tdev, k, ls));
-      if (need_selinv) ST_TRY(run_selinv(Si, true, ls));
+      return INLA_OK;
+    };
+    auto body = [&]() -> inla_status {
+      if (!seq) {
+        // assemble Q_prior, Q_c and b = tau_y A^T y (into x, solved in place)
+        ST_TRY(assemble(0));
+        ST_TRY(assemble(1));
+        ST_TRY(run_factor(F, ls));
+        HIP_TRY(launch_logdet_finish(fdev, 2 * k, logdet, info, ls));
+        ST_TRY(run_solve(Sv, xs, tmps, ls));
+        HIP_TRY(launch_terms(tdev, k, ls));
+        if (need_selinv) ST_TRY(run_selinv(Si, true, ls));
+      } else {
+        // Q_prior first (factor, log-determinant, gradient traces), then Q_c
+        // in the same storage
+        ST_TRY(assemble(0));
+        ST_TRY(run_factor(F, ls));
+        HIP_TRY(launch_logdet_finish(fdev, k, logdet, info, ls, 2));
+        if (grad) ST_TRY(run_selinv(Si, true, ls));
+        ST_TRY(assemble(1));
+        ST_TRY(run_factor(Fc, ls));
+        HIP_TRY(launch_logdet_finish(Fc.dev, k, logdet + 1, info + 1, ls, 2));
+        ST_TRY(run_solve(Sv, xs, tmps, ls));
+        HIP_TRY(launch_terms(tdev, k, ls));
+        if (need_selinv) ST_TRY(run_selinv(Sic, true, ls));
+      }
       HIP_TRY(launch_combine(cdev, k, ls));
       return INLA_OK;
     };
@@ -1087,6 +1175,9 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
       G.var = var_out != nullptr;
       G.mu = mu_out != nullptr;
       G.prof = g_prof.on;
+      G.seq = seq;
+      G.tile = tile;
+      G.variant = variant;
       G.gen = g_arena.gen;
       G.base = g_arena.base;
       G.exec = exec;
@@ -1100,6 +1191,148 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
     start = end;
   }
   return arena_done(s);
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: per call signature, the tile layout of the b x b products is
+// timed once for each candidate and the fastest is kept in memory and in a
+// small JSON file (one entry per line) that later processes read back
+// ---------------------------------------------------------------------------
+struct TileChoice {
+  int tile = 0;      // 64 or 128 (0: built-in rule)
+  int variant = 0;   // layout of the 128-wide kernel
+  double ms = 0.0;
+};
+std::unordered_map<std::string, TileChoice> g_tune;
+std::string g_tune_loaded;
+
+std::string tune_key(const inla_model *const *models, int n, bool grad, bool var) {
+  // the multiset of item shapes, order-free
+  std::vector<std::string> shapes;
+  for (int i = 0; i < n; ++i) {
+    const ModelDev &h = models[i]->host;
+    shapes.push_back(std::to_string(h.b) + "x" + std::to_string(h.nt) + "x" + std::to_string(h.a));
+  }
+  std::sort(shapes.begin(), shapes.end());
+  std::string all;
+  for (auto &x : shapes) all += x + ",";
+  unsigned long long hsh = 1469598103934665603ULL;   // FNV-1a
+  for (unsigned char c : all) hsh = (hsh ^ c) * 1099511628211ULL;
+  char buf[96];
+  snprintf(buf, sizeof(buf), "%s:n%d:%s:%016llx", grad ? "grad" : (var ? "var" : "f"), n,
+           shapes.back().c_str(), hsh);
+  return buf;
+}
+
+void tune_load(const std::string &path) {
+  if (g_tune_loaded == path) return;
+  g_tune_loaded = path;
+  FILE *fp = fopen(path.c_str(), "r");
+  if (!fp) return;
+  char line[512];
+  while (fgets(line, sizeof(line), fp)) {
+    char key[256];
+    TileChoice c;
+    if (sscanf(line, " \"%255[^\"]\": {\"tile\": %d, \"variant\": %d, \"ms\": %lf", key, &c.tile,
+               &c.variant, &c.ms) == 4 &&
+        (c.tile == 64 || c.tile == 128))
+      g_tune[key] = c;
+  }
+  fclose(fp);
+}
+
+void tune_save(const std::string &path) {
+  const std::string tmp = path + ".tmp";
+  FILE *fp = fopen(tmp.c_str(), "w");
+  if (!fp) return;
+  std::vector<std::string> keys;
+  for (auto &kv : g_tune) keys.push_back(kv.first);
+  std::sort(keys.begin(), keys.end());
+  fprintf(fp, "{\n");
+  for (size_t i = 0; i < keys.size(); ++i) {
+    const TileChoice &c = g_tune[keys[i]];
+    fprintf(fp, "  \"%s\": {\"tile\": %d, \"variant\": %d, \"ms\": %.4f}%s\n", keys[i].c_str(),
+            c.tile, c.variant, c.ms, i + 1 < keys.size() ? "," : "");
+  }
+  fprintf(fp, "}\n");
+  fclose(fp);
+  (void)rename(tmp.c_str(), path.c_str());
+}
+
+inla_status eval_impl(const inla_model *const *models, int32_t n_items, const double *theta_dev,
+                      double *f_dev, double *grad_dev, double *mu_out, double *var_out,
+                      int32_t *status_dev, const inla_opts *opts, hipStream_t s) {
+  if (!models || n_items < 1 || !theta_dev || !f_dev)
+    return fail(INLA_ERR_ARG, "need models, n_items >= 1, theta and f");
+  for (int i = 0; i < n_items; ++i)
+    if (!models[i]) return fail(INLA_ERR_ARG, "NULL model in batch");
+  if (opts && opts->keep_sigma != 0) return fail(INLA_ERR_ARG, "keep_sigma is reserved (must be 0)");
+  if (opts && opts->tile != 0 && opts->tile != 64 && opts->tile != 128)
+    return fail(INLA_ERR_ARG, "tile must be 0, 64 or 128");
+  if (opts && (opts->recompute < 0 || opts->recompute > 2))
+    return fail(INLA_ERR_ARG, "recompute must be 0, 1 or 2");
+  ST_TRY(ensure_streams());
+  double budget = opts ? opts->hbm_budget_bytes : 0.0;
+  if (!(budget > 0.0)) {
+    size_t fr = 0, tot = 0;
+    HIP_TRY(hipMemGetInfo(&fr, &tot));
+    budget = (double)fr + (double)g_arena.cap - 4.0 * (1ULL << 30);
+  }
+  const int seq_mode = opts ? opts->recompute : 0;
+  auto run = [&](const TileChoice &c, bool allow_graph) -> inla_status {
+    g_tile_pref = c.tile;
+    set_big_variant(c.variant);
+    const inla_status st = eval_run(models, n_items, theta_dev, f_dev, grad_dev, mu_out, var_out,
+                                    status_dev, budget, seq_mode, allow_graph, s);
+    g_tile_pref = 0;
+    set_big_variant(0);
+    return st;
+  };
+  TileChoice choice;
+  if (opts && opts->tile != 0) {
+    choice.tile = opts->tile;
+  } else if (opts && opts->autotune_cache && opts->autotune_cache[0]) {
+    const std::string path = opts->autotune_cache;
+    tune_load(path);
+    const std::string key = tune_key(models, n_items, grad_dev != nullptr, var_out != nullptr);
+    auto itc = g_tune.find(key);
+    if (itc != g_tune.end()) {
+      choice = itc->second;
+    } else {
+      // time every candidate eagerly (one untimed run, one timed) on the
+      // caller's stream; every run computes the same outputs
+      const TileChoice cands[3] = {{64, 0, 0.0}, {128, 0, 0.0}, {128, 1, 0.0}};
+      hipEvent_t e0, e1;
+      HIP_TRY(hipEventCreate(&e0));
+      HIP_TRY(hipEventCreate(&e1));
+      bool have = false;
+      for (const TileChoice &c0 : cands) {
+        TileChoice c = c0;
+        inla_status st = run(c, false);
+        if (st == INLA_OK) {
+          HIP_TRY(hipEventRecord(e0, s));
+          st = run(c, false);
+          HIP_TRY(hipEventRecord(e1, s));
+        }
+        if (st != INLA_OK) {
+          (void)hipEventDestroy(e0);
+          (void)hipEventDestroy(e1);
+          return st;
+        }
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        c.ms = ms;
+        if (!have || c.ms < choice.ms) choice = c;
+        have = true;
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      g_tune[key] = choice;
+      tune_save(path);
+    }
+  }
+  return run(choice, true);
 }
 
 }  // namespace

@@ -232,3 +232,64 @@ def test_hbm_admission_waves_match_single_wave(P, monkeypatch):
     assert torch.equal(one["f"], waves["f"]) and torch.equal(one["grad"], waves["grad"])
     with pytest.raises(P.InlaError):
         P.eval_f_grad(Ms, th, budget=1.0e3)
+
+
+def test_shared_storage_mode_matches_two_matrix_mode(P):
+    """recompute=1 (Q_prior then Q_c in one storage) gives the same results bitwise."""
+    mds = [make_model(5, 3, 2, 21), make_model(8, 4, 3, 22), make_model(6, 2, 1, 23)]
+    Ms = [P.Model.from_data(m) for m in mds]
+    th = np.array([[0.1, 0.8, 0.5, 2.0], [0.3, 1.1, 1.0, 3.0], [-0.2, 0.6, 0.2, 2.5]])
+    two = P.eval_f_grad(Ms, th, want_mu=True, want_var=True, recompute=2, tile=64)
+    one = P.eval_f_grad(Ms, th, want_mu=True, want_var=True, recompute=1, tile=64)
+    torch.cuda.synchronize()
+    for key in ("f", "grad", "mu", "var", "status"):
+        assert torch.equal(two[key], one[key]), key
+    # any budget, mode and number of admission waves gives the same results
+    ran = 0
+    for budget in (1e5, 2e5, 4e5, 8e5, 1.6e6, 3.2e6, 6.4e6):
+        for mode in (0, 1, 2):
+            try:
+                got = P.eval_f_grad(Ms, th, recompute=mode, tile=64, budget=budget)
+            except P.InlaError:
+                continue
+            torch.cuda.synchronize()
+            assert torch.equal(got["f"], two["f"]) and torch.equal(got["grad"], two["grad"])
+            ran += 1
+    assert ran >= 6
+    for i, md in enumerate(mds):
+        assert rel(one["f"][i].item(), O.eval_f_dense(md, th[i])["f"]) < 1e-10
+
+
+def test_autotune_cache(P, tmp_path):
+    """The autotuner times the tile layouts once, stores the winner, and reuses it."""
+    import json
+    md = config_model("c4small")
+    M = P.Model.from_data(md)
+    path = tmp_path / "tune.json"
+    out = P.eval_f_grad([M, M], np.stack([THETA0, THETA0 + 0.05]), autotune_cache=path)
+    torch.cuda.synchronize()
+    entries = json.loads(path.read_text())
+    assert len(entries) == 1
+    (key, val), = entries.items()
+    assert key.startswith("grad:n2:") and val["tile"] in (64, 128) and val["ms"] > 0
+    again = P.eval_f_grad([M, M], np.stack([THETA0, THETA0 + 0.05]), autotune_cache=path)
+    torch.cuda.synchronize()
+    assert len(json.loads(path.read_text())) == 1
+    assert torch.equal(out["f"], again["f"])
+    assert rel(out["f"][0].item(), O.eval_f_dense(md, THETA0)["f"]) < 1e-10
+
+
+def test_objective_autograd(P):
+    """torch.autograd through the objective gives the adjoint gradient; no-grad runs f only."""
+    md = config_model("c4small")
+    M = P.Model.from_data(md)
+    th = torch.tensor(np.stack([THETA0, THETA0 + 0.1]), dtype=torch.float64, device="cuda",
+                      requires_grad=True)
+    f = P.objective(th, [M, M])
+    (2.0 * f[0] + 3.0 * f[1]).backward()
+    g = P.eval_f_grad([M, M], th.detach())["grad"]
+    assert torch.allclose(th.grad[0], 2.0 * g[0], rtol=1e-14, atol=0)
+    assert torch.allclose(th.grad[1], 3.0 * g[1], rtol=1e-14, atol=0)
+    with torch.no_grad():
+        f2 = P.objective(th, [M, M])
+    assert torch.equal(f2, f.detach())
