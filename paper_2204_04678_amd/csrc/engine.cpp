@@ -830,7 +830,7 @@ size_t theta_item_bytes(const ModelDev &h, bool selinv, bool seq) {
   const int nP = ntile(h.b);
   size_t per = bta_doubles(h.b, h.nt, h.a) * 8 + (2 * bb + ab) * 8 + ((size_t)h.nt * nP + 1) * 8 +
                4 * kAlign * 4;
-  if (selinv) per += (2 * bb + 2 * ab + (size_t)h.a * h.a) * 8 + ((size_t)h.nt + 1) * 32;
+  if (selinv) per += (2 * bb + 2 * ab + (size_t)h.a * h.a) * 8 + ((size_t)h.nt + 1) * kTraceBlocks * 32;
   return (seq ? 1 : 2) * per + ((size_t)h.n + std::max(h.b, h.a) + kTermBlocks * 4) * 8 + 4096;
 }
 
@@ -985,14 +985,14 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
         if (w == 1 && seq) {
           // Q_c reuses the storage and workspaces of Q_prior (aliased below,
           // once the arena has placed them); only its trace partials are its own
-          if (grad) L.add(&it.trpart, ((size_t)h.nt + 1) * 4);
+          if (grad) L.add(&it.trpart, ((size_t)h.nt + 1) * kTraceBlocks * 4);
           continue;
         }
         L.add(&Dbase[2 * q + w], bta_doubles(h.b, h.nt, h.a));
         layout_factor_ws(L, it);
         if (need_selinv) {
           layout_selinv_ws(L, it);
-          if (grad) L.add(&it.trpart, ((size_t)h.nt + 1) * 4);
+          if (grad) L.add(&it.trpart, ((size_t)h.nt + 1) * kTraceBlocks * 4);
         }
       }
       if (!mu_out && !graphable) L.add(&tb[q].x, (size_t)h.n);

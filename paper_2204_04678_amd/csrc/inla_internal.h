@@ -53,7 +53,7 @@ struct ItemDev {
   int *info;                     // first failing pivot (1-based row); kInfoNone = none
   // outputs of the selected inversion
   double *diag;                  // n marginal variances (or null)
-  double *trpart;                // (nt + 1) * 4 partial traces (or null)
+  double *trpart;                // (nt + 1) * kTraceBlocks * 4 partial traces (or null)
   const ModelDev *model;         // model whose derivative blocks the traces use (or null)
   const double *theta;           // 4 hyperparameters of this item (device)
   int which;                     // 0: Q_prior, 1: Q_c
@@ -91,6 +91,7 @@ enum Phase : int {
   PH_COUNT = 15
 };
 
+constexpr int kTraceBlocks = 16;   // workgroups per item in a trace reduction step
 constexpr int kBig = 128;        // edge of a big tile
 __host__ __device__ inline int nbig(int n) { return (n + kBig - 1) / kBig; }
 __host__ __device__ inline bool phase_is_product_x(int phase) {
@@ -201,8 +202,8 @@ struct CombineItem {
   const double *term_part;   // kTermBlocks * 4
   const double *mu;          // n (posterior mode)
   const double *logdet;      // [0] = log|Q_p|, [1] = log|Q_c|
-  const double *trp;         // (nt + 1) * 4 partial traces of Q_p (or null)
-  const double *trc;         // (nt + 1) * 4 partial traces of Q_c (or null)
+  const double *trp;         // (nt + 1) * kTraceBlocks * 4 partial traces of Q_p (or null)
+  const double *trc;         // (nt + 1) * kTraceBlocks * 4 partial traces of Q_c (or null)
   const int *info;           // [0] Q_p, [1] Q_c
   double *f;                 // 1
   double *grad;              // 4 (or null)

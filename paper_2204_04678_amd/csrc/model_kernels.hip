@@ -170,20 +170,25 @@ __global__ void solve_stage_kernel(const ItemDev *__restrict__ items, int t, int
   switch (stage) {
     case SV_F1:
     case SV_F2: {
+      // 8 rows per workgroup, 32 column lanes per row (columns cl, cl + 32, ...);
+      // the 32 partial sums of a row are added in a fixed order
       if (t >= nt) return;
-      const int r = blockIdx.x * 64 + lane;
+      const int rr = tid & 7, cl = tid >> 3;
+      const int r = blockIdx.x * 8 + rr;
       const double *M = (stage == SV_F1) ? (t > 0 ? it.S + (long long)(t - 1) * bb : nullptr)
                                          : it.D + (long long)t * bb;
       const double *v = (stage == SV_F1) ? x + (long long)(t - 1) * b : tmp;
-      const int jend = (stage == SV_F1) ? b : min(b, blockIdx.x * 64 + 64);
+      const int jend = (stage == SV_F1) ? b : min(b, blockIdx.x * 8 + 8);
       double acc = 0.0;
       if (M && r < b) {
-        for (int j = w; j < jend; j += 4) acc += M[r + (long long)j * b] * v[j];
+        for (int j = cl; j < jend; j += 32) acc = fma(M[r + (long long)j * b], v[j], acc);
       }
-      red[w][lane] = acc;
+      double *red8 = &red[0][0];   // [32][8]
+      red8[cl * 8 + rr] = acc;
       __syncthreads();
-      if (w == 0 && r < b) {
-        const double sum = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+      if (cl == 0 && r < b) {
+        double sum = 0.0;
+        for (int c = 0; c < 32; ++c) sum += red8[c * 8 + rr];
         if (stage == SV_F1) tmp[r] = x[(long long)t * b + r] - sum;
         else x[(long long)t * b + r] = sum;
       }
@@ -264,7 +269,7 @@ hipError_t launch_solve_stage(const ItemDev *items_dev, int n_items, int max_b, 
                               hipStream_t s) {
   int gx = 1;
   switch (stage) {
-    case SV_F1: case SV_F2: gx = (max_b + 63) / 64; break;
+    case SV_F1: case SV_F2: gx = (max_b + 7) / 8; break;
     case SV_B1: case SV_B2: gx = (max_b + 3) / 4; break;
     case SV_FA1: gx = max_a; break;
     default: gx = 1;
@@ -279,34 +284,39 @@ hipError_t launch_solve_stage(const ItemDev *items_dev, int n_items, int max_b, 
 // traces tr(Sigma dQ/dtheta_k) over the BTA pattern, and marginal variances
 // ---------------------------------------------------------------------------
 
+// Per step t (t = -1: the arrow block) and item, kTraceBlocks workgroups each
+// reduce a strided share of the pattern entries; workgroup k writes its four
+// partial traces to trpart[(step * kTraceBlocks + k) * 4 ..] with step = t
+// (t >= 0) or nt (arrow), and the combination adds them in a fixed order.
 __global__ __launch_bounds__(256) void trace_step_kernel(const ItemDev *__restrict__ items, int t) {
-  const ItemDev it = items[blockIdx.x];
+  const ItemDev it = items[blockIdx.y];
   if (!it.trpart && !it.diag) return;
   const int b = it.b, a = it.a, nt = it.nt;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, blk = blockIdx.x;
+  const int g0 = blk * 256 + tid, gs = kTraceBlocks * 256;
   __shared__ double red[4 * 256];
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   if (t < 0) {
     // arrow block: Sigma_T
     if (a > 0) {
-      if (it.diag && tid < a) it.diag[(long long)nt * b + tid] = it.ST[tid + (long long)tid * a];
+      if (it.diag && blk == 0 && tid < a) it.diag[(long long)nt * b + tid] = it.ST[tid + (long long)tid * a];
       if (it.trpart && it.which == 1 && it.model) {
         const double tauy = exp(it.theta[3]);
-        for (int k = tid; k < a * a; k += 256) v[3] += tauy * it.model->ZtZ[k] * it.ST[k];
+        for (int k = g0; k < a * a; k += gs) v[3] += tauy * it.model->ZtZ[k] * it.ST[k];
       }
     }
     if (!it.trpart) return;
     block_reduce<256>(v, red);
     if (tid == 0) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) it.trpart[(long long)nt * 4 + k] = red[k * 256];
+      for (int k = 0; k < 4; ++k) it.trpart[((long long)nt * kTraceBlocks + blk) * 4 + k] = red[k * 256];
     }
     return;
   }
   if (t >= nt) return;
   const double *SD = sig_D(it, t);
   if (it.diag) {
-    for (int s = tid; s < b; s += 256) it.diag[(long long)t * b + s] = SD[s + (long long)s * b];
+    for (int s = g0; s < b; s += gs) it.diag[(long long)t * b + s] = SD[s + (long long)s * b];
   }
   if (!it.trpart) return;
   const ModelDev &M = *it.model;
@@ -315,7 +325,7 @@ __global__ __launch_bounds__(256) void trace_step_kernel(const ItemDev *__restri
   const double dcD = ar1_ddiag(c, t, nt), dcS = ar1_doff(c);
   const bool hasS = t < nt - 1;
   const double *SS = hasS ? sig_S(it, t) : nullptr;
-  for (int e = tid; e < M.nnz; e += 256) {
+  for (int e = g0; e < M.nnz; e += gs) {
     const int i = M.rowidx[e], s = M.colidx[e];
     const double q = qs_entry(M, c, e), dq = dqs_entry(M, c, e);
     const double sd = SD[i + (long long)s * b];
@@ -333,18 +343,18 @@ __global__ __launch_bounds__(256) void trace_step_kernel(const ItemDev *__restri
   if (it.which == 1 && a > 0) {
     const double *SR = sig_R(it, t);
     const double *Z = M.ZtA + (long long)t * a * b;
-    for (int k = tid; k < a * b; k += 256) v[3] += 2.0 * c.tauy * Z[k] * SR[k];
+    for (int k = g0; k < a * b; k += gs) v[3] += 2.0 * c.tauy * Z[k] * SR[k];
   }
   block_reduce<256>(v, red);
   if (tid == 0) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) it.trpart[(long long)t * 4 + k] = red[k * 256];
+    for (int k = 0; k < 4; ++k) it.trpart[((long long)t * kTraceBlocks + blk) * 4 + k] = red[k * 256];
   }
 }
 
 hipError_t launch_trace_step(const ItemDev *items_dev, int n_items, int t, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(trace_step_kernel, dim3(n_items), dim3(256), 0, s, items_dev, t);
+  hipLaunchKernelGGL(trace_step_kernel, dim3(kTraceBlocks, n_items), dim3(256), 0, s, items_dev, t);
   return hipGetLastError();
 }
 
@@ -420,7 +430,7 @@ __global__ __launch_bounds__(256) void combine_kernel(const CombineItem *__restr
   const double q0 = red[0], q1 = red[256], q2 = red[512], rss = red[768];
   __syncthreads();
   double tp[4] = {0.0, 0.0, 0.0, 0.0}, tc[4] = {0.0, 0.0, 0.0, 0.0};
-  const int ntr = M.nt + 1;
+  const int ntr = (M.nt + 1) * kTraceBlocks;
   if (ci.trp) {
     for (int k = tid; k < ntr; k += 256) {
 #pragma unroll
