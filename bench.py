@@ -42,6 +42,32 @@ def flops_selinv(b, nt, a):
     return nt * (2.0 / 3.0) * b ** 3 + (nt - 1) * 4 * b ** 3 + nt * (4 * a * b * b + 2 * a * a * b)
 
 
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("bta_kernels.hip", "model_kernels.hip", "inla_internal.h"):
+        with open(os.path.join(ROOT, "paper_2204_04678_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def hbm_traffic(config, kernel):
+    """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter
+    summary of this workload (FETCH_SIZE and WRITE_SIZE, scaled by what they
+    read for a plain 1 GiB copy); None when there is none or the kernel
+    sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{config}_f_grad.txt")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = [json.loads(line[5:]) for line in fh if line.startswith("JSON ")]
+    if not rec or rec[0]["source_sha256"] != kernel_sources_sha256():
+        return None
+    ks = rec[0]["kernels"]
+    k = ks.get(kernel) or next((v for n, v in ks.items() if n.startswith(kernel + "<")), None)
+    return None if k is None else k["hbm_bytes_per_dispatch"]
+
+
 def cpu_baseline(md, theta, budget_s=20.0):
     """Oracle f(theta) on the host; the oracle's gradient is 2d+1 = 9 f evaluations."""
     import numpy as np
@@ -165,7 +191,9 @@ def main():
     achieved = pk["flops"] / (pk["ms"] * 1e-3) / 1e12 if pk["ms"] > 0 else 0.0
     roofline = {"bound": "mfma", "kernel": dom,
                 "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                "traffic": hbm_traffic(args.config, "inla::" + dom),
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
                 "launches_per_step": pk["launches"] / calls,
                 "avg_launch_us": round(pk["ms"] * 1e3 / max(pk["launches"], 1), 3),
                 "alg_flops_per_launch": pk["flops"] / max(pk["launches"], 1),
@@ -228,7 +256,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded grid model; no dataset)",
         "config": {"workload": workload, "b": b, "nt": nt, "a": a, "n": md.n, "items": n_items},
-        "pct_fp64_peak_whole_step": round(100 * F_alg * value / (PEAK_FP64_TFLOPS * 1e12), 3),
+        "pct_fp64_peak_whole_step": round(100 * F_alg / step_s / (PEAK_FP64_TFLOPS * 1e12), 3),
         "alg_flops_per_step": F_alg,
         "f": f_val,
         "grad": grad,
