@@ -43,7 +43,10 @@ struct Seg {
   double alpha;
 };
 
-enum TaskKind { TK_NONE = 0, TK_PRODUCT = 1, TK_COPY = 2, TK_ZERO = 3 };
+// TK_CHAIN: C = beta C - (A0 B0) A1^T with the 64-column intermediate A0 B0
+// kept in LDS (seg[0] = the first product, seg[1].A = A1).
+// TK_LCHAIN: C = -A1 (A0 B0), A1 a lower-triangular diagonal tile (seg[1].A).
+enum TaskKind { TK_NONE = 0, TK_PRODUCT = 1, TK_COPY = 2, TK_ZERO = 3, TK_CHAIN = 4, TK_LCHAIN = 5 };
 
 struct Task {
   int kind;
@@ -61,6 +64,7 @@ struct Task {
   long long ldl;
   double *ldsum;
   int row_off;
+  double *Mout;                   // Cholesky tasks: also M = inv(L)^T inv(L) here (or null)
   const double *src;              // copy source (ld = ldc)
 };
 
@@ -96,6 +100,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
   const bool arrow = a > 0;
   const bool last = (t == it.nt - 1);
   tk.kind = TK_PRODUCT; tk.nseg = 0; tk.beta = 0.0; tk.mirror = 0; tk.diagtile = 0; tk.chol = 0;
+  tk.Mout = nullptr;
   tk.Cm = nullptr; tk.Lout = nullptr; tk.ldsum = nullptr; tk.src = nullptr; tk.ldl = 0;
   tk.row_off = 0;
   double *Dt = it.D + (long long)t * bb;
@@ -107,56 +112,50 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       tk.C = Dt; tk.ldc = b; tk.beta = 1.0;
       tk.chol = 1; tk.Lout = it.W1; tk.ldl = b;
       tk.ldsum = it.ldpart + (long long)t * nP; tk.row_off = t * b;
+      tk.Mout = it.Mp;
       return;
     }
-    case PH_PANEL: {
-      const int i = p + 1 + q;
-      tk.m = tdim(b, i); tk.n = tdim(b, p);
-      tk.C = Dt + toff(b, i, p); tk.ldc = b;
-      set_seg(tk.seg[0], Dt + toff(b, i, p), 1, b, it.W1 + toff(b, p, p), 1, b, 0, tdim(b, p), 1.0);
-      tk.nseg = 1;
-      return;
-    }
-    case PH_TRAIL: {
+    case PH_STEP: {
+      // panel and trailing tasks exist for p < nP - 1, where tile p is full
+      const int npan = nP - 1 - p;
+      const int ntrail = npan * (npan + 1) / 2;
+      if (q >= npan + ntrail) {
+        // row p of X = inv(L_tt): X_pj = -X_pp sum_{m=j}^{p-1} L_pm X_mj, j < p
+        // (L from W2; X rows m < p, and X_pp, from earlier steps in W1)
+        const int j = q - npan - ntrail;
+        tk.kind = TK_LCHAIN;
+        tk.m = tdim(b, p); tk.n = kTile;
+        tk.C = it.W1 + toff(b, p, j); tk.ldc = b;
+        set_seg(tk.seg[0], it.W2 + (long long)p * kTile, 1, b, it.W1 + (long long)j * kTile * b, b,
+                1, j * kTile, p * kTile, 1.0);
+        set_seg(tk.seg[1], it.W1 + toff(b, p, p), 1, b, nullptr, 0, 0, 0, tdim(b, p), -1.0);
+        tk.nseg = 1;
+        return;
+      }
+      if (q < npan) {   // panel: W2(i,p) = A_ip inv(L_pp)^T
+        const int i = p + 1 + q;
+        tk.m = tdim(b, i); tk.n = kTile;
+        tk.C = it.W2 + toff(b, i, p); tk.ldc = b;
+        set_seg(tk.seg[0], Dt + toff(b, i, p), 1, b, it.W1 + toff(b, p, p), 1, b, 0, kTile, 1.0);
+        tk.nseg = 1;
+        return;
+      }
+      // trailing: A_ij -= (A_ip M_p) A_jp^T, M_p = inv(L_pp)^T inv(L_pp) = inv(A_pp)
       int ii, jj;
-      tri_decode(q, ii, jj);
+      tri_decode(q - npan, ii, jj);
       const int i = p + 1 + ii, j = p + 1 + jj;
+      tk.kind = TK_CHAIN;
       tk.m = tdim(b, i); tk.n = tdim(b, j);
       tk.C = Dt + toff(b, i, j); tk.ldc = b; tk.beta = 1.0;
-      set_seg(tk.seg[0], Dt + toff(b, i, p), 1, b, Dt + toff(b, j, p), 1, b, 0, tdim(b, p), -1.0);
+      set_seg(tk.seg[0], Dt + toff(b, i, p), 1, b, it.Mp + (long long)(p & 1) * kTile * kTile, kTile,
+              1, 0, kTile, 1.0);
+      set_seg(tk.seg[1], Dt + toff(b, j, p), 1, b, nullptr, 0, 0, 0, kTile, -1.0);
       tk.nseg = 1;
       if (i == p + 1 && j == p + 1) {
         tk.chol = 1; tk.Lout = it.W1 + toff(b, i, i); tk.ldl = b;
         tk.ldsum = it.ldpart + (long long)t * nP + i; tk.row_off = t * b + i * kTile;
+        tk.Mout = it.Mp + (long long)((p + 1) & 1) * kTile * kTile;
       }
-      return;
-    }
-    case PH_TRTRI: {
-      const int level = p >> 1, stage = p & 1;
-      const int s = 1 << (level - 1);
-      int idx = q, i = 0, j = 0, v0 = 0, uend = 0;
-      for (int u0 = 0; u0 + s < nP; u0 += 2 * s) {
-        const int vs = min(s, nP - (u0 + s));
-        if (idx < s * vs) {
-          i = u0 + s + idx / s;
-          j = u0 + idx % s;
-          v0 = u0 + s;
-          uend = u0 + s;
-          break;
-        }
-        idx -= s * vs;
-      }
-      tk.m = tdim(b, i); tk.n = tdim(b, j);
-      if (stage == 0) {   // T = L_VU X_UU
-        tk.C = it.W2 + toff(b, i, j); tk.ldc = b;
-        set_seg(tk.seg[0], Dt + (long long)i * kTile, 1, b, it.W1 + (long long)j * kTile * b, b, 1,
-                j * kTile, uend * kTile, 1.0);
-      } else {            // X_VU = -X_VV T
-        tk.C = it.W1 + toff(b, i, j); tk.ldc = b;
-        set_seg(tk.seg[0], it.W1 + (long long)i * kTile, 1, b, it.W2 + (long long)j * kTile * b, b,
-                1, v0 * kTile, min(b, (i + 1) * kTile), -1.0);
-      }
-      tk.nseg = 1;
       return;
     }
     case PH_OFFDIAG_X: {
@@ -340,6 +339,7 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
   const bool arrow = a > 0;
   const bool last = (t == it.nt - 1);
   tk.kind = TK_PRODUCT; tk.nseg = 0; tk.beta = 0.0; tk.mirror = 0; tk.diagtile = 0; tk.chol = 0;
+  tk.Mout = nullptr;
   tk.Cm = nullptr; tk.Lout = nullptr; tk.ldsum = nullptr; tk.src = nullptr; tk.ldl = 0;
   tk.row_off = 0;
   double *Dt = it.D + (long long)t * bb;
@@ -608,8 +608,9 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 // (zeros above the diagonal) to Lout and sum log L_jj; a pivot that is not
 // positive sets *info to its 1-based row (row_off + local row) if smaller.
 // dlog holds 64 logs followed by a 16-entry column buffer (2 * kTile doubles).
+// If Mout is set, M = X^T X = inv(A) (64 x 64, column-major) is written there too.
 __device__ void chol_inv_tile(double *A, double *X, double *dlog, int w, double *Lout,
-                              long long ldl, double *ldsum, int row_off, int *info) {
+                              long long ldl, double *ldsum, int row_off, int *info, double *Mout) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nb = (w + 15) / 16;
   const int lr = lane & 15, lk = lane >> 4;
@@ -780,6 +781,142 @@ __device__ void chol_inv_tile(double *A, double *X, double *dlog, int w, double 
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     if (lane == 0) *ldsum = v;
   }
+  if (Mout) {
+    // M_rc = sum_k X_kr X_kc; wave (wr, wc) computes the 32 x 32 block (wr, wc).
+    // Only the lower triangle of X in LDS is defined: entries above it are read as 0.
+    const int wr = wv >> 1, wc = wv & 1;
+    d4 mac[2][2];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int nj = 0; nj < 2; ++nj) mac[mi][nj] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int kk = 0; kk < kTile; kk += 4) {
+      const int kq = kk + lk;
+      double av[2], bv[2];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi) {
+        const int r = wr * 32 + mi * 16 + lr;
+        const double v = X[kq * TLD + r];
+        av[mi] = (kq >= r) ? v : 0.0;
+      }
+#pragma unroll
+      for (int nj = 0; nj < 2; ++nj) {
+        const int c = wc * 32 + nj * 16 + lr;
+        const double v = X[kq * TLD + c];
+        bv[nj] = (kq >= c) ? v : 0.0;
+      }
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int nj = 0; nj < 2; ++nj)
+          mac[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mi], bv[nj], mac[mi][nj], 0, 0, 0);
+    }
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          gst(Mout + (wr * 32 + mi * 16 + lk + 4 * r) + (long long)(wc * 32 + nj * 16 + lr) * kTile,
+              mac[mi][nj][r]);
+  }
+}
+
+// TK_LCHAIN on a 64 x 64 tile: acc = -A1 (A0 B0), A1 (tk.m x tk.m, lower, from
+// global memory) multiplying the intermediate T = A0 B0 (tk.m x 64) from the left.
+template <int KC>
+__device__ __forceinline__ void left_chain_product(const Task &tk, double *smem, d4 (&acc)[2][2]) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  Task t1 = tk;
+  t1.nseg = 1;
+  run_product<KC, kTile, 2, 2, 2>(t1, smem, acc);   // rows >= tk.m come out zero
+  double *TA = smem, *TB = smem + kTile * TLD;
+  // T[k][c] -> TB[c][k]
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        TB[acc_col(wc, nj, lane) * TLD + acc_row(wr, mi, lane, r)] = acc[mi][nj][r];
+  const double *A1 = tk.seg[1].A;
+  const long long aks = tk.seg[1].aks;
+  const int w1 = tk.m;
+#pragma unroll
+  for (int q = 0; q < kTile * kTile / kThreads; ++q) {
+    const int e = tid + q * kThreads;
+    const int r = e & (kTile - 1), k = e / kTile;
+    const double v = gld(A1 + min(r, w1 - 1) + (long long)min(k, w1 - 1) * aks);
+    TA[r * TLD + k] = (r < w1 && k < w1) ? v : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int nj = 0; nj < 2; ++nj) acc[mi][nj] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int kk = 0; kk < kTile; kk += 4) {
+    const int kq = kk + (lane >> 4);
+    double av[2], bv[2];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi) av[mi] = TA[(wr * 32 + mi * 16 + (lane & 15)) * TLD + kq];
+#pragma unroll
+    for (int nj = 0; nj < 2; ++nj) bv[nj] = TB[(wc * 32 + nj * 16 + (lane & 15)) * TLD + kq];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int nj = 0; nj < 2; ++nj)
+        acc[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[mi], bv[nj], acc[mi][nj], 0, 0, 0);
+  }
+  __syncthreads();
+}
+
+// TK_CHAIN on a 64 x 64 tile: acc = -(A0 B0) A1^T.  The intermediate T = A0 B0
+// (tk.m x 64, k = 64) comes from the regular product loop; it and A1 are then
+// staged in LDS (row-major, ld TLD) for the second product (k = 64).
+template <int KC>
+__device__ __forceinline__ void chain_product(const Task &tk, double *smem, d4 (&acc)[2][2]) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  Task t1 = tk;
+  t1.n = kTile;
+  t1.nseg = 1;
+  run_product<KC, kTile, 2, 2, 2>(t1, smem, acc);   // ends with a barrier
+  double *TA = smem, *TB = smem + kTile * TLD;
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        TA[acc_row(wr, mi, lane, r) * TLD + acc_col(wc, nj, lane)] = acc[mi][nj][r];
+  const double *A1 = tk.seg[1].A;
+  const long long aks = tk.seg[1].aks;
+#pragma unroll
+  for (int q = 0; q < kTile * kTile / kThreads; ++q) {
+    const int e = tid + q * kThreads;
+    const int c = e & (kTile - 1), k = e / kTile;
+    TB[c * TLD + k] = gld(A1 + min(c, tk.n - 1) + (long long)k * aks);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int nj = 0; nj < 2; ++nj) acc[mi][nj] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int kk = 0; kk < kTile; kk += 4) {
+    const int kq = kk + (lane >> 4);
+    double av[2], bv[2];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi) av[mi] = TA[(wr * 32 + mi * 16 + (lane & 15)) * TLD + kq];
+#pragma unroll
+    for (int nj = 0; nj < 2; ++nj) bv[nj] = TB[(wc * 32 + nj * 16 + (lane & 15)) * TLD + kq];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int nj = 0; nj < 2; ++nj)
+        acc[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[mi], bv[nj], acc[mi][nj], 0, 0, 0);
+  }
+  __syncthreads();
 }
 
 // Owner of workgroup task q in a launch over n_items items whose task counts
@@ -862,7 +999,13 @@ __global__ __launch_bounds__(kThreads) void tile_phase_kernel(const ItemDev *__r
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
     for (int nj = 0; nj < 2; ++nj) acc[mi][nj] = d4{0.0, 0.0, 0.0, 0.0};
-  run_product<FAT ? kFatKC : kLeanKC, kTile, 2, 2, 2>(tk, smem, acc);
+  if constexpr (FAT) {
+    if (tk.kind == TK_CHAIN) chain_product<kFatKC>(tk, smem, acc);
+    else if (tk.kind == TK_LCHAIN) left_chain_product<kFatKC>(tk, smem, acc);
+    else run_product<kFatKC, kTile, 2, 2, 2>(tk, smem, acc);
+  } else {
+    run_product<kLeanKC, kTile, 2, 2, 2>(tk, smem, acc);
+  }
 
   if constexpr (FAT) {
     if (tk.chol) {
@@ -892,7 +1035,7 @@ __global__ __launch_bounds__(kThreads) void tile_phase_kernel(const ItemDev *__r
             A[row * TLD + col] = (row < tk.m && col < tk.n) ? v : pad;
           }
       __syncthreads();
-      chol_inv_tile(A, X, dlog, tk.m, tk.Lout, tk.ldl, tk.ldsum, tk.row_off, it.info);
+      chol_inv_tile(A, X, dlog, tk.m, tk.Lout, tk.ldl, tk.ldsum, tk.row_off, it.info, tk.Mout);
       return;
     }
   }

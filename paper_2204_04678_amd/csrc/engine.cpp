@@ -3,9 +3,11 @@
 // The engine turns each ABI call into a fixed sequence of batched kernel
 // launches on the caller's stream:
 //   factor   (per time step t, all items in lockstep)
-//       DIAG0, then for each 64-wide panel p: PANEL(p), TRAIL(p); then
-//       OFFDIAG (X = S[t] inv(L_tt)^T, R' = R[t] inv(L_tt)^T) and SCHUR
-//       (D[t+1] -= X X^T, R[t+1] -= R' X^T, T -= R' R'^T); finally ARROW.
+//       DIAG0, then for each 64-wide tile p one STEP(p) launch (panel p of L,
+//       the trailing update, the Cholesky + inverse of tile p+1, and row p of
+//       inv(L_tt)); then OFFDIAG (X = S[t] inv(L_tt)^T, R' = R[t] inv(L_tt)^T)
+//       and SCHUR (D[t+1] -= X X^T, R[t+1] -= R' X^T, T -= R' R'^T); finally
+//       ARROW.
 //   selected inversion (t = nt-1 .. 0), the block form of the Takahashi
 //   recursion (paper, Sec. "Partial Inversion"), derived from Sigma L = L^{-T}
 //   read block column by block column:
@@ -154,8 +156,7 @@ double phase_flops(const ItemDev &it, int phase, int t, int p) {
   const double b = it.b, a = it.a, b3 = b * b * b;
   const bool last = (t == it.nt - 1);
   switch (phase) {
-    case PH_DIAG0: return b3 / 3.0;                  // POTRF of the block, all panels
-    case PH_TRTRI: return (p & 1) ? 0.0 : b3 / (3.0 * trtri_levels(it.nP));  // TRTRI, spread
+    case PH_DIAG0: return 2.0 * b3 / 3.0;            // POTRF and TRTRI of the block, all steps
     case PH_OFFDIAG_X: return last ? 0.0 : b3;
     case PH_OFFDIAG: return a * b * b;
     case PH_SCHUR_X: return last ? 0.0 : b3;
@@ -310,14 +311,7 @@ inla_status run_factor(const Batch &B, hipStream_t s) {
     int mp = 0;
     for (const auto &it : B.host)
       if (t < it.nt) mp = std::max(mp, it.nP);
-    for (int p = 0; p + 1 < mp; ++p) {
-      ST_TRY(run_phase(B, PH_PANEL, t, p, s));
-      ST_TRY(run_phase(B, PH_TRAIL, t, p, s));
-    }
-    for (int level = 1; level <= trtri_levels(mp); ++level) {
-      ST_TRY(run_phase(B, PH_TRTRI, t, 2 * level, s));
-      ST_TRY(run_phase(B, PH_TRTRI, t, 2 * level + 1, s));
-    }
+    for (int p = 0; p < mp; ++p) ST_TRY(run_phase(B, PH_STEP, t, p, s));
     ST_TRY(run_pair(B, PH_OFFDIAG_X, PH_OFFDIAG, t, s));
     ST_TRY(run_pair(B, PH_SCHUR_X, PH_SCHUR, t, s));
   }
@@ -396,6 +390,7 @@ void layout_factor_ws(Layout &L, ItemDev &it) {
   L.add(&it.W1, bb);
   L.add(&it.W2, bb);
   L.add(&it.W3, std::max<size_t>((size_t)it.a * it.b, 1));
+  L.add(&it.Mp, 2 * (size_t)kTile * kTile);
   L.add(&it.ldpart, (size_t)it.nt * it.nP + 1);
   L.add(&it.info, 1);
 }
@@ -792,6 +787,7 @@ inla_status inla_selinv(const inla_bta *L_, inla_bta *sigma_or_null, double *dia
   const size_t bb = (size_t)it.b * it.b;
   L.add(&it.W2, bb);
   L.add(&it.W3, std::max<size_t>((size_t)it.a * it.b, 1));
+  L.add(&it.Mp, 2 * (size_t)kTile * kTile);
   if (sigma_or_null) {
     it.SD = sigma_or_null->D; it.sd_stride = (long long)bb;
     it.SS = sigma_or_null->S; it.ss_stride = (long long)bb;
@@ -828,8 +824,8 @@ struct ThetaItemBufs {
 size_t theta_item_bytes(const ModelDev &h, bool selinv, bool seq) {
   const size_t bb = (size_t)h.b * h.b, ab = (size_t)h.a * h.b;
   const int nP = ntile(h.b);
-  size_t per = bta_doubles(h.b, h.nt, h.a) * 8 + (2 * bb + ab) * 8 + ((size_t)h.nt * nP + 1) * 8 +
-               4 * kAlign * 4;
+  size_t per = bta_doubles(h.b, h.nt, h.a) * 8 + (2 * bb + ab + 2 * kTile * kTile) * 8 +
+               ((size_t)h.nt * nP + 1) * 8 + 5 * kAlign * 4;
   if (selinv) per += (2 * bb + 2 * ab + (size_t)h.a * h.a) * 8 + ((size_t)h.nt + 1) * kTraceBlocks * 32;
   return (seq ? 1 : 2) * per + ((size_t)h.n + std::max(h.b, h.a) + kTermBlocks * 4) * 8 + 4096;
 }
@@ -1018,7 +1014,8 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
       for (int q = 0; q < k; ++q) {
         const ItemDev &pv = tb[q].P;
         ItemDev &cv = tb[q].C;
-        cv.W1 = pv.W1; cv.W2 = pv.W2; cv.W3 = pv.W3; cv.ldpart = pv.ldpart; cv.info = pv.info;
+        cv.W1 = pv.W1; cv.W2 = pv.W2; cv.W3 = pv.W3; cv.Mp = pv.Mp;
+        cv.ldpart = pv.ldpart; cv.info = pv.info;
         cv.SD = pv.SD; cv.SR = pv.SR; cv.ST = pv.ST;
         Dbase[2 * q + 1] = Dbase[2 * q];
       }
@@ -1087,7 +1084,7 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
     // every descriptor must point into the arena before anything is launched
     for (int q = 0; q < k; ++q)
       for (const ItemDev *it : {&tb[q].P, &tb[q].C}) {
-        const bool ok = it->D && it->W1 && it->W2 && it->W3 && it->ldpart && it->info &&
+        const bool ok = it->D && it->W1 && it->W2 && it->W3 && it->Mp && it->ldpart && it->info &&
                         (!need_selinv || (it->SD && it->SR && it->ST)) &&
                         (!grad || it->trpart) && tb[q].x && tb[q].tmp && tb[q].term;
         if (!ok) return fail(INLA_ERR_STATE, "internal: workspace of item " +

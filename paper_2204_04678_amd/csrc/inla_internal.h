@@ -43,6 +43,7 @@ struct ItemDev {
   int b, nt, a, nP;              // block size, time blocks, arrow width, ceil(b / kTile)
   double *D, *S, *R, *T;         // BTA storage (Q in, factor out)
   double *W1, *W2, *W3;          // workspace: b*b, b*b, a*b
+  double *Mp;                    // 2 x 64 x 64: inverse of the current diagonal tile, by parity
   // Selected inversion: Sigma blocks.  When sd_stride != 0 the blocks of step t
   // live at SD + t*sd_stride etc. (caller storage); otherwise Sigma_D and
   // Sigma_R ping-pong between two buffers by the parity of t and Sigma_S uses
@@ -74,21 +75,23 @@ __host__ __device__ inline double *sig_R(const ItemDev &it, int t) {
 // run either on 64 x 64 tiles or on 128 x 128 "big" tiles (big = true).
 enum Phase : int {
   PH_DIAG0 = 0,      // Cholesky + inverse of tile (0,0) of D[t]
-  PH_PANEL = 1,      // panel p: L[i,p] = A[i,p] Linv_pp^T (i > p)
-  PH_TRAIL = 2,      // trailing update by panel p; Cholesky + inverse of tile (p+1,p+1)
-  PH_TRTRI = 3,      // inverse of L_tt by recursive doubling; p = 2*level + stage
-  PH_OFFDIAG_X = 4,  // X = S[t] Linv^T
-  PH_OFFDIAG = 5,    // R' = R[t] Linv^T; D[t] <- Linv (zeros above)
-  PH_SCHUR_X = 6,    // D[t+1] -= X X^T
-  PH_SCHUR = 7,      // R[t+1] -= R' X^T, T -= R' R'^T; copy X, R' back
-  PH_ARROW = 8,      // Cholesky + inverse of T
-  PH_SI_INIT = 9,    // Sigma_T = Linv_AA^T Linv_AA
-  PH_SI_VU_X = 10,   // V = L_{t+1,t} Linv_tt
-  PH_SI_VU = 11,     // U = L_{A,t} Linv_tt
-  PH_SI_SR_X = 12,   // Sigma_S[t]
-  PH_SI_SR = 13,     // Sigma_R[t]
-  PH_SI_SD_X = 14,   // Sigma_D[t] (lower tiles, mirrored)
-  PH_COUNT = 15
+  PH_STEP = 1,       // step p = 0..nP-1 of the tile Cholesky and of inv(L_tt):
+                     //   L[i,p] = A[i,p] X_pp^T into W2 (i > p),
+                     //   A[i,j] -= (A[i,p] M_p) A[j,p]^T with M_p = inv(A_pp) (p < j <= i),
+                     //   Cholesky + inverse X of tile (p+1,p+1),
+                     //   row p of X = inv(L_tt): X[p,j] = -X_pp sum_{j<=m<p} L[p,m] X[m,j] (j < p)
+  PH_OFFDIAG_X = 2,  // X = S[t] Linv^T
+  PH_OFFDIAG = 3,    // R' = R[t] Linv^T; D[t] <- Linv (zeros above)
+  PH_SCHUR_X = 4,    // D[t+1] -= X X^T
+  PH_SCHUR = 5,      // R[t+1] -= R' X^T, T -= R' R'^T; copy X, R' back
+  PH_ARROW = 6,      // Cholesky + inverse of T
+  PH_SI_INIT = 7,    // Sigma_T = Linv_AA^T Linv_AA
+  PH_SI_VU_X = 8,    // V = L_{t+1,t} Linv_tt
+  PH_SI_VU = 9,      // U = L_{A,t} Linv_tt
+  PH_SI_SR_X = 10,   // Sigma_S[t]
+  PH_SI_SR = 11,     // Sigma_R[t]
+  PH_SI_SD_X = 12,   // Sigma_D[t] (lower tiles, mirrored)
+  PH_COUNT = 13
 };
 
 constexpr int kTraceBlocks = 16;   // workgroups per item in a trace reduction step
@@ -105,21 +108,6 @@ __host__ __device__ inline int ntile(int n) { return (n + kTile - 1) / kTile; }
 // at level L (block size s = 2^(L-1) tiles) each pair of adjacent diagonal
 // blocks U = [u0, u0+s), V = [u0+s, min(u0+2s, nP)) gets
 //   X_VU = -X_VV (L_VU X_UU)   (stage 0: T = L_VU X_UU; stage 1: X_VU = -X_VV T).
-__host__ __device__ inline int trtri_levels(int nP) {
-  int L = 0;
-  while ((1 << L) < nP) ++L;
-  return L;
-}
-__host__ __device__ inline int trtri_tasks(int nP, int level) {
-  const int s = 1 << (level - 1);
-  int cnt = 0;
-  for (int u0 = 0; u0 + s < nP; u0 += 2 * s) {
-    const int vs = (nP - (u0 + s) < s) ? nP - (u0 + s) : s;
-    cnt += s * vs;
-  }
-  return cnt;
-}
-
 // Number of workgroup tasks of one item in (phase, t, p); big selects 128-tiles
 // for the _X phases.
 __host__ __device__ inline int phase_tasks(const ItemDev &it, int phase, int t, int p,
@@ -132,14 +120,8 @@ __host__ __device__ inline int phase_tasks(const ItemDev &it, int phase, int t, 
   const bool last = (t == it.nt - 1);
   switch (phase) {
     case PH_DIAG0: return 1;
-    case PH_PANEL:
-      return (p < nP - 1) ? (nP - 1 - p) : 0;
-    case PH_TRAIL:
-      return (p < nP - 1) ? (nP - 1 - p) * (nP - p) / 2 : 0;
-    case PH_TRTRI: {
-      const int level = p >> 1;
-      return (level >= 1 && level <= trtri_levels(nP)) ? trtri_tasks(nP, level) : 0;
-    }
+    case PH_STEP:   // panels, trailing tiles, row p of inv(L_tt)
+      return (p < nP) ? (nP - 1 - p) + (nP - 1 - p) * (nP - p) / 2 + p : 0;
     case PH_OFFDIAG_X: return last ? 0 : nQ * nQ;
     case PH_OFFDIAG: return (arrow ? nP : 0) + nP * nP;
     case PH_SCHUR_X: return last ? 0 : nQ * (nQ + 1) / 2;
@@ -156,7 +138,7 @@ __host__ __device__ inline int phase_tasks(const ItemDev &it, int phase, int t, 
 
 // Phases whose workgroups may run the in-tile Cholesky (large-LDS variant).
 __host__ __device__ inline bool phase_is_fat(int phase) {
-  return phase == PH_DIAG0 || phase == PH_TRAIL || phase == PH_ARROW;
+  return phase == PH_DIAG0 || phase == PH_STEP || phase == PH_ARROW;
 }
 
 // ---- launch wrappers (bta_kernels.hip) ----
