@@ -43,8 +43,9 @@ struct Seg {
   double alpha;
 };
 
-// TK_CHAIN: C = beta C - (A0 B0) A1^T with the 64-column intermediate A0 B0
-// kept in LDS (seg[0] = the first product, seg[1].A = A1).
+// TK_CHAIN: C = beta C - (A0 B0) A1^T (+ the plain product of seg[2], if any)
+// with the 64-column intermediate A0 B0 kept in LDS (seg[0] = the first
+// product, seg[1].A = A1).
 // TK_LCHAIN: C = -A1 (A0 B0), A1 a lower-triangular diagonal tile (seg[1].A).
 enum TaskKind { TK_NONE = 0, TK_PRODUCT = 1, TK_COPY = 2, TK_ZERO = 3, TK_CHAIN = 4, TK_LCHAIN = 5 };
 
@@ -65,6 +66,7 @@ struct Task {
   double *ldsum;
   int row_off;
   double *Mout;                   // Cholesky tasks: also M = inv(L)^T inv(L) here (or null)
+  int ti, tj;                     // 128-wide tiles: block coordinates of C (split-k scratch)
   const double *src;              // copy source (ld = ldc)
 };
 
@@ -115,14 +117,45 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       tk.Mout = it.Mp;
       return;
     }
-    case PH_STEP: {
-      // panel and trailing tasks exist for p < nP - 1, where tile p is full
+    case PH_STEP:
+    case PH_DIAGC:
+    case PH_STEPF: {
+      // Tiles p-1 and p are full wherever they are used here (they precede a tile).
       const int npan = nP - 1 - p;
-      const int ntrail = npan * (npan + 1) / 2;
-      if (q >= npan + ntrail) {
+      const int ncol = max(nP - 2 - p, 0);
+      const int ndef = (p >= 1) ? ncol * (ncol + 1) / 2 : 0;
+      int i = -1;   // column task for tile (i, p+1)
+      if (phase == PH_STEPF && p < nP - 1) {   // task 0 is the diagonal tile
+        if (q == 0) i = p + 1;
+        else --q;
+      }
+      if (i >= 0) {
+      } else if (phase == PH_DIAGC) {
+        i = p + 1;
+      } else if (q < npan) {   // panel: W2(i,p) = A_ip inv(L_pp)^T
+        const int ip = p + 1 + q;
+        tk.m = tdim(b, ip); tk.n = kTile;
+        tk.C = it.W2 + toff(b, ip, p); tk.ldc = b;
+        set_seg(tk.seg[0], Dt + toff(b, ip, p), 1, b, it.W1 + toff(b, p, p), 1, b, 0, kTile, 1.0);
+        tk.nseg = 1;
+        return;
+      } else if (q < npan + ncol) {
+        i = p + 2 + (q - npan);
+      } else if (q < npan + ncol + ndef) {
+        // the rest of panel p-1's update: A_ij -= L_{i,p-1} L_{j,p-1}^T, p+1 < j <= i
+        int ii, jj;
+        tri_decode(q - npan - ncol, ii, jj);
+        const int id = p + 2 + ii, jd = p + 2 + jj;
+        tk.m = tdim(b, id); tk.n = tdim(b, jd);
+        tk.C = Dt + toff(b, id, jd); tk.ldc = b; tk.beta = 1.0;
+        set_seg(tk.seg[0], it.W2 + toff(b, id, p - 1), 1, b, it.W2 + toff(b, jd, p - 1), 1, b, 0,
+                kTile, -1.0);
+        tk.nseg = 1;
+        return;
+      } else {
         // row p of X = inv(L_tt): X_pj = -X_pp sum_{m=j}^{p-1} L_pm X_mj, j < p
         // (L from W2; X rows m < p, and X_pp, from earlier steps in W1)
-        const int j = q - npan - ntrail;
+        const int j = q - npan - ncol - ndef;
         tk.kind = TK_LCHAIN;
         tk.m = tdim(b, p); tk.n = kTile;
         tk.C = it.W1 + toff(b, p, j); tk.ldc = b;
@@ -132,26 +165,22 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
         tk.nseg = 1;
         return;
       }
-      if (q < npan) {   // panel: W2(i,p) = A_ip inv(L_pp)^T
-        const int i = p + 1 + q;
-        tk.m = tdim(b, i); tk.n = kTile;
-        tk.C = it.W2 + toff(b, i, p); tk.ldc = b;
-        set_seg(tk.seg[0], Dt + toff(b, i, p), 1, b, it.W1 + toff(b, p, p), 1, b, 0, kTile, 1.0);
-        tk.nseg = 1;
-        return;
-      }
-      // trailing: A_ij -= (A_ip M_p) A_jp^T, M_p = inv(L_pp)^T inv(L_pp) = inv(A_pp)
-      int ii, jj;
-      tri_decode(q - npan, ii, jj);
-      const int i = p + 1 + ii, j = p + 1 + jj;
+      // column p+1: A_{i,p+1} -= L_{i,p-1} L_{p+1,p-1}^T + (A_ip M_p) A_{p+1,p}^T with
+      // M_p = inv(L_pp)^T inv(L_pp) = inv(A_pp)
+      const int jc = p + 1;
       tk.kind = TK_CHAIN;
-      tk.m = tdim(b, i); tk.n = tdim(b, j);
-      tk.C = Dt + toff(b, i, j); tk.ldc = b; tk.beta = 1.0;
+      tk.m = tdim(b, i); tk.n = tdim(b, jc);
+      tk.C = Dt + toff(b, i, jc); tk.ldc = b; tk.beta = 1.0;
       set_seg(tk.seg[0], Dt + toff(b, i, p), 1, b, it.Mp + (long long)(p & 1) * kTile * kTile, kTile,
               1, 0, kTile, 1.0);
-      set_seg(tk.seg[1], Dt + toff(b, j, p), 1, b, nullptr, 0, 0, 0, kTile, -1.0);
+      set_seg(tk.seg[1], Dt + toff(b, jc, p), 1, b, nullptr, 0, 0, 0, kTile, -1.0);
+      if (p >= 1)
+        set_seg(tk.seg[2], it.W2 + toff(b, i, p - 1), 1, b, it.W2 + toff(b, jc, p - 1), 1, b, 0,
+                kTile, -1.0);
+      else
+        set_seg(tk.seg[2], nullptr, 1, b, nullptr, 1, b, 0, 0, -1.0);
       tk.nseg = 1;
-      if (i == p + 1 && j == p + 1) {
+      if (i == jc) {
         tk.chol = 1; tk.Lout = it.W1 + toff(b, i, i); tk.ldl = b;
         tk.ldsum = it.ldpart + (long long)t * nP + i; tk.row_off = t * b + i * kTile;
         tk.Mout = it.Mp + (long long)((p + 1) & 1) * kTile * kTile;
@@ -348,7 +377,7 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
   switch (phase) {
     case PH_OFFDIAG_X:
       I = q / nQ; J = q % nQ;
-      tk.m = bdim(b, I); tk.n = bdim(b, J);
+      tk.m = bdim(b, I); tk.n = bdim(b, J); tk.ti = I; tk.tj = J;
       tk.C = it.W2 + boff(b, I, J); tk.ldc = b;
       set_seg(tk.seg[0], St + (long long)I * kBig, 1, b, it.W1 + (long long)J * kBig, 1, b, 0,
               min(b, (J + 1) * kBig), 1.0);
@@ -356,7 +385,7 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
       return;
     case PH_SCHUR_X:
       tri_decode(q, I, J);
-      tk.m = bdim(b, I); tk.n = bdim(b, J);
+      tk.m = bdim(b, I); tk.n = bdim(b, J); tk.ti = I; tk.tj = J;
       tk.C = it.D + (long long)(t + 1) * bb + boff(b, I, J); tk.ldc = b; tk.beta = 1.0;
       set_seg(tk.seg[0], it.W2 + (long long)I * kBig, 1, b, it.W2 + (long long)J * kBig, 1, b, 0, b,
               -1.0);
@@ -364,7 +393,7 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
       return;
     case PH_SI_VU_X:
       I = q / nQ; J = q % nQ;
-      tk.m = bdim(b, I); tk.n = bdim(b, J);
+      tk.m = bdim(b, I); tk.n = bdim(b, J); tk.ti = I; tk.tj = J;
       tk.C = it.W2 + boff(b, I, J); tk.ldc = b;
       set_seg(tk.seg[0], St + (long long)I * kBig, 1, b, Dt + (long long)J * kBig * b, b, 1,
               J * kBig, b, 1.0);
@@ -372,7 +401,7 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
       return;
     case PH_SI_SR_X:
       I = q / nQ; J = q % nQ;
-      tk.m = bdim(b, I); tk.n = bdim(b, J);
+      tk.m = bdim(b, I); tk.n = bdim(b, J); tk.ti = I; tk.tj = J;
       tk.C = sig_S(it, t) + boff(b, I, J); tk.ldc = b;
       set_seg(tk.seg[0], sig_D(it, t + 1) + (long long)I * kBig, 1, b,
               it.W2 + (long long)J * kBig * b, b, 1, 0, b, -1.0);
@@ -386,7 +415,7 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
     case PH_SI_SD_X: {
       tri_decode(q, I, J);
       double *SDt = sig_D(it, t);
-      tk.m = bdim(b, I); tk.n = bdim(b, J);
+      tk.m = bdim(b, I); tk.n = bdim(b, J); tk.ti = I; tk.tj = J;
       tk.C = SDt + boff(b, I, J); tk.ldc = b;
       tk.mirror = 1; tk.Cm = SDt + boff(b, J, I); tk.diagtile = (I == J);
       set_seg(tk.seg[0], Dt + (long long)I * kBig * b, b, 1, Dt + (long long)J * kBig * b, b, 1,
@@ -481,7 +510,8 @@ struct ChunkInfo {
 // constants so the task stays in registers.
 template <int KC, int ROWS, int WR, int WC, int DEPTH = 1>
 __device__ __forceinline__ void run_product(const Task &tk, double *smem,
-                                            d4 (&acc)[ROWS / WR / 16][ROWS / WC / 16]) {
+                                            d4 (&acc)[ROWS / WR / 16][ROWS / WC / 16],
+                                            int part = 0, int nparts = 1) {
   constexpr int NT = 64 * WR * WC;
   constexpr int NE = KC * ROWS / NT;
   constexpr int LD = ROWS + 2;
@@ -491,8 +521,10 @@ __device__ __forceinline__ void run_product(const Task &tk, double *smem,
   const int n0 = (tk.nseg > 0 && tk.seg[0].k1 > tk.seg[0].k0) ? (tk.seg[0].k1 - tk.seg[0].k0 + KC - 1) / KC : 0;
   const int n1 = (tk.nseg > 1 && tk.seg[1].k1 > tk.seg[1].k0) ? (tk.seg[1].k1 - tk.seg[1].k0 + KC - 1) / KC : 0;
   const int n2 = (tk.nseg > 2 && tk.seg[2].k1 > tk.seg[2].k0) ? (tk.seg[2].k1 - tk.seg[2].k0 + KC - 1) / KC : 0;
-  const int total = n0 + n1 + n2;
-  if (total == 0) return;
+  // this workgroup's share of the chunks (all of them unless the k range is split)
+  const int all = n0 + n1 + n2;
+  const int cb = (int)((long long)all * part / nparts), ce = (int)((long long)all * (part + 1) / nparts);
+  if (ce <= cb) return;
   // chunk c of the concatenated segments; the segment's fields are picked
   // with uniform selects so that a single copy of the load code exists
   auto fetch = [&](int c, double (&ra)[NE], double (&rb)[NE], ChunkInfo &ci) {
@@ -540,13 +572,13 @@ __device__ __forceinline__ void run_product(const Task &tk, double *smem,
   double ra0[NE], rb0[NE];
   ChunkInfo ci0;
   if constexpr (DEPTH == 1) {
-    fetch(0, ra0, rb0, ci0);
+    fetch(cb, ra0, rb0, ci0);
     stage(buf0, ra0, rb0, ci0);
     __syncthreads();
-    for (int c = 0; c < total; ++c) {
-      const int cur = c & 1;
-      const bool has_next = c + 1 < total;
-      fetch(min(c + 1, total - 1), ra0, rb0, ci0);
+    for (int c = cb; c < ce; ++c) {
+      const int cur = (c - cb) & 1;
+      const bool has_next = c + 1 < ce;
+      fetch(min(c + 1, ce - 1), ra0, rb0, ci0);
       compute(cur ? buf1 : buf0);
       if (has_next) stage(cur ? buf0 : buf1, ra0, rb0, ci0);
       __syncthreads();
@@ -557,21 +589,21 @@ __device__ __forceinline__ void run_product(const Task &tk, double *smem,
     // exactly the loads issued after it and leaves them in flight.
     double ra1[NE], rb1[NE];
     ChunkInfo ci1;
-    const int last = total - 1;
-    fetch(0, ra0, rb0, ci0);
-    fetch(min(1, last), ra1, rb1, ci1);
+    const int last = ce - 1;
+    fetch(cb, ra0, rb0, ci0);
+    fetch(min(cb + 1, last), ra1, rb1, ci1);
     stage(buf0, ra0, rb0, ci0);
     __syncthreads();
     // invariant at the top: buf0 holds chunk c, set 1 holds (or awaits) chunk c + 1
-    for (int c = 0; c < total; c += 2) {
+    for (int c = cb; c < ce; c += 2) {
       fetch(min(c + 2, last), ra0, rb0, ci0);
       compute(buf0);
-      if (c + 1 < total) stage(buf1, ra1, rb1, ci1);
+      if (c + 1 < ce) stage(buf1, ra1, rb1, ci1);
       __syncthreads();
-      if (c + 1 >= total) break;
+      if (c + 1 >= ce) break;
       fetch(min(c + 3, last), ra1, rb1, ci1);
       compute(buf1);
-      if (c + 2 < total) stage(buf0, ra0, rb0, ci0);
+      if (c + 2 < ce) stage(buf0, ra0, rb0, ci0);
       __syncthreads();
     }
   }
@@ -871,7 +903,7 @@ __device__ __forceinline__ void left_chain_product(const Task &tk, double *smem,
   __syncthreads();
 }
 
-// TK_CHAIN on a 64 x 64 tile: acc = -(A0 B0) A1^T.  The intermediate T = A0 B0
+// TK_CHAIN on a 64 x 64 tile: acc = -(A0 B0) A1^T (+ seg[2]).  The intermediate T = A0 B0
 // (tk.m x 64, k = 64) comes from the regular product loop; it and A1 are then
 // staged in LDS (row-major, ld TLD) for the second product (k = 64).
 template <int KC>
@@ -917,6 +949,12 @@ __device__ __forceinline__ void chain_product(const Task &tk, double *smem, d4 (
         acc[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[mi], bv[nj], acc[mi][nj], 0, 0, 0);
   }
   __syncthreads();
+  if (tk.seg[2].k1 > tk.seg[2].k0) {   // a further plain product term
+    Task t3 = tk;
+    t3.seg[0] = tk.seg[2];
+    t3.nseg = 1;
+    run_product<KC, kTile, 2, 2, 2>(t3, smem, acc);
+  }
 }
 
 // Owner of workgroup task q in a launch over n_items items whose task counts
@@ -953,7 +991,7 @@ __device__ __forceinline__ int find_item(const ItemDev *items, int n_items, int 
 // One launch covers the tasks of `phase` and, if phase2 >= 0, of `phase2` as
 // well (two independent phases of the same step), item by item.
 template <bool FAT>
-__global__ __launch_bounds__(kThreads) void tile_phase_kernel(const ItemDev *__restrict__ items,
+__global__ __launch_bounds__(kThreads, FAT ? 1 : 2) void tile_phase_kernel(const ItemDev *__restrict__ items,
                                                               int n_items, int phase, int phase2,
                                                               int t, int p) {
   __shared__ double smem[FAT ? kFatLds : kLeanLds];
@@ -999,13 +1037,10 @@ __global__ __launch_bounds__(kThreads) void tile_phase_kernel(const ItemDev *__r
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
     for (int nj = 0; nj < 2; ++nj) acc[mi][nj] = d4{0.0, 0.0, 0.0, 0.0};
-  if constexpr (FAT) {
-    if (tk.kind == TK_CHAIN) chain_product<kFatKC>(tk, smem, acc);
-    else if (tk.kind == TK_LCHAIN) left_chain_product<kFatKC>(tk, smem, acc);
-    else run_product<kFatKC, kTile, 2, 2, 2>(tk, smem, acc);
-  } else {
-    run_product<kLeanKC, kTile, 2, 2, 2>(tk, smem, acc);
-  }
+  constexpr int KC = FAT ? kFatKC : kLeanKC;
+  if (tk.kind == TK_CHAIN) chain_product<KC>(tk, smem, acc);
+  else if (tk.kind == TK_LCHAIN) left_chain_product<KC>(tk, smem, acc);
+  else run_product<KC, kTile, 2, 2, 2>(tk, smem, acc);
 
   if constexpr (FAT) {
     if (tk.chol) {
@@ -1101,13 +1136,19 @@ __device__ __forceinline__ int xcd_contiguous(int bid, int n) {
   return x * per + min(x, rem) + j;
 }
 
+// With ks > 1 the k range of every tile is split over ks workgroups (adjacent
+// task numbers, so on one XCD); part h writes its partial product, without
+// beta or mirroring, to it.P + h*b*b at the tile's position (ld b), and
+// splitk_reduce_kernel forms C.
 template <int V>
 __global__ __launch_bounds__(big_threads<V>(), BigCfg<V>::OCC) void tile_big_kernel(
-    const ItemDev *__restrict__ items, int n_items, int phase, int t) {
+    const ItemDev *__restrict__ items, int n_items, int phase, int t, int ks) {
   using C = BigCfg<V>;
   constexpr int MR = kBig / C::WR / 16, MC = kBig / C::WC / 16;
   __shared__ double smem[big_lds<V>()];
-  int q = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int qa = xcd_contiguous(blockIdx.x, gridDim.x);
+  int q = qa / ks;
+  const int part = qa - q * ks;
   const int ii = find_item(items, n_items, q,
                            [&](const ItemDev &x) { return phase_tasks(x, phase, t, 0, true); });
   if (ii >= n_items) return;
@@ -1122,7 +1163,22 @@ __global__ __launch_bounds__(big_threads<V>(), BigCfg<V>::OCC) void tile_big_ker
   for (int mi = 0; mi < MR; ++mi)
 #pragma unroll
     for (int nj = 0; nj < MC; ++nj) acc[mi][nj] = d4{0.0, 0.0, 0.0, 0.0};
-  run_product<C::KC, kBig, C::WR, C::WC, C::DEPTH>(tk, smem, acc);
+  run_product<C::KC, kBig, C::WR, C::WC, C::DEPTH>(tk, smem, acc, part, ks);
+  if (ks > 1) {
+    double *Pp = it.P + (long long)part * it.b * it.b + (long long)tk.ti * kBig +
+                 (long long)tk.tj * kBig * it.b;
+#pragma unroll
+    for (int mi = 0; mi < MR; ++mi)
+#pragma unroll
+      for (int nj = 0; nj < MC; ++nj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = wr * (kBig / C::WR) + mi * 16 + (lane >> 4) + 4 * r;
+          const int col = wc * (kBig / C::WC) + nj * 16 + (lane & 15);
+          if (row < tk.m && col < tk.n) gst(Pp + row + (long long)col * it.b, acc[mi][nj][r]);
+        }
+    return;
+  }
 #pragma unroll
   for (int mi = 0; mi < MR; ++mi)
 #pragma unroll
@@ -1169,16 +1225,56 @@ int big_variant() {
   return g_big_variant;
 }
 
+// C = beta C + sum of the ks partial products of a split-k launch, one
+// workgroup per 128-wide tile, with the task's mirroring rules.
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const ItemDev *__restrict__ items,
+                                                            int n_items, int phase, int t, int ks) {
+  int q = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int ii = find_item(items, n_items, q,
+                           [&](const ItemDev &x) { return phase_tasks(x, phase, t, 0, true); });
+  if (ii >= n_items) return;
+  const ItemDev it = items[ii];
+  Task tk;
+  decode_big(it, phase, t, q, tk);
+  if (tk.kind != TK_PRODUCT) return;
+  const long long bb = (long long)it.b * it.b;
+  const double *Pp = it.P + (long long)tk.ti * kBig + (long long)tk.tj * kBig * it.b;
+  for (int e = threadIdx.x; e < kBig * kBig; e += 256) {
+    const int row = e & (kBig - 1), col = e / kBig;
+    if (row >= tk.m || col >= tk.n) continue;
+    double v = 0.0;
+    for (int h = 0; h < ks; ++h) v += gld(Pp + h * bb + row + (long long)col * it.b);
+    double *cp = tk.C + row + (long long)col * tk.ldc;
+    if (tk.beta != 0.0) v += tk.beta * gld(cp);
+    if (tk.mirror && tk.diagtile) {
+      if (row >= col) {
+        gst(cp, v);
+        gst(tk.Cm + col + (long long)row * tk.ldc, v);
+      }
+    } else {
+      gst(cp, v);
+      if (tk.mirror) gst(tk.Cm + col + (long long)row * tk.ldc, v);
+    }
+  }
+}
+
 hipError_t launch_tile_phase(const ItemDev *items_dev, int n_items, int total, int phase,
-                             int phase2, int t, int p, bool big, hipStream_t s) {
+                             int phase2, int t, int p, bool big, hipStream_t s, int ks) {
   if (total <= 0) return hipSuccess;
   if (big && phase_is_product_x(phase) && phase2 < 0) {
+    const long long grid = (long long)total * ks;
     if (big_variant() == 0)
-      hipLaunchKernelGGL(tile_big_kernel<0>, dim3(total), dim3(big_threads<0>()), 0, s, items_dev,
-                         n_items, phase, t);
+      hipLaunchKernelGGL(tile_big_kernel<0>, dim3((unsigned)grid), dim3(big_threads<0>()), 0, s,
+                         items_dev, n_items, phase, t, ks);
     else
-      hipLaunchKernelGGL(tile_big_kernel<1>, dim3(total), dim3(big_threads<1>()), 0, s, items_dev,
-                         n_items, phase, t);
+      hipLaunchKernelGGL(tile_big_kernel<1>, dim3((unsigned)grid), dim3(big_threads<1>()), 0, s,
+                         items_dev, n_items, phase, t, ks);
+    if (ks > 1) {
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(splitk_reduce_kernel, dim3(total), dim3(256), 0, s, items_dev, n_items,
+                         phase, t, ks);
+    }
   } else if (phase_is_fat(phase) || (phase2 >= 0 && phase_is_fat(phase2))) {
     hipLaunchKernelGGL(tile_phase_kernel<true>, dim3(total), dim3(kThreads), 0, s, items_dev, n_items,
                        phase, phase2, t, p);

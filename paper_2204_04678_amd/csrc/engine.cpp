@@ -138,8 +138,11 @@ struct Batch {
   ItemDev *dev = nullptr;
   int max_nt = 0, max_b = 0, max_a = 0;
   bool big = false;
+  bool split = false;   // every item has split-k scratch
   void finalize() {
     big = use_big_tiles(host);
+    split = !host.empty();
+    for (auto &it : host) split = split && it.P;
     for (auto &it : host) {
       max_nt = std::max(max_nt, it.nt);
       max_b = std::max(max_b, it.b);
@@ -176,6 +179,16 @@ double phase_flops(const ItemDev &it, int phase, int t, int p) {
 // choice (g_tile_pref), else 128-wide tiles when a launch has enough of them
 // to fill the chip and 64-wide ones otherwise.  INLA_TILE=64|128 in the
 // environment overrides both.
+// With split-k scratch (every item has P), 128-tile launches of fewer than
+// kSplitTiles tiles split their k range over kSplitK workgroups.  The built-in
+// rule picks 128-wide tiles only from kSplitTiles tiles per launch on: below
+// that the 64-wide kernel was faster on every workload measured (b = 1024 with
+// two matrices, b = 1600 with two), split or not; the autotuner and the tile
+// option can still ask for 128 (then split) there.
+constexpr long long kSplitTiles = 384;
+// Below this many 64-tiles (summed nP^2 over the items of a factor launch)
+// each Cholesky step is one fused launch (see run_factor).
+constexpr long long kStepFusedTiles = 1024;
 int g_tile_pref = 0;
 bool use_big_tiles(const std::vector<ItemDev> &items) {
   const char *e = getenv("INLA_TILE");
@@ -184,7 +197,7 @@ bool use_big_tiles(const std::vector<ItemDev> &items) {
   if (force == 128) return true;
   long long big = 0;
   for (const auto &it : items) big += (long long)nbig(it.b) * nbig(it.b);
-  return big >= 256;
+  return big >= kSplitTiles;
 }
 
 #define ST_TRY_INNER(expr)               \
@@ -253,14 +266,35 @@ inla_status run_phase(const Batch &B, int phase, int t, int p, hipStream_t s) {
   double flops = 0.0;
   if (g_prof.on)
     for (const auto &it : B.host) flops += phase_flops(it, phase, t, p);
+  const int ks = (big && B.split && total < kSplitTiles) ? kSplitK : 1;
   ProfScope ps(phase, flops, s, big ? PK_BIG : (phase_is_fat(phase) ? PK_FAT : PK_LEAN));
-  HIP_TRY(launch_tile_phase(B.dev, (int)B.host.size(), (int)total, phase, -1, t, p, big, s));
+  HIP_TRY(launch_tile_phase(B.dev, (int)B.host.size(), (int)total, phase, -1, t, p, big, s, ks));
   return INLA_OK;
 }
 
 // Side stream (default priority) for phases that run beside a big-tile launch.
 hipStream_t g_side = nullptr;
 hipEvent_t g_fork = nullptr, g_join = nullptr;
+
+// Runs phase pm on s and the independent phase ps of the same step on the side
+// stream, joined back into s (in a captured graph: two parallel nodes).
+inla_status run_beside(const Batch &B, int pm, int ps, int t, int p, hipStream_t s) {
+  long long side = 0;
+  for (const auto &it : B.host) side += phase_tasks(it, ps, t, p);
+  if (side == 0) return run_phase(B, pm, t, p, s);
+  if (!g_side) {
+    HIP_TRY(hipStreamCreateWithFlags(&g_side, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&g_fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&g_join, hipEventDisableTiming));
+  }
+  HIP_TRY(hipEventRecord(g_fork, s));
+  HIP_TRY(hipStreamWaitEvent(g_side, g_fork, 0));
+  ST_TRY_INNER(run_phase(B, ps, t, p, g_side));
+  ST_TRY_INNER(run_phase(B, pm, t, p, s));
+  HIP_TRY(hipEventRecord(g_join, g_side));
+  HIP_TRY(hipStreamWaitEvent(s, g_join, 0));
+  return INLA_OK;
+}
 
 // Runs the b x b product phase px together with the independent phase pr of
 // the same step: in one 64-tile launch, or, with big tiles, px on s and pr on
@@ -311,7 +345,16 @@ inla_status run_factor(const Batch &B, hipStream_t s) {
     int mp = 0;
     for (const auto &it : B.host)
       if (t < it.nt) mp = std::max(mp, it.nP);
-    for (int p = 0; p < mp; ++p) ST_TRY(run_phase(B, PH_STEP, t, p, s));
+    // Few tiles per step: one launch of the Cholesky-capable kernel per step (its
+    // latency is the cost).  Many: the lean kernel for the step and the next
+    // diagonal tile beside it.
+    long long tiles2 = 0;
+    for (const auto &it : B.host)
+      if (t < it.nt) tiles2 += (long long)it.nP * it.nP;
+    for (int p = 0; p < mp; ++p) {
+      if (tiles2 < kStepFusedTiles) ST_TRY(run_phase(B, PH_STEPF, t, p, s));
+      else ST_TRY(run_beside(B, PH_STEP, PH_DIAGC, t, p, s));
+    }
     ST_TRY(run_pair(B, PH_OFFDIAG_X, PH_OFFDIAG, t, s));
     ST_TRY(run_pair(B, PH_SCHUR_X, PH_SCHUR, t, s));
   }
@@ -821,12 +864,13 @@ struct ThetaItemBufs {
 // Device bytes one (model, theta) item needs: two BTA matrices with their
 // workspaces, or one shared by Q_prior and Q_c when `seq` (the two are then
 // processed one after the other).
-size_t theta_item_bytes(const ModelDev &h, bool selinv, bool seq) {
+size_t theta_item_bytes(const ModelDev &h, bool selinv, bool seq, bool split) {
   const size_t bb = (size_t)h.b * h.b, ab = (size_t)h.a * h.b;
   const int nP = ntile(h.b);
   size_t per = bta_doubles(h.b, h.nt, h.a) * 8 + (2 * bb + ab + 2 * kTile * kTile) * 8 +
                ((size_t)h.nt * nP + 1) * 8 + 5 * kAlign * 4;
   if (selinv) per += (2 * bb + 2 * ab + (size_t)h.a * h.a) * 8 + ((size_t)h.nt + 1) * kTraceBlocks * 32;
+  if (split) per += (size_t)kSplitK * bb * 8 + kAlign;
   return (seq ? 1 : 2) * per + ((size_t)h.n + std::max(h.b, h.a) + kTermBlocks * 4) * 8 + 4096;
 }
 
@@ -888,14 +932,20 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
                      hipStream_t s) {
   const bool grad = grad_dev != nullptr;
   const bool need_selinv = grad || var_out != nullptr;
+  // split-k scratch when the whole call has few 128-wide tiles per launch
+  long long nb2 = 0;
+  for (int i = 0; i < n_items; ++i) nb2 += 2LL * nbig(models[i]->host.b) * nbig(models[i]->host.b);
+  const char *tile_env = getenv("INLA_TILE");
+  const int tile_force = tile_env ? atoi(tile_env) : g_tile_pref;
+  const bool split_wanted = nb2 < kSplitTiles && tile_force == 128;
   // HBM admission: split the items into waves whose storage fits the budget
-  auto waves_for = [&](bool seq, std::vector<size_t> &bytes, double &all) -> int {
+  auto waves_for = [&](bool seq, bool split, std::vector<size_t> &bytes, double &all) -> int {
     bytes.assign(n_items, 0);
     all = 0.0;
     int waves = 0;
     double acc = budget + 1.0;
     for (int i = 0; i < n_items; ++i) {
-      bytes[i] = theta_item_bytes(models[i]->host, need_selinv, seq);
+      bytes[i] = theta_item_bytes(models[i]->host, need_selinv, seq, split);
       all += (double)bytes[i];
       if ((double)bytes[i] > budget) return INT_MAX;
       if (acc + (double)bytes[i] > budget) {
@@ -906,28 +956,40 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
     }
     return waves;
   };
+  // layouts in order of preference; the first with the fewest waves wins
+  struct Plan { bool seq, split; };
+  std::vector<Plan> plans;
+  for (int sq = 0; sq < 2; ++sq) {
+    const bool seq_c = sq == 1;
+    if ((seq_mode == 1 && !seq_c) || (seq_mode == 2 && seq_c)) continue;
+    if (split_wanted) plans.push_back({seq_c, true});
+    plans.push_back({seq_c, false});
+  }
   std::vector<size_t> bytes;
   double all = 0.0;
-  bool seq = seq_mode == 1;
-  int waves = waves_for(seq, bytes, all);
-  if (seq_mode == 0) {
+  bool seq = false, split = false;
+  int waves = INT_MAX;
+  for (const Plan &pl : plans) {
     std::vector<size_t> b1;
     double a1 = 0.0;
-    const int w1 = waves_for(true, b1, a1);
+    const int w1 = waves_for(pl.seq, pl.split, b1, a1);
     if (w1 < waves) {
-      seq = true;
       waves = w1;
+      seq = pl.seq;
+      split = pl.split;
       bytes.swap(b1);
       all = a1;
     }
   }
   if (waves == INT_MAX) {
-    for (int i = 0; i < n_items; ++i)
-      if ((double)bytes[i] > budget || bytes[i] == 0)
-        return fail(INLA_ERR_BUDGET, "item " + std::to_string(i) + " needs " +
-                                         std::to_string(theta_item_bytes(models[i]->host,
-                                                                         need_selinv, seq)) +
+    const Plan pl = plans.back();   // the smallest layout
+    for (int i = 0; i < n_items; ++i) {
+      const size_t need = theta_item_bytes(models[i]->host, need_selinv, pl.seq, pl.split);
+      if ((double)need > budget)
+        return fail(INLA_ERR_BUDGET, "item " + std::to_string(i) + " needs " + std::to_string(need) +
                                          " bytes, above the HBM budget");
+    }
+    return fail(INLA_ERR_BUDGET, "no layout fits the HBM budget");
   }
   // per-item output offsets into the concatenated mu / var buffers
   std::vector<long long> voff(n_items + 1, 0);
@@ -986,6 +1048,7 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
         }
         L.add(&Dbase[2 * q + w], bta_doubles(h.b, h.nt, h.a));
         layout_factor_ws(L, it);
+        if (split) L.add(&it.P, (size_t)kSplitK * h.b * h.b);
         if (need_selinv) {
           layout_selinv_ws(L, it);
           if (grad) L.add(&it.trpart, ((size_t)h.nt + 1) * kTraceBlocks * 4);
@@ -1014,7 +1077,7 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
       for (int q = 0; q < k; ++q) {
         const ItemDev &pv = tb[q].P;
         ItemDev &cv = tb[q].C;
-        cv.W1 = pv.W1; cv.W2 = pv.W2; cv.W3 = pv.W3; cv.Mp = pv.Mp;
+        cv.W1 = pv.W1; cv.W2 = pv.W2; cv.W3 = pv.W3; cv.Mp = pv.Mp; cv.P = pv.P;
         cv.ldpart = pv.ldpart; cv.info = pv.info;
         cv.SD = pv.SD; cv.SR = pv.SR; cv.ST = pv.ST;
         Dbase[2 * q + 1] = Dbase[2 * q];

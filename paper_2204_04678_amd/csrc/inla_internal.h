@@ -44,6 +44,7 @@ struct ItemDev {
   double *D, *S, *R, *T;         // BTA storage (Q in, factor out)
   double *W1, *W2, *W3;          // workspace: b*b, b*b, a*b
   double *Mp;                    // 2 x 64 x 64: inverse of the current diagonal tile, by parity
+  double *P;                     // kSplitK * b * b split-k partial products (or null: no split)
   // Selected inversion: Sigma blocks.  When sd_stride != 0 the blocks of step t
   // live at SD + t*sd_stride etc. (caller storage); otherwise Sigma_D and
   // Sigma_R ping-pong between two buffers by the parity of t and Sigma_S uses
@@ -75,23 +76,28 @@ __host__ __device__ inline double *sig_R(const ItemDev &it, int t) {
 // run either on 64 x 64 tiles or on 128 x 128 "big" tiles (big = true).
 enum Phase : int {
   PH_DIAG0 = 0,      // Cholesky + inverse of tile (0,0) of D[t]
-  PH_STEP = 1,       // step p = 0..nP-1 of the tile Cholesky and of inv(L_tt):
-                     //   L[i,p] = A[i,p] X_pp^T into W2 (i > p),
-                     //   A[i,j] -= (A[i,p] M_p) A[j,p]^T with M_p = inv(A_pp) (p < j <= i),
-                     //   Cholesky + inverse X of tile (p+1,p+1),
+  PH_STEP = 1,       // step p = 0..nP-1 of the tile Cholesky and of inv(L_tt) (with lookahead):
+                     //   panel p: L[i,p] = A[i,p] X_pp^T into W2 (i > p),
+                     //   column p+1 below the diagonal: A[i,p+1] -= L[i,p-1] L[p+1,p-1]^T
+                     //     + (A[i,p] M_p) A[p+1,p]^T with M_p = inv(A_pp) (i > p+1),
+                     //   the rest of panel p-1's update: A[i,j] -= L[i,p-1] L[j,p-1]^T (j > p+1),
                      //   row p of X = inv(L_tt): X[p,j] = -X_pp sum_{j<=m<p} L[p,m] X[m,j] (j < p)
-  PH_OFFDIAG_X = 2,  // X = S[t] Linv^T
-  PH_OFFDIAG = 3,    // R' = R[t] Linv^T; D[t] <- Linv (zeros above)
-  PH_SCHUR_X = 4,    // D[t+1] -= X X^T
-  PH_SCHUR = 5,      // R[t+1] -= R' X^T, T -= R' R'^T; copy X, R' back
-  PH_ARROW = 6,      // Cholesky + inverse of T
-  PH_SI_INIT = 7,    // Sigma_T = Linv_AA^T Linv_AA
-  PH_SI_VU_X = 8,    // V = L_{t+1,t} Linv_tt
-  PH_SI_VU = 9,      // U = L_{A,t} Linv_tt
-  PH_SI_SR_X = 10,   // Sigma_S[t]
-  PH_SI_SR = 11,     // Sigma_R[t]
-  PH_SI_SD_X = 12,   // Sigma_D[t] (lower tiles, mirrored)
-  PH_COUNT = 13
+  PH_DIAGC = 2,      // beside STEP(p): tile (p+1,p+1) updated as its column, then its
+                     //   Cholesky + inverse and M_{p+1}
+  PH_STEPF = 3,      // DIAGC(p) and STEP(p) as one launch of the Cholesky-capable kernel
+                     //   (few tasks per step: the launch latency dominates)
+  PH_OFFDIAG_X = 4,  // X = S[t] Linv^T
+  PH_OFFDIAG = 5,    // R' = R[t] Linv^T; D[t] <- Linv (zeros above)
+  PH_SCHUR_X = 6,    // D[t+1] -= X X^T
+  PH_SCHUR = 7,      // R[t+1] -= R' X^T, T -= R' R'^T; copy X, R' back
+  PH_ARROW = 8,      // Cholesky + inverse of T
+  PH_SI_INIT = 9,    // Sigma_T = Linv_AA^T Linv_AA
+  PH_SI_VU_X = 10,   // V = L_{t+1,t} Linv_tt
+  PH_SI_VU = 11,     // U = L_{A,t} Linv_tt
+  PH_SI_SR_X = 12,   // Sigma_S[t]
+  PH_SI_SR = 13,     // Sigma_R[t]
+  PH_SI_SD_X = 14,   // Sigma_D[t] (lower tiles, mirrored)
+  PH_COUNT = 15
 };
 
 constexpr int kTraceBlocks = 16;   // workgroups per item in a trace reduction step
@@ -120,8 +126,14 @@ __host__ __device__ inline int phase_tasks(const ItemDev &it, int phase, int t, 
   const bool last = (t == it.nt - 1);
   switch (phase) {
     case PH_DIAG0: return 1;
-    case PH_STEP:   // panels, trailing tiles, row p of inv(L_tt)
-      return (p < nP) ? (nP - 1 - p) + (nP - 1 - p) * (nP - p) / 2 + p : 0;
+    case PH_STEP:     // panels, column p+1, deferred trailing tiles, row p of inv(L_tt)
+    case PH_STEPF: {  // the same plus the diagonal tile of column p+1
+      if (p >= nP) return 0;
+      const int ncol = (nP - 2 - p > 0) ? nP - 2 - p : 0;
+      return (nP - 1 - p) + ncol + (p >= 1 ? ncol * (ncol + 1) / 2 : 0) + p +
+             ((phase == PH_STEPF && p < nP - 1) ? 1 : 0);
+    }
+    case PH_DIAGC: return (p < nP - 1) ? 1 : 0;
     case PH_OFFDIAG_X: return last ? 0 : nQ * nQ;
     case PH_OFFDIAG: return (arrow ? nP : 0) + nP * nP;
     case PH_SCHUR_X: return last ? 0 : nQ * (nQ + 1) / 2;
@@ -138,12 +150,13 @@ __host__ __device__ inline int phase_tasks(const ItemDev &it, int phase, int t, 
 
 // Phases whose workgroups may run the in-tile Cholesky (large-LDS variant).
 __host__ __device__ inline bool phase_is_fat(int phase) {
-  return phase == PH_DIAG0 || phase == PH_STEP || phase == PH_ARROW;
+  return phase == PH_DIAG0 || phase == PH_DIAGC || phase == PH_STEPF || phase == PH_ARROW;
 }
 
 // ---- launch wrappers (bta_kernels.hip) ----
 hipError_t launch_tile_phase(const ItemDev *items_dev, int n_items, int total, int phase,
-                             int phase2, int t, int p, bool big, hipStream_t s);
+                             int phase2, int t, int p, bool big, hipStream_t s, int ks = 1);
+constexpr int kSplitK = 2;        // k-split of 128-tile launches with too few tiles
 hipError_t launch_fill(double *ptr, long long n, double v, hipStream_t s);
 hipError_t launch_fill_int(int *ptr, long long n, int v, hipStream_t s);
 hipError_t launch_logdet_finish(const ItemDev *items_dev, int n_items, double *logdet_out,
