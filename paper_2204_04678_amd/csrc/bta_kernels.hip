@@ -31,6 +31,9 @@ template <> struct BigCfg<0> {   // 8 waves of 64 x 32, two waves per SIMD
 template <> struct BigCfg<1> {   // 4 waves of 64 x 64, one wave per SIMD
   static constexpr int WR = 2, WC = 2, KC = 16, DEPTH = 2, OCC = 1;
 };
+template <> struct BigCfg<2> {   // 8 waves of 64 x 32, deeper k-chunk, one register set
+  static constexpr int WR = 2, WC = 4, KC = 32, DEPTH = 1, OCC = 1;
+};
 template <int V> constexpr int big_threads() { return 64 * BigCfg<V>::WR * BigCfg<V>::WC; }
 template <int V> constexpr int big_lds() { return 2 * 2 * BigCfg<V>::KC * (kBig + 2); }
 
@@ -494,7 +497,7 @@ __device__ __forceinline__ T pick3(bool s1, bool s2, T v0, T v1, T v2) {
 
 // Geometry of the chunk held in the staging registers.
 struct ChunkInfo {
-  bool fa, fb;
+  bool fa, fb;     // operand rows contiguous
   int kc, k1;
   double alpha;
 };
@@ -1218,10 +1221,10 @@ __global__ __launch_bounds__(big_threads<V>(), BigCfg<V>::OCC) void tile_big_ker
 // Layout of the big-tile kernel: the engine's choice (the autotuner's, else
 // 0); INLA_BIG_VARIANT=0|1 in the environment overrides it.
 static int g_big_variant = 0;
-void set_big_variant(int v) { g_big_variant = (v == 1) ? 1 : 0; }
+void set_big_variant(int v) { g_big_variant = (v >= 0 && v < kBigVariants) ? v : 0; }
 int big_variant() {
   const char *e = getenv("INLA_BIG_VARIANT");
-  if (e && (e[0] == '0' || e[0] == '1')) return e[0] - '0';
+  if (e && e[0] >= '0' && e[0] < '0' + kBigVariants) return e[0] - '0';
   return g_big_variant;
 }
 
@@ -1263,12 +1266,19 @@ hipError_t launch_tile_phase(const ItemDev *items_dev, int n_items, int total, i
   if (total <= 0) return hipSuccess;
   if (big && phase_is_product_x(phase) && phase2 < 0) {
     const long long grid = (long long)total * ks;
-    if (big_variant() == 0)
-      hipLaunchKernelGGL(tile_big_kernel<0>, dim3((unsigned)grid), dim3(big_threads<0>()), 0, s,
-                         items_dev, n_items, phase, t, ks);
-    else
-      hipLaunchKernelGGL(tile_big_kernel<1>, dim3((unsigned)grid), dim3(big_threads<1>()), 0, s,
-                         items_dev, n_items, phase, t, ks);
+    switch (big_variant()) {
+      case 1:
+        hipLaunchKernelGGL(tile_big_kernel<1>, dim3((unsigned)grid), dim3(big_threads<1>()), 0, s,
+                           items_dev, n_items, phase, t, ks);
+        break;
+      case 2:
+        hipLaunchKernelGGL(tile_big_kernel<2>, dim3((unsigned)grid), dim3(big_threads<2>()), 0, s,
+                           items_dev, n_items, phase, t, ks);
+        break;
+      default:
+        hipLaunchKernelGGL(tile_big_kernel<0>, dim3((unsigned)grid), dim3(big_threads<0>()), 0, s,
+                           items_dev, n_items, phase, t, ks);
+    }
     if (ks > 1) {
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
