@@ -60,7 +60,7 @@ struct Task {
   double beta;                    // C = beta*C + sum_s alpha_s op(A_s) op(B_s)^T
   int nseg;
   Seg seg[3];
-  int mirror;                     // also store C^T at Cm (symmetric output)
+  int mirror;                     // 1: also store C^T at Cm (symmetric output); 2: zeros there
   int diagtile;                   // mirror: lower entries only
   double *Cm;
   int chol;                       // Cholesky + inverse of the result tile -> Lout
@@ -115,7 +115,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
     case PH_DIAG0: {
       tk.m = tk.n = tdim(b, 0);
       tk.C = Dt; tk.ldc = b; tk.beta = 1.0;
-      tk.chol = 1; tk.Lout = it.W1; tk.ldl = b;
+      tk.chol = 1; tk.Lout = Dt; tk.ldl = b;
       tk.ldsum = it.ldpart + (long long)t * nP; tk.row_off = t * b;
       tk.Mout = it.Mp;
       return;
@@ -139,7 +139,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
         const int ip = p + 1 + q;
         tk.m = tdim(b, ip); tk.n = kTile;
         tk.C = it.W2 + toff(b, ip, p); tk.ldc = b;
-        set_seg(tk.seg[0], Dt + toff(b, ip, p), 1, b, it.W1 + toff(b, p, p), 1, b, 0, kTile, 1.0);
+        set_seg(tk.seg[0], Dt + toff(b, ip, p), 1, b, Dt + toff(b, p, p), 1, b, 0, kTile, 1.0);
         tk.nseg = 1;
         return;
       } else if (q < npan + ncol) {
@@ -156,15 +156,18 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
         tk.nseg = 1;
         return;
       } else {
-        // row p of X = inv(L_tt): X_pj = -X_pp sum_{m=j}^{p-1} L_pm X_mj, j < p
-        // (L from W2; X rows m < p, and X_pp, from earlier steps in W1)
+        // row p of X = inv(L_tt): X_pj = -X_pp sum_{m=j}^{p-1} L_pm X_mj, j < p.
+        // X is built in place of D[t]: its columns j < p are no longer needed
+        // by the factorization (L is in W2); the tile (j,p) above the diagonal
+        // is set to zero at the same time.
         const int j = q - npan - ncol - ndef;
         tk.kind = TK_LCHAIN;
         tk.m = tdim(b, p); tk.n = kTile;
-        tk.C = it.W1 + toff(b, p, j); tk.ldc = b;
-        set_seg(tk.seg[0], it.W2 + (long long)p * kTile, 1, b, it.W1 + (long long)j * kTile * b, b,
-                1, j * kTile, p * kTile, 1.0);
-        set_seg(tk.seg[1], it.W1 + toff(b, p, p), 1, b, nullptr, 0, 0, 0, tdim(b, p), -1.0);
+        tk.C = Dt + toff(b, p, j); tk.ldc = b;
+        tk.mirror = 2; tk.Cm = Dt + toff(b, j, p);
+        set_seg(tk.seg[0], it.W2 + (long long)p * kTile, 1, b, Dt + (long long)j * kTile * b, b, 1,
+                j * kTile, p * kTile, 1.0);
+        set_seg(tk.seg[1], Dt + toff(b, p, p), 1, b, nullptr, 0, 0, 0, tdim(b, p), -1.0);
         tk.nseg = 1;
         return;
       }
@@ -184,7 +187,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
         set_seg(tk.seg[2], nullptr, 1, b, nullptr, 1, b, 0, 0, -1.0);
       tk.nseg = 1;
       if (i == jc) {
-        tk.chol = 1; tk.Lout = it.W1 + toff(b, i, i); tk.ldl = b;
+        tk.chol = 1; tk.Lout = Dt + toff(b, i, i); tk.ldl = b;
         tk.ldsum = it.ldpart + (long long)t * nP + i; tk.row_off = t * b + i * kTile;
         tk.Mout = it.Mp + (long long)((p + 1) & 1) * kTile * kTile;
       }
@@ -194,7 +197,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       const int i = q / nP, j = q % nP;
       tk.m = tdim(b, i); tk.n = tdim(b, j);
       tk.C = it.W2 + toff(b, i, j); tk.ldc = b;
-      set_seg(tk.seg[0], St + (long long)i * kTile, 1, b, it.W1 + (long long)j * kTile, 1, b, 0,
+      set_seg(tk.seg[0], St + (long long)i * kTile, 1, b, Dt + (long long)j * kTile, 1, b, 0,
               min(b, (j + 1) * kTile), 1.0);
       tk.nseg = 1;
       return;
@@ -206,20 +209,14 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
           const int j = idx;
           tk.m = a; tk.n = tdim(b, j);
           tk.C = it.W3 + (long long)j * kTile * a; tk.ldc = a;
-          set_seg(tk.seg[0], Rt, 1, a, it.W1 + (long long)j * kTile, 1, b, 0, min(b, (j + 1) * kTile),
+          set_seg(tk.seg[0], Rt, 1, a, Dt + (long long)j * kTile, 1, b, 0, min(b, (j + 1) * kTile),
                   1.0);
           tk.nseg = 1;
           return;
         }
         idx -= nP;
       }
-      {
-        // D[t] <- inv(L_tt): lower tiles copied from the workspace, upper tiles zero
-        const int i = idx / nP, j = idx % nP;
-        tk.kind = (i >= j) ? TK_COPY : TK_ZERO;
-        tk.m = tdim(b, i); tk.n = tdim(b, j);
-        tk.src = it.W1 + toff(b, i, j); tk.C = Dt + toff(b, i, j); tk.ldc = b;
-      }
+      tk.kind = TK_NONE;
       return;
     }
     case PH_SCHUR_X: {
@@ -382,7 +379,7 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
       I = q / nQ; J = q % nQ;
       tk.m = bdim(b, I); tk.n = bdim(b, J); tk.ti = I; tk.tj = J;
       tk.C = it.W2 + boff(b, I, J); tk.ldc = b;
-      set_seg(tk.seg[0], St + (long long)I * kBig, 1, b, it.W1 + (long long)J * kBig, 1, b, 0,
+      set_seg(tk.seg[0], St + (long long)I * kBig, 1, b, Dt + (long long)J * kBig, 1, b, 0,
               min(b, (J + 1) * kBig), 1.0);
       tk.nseg = 1;
       return;
@@ -1121,7 +1118,7 @@ __global__ __launch_bounds__(kThreads, FAT ? 1 : 2) void tile_phase_kernel(const
             }
           } else {
             gst(cp, v);
-            if (tk.mirror) gst(tk.Cm + col + row * tk.ldc, v);
+            if (tk.mirror) gst(tk.Cm + col + row * tk.ldc, tk.mirror == 2 ? 0.0 : v);
           }
         }
       }
@@ -1211,7 +1208,7 @@ __global__ __launch_bounds__(big_threads<V>(), BigCfg<V>::OCC) void tile_big_ker
             }
           } else {
             gst(cp, v);
-            if (tk.mirror) gst(tk.Cm + col + row * tk.ldc, v);
+            if (tk.mirror) gst(tk.Cm + col + row * tk.ldc, tk.mirror == 2 ? 0.0 : v);
           }
         }
       }

@@ -4,10 +4,11 @@
 // launches on the caller's stream:
 //   factor   (per time step t, all items in lockstep)
 //       DIAG0, then for each 64-wide tile p one STEP(p) launch (panel p of L,
-//       the trailing update, the Cholesky + inverse of tile p+1, and row p of
-//       inv(L_tt)); then OFFDIAG (X = S[t] inv(L_tt)^T, R' = R[t] inv(L_tt)^T)
-//       and SCHUR (D[t+1] -= X X^T, R[t+1] -= R' X^T, T -= R' R'^T); finally
-//       ARROW.
+//       the lookahead update of column p+1, the rest of panel p-1's update,
+//       row p of inv(L_tt) written in place into D[t]) with the Cholesky +
+//       inverse of tile p+1 fused or beside it; then OFFDIAG (X = S[t]
+//       inv(L_tt)^T, R' = R[t] inv(L_tt)^T) and SCHUR (D[t+1] -= X X^T,
+//       R[t+1] -= R' X^T, T -= R' R'^T); finally ARROW.
 //   selected inversion (t = nt-1 .. 0), the block form of the Takahashi
 //   recursion (paper, Sec. "Partial Inversion"), derived from Sigma L = L^{-T}
 //   read block column by block column:

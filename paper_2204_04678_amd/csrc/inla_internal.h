@@ -42,7 +42,8 @@ struct ModelDev {
 struct ItemDev {
   int b, nt, a, nP;              // block size, time blocks, arrow width, ceil(b / kTile)
   double *D, *S, *R, *T;         // BTA storage (Q in, factor out)
-  double *W1, *W2, *W3;          // workspace: b*b, b*b, a*b
+  double *W1, *W2, *W3;          // workspace: b*b (Sigma_S in the selected inversion),
+                                 //   b*b (panels of L_tt, then S[t] Linv^T), a*b
   double *Mp;                    // 2 x 64 x 64: inverse of the current diagonal tile, by parity
   double *P;                     // kSplitK * b * b split-k partial products (or null: no split)
   // Selected inversion: Sigma blocks.  When sd_stride != 0 the blocks of step t
@@ -87,7 +88,7 @@ enum Phase : int {
   PH_STEPF = 3,      // DIAGC(p) and STEP(p) as one launch of the Cholesky-capable kernel
                      //   (few tasks per step: the launch latency dominates)
   PH_OFFDIAG_X = 4,  // X = S[t] Linv^T
-  PH_OFFDIAG = 5,    // R' = R[t] Linv^T; D[t] <- Linv (zeros above)
+  PH_OFFDIAG = 5,    // R' = R[t] Linv^T
   PH_SCHUR_X = 6,    // D[t+1] -= X X^T
   PH_SCHUR = 7,      // R[t+1] -= R' X^T, T -= R' R'^T; copy X, R' back
   PH_ARROW = 8,      // Cholesky + inverse of T
@@ -135,7 +136,7 @@ __host__ __device__ inline int phase_tasks(const ItemDev &it, int phase, int t, 
     }
     case PH_DIAGC: return (p < nP - 1) ? 1 : 0;
     case PH_OFFDIAG_X: return last ? 0 : nQ * nQ;
-    case PH_OFFDIAG: return (arrow ? nP : 0) + nP * nP;
+    case PH_OFFDIAG: return arrow ? nP : 0;
     case PH_SCHUR_X: return last ? 0 : nQ * (nQ + 1) / 2;
     case PH_SCHUR:
       return (last ? 0 : nP * nP) + (arrow ? ((last ? 0 : nP) + 1 + nP) : 0);
