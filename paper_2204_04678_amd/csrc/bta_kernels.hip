@@ -8,6 +8,7 @@
 // factorization and log-determinant, Sec. "Partial Inversion" for the
 // selected inversion; the block recursions are written out in the host engine.
 #include <climits>
+#include <type_traits>
 
 #include "inla_internal.h"
 
@@ -23,16 +24,28 @@ constexpr int kLeanLds = 2 * 2 * kLeanKC * LDP;                      // double-b
 constexpr int kFatLds = 2 * kTile * TLD + 2 * kTile;                 // tile + inverse + logs
 static_assert(kFatLds >= 2 * 2 * kFatKC * LDP, "fat LDS must hold the product panels too");
 // Big-tile kernel layouts: WR x WC waves over a 128 x 128 tile, k-chunk KC,
-// register prefetch depth DEPTH, and the waves per SIMD it is built for.
+// register prefetch depth DEPTH (register-staged layouts) or direct loads into
+// LDS (DMA), and the minimum waves per SIMD it is built for (OCC).
 template <int V> struct BigCfg;
-template <> struct BigCfg<0> {   // 8 waves of 64 x 32, two waves per SIMD
+template <> struct BigCfg<0> {   // 8 waves of 64 x 32, two register sets
   static constexpr int WR = 2, WC = 4, KC = 16, DEPTH = 2, OCC = 1;
+  static constexpr bool DMA = false;
 };
 template <> struct BigCfg<1> {   // 4 waves of 64 x 64, one wave per SIMD
   static constexpr int WR = 2, WC = 2, KC = 16, DEPTH = 2, OCC = 1;
+  static constexpr bool DMA = false;
 };
 template <> struct BigCfg<2> {   // 8 waves of 64 x 32, deeper k-chunk, one register set
   static constexpr int WR = 2, WC = 4, KC = 32, DEPTH = 1, OCC = 1;
+  static constexpr bool DMA = false;
+};
+template <> struct BigCfg<3> {   // 8 waves of 64 x 32, direct loads, k-chunk 32
+  static constexpr int WR = 2, WC = 4, KC = 32, DEPTH = 1, OCC = 2;
+  static constexpr bool DMA = true;
+};
+template <> struct BigCfg<4> {   // 8 waves of 64 x 32, direct loads, k-chunk 16
+  static constexpr int WR = 2, WC = 4, KC = 16, DEPTH = 1, OCC = 2;
+  static constexpr bool DMA = true;
 };
 template <int V> constexpr int big_threads() { return 64 * BigCfg<V>::WR * BigCfg<V>::WC; }
 template <int V> constexpr int big_lds() { return 2 * 2 * BigCfg<V>::KC * (kBig + 2); }
@@ -609,11 +622,243 @@ __device__ __forceinline__ void run_product(const Task &tk, double *smem,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Direct-to-LDS staging for the 128-wide tile kernel
+// ---------------------------------------------------------------------------
+// global_load_lds_dwordx4 (dword) moves 16 (4) bytes per lane from any global
+// address straight into LDS at M0 + 16 (4) * lane, with no registers and no
+// LDS store instructions in between.  Each chunk of KC k-values of an operand
+// lands in one of two layouts:
+//   P[k][row] (row length kBig + 2): operands whose rows are contiguous
+//     (op(X)(r, k) = X[r + k*ks]); one k-column of 128 rows is 1 KiB, one
+//     wave instruction.
+//   Q[row][k] (row length KC, no padding): operands whose k runs are
+//     contiguous (op(X)(r, k) = X[r*rs + k]); the 16-byte slot j of row r
+//     holds k = 2(j ^ qswz(r)), 2(j ^ qswz(r)) + 1, so that the 16-byte reads
+//     of 8 (16) consecutive rows fall on distinct banks.
+// Out-of-range k reads a 16-byte block of zeros; rows past the tile's end
+// repeat the last row (those rows of the product are never stored).
+// Global addresses need only dword alignment, which every double satisfies.
+__device__ double g_dma_zeros[4];
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
+__device__ __forceinline__ void dma16(const void *src, double *dst) {
+  __builtin_amdgcn_global_load_lds((glb_void_t *)src, (lds_void_t *)dst, 16, 0, 0);
+}
+__device__ __forceinline__ void dma4(const void *src, double *dst) {
+  __builtin_amdgcn_global_load_lds((glb_void_t *)src, (lds_void_t *)dst, 4, 0, 0);
+}
+
+template <int KC>
+__device__ __forceinline__ int qswz(int r16) {
+  // KC = 16: 8 slots of 16 bytes per row; KC = 32: 16 slots
+  return KC == 16 ? ((r16 & 7) ^ (r16 >> 3)) : (r16 & 15);
+}
+
+// Issue the direct loads of rows [0, rows) x k in [kc, kc + KC) of
+// op(X)(r, k) = X[r*rs + k*ks] into dst (layout P if rs == 1, else Q); wave w
+// of NW takes every NW-th instruction.
+template <int KC, int NW>
+__device__ __forceinline__ void dma_operand(const double *X, int rs, int ks, int rows, int kc,
+                                            int k1, double *dst, int w, int lane) {
+  constexpr int LD = kBig + 2;
+  constexpr int SPR = KC / 2;   // 16-byte slots per Q row
+  const double *zero = g_dma_zeros;
+  if (rs == 1) {
+    if ((rows & 1) == 0) {
+      const int r = min(2 * lane, rows - 2);
+#pragma unroll 1
+      for (int i = 0; i < KC / NW; ++i) {
+        const int h = w + i * NW, k = kc + h;
+        dma16(k < k1 ? X + r + (long long)k * ks : zero, dst + h * LD);
+      }
+    } else {
+#pragma unroll 1
+      for (int i = 0; i < 4 * KC / NW; ++i) {
+        const int h = w + i * NW, kk = h >> 2, qd = h & 3;
+        const int d = qd * 64 + lane, r = min(d >> 1, rows - 1), k = kc + kk;
+        const char *src = (const char *)(X + r + (long long)k * ks) + (d & 1) * 4;
+        dma4(k < k1 ? (const void *)src : (const void *)zero, dst + kk * LD + qd * 32);
+      }
+    }
+  } else if (ks == 1 && (kc + KC <= k1 || ((k1 - kc) & 1) == 0)) {
+#pragma unroll 1
+    for (int i = 0; i < KC / NW; ++i) {
+      const int h = w + i * NW, slot = h * 64 + lane;
+      const int row = slot / SPR, j = (slot % SPR) ^ qswz<KC>(row & 15);
+      const int k = kc + 2 * j, r = min(row, rows - 1);
+      dma16(k < k1 ? X + (long long)r * rs + k : zero, dst + h * 128);
+    }
+  } else {
+#pragma unroll 1
+    for (int i = 0; i < 4 * KC / NW; ++i) {
+      const int h = w + i * NW, d = h * 64 + lane, slot = d >> 2, e = d & 3;
+      const int row = slot / SPR, j = (slot % SPR) ^ qswz<KC>(row & 15);
+      const int k = kc + 2 * j + (e >> 1), r = min(row, rows - 1);
+      const char *src = (const char *)(X + (long long)r * rs + (long long)k * ks) + (e & 1) * 4;
+      dma4(k < k1 ? (const void *)src : (const void *)zero, dst + h * 32);
+    }
+  }
+}
+
+// acc += sum over segments of alpha_s op(A_s) op(B_s)^T on a 128 x 128 tile,
+// as run_product but staged with direct loads into two LDS buffers (separate
+// arrays, so the compiler knows that loads into one never wait on reads of
+// the other).  The loads of chunk c + 1 are issued before chunk c is
+// multiplied and waited for after it.  Within a group of 8 k-values, MFMA
+// step s of lane group g = lane / 16 takes k = 2g + s, which lets a Q row
+// deliver both steps' values with one 16-byte read.  The alphas are applied
+// to the accumulator: at a change of segment it is rescaled by
+// alpha_old / alpha_new (segment weights are nonzero), and once at the end.
+template <int KC, int WR, int WC>
+__device__ __forceinline__ void run_product_dma(const Task &tk, double *buf0, double *buf1,
+                                                d4 (&acc)[kBig / WR / 16][kBig / WC / 16],
+                                                int part = 0, int nparts = 1) {
+  constexpr int NW = WR * WC;
+  constexpr int LD = kBig + 2;
+  constexpr int MR = kBig / WR / 16, MC = kBig / WC / 16;
+  constexpr int OPS = KC * LD;    // doubles of one operand's panel (P is the larger layout)
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = w / WC, wc = w % WC;
+  const int n0 = (tk.nseg > 0 && tk.seg[0].k1 > tk.seg[0].k0) ? (tk.seg[0].k1 - tk.seg[0].k0 + KC - 1) / KC : 0;
+  const int n1 = (tk.nseg > 1 && tk.seg[1].k1 > tk.seg[1].k0) ? (tk.seg[1].k1 - tk.seg[1].k0 + KC - 1) / KC : 0;
+  const int n2 = (tk.nseg > 2 && tk.seg[2].k1 > tk.seg[2].k0) ? (tk.seg[2].k1 - tk.seg[2].k0 + KC - 1) / KC : 0;
+  const int all = n0 + n1 + n2;
+  const int cb = (int)((long long)all * part / nparts), ce = (int)((long long)all * (part + 1) / nparts);
+  if (ce <= cb) return;
+  // per-lane LDS offsets (doubles): P reads at k = 2g (+ 8i + s), Q reads of slot 4i + g
+  const int g = lane >> 4, r16 = lane & 15;
+  const int pa = 2 * g * LD + wr * (kBig / WR) + r16, pb = 2 * g * LD + wc * (kBig / WC) + r16;
+  int qo[KC / 8];
+#pragma unroll
+  for (int i = 0; i < KC / 8; ++i) qo[i] = r16 * KC + (((4 * i + g) ^ qswz<KC>(r16)) << 1);
+  const int qa = wr * (kBig / WR) * KC, qb = wc * (kBig / WC) * KC;
+  // chunk c: issue its loads into dst; returns the layouts (bit 0: A in Q, bit 1: B in Q)
+  auto issue = [&](int c, double *dst) -> int {
+    const bool s1 = c >= n0, s2 = c >= n0 + n1;
+    const double *A = pick3(s1, s2, tk.seg[0].A, tk.seg[1].A, tk.seg[2].A);
+    const double *B = pick3(s1, s2, tk.seg[0].B, tk.seg[1].B, tk.seg[2].B);
+    const int ars = pick3(s1, s2, tk.seg[0].ars, tk.seg[1].ars, tk.seg[2].ars);
+    const int aks = pick3(s1, s2, tk.seg[0].aks, tk.seg[1].aks, tk.seg[2].aks);
+    const int brs = pick3(s1, s2, tk.seg[0].brs, tk.seg[1].brs, tk.seg[2].brs);
+    const int bks = pick3(s1, s2, tk.seg[0].bks, tk.seg[1].bks, tk.seg[2].bks);
+    const int k0 = pick3(s1, s2, tk.seg[0].k0, tk.seg[1].k0, tk.seg[2].k0);
+    const int k1 = pick3(s1, s2, tk.seg[0].k1, tk.seg[1].k1, tk.seg[2].k1);
+    const int kc = k0 + (c - (s2 ? n0 + n1 : (s1 ? n0 : 0))) * KC;
+    dma_operand<KC, NW>(A, ars, aks, tk.m, kc, k1, dst, w, lane);
+    dma_operand<KC, NW>(B, brs, bks, tk.n, kc, k1, dst + OPS, w, lane);
+    return (ars != 1 ? 1 : 0) | (brs != 1 ? 2 : 0);
+  };
+  auto seg_alpha = [&](int c) {
+    const bool s1 = c >= n0, s2 = c >= n0 + n1;
+    return pick3(s1, s2, tk.seg[0].alpha, tk.seg[1].alpha, tk.seg[2].alpha);
+  };
+  auto mma = [&](const double (&a0)[MR], const double (&a1)[MR], const double (&b0)[MC],
+                 const double (&b1)[MC]) {
+#pragma unroll
+    for (int mi = 0; mi < MR; ++mi)
+#pragma unroll
+      for (int nj = 0; nj < MC; ++nj)
+        acc[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[mi], b0[nj], acc[mi][nj], 0, 0, 0);
+#pragma unroll
+    for (int mi = 0; mi < MR; ++mi)
+#pragma unroll
+      for (int nj = 0; nj < MC; ++nj)
+        acc[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[mi], b1[nj], acc[mi][nj], 0, 0, 0);
+  };
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  // one chunk with the operand layouts fixed at compile time (AQ / BQ: layout Q)
+  auto compute_as = [&](const double *buf, auto aq_t, auto bq_t) {
+    constexpr bool AQ = decltype(aq_t)::value, BQ = decltype(bq_t)::value;
+    const double *As = buf, *Bs = buf + OPS;
+#pragma unroll
+    for (int i = 0; i < KC / 8; ++i) {
+      double a0[MR], a1[MR], b0[MC], b1[MC];
+#pragma unroll
+      for (int x = 0; x < MR; ++x) {
+        if constexpr (AQ) {
+          const d2 v = *(const d2 *)(As + qa + x * 16 * KC + qo[i]);
+          a0[x] = v.x; a1[x] = v.y;
+        } else {
+          a0[x] = As[pa + 8 * i * LD + x * 16];
+          a1[x] = As[pa + (8 * i + 1) * LD + x * 16];
+        }
+      }
+#pragma unroll
+      for (int x = 0; x < MC; ++x) {
+        if constexpr (BQ) {
+          const d2 v = *(const d2 *)(Bs + qb + x * 16 * KC + qo[i]);
+          b0[x] = v.x; b1[x] = v.y;
+        } else {
+          b0[x] = Bs[pb + 8 * i * LD + x * 16];
+          b1[x] = Bs[pb + (8 * i + 1) * LD + x * 16];
+        }
+      }
+      mma(a0, a1, b0, b1);
+    }
+  };
+  auto compute = [&](const double *buf, int lay) {
+    using F = std::integral_constant<bool, false>;
+    using T = std::integral_constant<bool, true>;
+    switch (lay) {
+      case 0: compute_as(buf, F{}, F{}); break;
+      case 1: compute_as(buf, T{}, F{}); break;
+      case 2: compute_as(buf, F{}, T{}); break;
+      default: compute_as(buf, T{}, T{}); break;
+    }
+  };
+  double cur = seg_alpha(cb);
+  auto rescale = [&](int c) {
+    const double al = seg_alpha(c);
+    if (al != cur) {
+      const double f = cur / al;
+#pragma unroll
+      for (int mi = 0; mi < MR; ++mi)
+#pragma unroll
+        for (int nj = 0; nj < MC; ++nj) acc[mi][nj] *= f;
+      cur = al;
+    }
+  };
+  constexpr unsigned kVmcnt0 = 0x0F70;   // s_waitcnt vmcnt(0), other counters free
+  int lay0 = issue(cb, buf0), lay1 = 0;
+  __builtin_amdgcn_s_waitcnt(kVmcnt0);
+  __syncthreads();
+  for (int c = cb; c < ce; c += 2) {
+    if (c + 1 < ce) lay1 = issue(c + 1, buf1);
+    __builtin_amdgcn_sched_barrier(0);
+    rescale(c);
+    compute(buf0, lay0);
+    __builtin_amdgcn_s_waitcnt(kVmcnt0);
+    __syncthreads();
+    if (c + 1 >= ce) break;
+    if (c + 2 < ce) lay0 = issue(c + 2, buf0);
+    __builtin_amdgcn_sched_barrier(0);
+    rescale(c + 1);
+    compute(buf1, lay1);
+    __builtin_amdgcn_s_waitcnt(kVmcnt0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int mi = 0; mi < MR; ++mi)
+#pragma unroll
+    for (int nj = 0; nj < MC; ++nj) acc[mi][nj] *= cur;
+}
+
 // Output mapping of v_mfma_f64_16x16x4f64: lane l, element r -> row (l>>4) + 4r, col l&15.
 __device__ inline int acc_row(int wr, int mi, int lane, int r) {
   return wr * 32 + mi * 16 + (lane >> 4) + 4 * r;
 }
 __device__ inline int acc_col(int wc, int nj, int lane) { return wc * 32 + nj * 16 + (lane & 15); }
+
+// Value of x in lane m of the wave (m a compile-time constant), as a scalar.
+__device__ __forceinline__ double lane_value(double x, int m) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, m);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), m);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
 
 // 1/x and 1/sqrt(x) from the hardware estimates, each refined by two Newton
 // steps (r <- r + r(1 - x r) and y <- y + y(1 - x y^2)/2), which take the
@@ -639,22 +884,20 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 // (X_ij = -X_ii sum_m L_im X_mj) run on the matrix cores.  Writes inv(L)
 // (zeros above the diagonal) to Lout and sum log L_jj; a pivot that is not
 // positive sets *info to its 1-based row (row_off + local row) if smaller.
-// dlog holds 64 logs followed by a 16-entry column buffer (2 * kTile doubles).
+// dlog holds the 64 logs of the diagonal (its 2 * kTile doubles leave room).
 // If Mout is set, M = X^T X = inv(A) (64 x 64, column-major) is written there too.
 __device__ void chol_inv_tile(double *A, double *X, double *dlog, int w, double *Lout,
                               long long ldl, double *ldsum, int row_off, int *info, double *Mout) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nb = (w + 15) / 16;
   const int lr = lane & 15, lk = lane >> 4;
-  double *col = dlog + kTile;   // 16-entry column broadcast buffer
   for (int k = 0; k < nb; ++k) {
     // (a) factor and invert the diagonal block (k,k) in wave 0.  Cholesky,
-    //     right-looking: lane i holds row i; at pivot j the lanes publish
-    //     column j in LDS and read it back whole (broadcast reads), so the
-    //     update needs no cross-lane moves.  Then the inverse by forward
+    //     right-looking: lane i holds row i (lanes 16..63 hold copies); at
+    //     pivot j column j is read out of lanes j..15 into scalar registers
+    //     (v_readlane), so the only latency between pivots is the pivot's
+    //     reciprocal and one update.  Then the inverse by forward
     //     substitution, lane c computing column c from the rows of L in LDS.
-    //     Reads follow writes of the same wave in order; the wave barriers
-    //     keep the compiler from moving LDS accesses across them.
     if (wv == 0) {
       const int r0 = 16 * k;
       double a[16], rinv[16];
@@ -666,12 +909,9 @@ __device__ void chol_inv_tile(double *A, double *X, double *dlog, int w, double 
       for (int c = 0; c < 16; ++c) a[c] = A[(r0 + lr16) * TLD + r0 + c];
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        if (lane < 16) col[lane] = a[j];
-        __builtin_amdgcn_wave_barrier();
         double cv[16];
 #pragma unroll
-        for (int m = j; m < 16; ++m) cv[m] = col[m];
-        __builtin_amdgcn_wave_barrier();
+        for (int m = j; m < 16; ++m) cv[m] = lane_value(a[j], m);
         const double piv = cv[j];
         const double ip = recip_nr(piv);
         const double rs = rsqrt_nr(piv);
@@ -681,11 +921,6 @@ __device__ void chol_inv_tile(double *A, double *X, double *dlog, int w, double 
 #pragma unroll
         for (int m = j + 1; m < 16; ++m) a[m] = fma(-wj, cv[m], a[m]);
         a[j] *= rs;
-        // one pivot at a time: the empty asm statements make this step's
-        // updates happen here (deferring them would keep every step's column
-        // live at once)
-#pragma unroll
-        for (int m = j; m < 16; ++m) asm volatile("" : "+v"(a[m]));
       }
       if (lane < 16) {
 #pragma unroll
@@ -1145,7 +1380,6 @@ __global__ __launch_bounds__(big_threads<V>(), BigCfg<V>::OCC) void tile_big_ker
     const ItemDev *__restrict__ items, int n_items, int phase, int t, int ks) {
   using C = BigCfg<V>;
   constexpr int MR = kBig / C::WR / 16, MC = kBig / C::WC / 16;
-  __shared__ double smem[big_lds<V>()];
   const int qa = xcd_contiguous(blockIdx.x, gridDim.x);
   int q = qa / ks;
   const int part = qa - q * ks;
@@ -1163,7 +1397,14 @@ __global__ __launch_bounds__(big_threads<V>(), BigCfg<V>::OCC) void tile_big_ker
   for (int mi = 0; mi < MR; ++mi)
 #pragma unroll
     for (int nj = 0; nj < MC; ++nj) acc[mi][nj] = d4{0.0, 0.0, 0.0, 0.0};
-  run_product<C::KC, kBig, C::WR, C::WC, C::DEPTH>(tk, smem, acc, part, ks);
+  if constexpr (C::DMA) {
+    __shared__ __attribute__((aligned(16))) double stage0[big_lds<V>() / 2];
+    __shared__ __attribute__((aligned(16))) double stage1[big_lds<V>() / 2];
+    run_product_dma<C::KC, C::WR, C::WC>(tk, stage0, stage1, acc, part, ks);
+  } else {
+    __shared__ double smem[big_lds<V>()];
+    run_product<C::KC, kBig, C::WR, C::WC, C::DEPTH>(tk, smem, acc, part, ks);
+  }
   if (ks > 1) {
     double *Pp = it.P + (long long)part * it.b * it.b + (long long)tk.ti * kBig +
                  (long long)tk.tj * kBig * it.b;
@@ -1216,7 +1457,7 @@ __global__ __launch_bounds__(big_threads<V>(), BigCfg<V>::OCC) void tile_big_ker
 }
 
 // Layout of the big-tile kernel: the engine's choice (the autotuner's, else
-// 0); INLA_BIG_VARIANT=0|1 in the environment overrides it.
+// 0); INLA_BIG_VARIANT=0..4 in the environment overrides it.
 static int g_big_variant = 0;
 void set_big_variant(int v) { g_big_variant = (v >= 0 && v < kBigVariants) ? v : 0; }
 int big_variant() {
@@ -1264,6 +1505,14 @@ hipError_t launch_tile_phase(const ItemDev *items_dev, int n_items, int total, i
   if (big && phase_is_product_x(phase) && phase2 < 0) {
     const long long grid = (long long)total * ks;
     switch (big_variant()) {
+      case 4:
+        hipLaunchKernelGGL(tile_big_kernel<4>, dim3((unsigned)grid), dim3(big_threads<4>()), 0, s,
+                           items_dev, n_items, phase, t, ks);
+        break;
+      case 3:
+        hipLaunchKernelGGL(tile_big_kernel<3>, dim3((unsigned)grid), dim3(big_threads<3>()), 0, s,
+                           items_dev, n_items, phase, t, ks);
+        break;
       case 1:
         hipLaunchKernelGGL(tile_big_kernel<1>, dim3((unsigned)grid), dim3(big_threads<1>()), 0, s,
                            items_dev, n_items, phase, t, ks);

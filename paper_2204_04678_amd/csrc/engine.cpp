@@ -1362,8 +1362,8 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
     } else {
       // time every candidate eagerly (one untimed run, one timed) on the
       // caller's stream; every run computes the same outputs
-      const TileChoice cands[1 + kBigVariants] = {{64, 0, 0.0}, {128, 0, 0.0}, {128, 1, 0.0},
-                                                   {128, 2, 0.0}};
+      const TileChoice cands[1 + kBigVariants] = {{64, 0, 0.0},  {128, 0, 0.0}, {128, 1, 0.0},
+                                                   {128, 2, 0.0}, {128, 3, 0.0}, {128, 4, 0.0}};
       hipEvent_t e0, e1;
       HIP_TRY(hipEventCreate(&e0));
       HIP_TRY(hipEventCreate(&e1));

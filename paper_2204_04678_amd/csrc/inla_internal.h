@@ -163,8 +163,9 @@ hipError_t launch_fill_int(int *ptr, long long n, int v, hipStream_t s);
 hipError_t launch_logdet_finish(const ItemDev *items_dev, int n_items, double *logdet_out,
                                 int *info_out, hipStream_t s, int stride = 1);
 // Layout of the 128-wide tile kernel (0: 8 waves of 64 x 32, k-chunk 16, two
-// register sets; 1: 4 waves of 64 x 64; 2: as 0 with k-chunk 32, one set).
-constexpr int kBigVariants = 3;
+// register sets; 1: 4 waves of 64 x 64; 2: as 0 with k-chunk 32, one set;
+// 3, 4: 8 waves of 64 x 32 staged by direct loads into LDS, k-chunk 32 / 16).
+constexpr int kBigVariants = 5;
 void set_big_variant(int v);
 int big_variant();
 // ---- model kernels (model_kernels.hip) ----

@@ -18,11 +18,17 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-@pytest.fixture(params=["64", "128"], ids=["tile64", "tile128"])
+@pytest.fixture(params=[("64", None), ("128", "0"), ("128", "3"), ("128", "4")],
+                ids=["tile64", "tile128", "tile128dma32", "tile128dma16"])
 def tile(request, monkeypatch):
-    """Run the b x b product phases on 64- or 128-wide tiles."""
-    monkeypatch.setenv("INLA_TILE", request.param)
-    return request.param
+    """Run the b x b product phases on 64- or 128-wide tiles; the 128-wide
+    ones with register staging (layout 0) or direct-to-LDS staging with
+    k-chunks of 32 and 16 (layouts 3 and 4)."""
+    size, variant = request.param
+    monkeypatch.setenv("INLA_TILE", size)
+    if variant is not None:
+        monkeypatch.setenv("INLA_BIG_VARIANT", variant)
+    return size
 
 
 @pytest.fixture(scope="module")
