@@ -43,8 +43,12 @@ template <> struct BigCfg<3> {   // 8 waves of 64 x 32, direct loads, k-chunk 32
   static constexpr int WR = 2, WC = 4, KC = 32, DEPTH = 1, OCC = 2;
   static constexpr bool DMA = true;
 };
-template <> struct BigCfg<4> {   // 8 waves of 64 x 32, direct loads, k-chunk 16
-  static constexpr int WR = 2, WC = 4, KC = 16, DEPTH = 1, OCC = 2;
+template <> struct BigCfg<4> {   // 8 waves of 64 x 32, direct loads, k-chunk 16, 2 workgroups per CU
+  static constexpr int WR = 2, WC = 4, KC = 16, DEPTH = 1, OCC = 4;
+  static constexpr bool DMA = true;
+};
+template <> struct BigCfg<5> {   // 4 waves of 64 x 64, direct loads, k-chunk 16, 2 workgroups per CU
+  static constexpr int WR = 2, WC = 2, KC = 16, DEPTH = 1, OCC = 2;
   static constexpr bool DMA = true;
 };
 template <int V> constexpr int big_threads() { return 64 * BigCfg<V>::WR * BigCfg<V>::WC; }
@@ -628,12 +632,12 @@ __device__ __forceinline__ void run_product(const Task &tk, double *smem,
 // global_load_lds_dwordx4 (dword) moves 16 (4) bytes per lane from any global
 // address straight into LDS at M0 + 16 (4) * lane, with no registers and no
 // LDS store instructions in between.  Each chunk of KC k-values of an operand
-// lands in one of two layouts:
-//   P[k][row] (row length kBig + 2): operands whose rows are contiguous
-//     (op(X)(r, k) = X[r + k*ks]); one k-column of 128 rows is 1 KiB, one
+// lands in one of two layouts, fixed per launch and operand:
+//   P[k][row] (row length kBig + 2), for operands whose rows are contiguous
+//     (op(X)(r, k) = X[r + k*ks]): one k-column of 128 rows is 1 KiB, one
 //     wave instruction.
-//   Q[row][k] (row length KC, no padding): operands whose k runs are
-//     contiguous (op(X)(r, k) = X[r*rs + k]); the 16-byte slot j of row r
+//   Q[row][k] (row length KC, no padding), for operands whose k runs are
+//     contiguous (op(X)(r, k) = X[r*rs + k]): the 16-byte slot j of row r
 //     holds k = 2(j ^ qswz(r)), 2(j ^ qswz(r)) + 1, so that the 16-byte reads
 //     of 8 (16) consecutive rows fall on distinct banks.
 // Out-of-range k reads a 16-byte block of zeros; rows past the tile's end
@@ -657,16 +661,19 @@ __device__ __forceinline__ int qswz(int r16) {
 }
 
 // Issue the direct loads of rows [0, rows) x k in [kc, kc + KC) of
-// op(X)(r, k) = X[r*rs + k*ks] into dst (layout P if rs == 1, else Q); wave w
-// of NW takes every NW-th instruction.
-template <int KC, int NW>
+// op(X)(r, k) = X[r*rs + k*ks] into dst in layout Q (QL) or P; wave w of NW
+// takes every NW-th instruction.  16-byte pieces where the operand's
+// contiguous direction matches the layout (and, in P, an even row count keeps
+// the last pair inside the operand; in Q, k-pairs do not straddle k1), else
+// 4-byte pieces with any strides.
+template <int KC, int NW, bool QL>
 __device__ __forceinline__ void dma_operand(const double *X, int rs, int ks, int rows, int kc,
                                             int k1, double *dst, int w, int lane) {
   constexpr int LD = kBig + 2;
   constexpr int SPR = KC / 2;   // 16-byte slots per Q row
   const double *zero = g_dma_zeros;
-  if (rs == 1) {
-    if ((rows & 1) == 0) {
+  if constexpr (!QL) {
+    if (rs == 1 && (rows & 1) == 0) {
       const int r = min(2 * lane, rows - 2);
 #pragma unroll 1
       for (int i = 0; i < KC / NW; ++i) {
@@ -678,26 +685,28 @@ __device__ __forceinline__ void dma_operand(const double *X, int rs, int ks, int
       for (int i = 0; i < 4 * KC / NW; ++i) {
         const int h = w + i * NW, kk = h >> 2, qd = h & 3;
         const int d = qd * 64 + lane, r = min(d >> 1, rows - 1), k = kc + kk;
-        const char *src = (const char *)(X + r + (long long)k * ks) + (d & 1) * 4;
+        const char *src = (const char *)(X + (long long)r * rs + (long long)k * ks) + (d & 1) * 4;
         dma4(k < k1 ? (const void *)src : (const void *)zero, dst + kk * LD + qd * 32);
       }
     }
-  } else if (ks == 1 && (kc + KC <= k1 || ((k1 - kc) & 1) == 0)) {
-#pragma unroll 1
-    for (int i = 0; i < KC / NW; ++i) {
-      const int h = w + i * NW, slot = h * 64 + lane;
-      const int row = slot / SPR, j = (slot % SPR) ^ qswz<KC>(row & 15);
-      const int k = kc + 2 * j, r = min(row, rows - 1);
-      dma16(k < k1 ? X + (long long)r * rs + k : zero, dst + h * 128);
-    }
   } else {
+    if (ks == 1 && (kc + KC <= k1 || ((k1 - kc) & 1) == 0)) {
 #pragma unroll 1
-    for (int i = 0; i < 4 * KC / NW; ++i) {
-      const int h = w + i * NW, d = h * 64 + lane, slot = d >> 2, e = d & 3;
-      const int row = slot / SPR, j = (slot % SPR) ^ qswz<KC>(row & 15);
-      const int k = kc + 2 * j + (e >> 1), r = min(row, rows - 1);
-      const char *src = (const char *)(X + (long long)r * rs + (long long)k * ks) + (e & 1) * 4;
-      dma4(k < k1 ? (const void *)src : (const void *)zero, dst + h * 32);
+      for (int i = 0; i < KC / NW; ++i) {
+        const int h = w + i * NW, slot = h * 64 + lane;
+        const int row = slot / SPR, j = (slot % SPR) ^ qswz<KC>(row & 15);
+        const int k = kc + 2 * j, r = min(row, rows - 1);
+        dma16(k < k1 ? X + (long long)r * rs + k : zero, dst + h * 128);
+      }
+    } else {
+#pragma unroll 1
+      for (int i = 0; i < 4 * KC / NW; ++i) {
+        const int h = w + i * NW, d = h * 64 + lane, slot = d >> 2, e = d & 3;
+        const int row = slot / SPR, j = (slot % SPR) ^ qswz<KC>(row & 15);
+        const int k = kc + 2 * j + (e >> 1), r = min(row, rows - 1);
+        const char *src = (const char *)(X + (long long)r * rs + (long long)k * ks) + (e & 1) * 4;
+        dma4(k < k1 ? (const void *)src : (const void *)zero, dst + h * 32);
+      }
     }
   }
 }
@@ -711,7 +720,7 @@ __device__ __forceinline__ void dma_operand(const double *X, int rs, int ks, int
 // deliver both steps' values with one 16-byte read.  The alphas are applied
 // to the accumulator: at a change of segment it is rescaled by
 // alpha_old / alpha_new (segment weights are nonzero), and once at the end.
-template <int KC, int WR, int WC>
+template <int KC, int WR, int WC, bool AQ, bool BQ>
 __device__ __forceinline__ void run_product_dma(const Task &tk, double *buf0, double *buf1,
                                                 d4 (&acc)[kBig / WR / 16][kBig / WC / 16],
                                                 int part = 0, int nparts = 1) {
@@ -735,8 +744,8 @@ __device__ __forceinline__ void run_product_dma(const Task &tk, double *buf0, do
 #pragma unroll
   for (int i = 0; i < KC / 8; ++i) qo[i] = r16 * KC + (((4 * i + g) ^ qswz<KC>(r16)) << 1);
   const int qa = wr * (kBig / WR) * KC, qb = wc * (kBig / WC) * KC;
-  // chunk c: issue its loads into dst; returns the layouts (bit 0: A in Q, bit 1: B in Q)
-  auto issue = [&](int c, double *dst) -> int {
+  // chunk c: issue its loads into dst
+  auto issue = [&](int c, double *dst) {
     const bool s1 = c >= n0, s2 = c >= n0 + n1;
     const double *A = pick3(s1, s2, tk.seg[0].A, tk.seg[1].A, tk.seg[2].A);
     const double *B = pick3(s1, s2, tk.seg[0].B, tk.seg[1].B, tk.seg[2].B);
@@ -747,9 +756,8 @@ __device__ __forceinline__ void run_product_dma(const Task &tk, double *buf0, do
     const int k0 = pick3(s1, s2, tk.seg[0].k0, tk.seg[1].k0, tk.seg[2].k0);
     const int k1 = pick3(s1, s2, tk.seg[0].k1, tk.seg[1].k1, tk.seg[2].k1);
     const int kc = k0 + (c - (s2 ? n0 + n1 : (s1 ? n0 : 0))) * KC;
-    dma_operand<KC, NW>(A, ars, aks, tk.m, kc, k1, dst, w, lane);
-    dma_operand<KC, NW>(B, brs, bks, tk.n, kc, k1, dst + OPS, w, lane);
-    return (ars != 1 ? 1 : 0) | (brs != 1 ? 2 : 0);
+    dma_operand<KC, NW, AQ>(A, ars, aks, tk.m, kc, k1, dst, w, lane);
+    dma_operand<KC, NW, BQ>(B, brs, bks, tk.n, kc, k1, dst + OPS, w, lane);
   };
   auto seg_alpha = [&](int c) {
     const bool s1 = c >= n0, s2 = c >= n0 + n1;
@@ -769,9 +777,8 @@ __device__ __forceinline__ void run_product_dma(const Task &tk, double *buf0, do
         acc[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[mi], b1[nj], acc[mi][nj], 0, 0, 0);
   };
   typedef double d2 __attribute__((ext_vector_type(2)));
-  // one chunk with the operand layouts fixed at compile time (AQ / BQ: layout Q)
-  auto compute_as = [&](const double *buf, auto aq_t, auto bq_t) {
-    constexpr bool AQ = decltype(aq_t)::value, BQ = decltype(bq_t)::value;
+  // one chunk (layouts AQ / BQ: operand in layout Q)
+  auto compute = [&](const double *buf) {
     const double *As = buf, *Bs = buf + OPS;
 #pragma unroll
     for (int i = 0; i < KC / 8; ++i) {
@@ -799,16 +806,6 @@ __device__ __forceinline__ void run_product_dma(const Task &tk, double *buf0, do
       mma(a0, a1, b0, b1);
     }
   };
-  auto compute = [&](const double *buf, int lay) {
-    using F = std::integral_constant<bool, false>;
-    using T = std::integral_constant<bool, true>;
-    switch (lay) {
-      case 0: compute_as(buf, F{}, F{}); break;
-      case 1: compute_as(buf, T{}, F{}); break;
-      case 2: compute_as(buf, F{}, T{}); break;
-      default: compute_as(buf, T{}, T{}); break;
-    }
-  };
   double cur = seg_alpha(cb);
   auto rescale = [&](int c) {
     const double al = seg_alpha(c);
@@ -822,21 +819,21 @@ __device__ __forceinline__ void run_product_dma(const Task &tk, double *buf0, do
     }
   };
   constexpr unsigned kVmcnt0 = 0x0F70;   // s_waitcnt vmcnt(0), other counters free
-  int lay0 = issue(cb, buf0), lay1 = 0;
+  issue(cb, buf0);
   __builtin_amdgcn_s_waitcnt(kVmcnt0);
   __syncthreads();
   for (int c = cb; c < ce; c += 2) {
-    if (c + 1 < ce) lay1 = issue(c + 1, buf1);
+    if (c + 1 < ce) issue(c + 1, buf1);
     __builtin_amdgcn_sched_barrier(0);
     rescale(c);
-    compute(buf0, lay0);
+    compute(buf0);
     __builtin_amdgcn_s_waitcnt(kVmcnt0);
     __syncthreads();
     if (c + 1 >= ce) break;
-    if (c + 2 < ce) lay0 = issue(c + 2, buf0);
+    if (c + 2 < ce) issue(c + 2, buf0);
     __builtin_amdgcn_sched_barrier(0);
     rescale(c + 1);
-    compute(buf1, lay1);
+    compute(buf1);
     __builtin_amdgcn_s_waitcnt(kVmcnt0);
     __syncthreads();
   }
@@ -1375,7 +1372,8 @@ __device__ __forceinline__ int xcd_contiguous(int bid, int n) {
 // task numbers, so on one XCD); part h writes its partial product, without
 // beta or mirroring, to it.P + h*b*b at the tile's position (ld b), and
 // splitk_reduce_kernel forms C.
-template <int V>
+// LAY (layouts staged by direct loads): bit 0 A in layout Q, bit 1 B in layout Q.
+template <int V, int LAY = 0>
 __global__ __launch_bounds__(big_threads<V>(), BigCfg<V>::OCC) void tile_big_kernel(
     const ItemDev *__restrict__ items, int n_items, int phase, int t, int ks) {
   using C = BigCfg<V>;
@@ -1400,7 +1398,8 @@ __global__ __launch_bounds__(big_threads<V>(), BigCfg<V>::OCC) void tile_big_ker
   if constexpr (C::DMA) {
     __shared__ __attribute__((aligned(16))) double stage0[big_lds<V>() / 2];
     __shared__ __attribute__((aligned(16))) double stage1[big_lds<V>() / 2];
-    run_product_dma<C::KC, C::WR, C::WC>(tk, stage0, stage1, acc, part, ks);
+    run_product_dma<C::KC, C::WR, C::WC, (LAY & 1) != 0, (LAY & 2) != 0>(tk, stage0, stage1, acc,
+                                                                         part, ks);
   } else {
     __shared__ double smem[big_lds<V>()];
     run_product<C::KC, kBig, C::WR, C::WC, C::DEPTH>(tk, smem, acc, part, ks);
@@ -1457,9 +1456,11 @@ __global__ __launch_bounds__(big_threads<V>(), BigCfg<V>::OCC) void tile_big_ker
 }
 
 // Layout of the big-tile kernel: the engine's choice (the autotuner's, else
-// 0); INLA_BIG_VARIANT=0..4 in the environment overrides it.
-static int g_big_variant = 0;
-void set_big_variant(int v) { g_big_variant = (v >= 0 && v < kBigVariants) ? v : 0; }
+// the default); INLA_BIG_VARIANT=0..5 in the environment overrides it.
+static int g_big_variant = kDefaultBigVariant;
+void set_big_variant(int v) {
+  g_big_variant = (v >= 0 && v < kBigVariants) ? v : kDefaultBigVariant;
+}
 int big_variant() {
   const char *e = getenv("INLA_BIG_VARIANT");
   if (e && e[0] >= '0' && e[0] < '0' + kBigVariants) return e[0] - '0';
@@ -1499,26 +1500,50 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const ItemDev *__res
   }
 }
 
+// Direct-load layouts of the product phases' operands: rows of S, W2 and D
+// (layout P) in the factorization; Sigma_{t+1} D rows against inv(L) columns
+// in V and the S row of Sigma (P, Q); inv(L) and workspace columns (Q, Q)
+// for the diagonal of Sigma.
+inline int big_layouts(int phase) {
+  switch (phase) {
+    case PH_SI_VU_X: case PH_SI_SR_X: return 2;
+    case PH_SI_SD_X: return 3;
+    default: return 0;
+  }
+}
+template <int V>
+void launch_big_dma(int phase, long long grid, hipStream_t s, const ItemDev *items_dev, int n_items,
+                    int t, int ks) {
+  switch (big_layouts(phase)) {
+    case 2:
+      hipLaunchKernelGGL((tile_big_kernel<V, 2>), dim3((unsigned)grid), dim3(big_threads<V>()), 0, s,
+                         items_dev, n_items, phase, t, ks);
+      break;
+    case 3:
+      hipLaunchKernelGGL((tile_big_kernel<V, 3>), dim3((unsigned)grid), dim3(big_threads<V>()), 0, s,
+                         items_dev, n_items, phase, t, ks);
+      break;
+    default:
+      hipLaunchKernelGGL((tile_big_kernel<V, 0>), dim3((unsigned)grid), dim3(big_threads<V>()), 0, s,
+                         items_dev, n_items, phase, t, ks);
+  }
+}
+
 hipError_t launch_tile_phase(const ItemDev *items_dev, int n_items, int total, int phase,
                              int phase2, int t, int p, bool big, hipStream_t s, int ks) {
   if (total <= 0) return hipSuccess;
   if (big && phase_is_product_x(phase) && phase2 < 0) {
     const long long grid = (long long)total * ks;
     switch (big_variant()) {
-      case 4:
-        hipLaunchKernelGGL(tile_big_kernel<4>, dim3((unsigned)grid), dim3(big_threads<4>()), 0, s,
-                           items_dev, n_items, phase, t, ks);
-        break;
-      case 3:
-        hipLaunchKernelGGL(tile_big_kernel<3>, dim3((unsigned)grid), dim3(big_threads<3>()), 0, s,
+      case 5: launch_big_dma<5>(phase, grid, s, items_dev, n_items, t, ks); break;
+      case 4: launch_big_dma<4>(phase, grid, s, items_dev, n_items, t, ks); break;
+      case 3: launch_big_dma<3>(phase, grid, s, items_dev, n_items, t, ks); break;
+      case 2:
+        hipLaunchKernelGGL(tile_big_kernel<2>, dim3((unsigned)grid), dim3(big_threads<2>()), 0, s,
                            items_dev, n_items, phase, t, ks);
         break;
       case 1:
         hipLaunchKernelGGL(tile_big_kernel<1>, dim3((unsigned)grid), dim3(big_threads<1>()), 0, s,
-                           items_dev, n_items, phase, t, ks);
-        break;
-      case 2:
-        hipLaunchKernelGGL(tile_big_kernel<2>, dim3((unsigned)grid), dim3(big_threads<2>()), 0, s,
                            items_dev, n_items, phase, t, ks);
         break;
       default:

@@ -1261,7 +1261,7 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
 // ---------------------------------------------------------------------------
 struct TileChoice {
   int tile = 0;      // 64 or 128 (0: built-in rule)
-  int variant = 0;   // layout of the 128-wide kernel
+  int variant = kDefaultBigVariant;   // layout of the 128-wide kernel
   double ms = 0.0;
 };
 std::unordered_map<std::string, TileChoice> g_tune;
@@ -1346,7 +1346,7 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
     const inla_status st = eval_run(models, n_items, theta_dev, f_dev, grad_dev, mu_out, var_out,
                                     status_dev, budget, seq_mode, allow_graph, s);
     g_tile_pref = 0;
-    set_big_variant(0);
+    set_big_variant(kDefaultBigVariant);
     return st;
   };
   TileChoice choice;
@@ -1363,7 +1363,8 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
       // time every candidate eagerly (one untimed run, one timed) on the
       // caller's stream; every run computes the same outputs
       const TileChoice cands[1 + kBigVariants] = {{64, 0, 0.0},  {128, 0, 0.0}, {128, 1, 0.0},
-                                                   {128, 2, 0.0}, {128, 3, 0.0}, {128, 4, 0.0}};
+                                                   {128, 2, 0.0}, {128, 3, 0.0}, {128, 4, 0.0},
+                                                   {128, 5, 0.0}};
       hipEvent_t e0, e1;
       HIP_TRY(hipEventCreate(&e0));
       HIP_TRY(hipEventCreate(&e1));

@@ -164,8 +164,11 @@ hipError_t launch_logdet_finish(const ItemDev *items_dev, int n_items, double *l
                                 int *info_out, hipStream_t s, int stride = 1);
 // Layout of the 128-wide tile kernel (0: 8 waves of 64 x 32, k-chunk 16, two
 // register sets; 1: 4 waves of 64 x 64; 2: as 0 with k-chunk 32, one set;
-// 3, 4: 8 waves of 64 x 32 staged by direct loads into LDS, k-chunk 32 / 16).
-constexpr int kBigVariants = 5;
+// 3, 4: 8 waves of 64 x 32 staged by direct loads into LDS, k-chunk 32 / 16,
+// the latter two workgroups per compute unit; 5: 4 waves of 64 x 64, direct
+// loads, k-chunk 16, two workgroups per compute unit).
+constexpr int kBigVariants = 6;
+constexpr int kDefaultBigVariant = 4;
 void set_big_variant(int v);
 int big_variant();
 // ---- model kernels (model_kernels.hip) ----

@@ -18,12 +18,12 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-@pytest.fixture(params=[("64", None), ("128", "0"), ("128", "3"), ("128", "4")],
-                ids=["tile64", "tile128", "tile128dma32", "tile128dma16"])
+@pytest.fixture(params=[("64", None), ("128", "0"), ("128", "3"), ("128", "4"), ("128", "5")],
+                ids=["tile64", "tile128", "tile128dma32", "tile128dma16", "tile128dma16w4"])
 def tile(request, monkeypatch):
     """Run the b x b product phases on 64- or 128-wide tiles; the 128-wide
-    ones with register staging (layout 0) or direct-to-LDS staging with
-    k-chunks of 32 and 16 (layouts 3 and 4)."""
+    ones with register staging (layout 0) or direct-to-LDS staging (layouts
+    3-5: 8 waves with k-chunks of 32 and 16, 4 waves with k-chunk 16)."""
     size, variant = request.param
     monkeypatch.setenv("INLA_TILE", size)
     if variant is not None:
