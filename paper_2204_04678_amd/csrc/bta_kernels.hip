@@ -66,7 +66,8 @@ struct Seg {
 // TK_CHAIN: C = beta C - (A0 B0) A1^T (+ the plain product of seg[2], if any)
 // with the 64-column intermediate A0 B0 kept in LDS (seg[0] = the first
 // product, seg[1].A = A1).
-// TK_LCHAIN: C = -A1 (A0 B0), A1 a lower-triangular diagonal tile (seg[1].A).
+// TK_LCHAIN: C = -A1 (S + A0 B0), A1 a lower-triangular diagonal tile (seg[1].A),
+// S the tile at src (ld = ldc) if src is set, else 0.
 enum TaskKind { TK_NONE = 0, TK_PRODUCT = 1, TK_COPY = 2, TK_ZERO = 3, TK_CHAIN = 4, TK_LCHAIN = 5 };
 
 struct Task {
@@ -87,7 +88,7 @@ struct Task {
   int row_off;
   double *Mout;                   // Cholesky tasks: also M = inv(L)^T inv(L) here (or null)
   int ti, tj;                     // 128-wide tiles: block coordinates of C (split-k scratch)
-  const double *src;              // copy source (ld = ldc)
+  const double *src;              // copy source; TK_LCHAIN: running-sum tile (ld = ldc)
 };
 
 // Loads and stores through the global address space (global_load / global_store
@@ -172,19 +173,32 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
                 kTile, -1.0);
         tk.nseg = 1;
         return;
-      } else {
-        // row p of X = inv(L_tt): X_pj = -X_pp sum_{m=j}^{p-1} L_pm X_mj, j < p.
-        // X is built in place of D[t]: its columns j < p are no longer needed
-        // by the factorization (L is in W2); the tile (j,p) above the diagonal
-        // is set to zero at the same time.
+      } else if (q < npan + ncol + ndef + p) {
+        // row p of X = inv(L_tt): X_pj = -X_pp (T_pj + L_{p,p-1} X_{p-1,j}), j < p,
+        // with the running sum T_pj = sum_{m=j}^{p-2} L_pm X_mj in W1 (none for
+        // j = p-1).  X is built in place of D[t]: its columns j < p are no
+        // longer needed by the factorization (L is in W2); the tile (j,p)
+        // above the diagonal is set to zero at the same time.
         const int j = q - npan - ncol - ndef;
         tk.kind = TK_LCHAIN;
         tk.m = tdim(b, p); tk.n = kTile;
         tk.C = Dt + toff(b, p, j); tk.ldc = b;
         tk.mirror = 2; tk.Cm = Dt + toff(b, j, p);
         set_seg(tk.seg[0], it.W2 + (long long)p * kTile, 1, b, Dt + (long long)j * kTile * b, b, 1,
-                j * kTile, p * kTile, 1.0);
+                (p - 1) * kTile, p * kTile, 1.0);
         set_seg(tk.seg[1], Dt + toff(b, p, p), 1, b, nullptr, 0, 0, 0, tdim(b, p), -1.0);
+        tk.nseg = 1;
+        tk.src = (j < p - 1) ? it.W1 + toff(b, p, j) : nullptr;
+        return;
+      } else {
+        // running sums of the later rows: T_rj (+)= L_{r,p-1} X_{p-1,j} for
+        // r > p, j < p (the term m = p-1, ready once row p-1 of X is)
+        const int e = q - npan - ncol - ndef - p;
+        const int r = p + 1 + e / p, j = e % p;
+        tk.m = tdim(b, r); tk.n = kTile;
+        tk.C = it.W1 + toff(b, r, j); tk.ldc = b; tk.beta = (j == p - 1) ? 0.0 : 1.0;
+        set_seg(tk.seg[0], it.W2 + (long long)r * kTile, 1, b, Dt + (long long)j * kTile * b, b, 1,
+                (p - 1) * kTile, p * kTile, 1.0);
         tk.nseg = 1;
         return;
       }
@@ -1095,6 +1109,19 @@ __device__ __forceinline__ void left_chain_product(const Task &tk, double *smem,
   Task t1 = tk;
   t1.nseg = 1;
   run_product<KC, kTile, 2, 2, 2>(t1, smem, acc);   // rows >= tk.m come out zero
+  if (tk.src) {
+    // plus the tile at src (ld = ldc): the running sum of the earlier terms
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = acc_row(wr, mi, lane, r), col = acc_col(wc, nj, lane);
+          const double v = gld(tk.src + min(row, tk.m - 1) + (long long)min(col, tk.n - 1) * tk.ldc);
+          if (row < tk.m && col < tk.n) acc[mi][nj][r] += v;
+        }
+  }
   double *TA = smem, *TB = smem + kTile * TLD;
   // T[k][c] -> TB[c][k]
 #pragma unroll

@@ -338,9 +338,6 @@ inla_status run_pair(const Batch &B, int px, int pr, int t, hipStream_t s) {
   } while (0)
 
 inla_status run_factor(const Batch &B, hipStream_t s) {
-  // the workspace that receives inv(L_tt) starts as zeros: its tiles above the
-  // diagonal are never written and the big-tile products read them as zeros
-  for (const auto &it : B.host) HIP_TRY(launch_fill(it.W1, (long long)it.b * it.b, 0.0, s));
   for (int t = 0; t < B.max_nt; ++t) {
     ST_TRY(run_phase(B, PH_DIAG0, t, 0, s));
     int mp = 0;

@@ -42,7 +42,8 @@ struct ModelDev {
 struct ItemDev {
   int b, nt, a, nP;              // block size, time blocks, arrow width, ceil(b / kTile)
   double *D, *S, *R, *T;         // BTA storage (Q in, factor out)
-  double *W1, *W2, *W3;          // workspace: b*b (Sigma_S in the selected inversion),
+  double *W1, *W2, *W3;          // workspace: b*b (running sums of inv(L_tt) rows in the
+                                 // factorization, Sigma_S in the selected inversion),
                                  //   b*b (panels of L_tt, then S[t] Linv^T), a*b
   double *Mp;                    // 2 x 64 x 64: inverse of the current diagonal tile, by parity
   double *P;                     // kSplitK * b * b split-k partial products (or null: no split)
@@ -127,12 +128,13 @@ __host__ __device__ inline int phase_tasks(const ItemDev &it, int phase, int t, 
   const bool last = (t == it.nt - 1);
   switch (phase) {
     case PH_DIAG0: return 1;
-    case PH_STEP:     // panels, column p+1, deferred trailing tiles, row p of inv(L_tt)
+    case PH_STEP:     // panels, column p+1, deferred trailing tiles, row p of inv(L_tt),
+                      // running sums of the later rows of inv(L_tt)
     case PH_STEPF: {  // the same plus the diagonal tile of column p+1
       if (p >= nP) return 0;
       const int ncol = (nP - 2 - p > 0) ? nP - 2 - p : 0;
       return (nP - 1 - p) + ncol + (p >= 1 ? ncol * (ncol + 1) / 2 : 0) + p +
-             ((phase == PH_STEPF && p < nP - 1) ? 1 : 0);
+             (nP - 1 - p) * p + ((phase == PH_STEPF && p < nP - 1) ? 1 : 0);
     }
     case PH_DIAGC: return (p < nP - 1) ? 1 : 0;
     case PH_OFFDIAG_X: return last ? 0 : nQ * nQ;
