@@ -144,8 +144,8 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       // Tiles p-1 and p are full wherever they are used here (they precede a tile).
       const int npan = nP - 1 - p;
       const int ncol = max(nP - 2 - p, 0);
-      const int ndef = (p >= 1) ? ncol * (ncol + 1) / 2 : 0;
-      int i = -1;   // column task for tile (i, p+1)
+      const int ndef = (p >= 1) ? ncol * (ncol + 1) / 2 : min(ncol, 1);
+      int i = -1, jc = p + 1;   // chained task for tile (i, jc)
       if (phase == PH_STEPF && p < nP - 1) {   // task 0 is the diagonal tile
         if (q == 0) i = p + 1;
         else --q;
@@ -163,36 +163,47 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       } else if (q < npan + ncol) {
         i = p + 2 + (q - npan);
       } else if (q < npan + ncol + ndef) {
-        // the rest of panel p-1's update: A_ij -= L_{i,p-1} L_{j,p-1}^T, p+1 < j <= i
+        // the rest of panel p-1's update: A_ij -= L_{i,p-1} L_{j,p-1}^T, p+1 < j <= i;
+        // the diagonal tile of column p+2 also takes column p's term here (a
+        // chained product through M_p), one step before it is factored
         int ii, jj;
         tri_decode(q - npan - ncol, ii, jj);
         const int id = p + 2 + ii, jd = p + 2 + jj;
-        tk.m = tdim(b, id); tk.n = tdim(b, jd);
-        tk.C = Dt + toff(b, id, jd); tk.ldc = b; tk.beta = 1.0;
-        set_seg(tk.seg[0], it.W2 + toff(b, id, p - 1), 1, b, it.W2 + toff(b, jd, p - 1), 1, b, 0,
-                kTile, -1.0);
-        tk.nseg = 1;
-        return;
+        if (id == p + 2) {
+          i = p + 2;
+          jc = p + 2;
+        } else {
+          tk.m = tdim(b, id); tk.n = tdim(b, jd);
+          tk.C = Dt + toff(b, id, jd); tk.ldc = b; tk.beta = 1.0;
+          set_seg(tk.seg[0], it.W2 + toff(b, id, p - 1), 1, b, it.W2 + toff(b, jd, p - 1), 1, b, 0,
+                  kTile, -1.0);
+          tk.nseg = 1;
+          return;
+        }
       } else if (q < npan + ncol + ndef + p) {
-        // row p of X = inv(L_tt): X_pj = -X_pp (T_pj + L_{p,p-1} X_{p-1,j}), j < p,
-        // with the running sum T_pj = sum_{m=j}^{p-2} L_pm X_mj in W1 (none for
-        // j = p-1).  X is built in place of D[t]: its columns j < p are no
-        // longer needed by the factorization (L is in W2); the tile (j,p)
-        // above the diagonal is set to zero at the same time.
+        // row p of X = inv(L_tt): X_pj = -X_pp sum_{m=j}^{p-1} L_pm X_mj, j < p.
+        // The fused step (few tiles: latency matters) keeps the running sum
+        // T_pj = sum_{m=j}^{p-2} L_pm X_mj in W1 (none for j = p-1) and adds the
+        // last term here; the batched step takes the whole sum in one product
+        // (throughput matters: no partial sums through memory).  X is built in
+        // place of D[t]: its columns j < p are no longer needed by the
+        // factorization (L is in W2); the tile (j,p) above the diagonal is set
+        // to zero at the same time.
         const int j = q - npan - ncol - ndef;
+        const bool sums = phase == PH_STEPF;
         tk.kind = TK_LCHAIN;
         tk.m = tdim(b, p); tk.n = kTile;
         tk.C = Dt + toff(b, p, j); tk.ldc = b;
         tk.mirror = 2; tk.Cm = Dt + toff(b, j, p);
         set_seg(tk.seg[0], it.W2 + (long long)p * kTile, 1, b, Dt + (long long)j * kTile * b, b, 1,
-                (p - 1) * kTile, p * kTile, 1.0);
+                sums ? (p - 1) * kTile : j * kTile, p * kTile, 1.0);
         set_seg(tk.seg[1], Dt + toff(b, p, p), 1, b, nullptr, 0, 0, 0, tdim(b, p), -1.0);
         tk.nseg = 1;
-        tk.src = (j < p - 1) ? it.W1 + toff(b, p, j) : nullptr;
+        tk.src = (sums && j < p - 1) ? it.W1 + toff(b, p, j) : nullptr;
         return;
       } else {
-        // running sums of the later rows: T_rj (+)= L_{r,p-1} X_{p-1,j} for
-        // r > p, j < p (the term m = p-1, ready once row p-1 of X is)
+        // (fused step) running sums of the later rows: T_rj (+)= L_{r,p-1} X_{p-1,j}
+        // for r > p, j < p (the term m = p-1, ready once row p-1 of X is)
         const int e = q - npan - ncol - ndef - p;
         const int r = p + 1 + e / p, j = e % p;
         tk.m = tdim(b, r); tk.n = kTile;
@@ -202,22 +213,24 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
         tk.nseg = 1;
         return;
       }
-      // column p+1: A_{i,p+1} -= L_{i,p-1} L_{p+1,p-1}^T + (A_ip M_p) A_{p+1,p}^T with
-      // M_p = inv(L_pp)^T inv(L_pp) = inv(A_pp)
-      const int jc = p + 1;
+      // column p+1 (and the diagonal tile of column p+2):
+      // A_{i,jc} -= L_{i,p-1} L_{jc,p-1}^T + (A_ip M_p) A_{jc,p}^T with
+      // M_p = inv(L_pp)^T inv(L_pp) = inv(A_pp); the diagonal tile factored in
+      // this step took its column p-1 term in the previous one
+      const bool fac = (i == p + 1 && jc == p + 1);
       tk.kind = TK_CHAIN;
       tk.m = tdim(b, i); tk.n = tdim(b, jc);
       tk.C = Dt + toff(b, i, jc); tk.ldc = b; tk.beta = 1.0;
       set_seg(tk.seg[0], Dt + toff(b, i, p), 1, b, it.Mp + (long long)(p & 1) * kTile * kTile, kTile,
               1, 0, kTile, 1.0);
       set_seg(tk.seg[1], Dt + toff(b, jc, p), 1, b, nullptr, 0, 0, 0, kTile, -1.0);
-      if (p >= 1)
+      if (p >= 1 && !fac)
         set_seg(tk.seg[2], it.W2 + toff(b, i, p - 1), 1, b, it.W2 + toff(b, jc, p - 1), 1, b, 0,
                 kTile, -1.0);
       else
         set_seg(tk.seg[2], nullptr, 1, b, nullptr, 1, b, 0, 0, -1.0);
       tk.nseg = 1;
-      if (i == jc) {
+      if (fac) {
         tk.chol = 1; tk.Lout = Dt + toff(b, i, i); tk.ldl = b;
         tk.ldsum = it.ldpart + (long long)t * nP + i; tk.row_off = t * b + i * kTile;
         tk.Mout = it.Mp + (long long)((p + 1) & 1) * kTile * kTile;
@@ -895,7 +908,7 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 // (X_ij = -X_ii sum_m L_im X_mj) run on the matrix cores.  Writes inv(L)
 // (zeros above the diagonal) to Lout and sum log L_jj; a pivot that is not
 // positive sets *info to its 1-based row (row_off + local row) if smaller.
-// dlog holds the 64 logs of the diagonal (its 2 * kTile doubles leave room).
+// dlog holds the 64 diagonal entries of L (its 2 * kTile doubles leave room).
 // If Mout is set, M = X^T X = inv(A) (64 x 64, column-major) is written there too.
 __device__ void chol_inv_tile(double *A, double *X, double *dlog, int w, double *Lout,
                               long long ldl, double *ldsum, int row_off, int *info, double *Mout) {
@@ -944,7 +957,7 @@ __device__ void chol_inv_tile(double *A, double *X, double *dlog, int w, double 
       const bool ok = (dg > 0.0) || lane >= 16 || r0 + lane >= w;
       const unsigned long long badm = __ballot(!ok);
       if (badm && lane == 0) atomicMin(info, row_off + r0 + __ffsll(badm));
-      if (lane < 16) dlog[r0 + lane] = (r0 + lane < w) ? log(dg) : 0.0;
+      if (lane < 16) dlog[r0 + lane] = dg;   // logs taken once, at the end
       __builtin_amdgcn_wave_barrier();
       // X = L^{-1}: X_ic = (delta_ic - sum_{m<i} L_im X_mc) / L_ii; entries
       // above the diagonal come out zero because the right-hand side is e_c
@@ -1054,7 +1067,7 @@ __device__ void chol_inv_tile(double *A, double *X, double *dlog, int w, double 
     if (r < w && c < w) gst(Lout + r + (long long)c * ldl, (c <= r) ? X[r * TLD + c] : 0.0);
   }
   if (wv == 0) {
-    double v = (lane < w) ? dlog[lane] : 0.0;
+    double v = (lane < w) ? log(dlog[lane]) : 0.0;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     if (lane == 0) *ldsum = v;

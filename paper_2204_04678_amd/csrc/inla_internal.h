@@ -128,13 +128,14 @@ __host__ __device__ inline int phase_tasks(const ItemDev &it, int phase, int t, 
   const bool last = (t == it.nt - 1);
   switch (phase) {
     case PH_DIAG0: return 1;
-    case PH_STEP:     // panels, column p+1, deferred trailing tiles, row p of inv(L_tt),
-                      // running sums of the later rows of inv(L_tt)
-    case PH_STEPF: {  // the same plus the diagonal tile of column p+1
+    case PH_STEP:     // panels, column p+1, deferred trailing tiles, row p of inv(L_tt)
+    case PH_STEPF: {  // the same plus the diagonal tile of column p+1 and the running
+                      // sums of the later rows of inv(L_tt)
       if (p >= nP) return 0;
       const int ncol = (nP - 2 - p > 0) ? nP - 2 - p : 0;
-      return (nP - 1 - p) + ncol + (p >= 1 ? ncol * (ncol + 1) / 2 : 0) + p +
-             (nP - 1 - p) * p + ((phase == PH_STEPF && p < nP - 1) ? 1 : 0);
+      return (nP - 1 - p) + ncol + (p >= 1 ? ncol * (ncol + 1) / 2 : (ncol > 0 ? 1 : 0)) + p +
+             ((phase == PH_STEPF) ? (nP - 1 - p) * p : 0) +
+             ((phase == PH_STEPF && p < nP - 1) ? 1 : 0);
     }
     case PH_DIAGC: return (p < nP - 1) ? 1 : 0;
     case PH_OFFDIAG_X: return last ? 0 : nQ * nQ;
