@@ -238,7 +238,8 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       return;
     }
     case PH_OFFDIAG_X: {
-      const int i = q / nP, j = q % nP;
+      // k runs to the end of tile column j: the longest tiles first
+      const int j = nP - 1 - q / nP, i = q % nP;
       tk.m = tdim(b, i); tk.n = tdim(b, j);
       tk.C = it.W2 + toff(b, i, j); tk.ldc = b;
       set_seg(tk.seg[0], St + (long long)i * kTile, 1, b, Dt + (long long)j * kTile, 1, b, 0,
@@ -330,7 +331,8 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       return;
     }
     case PH_SI_VU_X: {
-      const int i = q / nP, j = q % nP;
+      // k starts at tile column j: the longest tiles first
+      const int j = q / nP, i = q % nP;
       tk.m = tdim(b, i); tk.n = tdim(b, j);
       tk.C = it.W2 + toff(b, i, j); tk.ldc = b;
       set_seg(tk.seg[0], St + (long long)i * kTile, 1, b, Dt + (long long)j * kTile * b, b, 1,
@@ -420,7 +422,9 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
   int I, J;
   switch (phase) {
     case PH_OFFDIAG_X:
-      I = q / nQ; J = q % nQ;
+      // k runs to the end of tile column J: tiles of the last columns (the
+      // longest) first, so that the short ones fill the end of the launch
+      J = nQ - 1 - q / nQ; I = q % nQ;
       tk.m = bdim(b, I); tk.n = bdim(b, J); tk.ti = I; tk.tj = J;
       tk.C = it.W2 + boff(b, I, J); tk.ldc = b;
       set_seg(tk.seg[0], St + (long long)I * kBig, 1, b, Dt + (long long)J * kBig, 1, b, 0,
@@ -436,7 +440,8 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
       tk.nseg = 1;
       return;
     case PH_SI_VU_X:
-      I = q / nQ; J = q % nQ;
+      // k starts at tile column J: the first columns (the longest) first
+      J = q / nQ; I = q % nQ;
       tk.m = bdim(b, I); tk.n = bdim(b, J); tk.ti = I; tk.tj = J;
       tk.C = it.W2 + boff(b, I, J); tk.ldc = b;
       set_seg(tk.seg[0], St + (long long)I * kBig, 1, b, Dt + (long long)J * kBig * b, b, 1,

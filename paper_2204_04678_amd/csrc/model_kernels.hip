@@ -81,30 +81,44 @@ __device__ inline void block_reduce(double (&v)[4], double *red) {
 // assembly
 // ---------------------------------------------------------------------------
 
-// One workgroup writes column s of one b x b block (D[t] for blockIdx.y < nt,
-// S[t] for blockIdx.y - nt).  Entries outside the pattern are zero.
-__global__ void assemble_blocks_kernel(const ModelDev *__restrict__ Mp, const double *theta,
-                                       int which, double *D, double *S) {
+// Each workgroup writes kAsmCols columns of one b x b block (D[t] for
+// blockIdx.y < nt, S[t] for blockIdx.y - nt).  A column is built in LDS, in
+// pieces of kAsmRows rows: zeros, then the pattern's entries scattered to
+// their rows (distinct within a column), then one coalesced store; entries
+// outside the pattern are zero.
+constexpr int kAsmCols = 4;
+constexpr int kAsmRows = 2048;
+__global__ __launch_bounds__(256) void assemble_blocks_kernel(const ModelDev *__restrict__ Mp,
+                                                              const double *theta, int which,
+                                                              double *D, double *S) {
+  __shared__ double piece[kAsmRows];
   const ModelDev &M = *Mp;
   const int b = M.b, nt = M.nt;
-  const int s = blockIdx.x;
   const int blk = blockIdx.y;
   const bool isS = blk >= nt;
   const int t = isS ? blk - nt : blk;
   const Coef c = make_coef(M, theta);
   const double cblk = isS ? ar1_off(c) : ar1_diag(c, t, nt);
-  double *col = (isS ? S : D) + (long long)t * b * b + (long long)s * b;
-  const int e0 = M.colptr[s], e1 = M.colptr[s + 1];
-  for (int i = threadIdx.x; i < b; i += blockDim.x) {
-    double v = 0.0;
-    for (int e = e0; e < e1; ++e) {
-      if (M.rowidx[e] == i) {
-        v = cblk * qs_entry(M, c, e);
-        if (!isS && which) v += c.tauy * M.AtA[(long long)t * M.nnz + e];
-        break;
+  const bool add_obs = !isS && which;
+  for (int s = blockIdx.x * kAsmCols; s < min(b, (blockIdx.x + 1) * kAsmCols); ++s) {
+    double *col = (isS ? S : D) + (long long)t * b * b + (long long)s * b;
+    const int e0 = M.colptr[s], e1 = M.colptr[s + 1];
+    for (int r0 = 0; r0 < b; r0 += kAsmRows) {
+      const int rn = min(kAsmRows, b - r0);
+      for (int i = threadIdx.x; i < rn; i += blockDim.x) piece[i] = 0.0;
+      __syncthreads();
+      for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        const int i = M.rowidx[e] - r0;
+        if (i >= 0 && i < rn) {
+          double v = cblk * qs_entry(M, c, e);
+          if (add_obs) v += c.tauy * M.AtA[(long long)t * M.nnz + e];
+          piece[i] = v;
+        }
       }
+      __syncthreads();
+      for (int i = threadIdx.x; i < rn; i += blockDim.x) col[r0 + i] = piece[i];
+      __syncthreads();
     }
-    col[i] = v;
   }
 }
 
@@ -137,8 +151,8 @@ __global__ void assemble_arrow_kernel(const ModelDev *__restrict__ Mp, const dou
 hipError_t launch_assemble(const ModelDev *model_dev, int b, int nt, int a, const double *theta,
                            int which, double *D, double *S, double *R, double *T, double *rhs,
                            hipStream_t s) {
-  hipLaunchKernelGGL(assemble_blocks_kernel, dim3(b, 2 * nt - 1), dim3(256), 0, s, model_dev, theta,
-                     which, D, S);
+  hipLaunchKernelGGL(assemble_blocks_kernel, dim3((b + kAsmCols - 1) / kAsmCols, 2 * nt - 1),
+                     dim3(256), 0, s, model_dev, theta, which, D, S);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const long long total = (long long)nt * a * b + (long long)a * a + (rhs ? (long long)b * nt + a : 0);
