@@ -188,12 +188,23 @@ double phase_flops(const ItemDev &it, int phase, int t, int p) {
 // option can still ask for 128 (then split) there.
 constexpr long long kSplitTiles = 384;
 // Below this many 64-tiles (summed nP^2 over the items of a factor launch)
-// each Cholesky step is one fused launch (see run_factor).
-constexpr long long kStepFusedTiles = 1024;
+// each Cholesky step is one fused launch (see run_factor).  Measured on
+// b = 2025 with 2, 4 and 8 matrices (2048, 4096, 8192 tiles): fused 23%, 11%
+// faster and 1% slower per evaluation; b = 1600 with 2 matrices: 13% faster.
+constexpr long long kStepFusedTiles = 6144;
+// INLA_STEP_FUSED=1 (0) in the environment makes every Cholesky step fused (batched).
+int step_fused_override() {
+  const char *e = getenv("INLA_STEP_FUSED");
+  return (e && (e[0] == '0' || e[0] == '1')) ? e[0] - '0' : -1;
+}
 int g_tile_pref = 0;
-bool use_big_tiles(const std::vector<ItemDev> &items) {
+// The tile size asked for: INLA_TILE in the environment, else the engine's choice.
+int tile_request() {
   const char *e = getenv("INLA_TILE");
-  const int force = e ? atoi(e) : g_tile_pref;
+  return e ? atoi(e) : g_tile_pref;
+}
+bool use_big_tiles(const std::vector<ItemDev> &items) {
+  const int force = tile_request();
   if (force == 64) return false;
   if (force == 128) return true;
   long long big = 0;
@@ -349,8 +360,10 @@ inla_status run_factor(const Batch &B, hipStream_t s) {
     long long tiles2 = 0;
     for (const auto &it : B.host)
       if (t < it.nt) tiles2 += (long long)it.nP * it.nP;
+    const int fo = step_fused_override();
+    const bool fused = fo < 0 ? tiles2 < kStepFusedTiles : fo == 1;
     for (int p = 0; p < mp; ++p) {
-      if (tiles2 < kStepFusedTiles) ST_TRY(run_phase(B, PH_STEPF, t, p, s));
+      if (fused) ST_TRY(run_phase(B, PH_STEPF, t, p, s));
       else ST_TRY(run_beside(B, PH_STEP, PH_DIAGC, t, p, s));
     }
     ST_TRY(run_pair(B, PH_OFFDIAG_X, PH_OFFDIAG, t, s));
@@ -879,7 +892,7 @@ struct EvalGraph {
   bool valid = false;
   std::vector<const inla_model *> models;
   bool grad = false, var = false, mu = false, prof = false, seq = false;
-  int tile = 0, variant = 0;
+  int tile = 0, variant = 0, step = -1;
   unsigned long long gen = 0;
   char *base = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -933,9 +946,7 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
   // split-k scratch when the whole call has few 128-wide tiles per launch
   long long nb2 = 0;
   for (int i = 0; i < n_items; ++i) nb2 += 2LL * nbig(models[i]->host.b) * nbig(models[i]->host.b);
-  const char *tile_env = getenv("INLA_TILE");
-  const int tile_force = tile_env ? atoi(tile_env) : g_tile_pref;
-  const bool split_wanted = nb2 < kSplitTiles && tile_force == 128;
+  const bool split_wanted = nb2 < kSplitTiles && tile_request() == 128;
   // HBM admission: split the items into waves whose storage fits the budget
   auto waves_for = [&](bool seq, bool split, std::vector<size_t> &bytes, double &all) -> int {
     bytes.assign(n_items, 0);
@@ -993,7 +1004,7 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
   std::vector<long long> voff(n_items + 1, 0);
   for (int i = 0; i < n_items; ++i) voff[i + 1] = voff[i] + models[i]->n;
   const long long ntot = voff[n_items];
-  const int tile = g_tile_pref, variant = big_variant();
+  const int tile = tile_request(), variant = big_variant(), step = step_fused_override();
 
   // replay a captured graph when the call matches it and nothing else has
   // laid out the workspace since
@@ -1003,7 +1014,8 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
   if (graphable && g_graph.valid && g_graph.models == key && g_graph.grad == grad &&
       g_graph.var == (var_out != nullptr) && g_graph.mu == (mu_out != nullptr) &&
       g_graph.prof == g_prof.on && g_graph.seq == seq && g_graph.tile == tile &&
-      g_graph.variant == variant && g_graph.gen == g_arena.gen && g_graph.base == g_arena.base) {
+      g_graph.variant == variant && g_graph.step == step && g_graph.gen == g_arena.gen &&
+      g_graph.base == g_arena.base) {
     if (g_arena.last && g_arena.last_stream != s) HIP_TRY(hipStreamWaitEvent(s, g_arena.last, 0));
     HIP_TRY(hipMemcpyAsync(g_graph.th, theta_dev, (size_t)n_items * 32, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipGraphLaunch(g_graph.exec, s));
@@ -1236,6 +1248,7 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
       G.seq = seq;
       G.tile = tile;
       G.variant = variant;
+      G.step = step;
       G.gen = g_arena.gen;
       G.base = g_arena.base;
       G.exec = exec;

@@ -121,6 +121,31 @@ def test_solve_and_selinv_random_bta(P, tile, b, nt, a):
         assert blk_err(g, e) < 1e-10, name
 
 
+@pytest.mark.parametrize("fused", ["0", "1"], ids=["batched_step", "fused_step"])
+@pytest.mark.parametrize("b,nt,a", [(300, 3, 3), (257, 2, 1), (520, 2, 2), (130, 2, 0)])
+def test_step_paths_factor_and_selinv(P, monkeypatch, fused, b, nt, a):
+    """Both forms of the tile Cholesky step (one fused launch per step with running
+    sums for the rows of inv(L_tt); or the lean launch with the next diagonal tile
+    beside it and one long product per row) against the oracle."""
+    print(f"step path fused={fused} b={b} nt={nt} a={a}", flush=True)
+    monkeypatch.setenv("INLA_STEP_FUSED", fused)
+    Q = rand_spd_bta(b, nt, a, seed=11 + b + nt + a)
+    Qt = P.BtaTensors.from_blocks(*O.bta_blocks(Q, b, nt, a))
+    ld, info = P.factor_logdet(Qt)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    L = np.linalg.cholesky(Q)
+    assert rel(ld.item(), 2.0 * math.fsum(np.log(np.diag(L)))) < 1e-12
+    for g, e, name in zip(Qt.to_blocks(), expected_factor(Q, b, nt, a), "DSRT"):
+        assert blk_err(g, e) < 1e-11, name
+    sig, diag = P.selinv(Qt, keep_sigma=True)
+    torch.cuda.synchronize()
+    Sinv = np.linalg.inv(Q)
+    np.testing.assert_allclose(diag.cpu().numpy(), np.diag(Sinv), rtol=1e-10)
+    for g, e, name in zip(sig.to_blocks(), O.bta_blocks(Sinv, b, nt, a), "DSRT"):
+        assert blk_err(g, e) < 1e-10, name
+
+
 def test_not_spd_reports_pivot(P):
     b, nt, a = 70, 3, 2
     Q = rand_spd_bta(b, nt, a, seed=5)
