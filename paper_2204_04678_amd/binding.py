@@ -362,7 +362,7 @@ PRODUCT_X = ("offdiag_x", "schur_x", "si_vu_x", "si_sr_x", "si_sd_x")   # b x b 
 FAT_PHASES = ("diag0", "diagc", "stepf", "arrow")   # run by the Cholesky-capable tile kernel
 
 
-KERNEL_KINDS = ["tile_phase_kernel<false>", "tile_phase_kernel<true>", "tile_big_kernel", "other"]
+KERNEL_KINDS = ["tile_phase_kernel<false>", "tile_phase_kernel<true>", "tile_product_kernel", "other"]
 
 
 def profile_end():

@@ -23,36 +23,49 @@ constexpr int kFatKC = 32;        // k-chunk of the Cholesky-capable kernel
 constexpr int kLeanLds = 2 * 2 * kLeanKC * LDP;                      // double-buffered panels
 constexpr int kFatLds = 2 * kTile * TLD + 2 * kTile;                 // tile + inverse + logs
 static_assert(kFatLds >= 2 * 2 * kFatKC * LDP, "fat LDS must hold the product panels too");
-// Big-tile kernel layouts: WR x WC waves over a 128 x 128 tile, k-chunk KC,
-// register prefetch depth DEPTH (register-staged layouts) or direct loads into
-// LDS (DMA), and the minimum waves per SIMD it is built for (OCC).
+// Product kernel layouts: WR x WC waves over a TS x TS output tile, k-chunk
+// KC, register prefetch depth DEPTH (register-staged layouts) or direct loads
+// into LDS (DMA), and the minimum waves per SIMD it is built for (OCC).
 template <int V> struct BigCfg;
-template <> struct BigCfg<0> {   // 8 waves of 64 x 32, two register sets
-  static constexpr int WR = 2, WC = 4, KC = 16, DEPTH = 2, OCC = 1;
+template <> struct BigCfg<0> {   // 128: 8 waves of 64 x 32, two register sets
+  static constexpr int TS = 128, WR = 2, WC = 4, KC = 16, DEPTH = 2, OCC = 1;
   static constexpr bool DMA = false;
 };
-template <> struct BigCfg<1> {   // 4 waves of 64 x 64, one wave per SIMD
-  static constexpr int WR = 2, WC = 2, KC = 16, DEPTH = 2, OCC = 1;
+template <> struct BigCfg<1> {   // 128: 4 waves of 64 x 64, one wave per SIMD
+  static constexpr int TS = 128, WR = 2, WC = 2, KC = 16, DEPTH = 2, OCC = 1;
   static constexpr bool DMA = false;
 };
-template <> struct BigCfg<2> {   // 8 waves of 64 x 32, deeper k-chunk, one register set
-  static constexpr int WR = 2, WC = 4, KC = 32, DEPTH = 1, OCC = 1;
+template <> struct BigCfg<2> {   // 128: 8 waves of 64 x 32, deeper k-chunk, one register set
+  static constexpr int TS = 128, WR = 2, WC = 4, KC = 32, DEPTH = 1, OCC = 1;
   static constexpr bool DMA = false;
 };
-template <> struct BigCfg<3> {   // 8 waves of 64 x 32, direct loads, k-chunk 32
-  static constexpr int WR = 2, WC = 4, KC = 32, DEPTH = 1, OCC = 2;
+template <> struct BigCfg<3> {   // 128: 8 waves of 64 x 32, direct loads, k-chunk 32
+  static constexpr int TS = 128, WR = 2, WC = 4, KC = 32, DEPTH = 1, OCC = 2;
   static constexpr bool DMA = true;
 };
-template <> struct BigCfg<4> {   // 8 waves of 64 x 32, direct loads, k-chunk 16, 2 workgroups per CU
-  static constexpr int WR = 2, WC = 4, KC = 16, DEPTH = 1, OCC = 4;
+template <> struct BigCfg<4> {   // 128: 8 waves of 64 x 32, direct loads, k-chunk 16, 2 workgroups per CU
+  static constexpr int TS = 128, WR = 2, WC = 4, KC = 16, DEPTH = 1, OCC = 4;
   static constexpr bool DMA = true;
 };
-template <> struct BigCfg<5> {   // 4 waves of 64 x 64, direct loads, k-chunk 16, 2 workgroups per CU
-  static constexpr int WR = 2, WC = 2, KC = 16, DEPTH = 1, OCC = 2;
+template <> struct BigCfg<5> {   // 128: 4 waves of 64 x 64, direct loads, k-chunk 16, 2 workgroups per CU
+  static constexpr int TS = 128, WR = 2, WC = 2, KC = 16, DEPTH = 1, OCC = 2;
   static constexpr bool DMA = true;
 };
+template <> struct BigCfg<6> {   // 64: 4 waves of 32 x 32, direct loads, k-chunk 32, 2 workgroups per CU
+  static constexpr int TS = 64, WR = 2, WC = 2, KC = 32, DEPTH = 1, OCC = 2;
+  static constexpr bool DMA = true;
+};
+template <> struct BigCfg<7> {   // 64: 4 waves of 32 x 32, direct loads, k-chunk 16, 4 workgroups per CU
+  static constexpr int TS = 64, WR = 2, WC = 2, KC = 16, DEPTH = 1, OCC = 4;
+  static constexpr bool DMA = true;
+};
+// Row length of a [k][row] LDS panel of a TS-row tile: 128 rows are padded by
+// two; 64 rows stay unpadded so that one 1 KiB direct load fills two k-columns.
+template <int TS> constexpr int pld() { return TS == 128 ? TS + 2 : TS; }
 template <int V> constexpr int big_threads() { return 64 * BigCfg<V>::WR * BigCfg<V>::WC; }
-template <int V> constexpr int big_lds() { return 2 * 2 * BigCfg<V>::KC * (kBig + 2); }
+template <int V> constexpr int big_lds() {
+  return 2 * 2 * BigCfg<V>::KC * (BigCfg<V>::DMA ? pld<BigCfg<V>::TS>() : kBig + 2);
+}
 
 struct Seg {
   const double *A;
@@ -398,18 +411,20 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
   }
 }
 
-// Map (item, product phase, t, local task q) to one 128 x 128 output tile.  The
-// k ranges are those of the 64-tile form widened to the big tile; the extra
-// range only meets entries that are stored as zeros (the workspace holding
-// inv(L_tt) is cleared before the factorization, and the factor blocks keep
-// zeros above their diagonal).
+// Map (item, product phase, t, local task q) to one TS x TS output tile (TS =
+// 64 or 128).  For 128 the k ranges are those of the 64-tile form widened to
+// the big tile; the extra range only meets entries that are stored as zeros
+// (inv(L_tt) and the factor blocks keep zeros above their diagonal).
+template <int TS>
 __device__ __forceinline__ long long boff(int b, int I, int J) {
-  return (long long)I * kBig + (long long)J * kBig * b;
+  return (long long)I * TS + (long long)J * TS * b;
 }
-__device__ __forceinline__ int bdim(int n, int I) { return min(kBig, n - I * kBig); }
+template <int TS>
+__device__ __forceinline__ int bdim(int n, int I) { return min(TS, n - I * TS); }
 
+template <int TS>
 __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, int q, Task &tk) {
-  const int b = it.b, a = it.a, nQ = nbig(it.b);
+  const int b = it.b, a = it.a, nQ = (it.b + TS - 1) / TS;
   const long long bb = (long long)b * b;
   const bool arrow = a > 0;
   const bool last = (t == it.nt - 1);
@@ -425,54 +440,54 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
       // k runs to the end of tile column J: tiles of the last columns (the
       // longest) first, so that the short ones fill the end of the launch
       J = nQ - 1 - q / nQ; I = q % nQ;
-      tk.m = bdim(b, I); tk.n = bdim(b, J); tk.ti = I; tk.tj = J;
-      tk.C = it.W2 + boff(b, I, J); tk.ldc = b;
-      set_seg(tk.seg[0], St + (long long)I * kBig, 1, b, Dt + (long long)J * kBig, 1, b, 0,
-              min(b, (J + 1) * kBig), 1.0);
+      tk.m = bdim<TS>(b, I); tk.n = bdim<TS>(b, J); tk.ti = I; tk.tj = J;
+      tk.C = it.W2 + boff<TS>(b, I, J); tk.ldc = b;
+      set_seg(tk.seg[0], St + (long long)I * TS, 1, b, Dt + (long long)J * TS, 1, b, 0,
+              min(b, (J + 1) * TS), 1.0);
       tk.nseg = 1;
       return;
     case PH_SCHUR_X:
       tri_decode(q, I, J);
-      tk.m = bdim(b, I); tk.n = bdim(b, J); tk.ti = I; tk.tj = J;
-      tk.C = it.D + (long long)(t + 1) * bb + boff(b, I, J); tk.ldc = b; tk.beta = 1.0;
-      set_seg(tk.seg[0], it.W2 + (long long)I * kBig, 1, b, it.W2 + (long long)J * kBig, 1, b, 0, b,
+      tk.m = bdim<TS>(b, I); tk.n = bdim<TS>(b, J); tk.ti = I; tk.tj = J;
+      tk.C = it.D + (long long)(t + 1) * bb + boff<TS>(b, I, J); tk.ldc = b; tk.beta = 1.0;
+      set_seg(tk.seg[0], it.W2 + (long long)I * TS, 1, b, it.W2 + (long long)J * TS, 1, b, 0, b,
               -1.0);
       tk.nseg = 1;
       return;
     case PH_SI_VU_X:
       // k starts at tile column J: the first columns (the longest) first
       J = q / nQ; I = q % nQ;
-      tk.m = bdim(b, I); tk.n = bdim(b, J); tk.ti = I; tk.tj = J;
-      tk.C = it.W2 + boff(b, I, J); tk.ldc = b;
-      set_seg(tk.seg[0], St + (long long)I * kBig, 1, b, Dt + (long long)J * kBig * b, b, 1,
-              J * kBig, b, 1.0);
+      tk.m = bdim<TS>(b, I); tk.n = bdim<TS>(b, J); tk.ti = I; tk.tj = J;
+      tk.C = it.W2 + boff<TS>(b, I, J); tk.ldc = b;
+      set_seg(tk.seg[0], St + (long long)I * TS, 1, b, Dt + (long long)J * TS * b, b, 1,
+              J * TS, b, 1.0);
       tk.nseg = 1;
       return;
     case PH_SI_SR_X:
       I = q / nQ; J = q % nQ;
-      tk.m = bdim(b, I); tk.n = bdim(b, J); tk.ti = I; tk.tj = J;
-      tk.C = sig_S(it, t) + boff(b, I, J); tk.ldc = b;
-      set_seg(tk.seg[0], sig_D(it, t + 1) + (long long)I * kBig, 1, b,
-              it.W2 + (long long)J * kBig * b, b, 1, 0, b, -1.0);
+      tk.m = bdim<TS>(b, I); tk.n = bdim<TS>(b, J); tk.ti = I; tk.tj = J;
+      tk.C = sig_S(it, t) + boff<TS>(b, I, J); tk.ldc = b;
+      set_seg(tk.seg[0], sig_D(it, t + 1) + (long long)I * TS, 1, b,
+              it.W2 + (long long)J * TS * b, b, 1, 0, b, -1.0);
       tk.nseg = 1;
       if (arrow) {
-        set_seg(tk.seg[1], sig_R(it, t + 1) + (long long)I * kBig * a, a, 1,
-                it.W3 + (long long)J * kBig * a, a, 1, 0, a, -1.0);
+        set_seg(tk.seg[1], sig_R(it, t + 1) + (long long)I * TS * a, a, 1,
+                it.W3 + (long long)J * TS * a, a, 1, 0, a, -1.0);
         tk.nseg = 2;
       }
       return;
     case PH_SI_SD_X: {
       tri_decode(q, I, J);
       double *SDt = sig_D(it, t);
-      tk.m = bdim(b, I); tk.n = bdim(b, J); tk.ti = I; tk.tj = J;
-      tk.C = SDt + boff(b, I, J); tk.ldc = b;
-      tk.mirror = 1; tk.Cm = SDt + boff(b, J, I); tk.diagtile = (I == J);
-      set_seg(tk.seg[0], Dt + (long long)I * kBig * b, b, 1, Dt + (long long)J * kBig * b, b, 1,
-              I * kBig, b, 1.0);
-      set_seg(tk.seg[1], sig_S(it, t) + (long long)I * kBig * b, b, 1,
-              it.W2 + (long long)J * kBig * b, b, 1, 0, last ? 0 : b, -1.0);
-      set_seg(tk.seg[2], sig_R(it, t) + (long long)I * kBig * a, a, 1,
-              it.W3 + (long long)J * kBig * a, a, 1, 0, a, -1.0);
+      tk.m = bdim<TS>(b, I); tk.n = bdim<TS>(b, J); tk.ti = I; tk.tj = J;
+      tk.C = SDt + boff<TS>(b, I, J); tk.ldc = b;
+      tk.mirror = 1; tk.Cm = SDt + boff<TS>(b, J, I); tk.diagtile = (I == J);
+      set_seg(tk.seg[0], Dt + (long long)I * TS * b, b, 1, Dt + (long long)J * TS * b, b, 1,
+              I * TS, b, 1.0);
+      set_seg(tk.seg[1], sig_S(it, t) + (long long)I * TS * b, b, 1,
+              it.W2 + (long long)J * TS * b, b, 1, 0, last ? 0 : b, -1.0);
+      set_seg(tk.seg[2], sig_R(it, t) + (long long)I * TS * a, a, 1,
+              it.W3 + (long long)J * TS * a, a, 1, 0, a, -1.0);
       tk.nseg = 3;
       return;
     }
@@ -659,15 +674,15 @@ __device__ __forceinline__ void run_product(const Task &tk, double *smem,
 }
 
 // ---------------------------------------------------------------------------
-// Direct-to-LDS staging for the 128-wide tile kernel
+// Direct-to-LDS staging for the product kernel (TS = 64 or 128 rows)
 // ---------------------------------------------------------------------------
 // global_load_lds_dwordx4 (dword) moves 16 (4) bytes per lane from any global
 // address straight into LDS at M0 + 16 (4) * lane, with no registers and no
 // LDS store instructions in between.  Each chunk of KC k-values of an operand
 // lands in one of two layouts, fixed per launch and operand:
-//   P[k][row] (row length kBig + 2), for operands whose rows are contiguous
-//     (op(X)(r, k) = X[r + k*ks]): one k-column of 128 rows is 1 KiB, one
-//     wave instruction.
+//   P[k][row] (row length pld<TS>), for operands whose rows are contiguous
+//     (op(X)(r, k) = X[r + k*ks]): one wave instruction fills 1 KiB, one
+//     k-column of 128 rows or two of 64.
 //   Q[row][k] (row length KC, no padding), for operands whose k runs are
 //     contiguous (op(X)(r, k) = X[r*rs + k]): the 16-byte slot j of row r
 //     holds k = 2(j ^ qswz(r)), 2(j ^ qswz(r)) + 1, so that the 16-byte reads
@@ -693,29 +708,31 @@ __device__ __forceinline__ int qswz(int r16) {
 }
 
 // Issue the direct loads of rows [0, rows) x k in [kc, kc + KC) of
-// op(X)(r, k) = X[r*rs + k*ks] into dst in layout Q (QL) or P; wave w of NW
-// takes every NW-th instruction.  16-byte pieces where the operand's
-// contiguous direction matches the layout (and, in P, an even row count keeps
-// the last pair inside the operand; in Q, k-pairs do not straddle k1), else
-// 4-byte pieces with any strides.
-template <int KC, int NW, bool QL>
+// op(X)(r, k) = X[r*rs + k*ks] into dst in layout Q (QL) or P for a panel of
+// TS rows; wave w of NW takes every NW-th instruction.  16-byte pieces where
+// the operand's contiguous direction matches the layout (and, in P, an even
+// row count keeps the last pair inside the operand; in Q, k-pairs do not
+// straddle k1), else 4-byte pieces with any strides.
+template <int KC, int NW, bool QL, int TS>
 __device__ __forceinline__ void dma_operand(const double *X, int rs, int ks, int rows, int kc,
                                             int k1, double *dst, int w, int lane) {
-  constexpr int LD = kBig + 2;
-  constexpr int SPR = KC / 2;   // 16-byte slots per Q row
+  constexpr int LD = pld<TS>();
+  constexpr int SPR = KC / 2;          // 16-byte slots per Q row
+  constexpr int CPI = 128 / TS;        // k-columns per 16-byte P instruction
+  constexpr int DPC = TS / 32;         // 4-byte instructions per P k-column
   const double *zero = g_dma_zeros;
   if constexpr (!QL) {
     if (rs == 1 && (rows & 1) == 0) {
-      const int r = min(2 * lane, rows - 2);
+      const int r = min(2 * (lane % (TS / 2)), rows - 2), kl = lane / (TS / 2);
 #pragma unroll 1
-      for (int i = 0; i < KC / NW; ++i) {
-        const int h = w + i * NW, k = kc + h;
-        dma16(k < k1 ? X + r + (long long)k * ks : zero, dst + h * LD);
+      for (int i = 0; i < KC / CPI / NW; ++i) {
+        const int h = w + i * NW, k = kc + h * CPI + kl;
+        dma16(k < k1 ? X + r + (long long)k * ks : zero, dst + h * CPI * LD);
       }
     } else {
 #pragma unroll 1
-      for (int i = 0; i < 4 * KC / NW; ++i) {
-        const int h = w + i * NW, kk = h >> 2, qd = h & 3;
+      for (int i = 0; i < DPC * KC / NW; ++i) {
+        const int h = w + i * NW, kk = h / DPC, qd = h % DPC;
         const int d = qd * 64 + lane, r = min(d >> 1, rows - 1), k = kc + kk;
         const char *src = (const char *)(X + (long long)r * rs + (long long)k * ks) + (d & 1) * 4;
         dma4(k < k1 ? (const void *)src : (const void *)zero, dst + kk * LD + qd * 32);
@@ -724,7 +741,7 @@ __device__ __forceinline__ void dma_operand(const double *X, int rs, int ks, int
   } else {
     if (ks == 1 && (kc + KC <= k1 || ((k1 - kc) & 1) == 0)) {
 #pragma unroll 1
-      for (int i = 0; i < KC / NW; ++i) {
+      for (int i = 0; i < KC * TS / 128 / NW; ++i) {
         const int h = w + i * NW, slot = h * 64 + lane;
         const int row = slot / SPR, j = (slot % SPR) ^ qswz<KC>(row & 15);
         const int k = kc + 2 * j, r = min(row, rows - 1);
@@ -732,7 +749,7 @@ __device__ __forceinline__ void dma_operand(const double *X, int rs, int ks, int
       }
     } else {
 #pragma unroll 1
-      for (int i = 0; i < 4 * KC / NW; ++i) {
+      for (int i = 0; i < KC * TS / 32 / NW; ++i) {
         const int h = w + i * NW, d = h * 64 + lane, slot = d >> 2, e = d & 3;
         const int row = slot / SPR, j = (slot % SPR) ^ qswz<KC>(row & 15);
         const int k = kc + 2 * j + (e >> 1), r = min(row, rows - 1);
@@ -743,7 +760,7 @@ __device__ __forceinline__ void dma_operand(const double *X, int rs, int ks, int
   }
 }
 
-// acc += sum over segments of alpha_s op(A_s) op(B_s)^T on a 128 x 128 tile,
+// acc += sum over segments of alpha_s op(A_s) op(B_s)^T on a TS x TS tile,
 // as run_product but staged with direct loads into two LDS buffers (separate
 // arrays, so the compiler knows that loads into one never wait on reads of
 // the other).  The loads of chunk c + 1 are issued before chunk c is
@@ -752,13 +769,13 @@ __device__ __forceinline__ void dma_operand(const double *X, int rs, int ks, int
 // deliver both steps' values with one 16-byte read.  The alphas are applied
 // to the accumulator: at a change of segment it is rescaled by
 // alpha_old / alpha_new (segment weights are nonzero), and once at the end.
-template <int KC, int WR, int WC, bool AQ, bool BQ>
+template <int KC, int WR, int WC, bool AQ, bool BQ, int TS>
 __device__ __forceinline__ void run_product_dma(const Task &tk, double *buf0, double *buf1,
-                                                d4 (&acc)[kBig / WR / 16][kBig / WC / 16],
+                                                d4 (&acc)[TS / WR / 16][TS / WC / 16],
                                                 int part = 0, int nparts = 1) {
   constexpr int NW = WR * WC;
-  constexpr int LD = kBig + 2;
-  constexpr int MR = kBig / WR / 16, MC = kBig / WC / 16;
+  constexpr int LD = pld<TS>();
+  constexpr int MR = TS / WR / 16, MC = TS / WC / 16;
   constexpr int OPS = KC * LD;    // doubles of one operand's panel (P is the larger layout)
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -771,11 +788,11 @@ __device__ __forceinline__ void run_product_dma(const Task &tk, double *buf0, do
   if (ce <= cb) return;
   // per-lane LDS offsets (doubles): P reads at k = 2g (+ 8i + s), Q reads of slot 4i + g
   const int g = lane >> 4, r16 = lane & 15;
-  const int pa = 2 * g * LD + wr * (kBig / WR) + r16, pb = 2 * g * LD + wc * (kBig / WC) + r16;
+  const int pa = 2 * g * LD + wr * (TS / WR) + r16, pb = 2 * g * LD + wc * (TS / WC) + r16;
   int qo[KC / 8];
 #pragma unroll
   for (int i = 0; i < KC / 8; ++i) qo[i] = r16 * KC + (((4 * i + g) ^ qswz<KC>(r16)) << 1);
-  const int qa = wr * (kBig / WR) * KC, qb = wc * (kBig / WC) * KC;
+  const int qa = wr * (TS / WR) * KC, qb = wc * (TS / WC) * KC;
   // chunk c: issue its loads into dst
   auto issue = [&](int c, double *dst) {
     const bool s1 = c >= n0, s2 = c >= n0 + n1;
@@ -788,8 +805,8 @@ __device__ __forceinline__ void run_product_dma(const Task &tk, double *buf0, do
     const int k0 = pick3(s1, s2, tk.seg[0].k0, tk.seg[1].k0, tk.seg[2].k0);
     const int k1 = pick3(s1, s2, tk.seg[0].k1, tk.seg[1].k1, tk.seg[2].k1);
     const int kc = k0 + (c - (s2 ? n0 + n1 : (s1 ? n0 : 0))) * KC;
-    dma_operand<KC, NW, AQ>(A, ars, aks, tk.m, kc, k1, dst, w, lane);
-    dma_operand<KC, NW, BQ>(B, brs, bks, tk.n, kc, k1, dst + OPS, w, lane);
+    dma_operand<KC, NW, AQ, TS>(A, ars, aks, tk.m, kc, k1, dst, w, lane);
+    dma_operand<KC, NW, BQ, TS>(B, brs, bks, tk.n, kc, k1, dst + OPS, w, lane);
   };
   auto seg_alpha = [&](int c) {
     const bool s1 = c >= n0, s2 = c >= n0 + n1;
@@ -1401,8 +1418,8 @@ __global__ __launch_bounds__(kThreads, FAT ? 1 : 2) void tile_phase_kernel(const
       }
 }
 
-// 128 x 128 output tiles for the b x b products: 8 waves in a 2 x 4
-// arrangement, 64 x 32 outputs (4 x 2 MFMA blocks) per wave.
+// Output tiles of the b x b products (TS x TS): WR x WC waves, each owning a
+// block of (TS / WR) x (TS / WC) outputs in 16 x 16 MFMA blocks.
 // The dispatcher deals workgroups round-robin to the 8 XCDs (workgroup id
 // mod 8), each with its own L2.  Renumbering so that XCD x receives one
 // contiguous range of tiles keeps tiles that share operand panels on one L2
@@ -1417,21 +1434,47 @@ __device__ __forceinline__ int xcd_contiguous(int bid, int n) {
 // task numbers, so on one XCD); part h writes its partial product, without
 // beta or mirroring, to it.P + h*b*b at the tile's position (ld b), and
 // splitk_reduce_kernel forms C.
+// With phase2 >= 0 (and ks = 1) the launch also runs the nside tasks of the
+// independent side phase phase2 of the same step (64-tile form: products of
+// the arrow rows and tile copies): they take the first workgroups, so they
+// start at once and spread over the XCDs, and the product tiles follow (their
+// count rounded up to a multiple of 8 so that the XCD of a workgroup is still
+// its number mod 8).
 // LAY (layouts staged by direct loads): bit 0 A in layout Q, bit 1 B in layout Q.
 template <int V, int LAY = 0>
-__global__ __launch_bounds__(big_threads<V>(), BigCfg<V>::OCC) void tile_big_kernel(
-    const ItemDev *__restrict__ items, int n_items, int phase, int t, int ks) {
+__global__ __launch_bounds__(big_threads<V>(), BigCfg<V>::OCC) void tile_product_kernel(
+    const ItemDev *__restrict__ items, int n_items, int phase, int phase2, int nside, int t,
+    int ks) {
   using C = BigCfg<V>;
-  constexpr int MR = kBig / C::WR / 16, MC = kBig / C::WC / 16;
-  const int qa = xcd_contiguous(blockIdx.x, gridDim.x);
-  int q = qa / ks;
-  const int part = qa - q * ks;
-  const int ii = find_item(items, n_items, q,
-                           [&](const ItemDev &x) { return phase_tasks(x, phase, t, 0, true); });
+  constexpr int TS = C::TS;
+  constexpr int MR = TS / C::WR / 16, MC = TS / C::WC / 16;
+  const int nsp = (nside + 7) & ~7;
+  const bool side = (int)blockIdx.x < nsp;
+  int q, part = 0;
+  if (side) {
+    if ((int)blockIdx.x >= nside) return;
+    q = blockIdx.x;
+  } else {
+    const int qa = xcd_contiguous(blockIdx.x - nsp, gridDim.x - nsp);
+    q = qa / ks;
+    part = qa - q * ks;
+  }
+  const int ii =
+      side ? find_item(items, n_items, q, [&](const ItemDev &x) { return phase_tasks(x, phase2, t, 0); })
+           : find_item(items, n_items, q,
+                       [&](const ItemDev &x) { return phase_tasks(x, phase, t, 0, TS == kBig); });
   if (ii >= n_items) return;
   const ItemDev it = items[ii];
   Task tk;
-  decode_big(it, phase, t, q, tk);
+  if (side) decode(it, phase2, t, 0, q, tk);
+  else decode_big<TS>(it, phase, t, q, tk);
+  if (tk.kind == TK_COPY) {
+    for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
+      const int r = e & (kTile - 1), c = e / kTile;
+      if (r < tk.m && c < tk.n) gst(tk.C + r + (long long)c * tk.ldc, gld(tk.src + r + (long long)c * tk.ldc));
+    }
+    return;
+  }
   if (tk.kind != TK_PRODUCT) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = w / C::WC, wc = w % C::WC;
@@ -1443,23 +1486,24 @@ __global__ __launch_bounds__(big_threads<V>(), BigCfg<V>::OCC) void tile_big_ker
   if constexpr (C::DMA) {
     __shared__ __attribute__((aligned(16))) double stage0[big_lds<V>() / 2];
     __shared__ __attribute__((aligned(16))) double stage1[big_lds<V>() / 2];
-    run_product_dma<C::KC, C::WR, C::WC, (LAY & 1) != 0, (LAY & 2) != 0>(tk, stage0, stage1, acc,
-                                                                         part, ks);
+    run_product_dma<C::KC, C::WR, C::WC, (LAY & 1) != 0, (LAY & 2) != 0, TS>(tk, stage0, stage1,
+                                                                             acc, part, ks);
   } else {
     __shared__ double smem[big_lds<V>()];
+    static_assert(TS == kBig, "register-staged layouts are 128-wide");
     run_product<C::KC, kBig, C::WR, C::WC, C::DEPTH>(tk, smem, acc, part, ks);
   }
   if (ks > 1) {
-    double *Pp = it.P + (long long)part * it.b * it.b + (long long)tk.ti * kBig +
-                 (long long)tk.tj * kBig * it.b;
+    double *Pp = it.P + (long long)part * it.b * it.b + (long long)tk.ti * TS +
+                 (long long)tk.tj * TS * it.b;
 #pragma unroll
     for (int mi = 0; mi < MR; ++mi)
 #pragma unroll
       for (int nj = 0; nj < MC; ++nj)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = wr * (kBig / C::WR) + mi * 16 + (lane >> 4) + 4 * r;
-          const int col = wc * (kBig / C::WC) + nj * 16 + (lane & 15);
+          const int row = wr * (TS / C::WR) + mi * 16 + (lane >> 4) + 4 * r;
+          const int col = wc * (TS / C::WC) + nj * 16 + (lane & 15);
           if (row < tk.m && col < tk.n) gst(Pp + row + (long long)col * it.b, acc[mi][nj][r]);
         }
     return;
@@ -1472,8 +1516,8 @@ __global__ __launch_bounds__(big_threads<V>(), BigCfg<V>::OCC) void tile_big_ker
       if (tk.beta != 0.0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = min(wr * (kBig / C::WR) + mi * 16 + (lane >> 4) + 4 * r, tk.m - 1);
-          const int col = min(wc * (kBig / C::WC) + nj * 16 + (lane & 15), tk.n - 1);
+          const int row = min(wr * (TS / C::WR) + mi * 16 + (lane >> 4) + 4 * r, tk.m - 1);
+          const int col = min(wc * (TS / C::WC) + nj * 16 + (lane & 15), tk.n - 1);
           cold[r] = gld(tk.C + row + col * tk.ldc);
         }
 #pragma unroll
@@ -1481,8 +1525,8 @@ __global__ __launch_bounds__(big_threads<V>(), BigCfg<V>::OCC) void tile_big_ker
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = wr * (kBig / C::WR) + mi * 16 + (lane >> 4) + 4 * r;
-        const int col = wc * (kBig / C::WC) + nj * 16 + (lane & 15);
+        const int row = wr * (TS / C::WR) + mi * 16 + (lane >> 4) + 4 * r;
+        const int col = wc * (TS / C::WC) + nj * 16 + (lane & 15);
         if (row < tk.m && col < tk.n) {
           const double v = acc[mi][nj][r];
           double *cp = tk.C + row + col * tk.ldc;
@@ -1498,6 +1542,20 @@ __global__ __launch_bounds__(big_threads<V>(), BigCfg<V>::OCC) void tile_big_ker
         }
       }
     }
+}
+
+// Layout of the 64-wide product phases: 0 the 64-tile kernel with the side
+// phase in the same launch, 1 / 2 the product kernel with direct loads
+// (layouts 6 / 7) and the side phase beside it; INLA_SMALL_VARIANT=0..2 in
+// the environment overrides the engine's choice.
+static int g_small_variant = kDefaultSmallVariant;
+void set_small_variant(int v) {
+  g_small_variant = (v >= 0 && v < kSmallVariants) ? v : kDefaultSmallVariant;
+}
+int small_variant() {
+  const char *e = getenv("INLA_SMALL_VARIANT");
+  if (e && e[0] >= '0' && e[0] < '0' + kSmallVariants) return e[0] - '0';
+  return g_small_variant;
 }
 
 // Layout of the big-tile kernel: the engine's choice (the autotuner's, else
@@ -1522,7 +1580,7 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const ItemDev *__res
   if (ii >= n_items) return;
   const ItemDev it = items[ii];
   Task tk;
-  decode_big(it, phase, t, q, tk);
+  decode_big<kBig>(it, phase, t, q, tk);
   if (tk.kind != TK_PRODUCT) return;
   const long long bb = (long long)it.b * it.b;
   const double *Pp = it.P + (long long)tk.ti * kBig + (long long)tk.tj * kBig * it.b;
@@ -1557,43 +1615,55 @@ inline int big_layouts(int phase) {
   }
 }
 template <int V>
-void launch_big_dma(int phase, long long grid, hipStream_t s, const ItemDev *items_dev, int n_items,
-                    int t, int ks) {
+void launch_big_dma(int phase, int phase2, int nside, long long grid, hipStream_t s,
+                    const ItemDev *items_dev, int n_items, int t, int ks) {
   switch (big_layouts(phase)) {
     case 2:
-      hipLaunchKernelGGL((tile_big_kernel<V, 2>), dim3((unsigned)grid), dim3(big_threads<V>()), 0, s,
-                         items_dev, n_items, phase, t, ks);
+      hipLaunchKernelGGL((tile_product_kernel<V, 2>), dim3((unsigned)grid), dim3(big_threads<V>()), 0, s,
+                         items_dev, n_items, phase, phase2, nside, t, ks);
       break;
     case 3:
-      hipLaunchKernelGGL((tile_big_kernel<V, 3>), dim3((unsigned)grid), dim3(big_threads<V>()), 0, s,
-                         items_dev, n_items, phase, t, ks);
+      hipLaunchKernelGGL((tile_product_kernel<V, 3>), dim3((unsigned)grid), dim3(big_threads<V>()), 0, s,
+                         items_dev, n_items, phase, phase2, nside, t, ks);
       break;
     default:
-      hipLaunchKernelGGL((tile_big_kernel<V, 0>), dim3((unsigned)grid), dim3(big_threads<V>()), 0, s,
-                         items_dev, n_items, phase, t, ks);
+      hipLaunchKernelGGL((tile_product_kernel<V, 0>), dim3((unsigned)grid), dim3(big_threads<V>()), 0, s,
+                         items_dev, n_items, phase, phase2, nside, t, ks);
   }
 }
 
 hipError_t launch_tile_phase(const ItemDev *items_dev, int n_items, int total, int phase,
-                             int phase2, int t, int p, bool big, hipStream_t s, int ks) {
+                             int phase2, int t, int p, bool big, hipStream_t s, int ks, int nside) {
   if (total <= 0) return hipSuccess;
-  if (big && phase_is_product_x(phase) && phase2 < 0) {
-    const long long grid = (long long)total * ks;
+  // the product kernel: 128-wide tiles, or 64-wide ones in a direct-load form;
+  // a side phase rides along only without split-k (total counts its tasks too)
+  const bool prod = phase_is_product_x(phase) && (big || small_variant() > 0) &&
+                    (phase2 < 0 || ks == 1);
+  if (prod) {
+    const int nsp = (phase2 >= 0) ? ((nside + 7) & ~7) : 0;
+    const int ph2 = (phase2 >= 0) ? phase2 : -1;
+    const int ns = (phase2 >= 0) ? nside : 0;
+    const long long grid = (long long)(total - ns) * ks + nsp;
+    if (!big) {
+      if (small_variant() == 2) launch_big_dma<7>(phase, ph2, ns, grid, s, items_dev, n_items, t, 1);
+      else launch_big_dma<6>(phase, ph2, ns, grid, s, items_dev, n_items, t, 1);
+      return hipGetLastError();
+    }
     switch (big_variant()) {
-      case 5: launch_big_dma<5>(phase, grid, s, items_dev, n_items, t, ks); break;
-      case 4: launch_big_dma<4>(phase, grid, s, items_dev, n_items, t, ks); break;
-      case 3: launch_big_dma<3>(phase, grid, s, items_dev, n_items, t, ks); break;
+      case 5: launch_big_dma<5>(phase, ph2, ns, grid, s, items_dev, n_items, t, ks); break;
+      case 4: launch_big_dma<4>(phase, ph2, ns, grid, s, items_dev, n_items, t, ks); break;
+      case 3: launch_big_dma<3>(phase, ph2, ns, grid, s, items_dev, n_items, t, ks); break;
       case 2:
-        hipLaunchKernelGGL(tile_big_kernel<2>, dim3((unsigned)grid), dim3(big_threads<2>()), 0, s,
-                           items_dev, n_items, phase, t, ks);
+        hipLaunchKernelGGL(tile_product_kernel<2>, dim3((unsigned)grid), dim3(big_threads<2>()), 0, s,
+                           items_dev, n_items, phase, ph2, ns, t, ks);
         break;
       case 1:
-        hipLaunchKernelGGL(tile_big_kernel<1>, dim3((unsigned)grid), dim3(big_threads<1>()), 0, s,
-                           items_dev, n_items, phase, t, ks);
+        hipLaunchKernelGGL(tile_product_kernel<1>, dim3((unsigned)grid), dim3(big_threads<1>()), 0, s,
+                           items_dev, n_items, phase, ph2, ns, t, ks);
         break;
       default:
-        hipLaunchKernelGGL(tile_big_kernel<0>, dim3((unsigned)grid), dim3(big_threads<0>()), 0, s,
-                           items_dev, n_items, phase, t, ks);
+        hipLaunchKernelGGL(tile_product_kernel<0>, dim3((unsigned)grid), dim3(big_threads<0>()), 0, s,
+                           items_dev, n_items, phase, ph2, ns, t, ks);
     }
     if (ks > 1) {
       hipError_t e = hipGetLastError();

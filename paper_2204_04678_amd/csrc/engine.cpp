@@ -222,8 +222,8 @@ bool use_big_tiles(const std::vector<ItemDev> &items) {
 enum ProfSlot : int { PS_SOLVE = PH_COUNT, PS_TRACE, PS_ASSEMBLE, PS_MISC, PS_COUNT };
 
 // Kernel behind a record: 0 tile_phase_kernel<false>, 1 tile_phase_kernel<true>,
-// 2 tile_big_kernel, 3 any other kernel.
-enum ProfKind : int { PK_LEAN = 0, PK_FAT = 1, PK_BIG = 2, PK_OTHER = 3, PK_COUNT = 4 };
+// 2 tile_product_kernel, 3 any other kernel.
+enum ProfKind : int { PK_LEAN = 0, PK_FAT = 1, PK_PROD = 2, PK_OTHER = 3, PK_COUNT = 4 };
 struct ProfRec {
   hipEvent_t e0, e1;
   int slot;
@@ -279,7 +279,8 @@ inla_status run_phase(const Batch &B, int phase, int t, int p, hipStream_t s) {
   if (g_prof.on)
     for (const auto &it : B.host) flops += phase_flops(it, phase, t, p);
   const int ks = (big && B.split && total < kSplitTiles) ? kSplitK : 1;
-  ProfScope ps(phase, flops, s, big ? PK_BIG : (phase_is_fat(phase) ? PK_FAT : PK_LEAN));
+  const bool prod = phase_is_product_x(phase) && (B.big || small_variant() > 0);
+  ProfScope ps(phase, flops, s, prod ? PK_PROD : (phase_is_fat(phase) ? PK_FAT : PK_LEAN));
   HIP_TRY(launch_tile_phase(B.dev, (int)B.host.size(), (int)total, phase, -1, t, p, big, s, ks));
   return INLA_OK;
 }
@@ -309,10 +310,11 @@ inla_status run_beside(const Batch &B, int pm, int ps, int t, int p, hipStream_t
 }
 
 // Runs the b x b product phase px together with the independent phase pr of
-// the same step: in one 64-tile launch, or, with big tiles, px on s and pr on
-// a side stream joined back into s.
+// the same step: with 64-wide tiles in one launch (of the 64-tile kernel, or
+// of the product kernel with pr's tasks first); with 128-wide tiles px on s
+// and pr on a side stream joined back into s.
 inla_status run_pair(const Batch &B, int px, int pr, int t, hipStream_t s) {
-  if (!B.big) {
+  if (!B.big && small_variant() == 0) {
     long long total = 0;
     double flops = 0.0;
     for (const auto &it : B.host) {
@@ -328,6 +330,21 @@ inla_status run_pair(const Batch &B, int px, int pr, int t, hipStream_t s) {
   long long rem = 0;
   for (const auto &it : B.host) rem += phase_tasks(it, pr, t, 0);
   if (rem == 0) return run_phase(B, px, t, 0, s);
+  if (!B.big) {
+    // one launch of the product kernel: the side phase's tasks first, then the
+    // tiles (with 128-wide tiles the side phase is larger, up to b^2 of copies
+    // per item, and is better beside the launch than ahead of its tiles)
+    long long tx = 0;
+    for (const auto &it : B.host) tx += phase_tasks(it, px, t, 0);
+    if (tx + rem + 8 > INT_MAX) return fail(INLA_ERR_ARG, "too many tile tasks in one launch");
+    double flops = 0.0;
+    if (g_prof.on)
+      for (const auto &it : B.host) flops += phase_flops(it, px, t, 0) + phase_flops(it, pr, t, 0);
+    ProfScope ps(px, flops, s, PK_PROD);
+    HIP_TRY(launch_tile_phase(B.dev, (int)B.host.size(), (int)(tx + rem), px, pr, t, 0, B.big, s, 1,
+                              (int)rem));
+    return INLA_OK;
+  }
   if (!g_side) {
     HIP_TRY(hipStreamCreateWithFlags(&g_side, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&g_fork, hipEventDisableTiming));
@@ -892,7 +909,7 @@ struct EvalGraph {
   bool valid = false;
   std::vector<const inla_model *> models;
   bool grad = false, var = false, mu = false, prof = false, seq = false;
-  int tile = 0, variant = 0, step = -1;
+  int tile = 0, variant = 0, small = 0, step = -1;
   unsigned long long gen = 0;
   char *base = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1004,7 +1021,8 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
   std::vector<long long> voff(n_items + 1, 0);
   for (int i = 0; i < n_items; ++i) voff[i + 1] = voff[i] + models[i]->n;
   const long long ntot = voff[n_items];
-  const int tile = tile_request(), variant = big_variant(), step = step_fused_override();
+  const int tile = tile_request(), variant = big_variant(), small = small_variant(),
+            step = step_fused_override();
 
   // replay a captured graph when the call matches it and nothing else has
   // laid out the workspace since
@@ -1014,7 +1032,8 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
   if (graphable && g_graph.valid && g_graph.models == key && g_graph.grad == grad &&
       g_graph.var == (var_out != nullptr) && g_graph.mu == (mu_out != nullptr) &&
       g_graph.prof == g_prof.on && g_graph.seq == seq && g_graph.tile == tile &&
-      g_graph.variant == variant && g_graph.step == step && g_graph.gen == g_arena.gen &&
+      g_graph.variant == variant && g_graph.small == small && g_graph.step == step &&
+      g_graph.gen == g_arena.gen &&
       g_graph.base == g_arena.base) {
     if (g_arena.last && g_arena.last_stream != s) HIP_TRY(hipStreamWaitEvent(s, g_arena.last, 0));
     HIP_TRY(hipMemcpyAsync(g_graph.th, theta_dev, (size_t)n_items * 32, hipMemcpyDeviceToDevice, s));
@@ -1248,6 +1267,7 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
       G.seq = seq;
       G.tile = tile;
       G.variant = variant;
+      G.small = small;
       G.step = step;
       G.gen = g_arena.gen;
       G.base = g_arena.base;
@@ -1272,6 +1292,7 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
 struct TileChoice {
   int tile = 0;      // 64 or 128 (0: built-in rule)
   int variant = kDefaultBigVariant;   // layout of the 128-wide kernel
+  int small = kDefaultSmallVariant;   // form of the 64-wide product phases
   double ms = 0.0;
 };
 std::unordered_map<std::string, TileChoice> g_tune;
@@ -1304,9 +1325,10 @@ void tune_load(const std::string &path) {
   while (fgets(line, sizeof(line), fp)) {
     char key[256];
     TileChoice c;
-    if (sscanf(line, " \"%255[^\"]\": {\"tile\": %d, \"variant\": %d, \"ms\": %lf", key, &c.tile,
-               &c.variant, &c.ms) == 4 &&
-        (c.tile == 64 || c.tile == 128))
+    if (sscanf(line, " \"%255[^\"]\": {\"tile\": %d, \"variant\": %d, \"small\": %d, \"ms\": %lf",
+               key, &c.tile, &c.variant, &c.small, &c.ms) == 5 &&
+        (c.tile == 64 || c.tile == 128) && c.variant >= 0 && c.variant < kBigVariants &&
+        c.small >= 0 && c.small < kSmallVariants)
       g_tune[key] = c;
   }
   fclose(fp);
@@ -1322,8 +1344,8 @@ void tune_save(const std::string &path) {
   fprintf(fp, "{\n");
   for (size_t i = 0; i < keys.size(); ++i) {
     const TileChoice &c = g_tune[keys[i]];
-    fprintf(fp, "  \"%s\": {\"tile\": %d, \"variant\": %d, \"ms\": %.4f}%s\n", keys[i].c_str(),
-            c.tile, c.variant, c.ms, i + 1 < keys.size() ? "," : "");
+    fprintf(fp, "  \"%s\": {\"tile\": %d, \"variant\": %d, \"small\": %d, \"ms\": %.4f}%s\n",
+            keys[i].c_str(), c.tile, c.variant, c.small, c.ms, i + 1 < keys.size() ? "," : "");
   }
   fprintf(fp, "}\n");
   fclose(fp);
@@ -1353,10 +1375,12 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
   auto run = [&](const TileChoice &c, bool allow_graph) -> inla_status {
     g_tile_pref = c.tile;
     set_big_variant(c.variant);
+    set_small_variant(c.small);
     const inla_status st = eval_run(models, n_items, theta_dev, f_dev, grad_dev, mu_out, var_out,
                                     status_dev, budget, seq_mode, allow_graph, s);
     g_tile_pref = 0;
     set_big_variant(kDefaultBigVariant);
+    set_small_variant(kDefaultSmallVariant);
     return st;
   };
   TileChoice choice;
@@ -1372,9 +1396,15 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
     } else {
       // time every candidate eagerly (one untimed run, one timed) on the
       // caller's stream; every run computes the same outputs
-      const TileChoice cands[1 + kBigVariants] = {{64, 0, 0.0},  {128, 0, 0.0}, {128, 1, 0.0},
-                                                   {128, 2, 0.0}, {128, 3, 0.0}, {128, 4, 0.0},
-                                                   {128, 5, 0.0}};
+      TileChoice cands[kSmallVariants + kBigVariants];
+      for (int v = 0; v < kSmallVariants; ++v) {
+        cands[v].tile = 64;
+        cands[v].small = v;
+      }
+      for (int v = 0; v < kBigVariants; ++v) {
+        cands[kSmallVariants + v].tile = 128;
+        cands[kSmallVariants + v].variant = v;
+      }
       hipEvent_t e0, e1;
       HIP_TRY(hipEventCreate(&e0));
       HIP_TRY(hipEventCreate(&e1));

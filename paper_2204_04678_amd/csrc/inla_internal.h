@@ -158,8 +158,12 @@ __host__ __device__ inline bool phase_is_fat(int phase) {
 }
 
 // ---- launch wrappers (bta_kernels.hip) ----
+// total counts the tasks of both phases; with the product kernel (big, or a
+// direct-load 64-wide form) and phase2 >= 0, nside of them are phase2's and
+// ks must be 1.
 hipError_t launch_tile_phase(const ItemDev *items_dev, int n_items, int total, int phase,
-                             int phase2, int t, int p, bool big, hipStream_t s, int ks = 1);
+                             int phase2, int t, int p, bool big, hipStream_t s, int ks = 1,
+                             int nside = 0);
 constexpr int kSplitK = 2;        // k-split of 128-tile launches with too few tiles
 hipError_t launch_fill(double *ptr, long long n, double v, hipStream_t s);
 hipError_t launch_fill_int(int *ptr, long long n, int v, hipStream_t s);
@@ -172,6 +176,12 @@ hipError_t launch_logdet_finish(const ItemDev *items_dev, int n_items, double *l
 // loads, k-chunk 16, two workgroups per compute unit).
 constexpr int kBigVariants = 6;
 constexpr int kDefaultBigVariant = 4;
+// Form of the 64-wide product phases (0: 64-tile kernel, the side phase in the
+// same launch; 1, 2: product kernel with direct loads, k-chunk 32 / 16).
+constexpr int kSmallVariants = 3;
+constexpr int kDefaultSmallVariant = 1;
+void set_small_variant(int v);
+int small_variant();
 void set_big_variant(int v);
 int big_variant();
 // ---- model kernels (model_kernels.hip) ----
