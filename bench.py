@@ -52,7 +52,8 @@ def kernel_sources_sha256():
 
 
 def hbm_traffic(config, kernel):
-    """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter
+    """HBM bytes per dispatch of `kernel` (averaged over its instantiations,
+    weighted by their dispatch counts) from the committed rocprofv3 counter
     summary of this workload (FETCH_SIZE and WRITE_SIZE, scaled by what they
     read for a plain 1 GiB copy); None when there is none or the kernel
     sources changed since the counters were taken."""
@@ -63,9 +64,12 @@ def hbm_traffic(config, kernel):
         rec = [json.loads(line[5:]) for line in fh if line.startswith("JSON ")]
     if not rec or rec[0]["source_sha256"] != kernel_sources_sha256():
         return None
-    ks = rec[0]["kernels"]
-    k = ks.get(kernel) or next((v for n, v in ks.items() if n.startswith(kernel + "<")), None)
-    return None if k is None else k["hbm_bytes_per_dispatch"]
+    # every instantiation of the kernel (tile edge, layout), weighted by dispatches
+    ks = [v for n, v in rec[0]["kernels"].items() if n == kernel or n.startswith(kernel + "<")]
+    nd = sum(v["dispatches"] for v in ks)
+    if nd == 0:
+        return None
+    return sum(v["hbm_bytes_per_dispatch"] * v["dispatches"] for v in ks) / nd
 
 
 def cpu_baseline(md, theta, budget_s=20.0):

@@ -34,6 +34,9 @@ _CONFIGS = {
     "c4": dict(N=40, nt=100, nb=6, seed=2208),
     "c4small": dict(N=6, nt=4, nb=6, seed=2208),
     "c5": dict(N=45, nt=200, nb=10, seed=2209),
+    # the line-search workload over 6 time steps: every launch does the same
+    # work as one of the 200-step run's (per-launch profiles)
+    "c5short": dict(N=45, nt=6, nb=10, seed=2209),
 }
 
 
@@ -172,6 +175,6 @@ def config_theta_batch(name: str) -> np.ndarray:
         return THETA0[None, :].copy()
     if name == "c2":
         return fd_stencil(THETA0, 1e-3)
-    if name == "c5":
+    if name in ("c5", "c5short"):
         return line_search_points(THETA0, _CONFIGS["c5"]["seed"])
     raise KeyError(name)

@@ -160,7 +160,11 @@ double phase_flops(const ItemDev &it, int phase, int t, int p) {
   const double b = it.b, a = it.a, b3 = b * b * b;
   const bool last = (t == it.nt - 1);
   switch (phase) {
-    case PH_DIAG0: return 2.0 * b3 / 3.0;            // POTRF and TRTRI of the block, all steps
+    // POTRF and TRTRI of the block (2 b^3 / 3) spread over its launches: the
+    // first diagonal tile, then every tile step equally
+    case PH_DIAG0: return 2.0 * b3 / 3.0 / it.nP;
+    case PH_STEP:
+    case PH_STEPF: return 2.0 * b3 / 3.0 * (it.nP - 1) / ((double)it.nP * it.nP);
     case PH_OFFDIAG_X: return last ? 0.0 : b3;
     case PH_OFFDIAG: return a * b * b;
     case PH_SCHUR_X: return last ? 0.0 : b3;

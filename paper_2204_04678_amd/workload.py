@@ -30,7 +30,7 @@ def main(argv):
         th = np.stack([t for _, t in items])
     else:
         md = config_model(name)
-        th = config_theta_batch(name) if name == "c5" else THETA0[None, :]
+        th = config_theta_batch(name) if name in ("c5", "c5short") else THETA0[None, :]
         models = [P.Model.from_data(md)] * th.shape[0]
     theta = torch.tensor(th, dtype=torch.float64, device="cuda")
     for s in range(steps):
