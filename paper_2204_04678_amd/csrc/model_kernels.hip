@@ -193,9 +193,17 @@ __global__ void solve_stage_kernel(const ItemDev *__restrict__ items, int t, int
                                          : it.D + (long long)t * bb;
       const double *v = (stage == SV_F1) ? x + (long long)(t - 1) * b : tmp;
       const int jend = (stage == SV_F1) ? b : min(b, blockIdx.x * 8 + 8);
+      // four independent partial sums per lane keep four loads in flight
       double acc = 0.0;
       if (M && r < b) {
-        for (int j = cl; j < jend; j += 32) acc = fma(M[r + (long long)j * b], v[j], acc);
+        double a4[4] = {0.0, 0.0, 0.0, 0.0};
+        int j = cl;
+        for (; j + 96 < jend; j += 128) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) a4[u] = fma(M[r + (long long)(j + 32 * u) * b], v[j + 32 * u], a4[u]);
+        }
+        for (; j < jend; j += 32) a4[0] = fma(M[r + (long long)j * b], v[j], a4[0]);
+        acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
       }
       double *red8 = &red[0][0];   // [32][8]
       red8[cl * 8 + rr] = acc;
@@ -254,7 +262,15 @@ __global__ void solve_stage_kernel(const ItemDev *__restrict__ items, int t, int
         if (t < nt - 1) {
           const double *X = it.S + (long long)t * bb + (long long)j * b;
           const double *xn = x + (long long)(t + 1) * b;
-          for (int i = lane; i < b; i += 64) acc += X[i] * xn[i];
+          // four independent partial sums keep four loads in flight
+          double a4[4] = {0.0, 0.0, 0.0, 0.0};
+          int i = lane;
+          for (; i + 192 < b; i += 256) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a4[u] = fma(X[i + 64 * u], xn[i + 64 * u], a4[u]);
+          }
+          for (; i < b; i += 64) a4[0] = fma(X[i], xn[i], a4[0]);
+          acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
         }
         if (a > 0) {
           const double *Rt = it.R + (long long)t * a * b + (long long)j * a;
@@ -263,7 +279,14 @@ __global__ void solve_stage_kernel(const ItemDev *__restrict__ items, int t, int
         }
       } else {
         const double *L = it.D + (long long)t * bb + (long long)j * b;
-        for (int i = j + lane; i < b; i += 64) acc += L[i] * tmp[i];
+        double a4[4] = {0.0, 0.0, 0.0, 0.0};
+        int i = j + lane;
+        for (; i + 192 < b; i += 256) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) a4[u] = fma(L[i + 64 * u], tmp[i + 64 * u], a4[u]);
+        }
+        for (; i < b; i += 64) a4[0] = fma(L[i], tmp[i], a4[0]);
+        acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
       }
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
