@@ -30,41 +30,54 @@ template <int V> struct BigCfg;
 template <> struct BigCfg<0> {   // 128: 8 waves of 64 x 32, two register sets
   static constexpr int TS = 128, WR = 2, WC = 4, KC = 16, DEPTH = 2, OCC = 1;
   static constexpr bool DMA = false;
+  static constexpr int STAGES = 2;
 };
 template <> struct BigCfg<1> {   // 128: 4 waves of 64 x 64, one wave per SIMD
   static constexpr int TS = 128, WR = 2, WC = 2, KC = 16, DEPTH = 2, OCC = 1;
   static constexpr bool DMA = false;
+  static constexpr int STAGES = 2;
 };
 template <> struct BigCfg<2> {   // 128: 8 waves of 64 x 32, deeper k-chunk, one register set
   static constexpr int TS = 128, WR = 2, WC = 4, KC = 32, DEPTH = 1, OCC = 1;
   static constexpr bool DMA = false;
+  static constexpr int STAGES = 2;
 };
 template <> struct BigCfg<3> {   // 128: 8 waves of 64 x 32, direct loads, k-chunk 32
   static constexpr int TS = 128, WR = 2, WC = 4, KC = 32, DEPTH = 1, OCC = 2;
   static constexpr bool DMA = true;
+  static constexpr int STAGES = 2;
 };
 template <> struct BigCfg<4> {   // 128: 8 waves of 64 x 32, direct loads, k-chunk 16, 2 workgroups per CU
   static constexpr int TS = 128, WR = 2, WC = 4, KC = 16, DEPTH = 1, OCC = 4;
   static constexpr bool DMA = true;
+  static constexpr int STAGES = 2;
 };
 template <> struct BigCfg<5> {   // 128: 4 waves of 64 x 64, direct loads, k-chunk 16, 2 workgroups per CU
   static constexpr int TS = 128, WR = 2, WC = 2, KC = 16, DEPTH = 1, OCC = 2;
   static constexpr bool DMA = true;
+  static constexpr int STAGES = 2;
 };
 template <> struct BigCfg<6> {   // 64: 4 waves of 32 x 32, direct loads, k-chunk 32, 2 workgroups per CU
   static constexpr int TS = 64, WR = 2, WC = 2, KC = 32, DEPTH = 1, OCC = 2;
   static constexpr bool DMA = true;
+  static constexpr int STAGES = 2;
 };
 template <> struct BigCfg<7> {   // 64: 4 waves of 32 x 32, direct loads, k-chunk 16, 4 workgroups per CU
   static constexpr int TS = 64, WR = 2, WC = 2, KC = 16, DEPTH = 1, OCC = 4;
   static constexpr bool DMA = true;
+  static constexpr int STAGES = 2;
+};
+template <> struct BigCfg<8> {   // 64: 4 waves of 32 x 32, direct loads, k-chunk 16, four LDS stages
+  static constexpr int TS = 64, WR = 2, WC = 2, KC = 16, DEPTH = 1, OCC = 2;
+  static constexpr bool DMA = true;
+  static constexpr int STAGES = 4;
 };
 // Row length of a [k][row] LDS panel of a TS-row tile: 128 rows are padded by
 // two; 64 rows stay unpadded so that one 1 KiB direct load fills two k-columns.
 template <int TS> constexpr int pld() { return TS == 128 ? TS + 2 : TS; }
 template <int V> constexpr int big_threads() { return 64 * BigCfg<V>::WR * BigCfg<V>::WC; }
 template <int V> constexpr int big_lds() {
-  return 2 * 2 * BigCfg<V>::KC * (BigCfg<V>::DMA ? pld<BigCfg<V>::TS>() : kBig + 2);
+  return BigCfg<V>::STAGES * 2 * BigCfg<V>::KC * (BigCfg<V>::DMA ? pld<BigCfg<V>::TS>() : kBig + 2);
 }
 
 struct Seg {
@@ -769,10 +782,12 @@ __device__ __forceinline__ void dma_operand(const double *X, int rs, int ks, int
 // deliver both steps' values with one 16-byte read.  The alphas are applied
 // to the accumulator: at a change of segment it is rescaled by
 // alpha_old / alpha_new (segment weights are nonzero), and once at the end.
-template <int KC, int WR, int WC, bool AQ, bool BQ, int TS>
+template <int KC, int WR, int WC, bool AQ, bool BQ, int TS, int S>
 __device__ __forceinline__ void run_product_dma(const Task &tk, double *buf0, double *buf1,
+                                                double *buf2, double *buf3,
                                                 d4 (&acc)[TS / WR / 16][TS / WC / 16],
                                                 int part = 0, int nparts = 1) {
+  static_assert(S == 2 || S == 4, "two or four LDS stages");
   constexpr int NW = WR * WC;
   constexpr int LD = pld<TS>();
   constexpr int MR = TS / WR / 16, MC = TS / WC / 16;
@@ -868,6 +883,53 @@ __device__ __forceinline__ void run_product_dma(const Task &tk, double *buf0, do
     }
   };
   constexpr unsigned kVmcnt0 = 0x0F70;   // s_waitcnt vmcnt(0), other counters free
+  if constexpr (S == 4) {
+    // Chunk c sits in stage (c - cb) mod 4; the loads of c + 3 are issued once
+    // every wave is past chunk c - 1 (the barrier), into that chunk's stage.
+    // Before chunk c its own loads must be in: every chunk issues at least
+    // kMin loads per wave and loads retire in order, so waiting until at most
+    // kMin * (chunks issued after c) are outstanding is enough.
+    constexpr int CPI = 128 / TS;
+    constexpr int kMin = 2 * ((KC / CPI / NW) < (KC * TS / 128 / NW) ? (KC / CPI / NW)
+                                                                       : (KC * TS / 128 / NW));
+    static_assert(kMin >= 1 && 2 * kMin < 64, "vmcnt range");
+    // The barrier is s_barrier alone: __syncthreads() would also fence memory
+    // and so wait for every load in flight.  This wave's LDS reads of the
+    // stage about to be refilled are waited for (lgkmcnt(0)) with the loads.
+    constexpr unsigned kLgkm0 = 0x0070;   // lgkmcnt(0) and vmcnt(0); OR in vmcnt
+    auto wait_for = [&](int cc) {
+      const int after = min(2, ce - 1 - cc);
+      if (after >= 2) __builtin_amdgcn_s_waitcnt(kLgkm0 | (2 * kMin));
+      else if (after == 1) __builtin_amdgcn_s_waitcnt(kLgkm0 | kMin);
+      else __builtin_amdgcn_s_waitcnt(kLgkm0);
+    };
+    auto step = [&](int cc, double *now, double *next) {
+      wait_for(cc);
+      __builtin_amdgcn_s_barrier();
+      if (cc + 3 < ce) issue(cc + 3, next);
+      __builtin_amdgcn_sched_barrier(0);
+      rescale(cc);
+      compute(now);
+    };
+    issue(cb, buf0);
+    if (cb + 1 < ce) issue(cb + 1, buf1);
+    if (cb + 2 < ce) issue(cb + 2, buf2);
+    for (int c = cb; c < ce; c += 4) {
+      step(c, buf0, buf3);
+      if (c + 1 >= ce) break;
+      step(c + 1, buf1, buf0);
+      if (c + 2 >= ce) break;
+      step(c + 2, buf2, buf1);
+      if (c + 3 >= ce) break;
+      step(c + 3, buf3, buf2);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int mi = 0; mi < MR; ++mi)
+#pragma unroll
+      for (int nj = 0; nj < MC; ++nj) acc[mi][nj] *= cur;
+    return;
+  }
   issue(cb, buf0);
   __builtin_amdgcn_s_waitcnt(kVmcnt0);
   __syncthreads();
@@ -1483,11 +1545,18 @@ __global__ __launch_bounds__(big_threads<V>(), BigCfg<V>::OCC) void tile_product
   for (int mi = 0; mi < MR; ++mi)
 #pragma unroll
     for (int nj = 0; nj < MC; ++nj) acc[mi][nj] = d4{0.0, 0.0, 0.0, 0.0};
-  if constexpr (C::DMA) {
+  if constexpr (C::DMA && C::STAGES == 4) {
+    __shared__ __attribute__((aligned(16))) double stage0[big_lds<V>() / 4];
+    __shared__ __attribute__((aligned(16))) double stage1[big_lds<V>() / 4];
+    __shared__ __attribute__((aligned(16))) double stage2[big_lds<V>() / 4];
+    __shared__ __attribute__((aligned(16))) double stage3[big_lds<V>() / 4];
+    run_product_dma<C::KC, C::WR, C::WC, (LAY & 1) != 0, (LAY & 2) != 0, TS, 4>(
+        tk, stage0, stage1, stage2, stage3, acc, part, ks);
+  } else if constexpr (C::DMA) {
     __shared__ __attribute__((aligned(16))) double stage0[big_lds<V>() / 2];
     __shared__ __attribute__((aligned(16))) double stage1[big_lds<V>() / 2];
-    run_product_dma<C::KC, C::WR, C::WC, (LAY & 1) != 0, (LAY & 2) != 0, TS>(tk, stage0, stage1,
-                                                                             acc, part, ks);
+    run_product_dma<C::KC, C::WR, C::WC, (LAY & 1) != 0, (LAY & 2) != 0, TS, 2>(
+        tk, stage0, stage1, nullptr, nullptr, acc, part, ks);
   } else {
     __shared__ double smem[big_lds<V>()];
     static_assert(TS == kBig, "register-staged layouts are 128-wide");
@@ -1545,9 +1614,10 @@ __global__ __launch_bounds__(big_threads<V>(), BigCfg<V>::OCC) void tile_product
 }
 
 // Layout of the 64-wide product phases: 0 the 64-tile kernel with the side
-// phase in the same launch, 1 / 2 the product kernel with direct loads
-// (layouts 6 / 7) and the side phase beside it; INLA_SMALL_VARIANT=0..2 in
-// the environment overrides the engine's choice.
+// phase in the same launch, 1 / 2 / 3 the product kernel with direct loads
+// (layouts 6 / 7 / 8) and the side phase in the same launch, 4 layout 6 or 7
+// by the size of the launch; INLA_SMALL_VARIANT=0..4 in the environment
+// overrides the engine's choice.
 static int g_small_variant = kDefaultSmallVariant;
 void set_small_variant(int v) {
   g_small_variant = (v >= 0 && v < kSmallVariants) ? v : kDefaultSmallVariant;
@@ -1645,7 +1715,22 @@ hipError_t launch_tile_phase(const ItemDev *items_dev, int n_items, int total, i
     const int ns = (phase2 >= 0) ? nside : 0;
     const long long grid = (long long)(total - ns) * ks + nsp;
     if (!big) {
-      if (small_variant() == 2) launch_big_dma<7>(phase, ph2, ns, grid, s, items_dev, n_items, t, 1);
+      int sv = small_variant();
+      if (sv == 4) {
+        // layout 6 (two workgroups per CU) unless the launch would need a
+        // second round of them; then layout 7 (four per CU) fits it in one
+        static int cus = 0;
+        if (cus == 0) {
+          int dev = 0;
+          if (hipGetDevice(&dev) != hipSuccess ||
+              hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+              cus <= 0)
+            cus = 256;
+        }
+        sv = (grid > 2LL * cus) ? 2 : 1;
+      }
+      if (sv == 3) launch_big_dma<8>(phase, ph2, ns, grid, s, items_dev, n_items, t, 1);
+      else if (sv == 2) launch_big_dma<7>(phase, ph2, ns, grid, s, items_dev, n_items, t, 1);
       else launch_big_dma<6>(phase, ph2, ns, grid, s, items_dev, n_items, t, 1);
       return hipGetLastError();
     }

@@ -177,9 +177,11 @@ hipError_t launch_logdet_finish(const ItemDev *items_dev, int n_items, double *l
 constexpr int kBigVariants = 6;
 constexpr int kDefaultBigVariant = 4;
 // Form of the 64-wide product phases (0: 64-tile kernel, the side phase in the
-// same launch; 1, 2: product kernel with direct loads, k-chunk 32 / 16).
-constexpr int kSmallVariants = 3;
-constexpr int kDefaultSmallVariant = 1;
+// same launch; 1, 2, 3: product kernel with direct loads, k-chunk 32 / 16 /
+// 16 with four LDS stages; 4: 1, or 2 when a launch has more workgroups than
+// two per compute unit).
+constexpr int kSmallVariants = 5;
+constexpr int kDefaultSmallVariant = 4;
 void set_small_variant(int v);
 int small_variant();
 void set_big_variant(int v);

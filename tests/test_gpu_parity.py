@@ -18,14 +18,16 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-@pytest.fixture(params=[("64", "0"), ("64", "1"), ("64", "2"), ("128", "0"), ("128", "3"),
-                        ("128", "4"), ("128", "5")],
-                ids=["tile64", "tile64dma32", "tile64dma16", "tile128", "tile128dma32",
-                     "tile128dma16", "tile128dma16w4"])
+@pytest.fixture(params=[("64", "0"), ("64", "1"), ("64", "2"), ("64", "3"), ("64", "4"),
+                        ("128", "0"), ("128", "3"), ("128", "4"), ("128", "5")],
+                ids=["tile64", "tile64dma32", "tile64dma16", "tile64dma16s4", "tile64auto",
+                     "tile128", "tile128dma32", "tile128dma16", "tile128dma16w4"])
 def tile(request, monkeypatch):
     """Run the b x b product phases on 64- or 128-wide tiles: 64 in the 64-tile
     kernel (form 0) or in the product kernel with direct-to-LDS staging (forms
-    1, 2: k-chunks of 32 and 16); 128 with register staging (layout 0) or
+    1, 2, 3: k-chunks of 32 and 16, and 16 with four LDS stages; form 4
+    picks 1 or 2 by launch size); 128 with
+    register staging (layout 0) or
     direct-to-LDS staging (layouts 3-5: 8 waves with k-chunks of 32 and 16,
     4 waves with k-chunk 16)."""
     size, variant = request.param
