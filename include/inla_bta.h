@@ -121,8 +121,9 @@ typedef struct {
  *                      autotune_cache is set, else a built-in rule
  *   autotune_cache   : path of a JSON file (or NULL).  On the first call with
  *                      a new signature (the multiset of item shapes and the
- *                      outputs asked for) every tile layout is timed once on
- *                      the caller's stream, synchronously, and the fastest is
+ *                      outputs asked for) every candidate (the tile edge and
+ *                      the product kernel's layout) is timed once on the
+ *                      caller's stream, synchronously, and the fastest is
  *                      stored; later calls and processes read it back.
  * Results with different tile layouts agree to rounding (about 1e-15
  * relative), not bitwise.
@@ -236,8 +237,9 @@ inla_status inla_eval_f_grad(const inla_model *const *models, int32_t n_items,
  * reductions, assembly, the rest, and a last slot whose out[0] is the number
  * of evaluations the records cover (a replayed graph re-records its events,
  * so it counts once) and out[1] the number of unreadable records, then four
- * slots per kernel: the 64-tile product kernel, the in-tile Cholesky kernel,
- * the 128-tile product kernel, and all other kernels.
+ * slots per kernel: the 64-tile kernel (Cholesky steps, side phases), the
+ * in-tile Cholesky kernel, the product kernel (64- or 128-wide tiles), and
+ * all other kernels.
  * inla_profile_slots() returns the slot count.  Profiling drops any captured
  * graph of inla_eval_f / inla_eval_f_grad when it starts and ends.
  */

@@ -698,8 +698,8 @@ __device__ __forceinline__ void run_product(const Task &tk, double *smem,
 //     k-column of 128 rows or two of 64.
 //   Q[row][k] (row length KC, no padding), for operands whose k runs are
 //     contiguous (op(X)(r, k) = X[r*rs + k]): the 16-byte slot j of row r
-//     holds k = 2(j ^ qswz(r)), 2(j ^ qswz(r)) + 1, so that the 16-byte reads
-//     of 8 (16) consecutive rows fall on distinct banks.
+//     holds k = 2(j ^ qswz(r)), 2(j ^ qswz(r)) + 1, which spreads the 16-byte
+//     reads of consecutive rows over the banks.
 // Out-of-range k reads a 16-byte block of zeros; rows past the tile's end
 // repeat the last row (those rows of the product are never stored).
 // Global addresses need only dword alignment, which every double satisfies.
@@ -714,10 +714,14 @@ __device__ __forceinline__ void dma4(const void *src, double *dst) {
   __builtin_amdgcn_global_load_lds((glb_void_t *)src, (lds_void_t *)dst, 4, 0, 0);
 }
 
+// Slot permutation of Q row r (r16 = r mod 16): KC = 16 has 8 slots of 16
+// bytes per row, KC = 32 has 16.  With these the 16-byte reads of the matrix
+// loop run free of LDS bank conflicts (rocprofv3 SQ_LDS_BANK_CONFLICT = 0 on
+// gfx950; (r mod 8) xor ((r / 8) mod 2) for KC = 16 gave one conflict cycle
+// per matrix instruction, without a measurable change in time).
 template <int KC>
 __device__ __forceinline__ int qswz(int r16) {
-  // KC = 16: 8 slots of 16 bytes per row; KC = 32: 16 slots
-  return KC == 16 ? ((r16 & 7) ^ (r16 >> 3)) : (r16 & 15);
+  return KC == 16 ? (r16 & 7) : (r16 & 15);
 }
 
 // Issue the direct loads of rows [0, rows) x k in [kc, kc + KC) of
@@ -1628,7 +1632,7 @@ int small_variant() {
   return g_small_variant;
 }
 
-// Layout of the big-tile kernel: the engine's choice (the autotuner's, else
+// Layout of the 128-wide product kernel: the engine's choice (the autotuner's, else
 // the default); INLA_BIG_VARIANT=0..5 in the environment overrides it.
 static int g_big_variant = kDefaultBigVariant;
 void set_big_variant(int v) {

@@ -289,7 +289,7 @@ inla_status run_phase(const Batch &B, int phase, int t, int p, hipStream_t s) {
   return INLA_OK;
 }
 
-// Side stream (default priority) for phases that run beside a big-tile launch.
+// Side stream (default priority) for phases that run beside another launch.
 hipStream_t g_side = nullptr;
 hipEvent_t g_fork = nullptr, g_join = nullptr;
 
