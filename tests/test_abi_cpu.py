@@ -45,3 +45,42 @@ def test_argument_errors_are_synchronous(libpath):
     bad = binding.Bta(0, 1, 0, None, None, None, None)
     assert L.inla_factor_logdet(ctypes.byref(bad), None, None, None) == -1
     assert L.inla_solve(ctypes.byref(bad), None, None, 1, None) == -1
+
+
+def test_batch_and_shape_errors_are_synchronous(libpath):
+    """Empty batches, NULL models, bad options and mismatched shapes are
+    rejected with INLA_ERR_ARG before any device call (the pointers below are
+    never dereferenced)."""
+    L = binding.lib(libpath)
+    dummy = ctypes.c_void_p(64)
+    empty = (ctypes.c_void_p * 1)()
+    assert L.inla_eval_f(empty, 0, dummy, dummy, None, None, None, None, None) == -1
+    assert b"n_items >= 1" in L.inla_last_error()
+    assert L.inla_eval_f_grad(empty, 0, dummy, dummy, dummy, None, None, None, None,
+                              None) == -1
+    assert b"n_items >= 1" in L.inla_last_error()
+    assert L.inla_eval_f(None, 1, dummy, dummy, None, None, None, None, None) == -1
+    holes = (ctypes.c_void_p * 2)(dummy.value, None)
+    assert L.inla_eval_f(holes, 2, dummy, dummy, None, None, None, None, None) == -1
+    assert b"NULL model" in L.inla_last_error()
+    one = (ctypes.c_void_p * 1)(dummy.value)
+    for field, value, msg in (("tile", 96, b"tile must be"), ("recompute", 3, b"recompute"),
+                              ("keep_sigma", 1, b"keep_sigma")):
+        o = binding.Opts()
+        setattr(o, field, value)
+        assert L.inla_eval_f(one, 1, dummy, dummy, None, None, None, ctypes.byref(o),
+                             None) == -1
+        assert msg in L.inla_last_error()
+    # arrow wider than 64, missing S with nt > 1, missing R/T with a > 0
+    for b, nt, a, S, R in ((8, 2, 65, dummy, dummy), (8, 2, 0, None, None),
+                           (8, 1, 2, None, None)):
+        q = binding.Bta(b, nt, a, dummy, S, R, R)
+        assert L.inla_factor_logdet(ctypes.byref(q), dummy, dummy, None) == -1
+        assert b"QL" in L.inla_last_error()
+    Lq = binding.Bta(8, 2, 1, dummy, dummy, dummy, dummy)
+    sig = binding.Bta(8, 3, 1, dummy, dummy, dummy, dummy)
+    assert L.inla_selinv(ctypes.byref(Lq), ctypes.byref(sig), None, None) == -1
+    assert b"sigma shape" in L.inla_last_error()
+    assert L.inla_assemble(None, dummy, 0, ctypes.byref(Lq), None, None) == -1
+    assert L.inla_assemble(dummy, dummy, 2, ctypes.byref(Lq), None, None) == -1
+    assert b"which" in L.inla_last_error()

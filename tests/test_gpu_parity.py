@@ -82,6 +82,30 @@ def blk_err(x, y):
     return np.abs(x - y).max() / max(np.abs(y).max(), 1e-300)
 
 
+def grad_term_magnitudes(md, theta):
+    """Per component of grad f, the sum of the absolute values of the terms the
+    gradient adds up: the prior term, half the two traces tr(Q^-1 dQ_k), half
+    the quadratic form mu^T dQ_p_k mu and, for the noise precision, the
+    residual and count terms (dense, small models only)."""
+    from oracle.inla_oracle import conditional_precision, dprecision, obs_matrix, theta_params
+    t = np.asarray(theta, dtype=np.float64)
+    tau_y = theta_params(t)[3]
+    Qp, Qc, rhs = conditional_precision(md, t)
+    Sp = np.linalg.inv(Qp.toarray())
+    Sc = np.linalg.inv(Qc.toarray())
+    mu = np.linalg.solve(Qc.toarray(), rhs)
+    dQp, dQc = dprecision(md, t)
+    r = md.y - obs_matrix(md) @ mu
+    pm = np.asarray(md.theta_prior_mean)
+    pp = np.asarray(md.theta_prior_prec)
+    out = np.empty(t.size)
+    for k in range(t.size):
+        out[k] = (abs(pp[k] * (t[k] - pm[k])) + 0.5 * abs(np.sum(Sp * dQp[k].toarray()))
+                  + 0.5 * abs(np.sum(Sc * dQc[k].toarray())) + 0.5 * abs(mu @ (dQp[k] @ mu)))
+    out[-1] += 0.5 * tau_y * float(r @ r) + 0.5 * md.m
+    return out
+
+
 SHAPES = [(1, 4, 2), (16, 1, 0), (64, 3, 1), (100, 3, 2), (130, 2, 3), (70, 4, 0), (200, 2, 5),
           (300, 2, 3), (257, 2, 1), (17, 3, 1), (520, 2, 2)]
 
@@ -104,7 +128,7 @@ def test_factor_logdet_random_bta(P, tile, b, nt, a):
 
 
 @pytest.mark.parametrize("b,nt,a", [(100, 3, 2), (64, 2, 1), (1, 5, 1), (130, 2, 0), (300, 3, 3),
-                                   (257, 2, 1)])
+                                   (257, 2, 1), (40, 1, 3), (1, 1, 0), (70, 2, 64)])
 def test_solve_and_selinv_random_bta(P, tile, b, nt, a):
     print(f"solve/selinv b={b} nt={nt} a={a} tile={tile}", flush=True)
     Q = rand_spd_bta(b, nt, a, seed=7 + b + nt + a)
@@ -219,6 +243,36 @@ def test_eval_f_grad_small(P, tile):
     gref = O.dense_gradient(md, THETA0)
     assert rel(out["f"].item(), O.eval_f_dense(md, THETA0)["f"]) < 1e-10
     assert np.max(np.abs(g - gref) / np.maximum(np.abs(gref), 1e-3 * np.abs(gref).max())) < 1e-9
+
+
+@pytest.mark.parametrize("N,nt,nb", [(4, 1, 2), (5, 3, 0), (1, 3, 1), (1, 1, 0), (6, 2, 64)],
+                         ids=["one_step", "no_fixed", "one_node", "scalar", "max_arrow"])
+def test_eval_f_grad_degenerate_models(P, N, nt, nb):
+    """One time step, no fixed effects, a one-node mesh (b = 1), a 1x1 problem
+    and the widest arrow the library accepts: f, grad f, mu and the variances
+    against the dense oracle.  The wide-arrow mesh has more observations than
+    fixed effects (144 > 64), so Q_c stays well conditioned (cond ~ 1e3); on a
+    smaller mesh the fixed effects are set by their vague prior alone and
+    cond(Q_c) ~ 1e7 puts the mean's rounding error itself near 1e-9."""
+    print(f"degenerate model N={N} nt={nt} nb={nb}", flush=True)
+    md = make_model(N, nt, nb, 5)
+    M = P.Model.from_data(md)
+    out = P.eval_f_grad(M, THETA0, want_mu=True, want_var=True)
+    torch.cuda.synchronize()
+    assert int(out["status"].item()) == 0
+    ref = O.eval_f_dense(md, THETA0)
+    assert rel(out["f"].item(), ref["f"]) < 1e-10
+    g = out["grad"].cpu().numpy()[0]
+    gref = O.dense_gradient(md, THETA0)
+    # each component is a sum of trace and quadratic terms that can cancel
+    # (with 64 fixed effects the two traces agree to 1e-4): rounding error is
+    # bounded relative to the terms' magnitudes, not to their sum
+    scale = np.maximum(grad_term_magnitudes(md, THETA0), 1e-3 * np.abs(gref).max())
+    assert np.max(np.abs(g - gref) / scale) < 1e-9
+    mu = out["mu"].cpu().numpy()
+    assert np.abs(mu - ref["mu"]).max() / np.abs(ref["mu"]).max() < 1e-9
+    var_ref = O.marginal_variances_dense(md, THETA0)
+    assert np.max(np.abs(out["var"].cpu().numpy() - var_ref) / var_ref) < 1e-9
 
 
 def test_batched_uneven_matches_single(P):
