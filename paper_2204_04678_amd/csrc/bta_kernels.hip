@@ -989,11 +989,43 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   return y;
 }
 
+// One 16 x 16 block of X = L^{-1} below the diagonal, by one wave:
+// X_ij = -X_ii sum_{m=j}^{i-1} L_im X_mj (L in A, X in X, both row-major with
+// ld TLD); P is the wave's own 16 x 16 scratch (ld TLD) for the sum.
+__device__ __forceinline__ void inv_block(const double *A, double *X, double *P, int i, int j) {
+  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int m = j; m < i; ++m) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double av = A[(16 * i + lr) * TLD + 16 * m + 4 * q + lk];
+      const double bv = X[(16 * m + 4 * q + lk) * TLD + 16 * j + lr];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) P[(lk + 4 * r) * TLD + lr] = acc[r];
+  // the wave reads back what its own lanes wrote (LDS operations of a wave
+  // complete in order)
+  __builtin_amdgcn_wave_barrier();
+  d4 acc2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double av = X[(16 * i + lr) * TLD + 16 * i + 4 * q + lk];
+    const double bv = P[(4 * q + lk) * TLD + lr];
+    acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc2, 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) X[(16 * i + lk + 4 * r) * TLD + 16 * j + lr] = -acc2[r];
+}
+
 // Cholesky + inverse of one 64 x 64 tile held in LDS (A, row-major, ld TLD;
 // rows/cols >= w padded with the identity).  16 x 16 diagonal blocks are
-// factored and inverted by one wave (rows in lanes, columns broadcast through
-// LDS); the panel solves, trailing updates and the block inverse X = L^{-1}
-// (X_ij = -X_ii sum_m L_im X_mj) run on the matrix cores.  Writes inv(L)
+// factored and inverted by one wave (rows in lanes, columns broadcast from
+// lane to lane); the panel solves, trailing updates and the blocks of
+// X = L^{-1} below the diagonal (X_ij = -X_ii sum_m L_im X_mj) run on the
+// matrix cores, the row blocks of X on the other waves while wave 0 factors
+// the next diagonal block.  Writes inv(L)
 // (zeros above the diagonal) to Lout and sum log L_jj; a pivot that is not
 // positive sets *info to its 1-based row (row_off + local row) if smaller.
 // dlog holds the 64 diagonal entries of L (its 2 * kTile doubles leave room).
@@ -1019,6 +1051,7 @@ __device__ void chol_inv_tile(double *A, double *X, double *dlog, int w, double 
       const int lr16 = lane & 15;
 #pragma unroll
       for (int c = 0; c < 16; ++c) a[c] = A[(r0 + lr16) * TLD + r0 + c];
+      double dg = 1.0;   // lane j keeps L_jj
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         double cv[16];
@@ -1028,6 +1061,8 @@ __device__ void chol_inv_tile(double *A, double *X, double *dlog, int w, double 
         const double ip = recip_nr(piv);
         const double rs = rsqrt_nr(piv);
         rinv[j] = rs;
+        // L_jj = piv / sqrt(piv), the same value on every lane
+        dg = (lr16 == j) ? piv * rs : dg;
         // A_im -= L_ij L_mj = A_ij A_mj / piv for m > j; then L_ij = A_ij / sqrt(piv)
         const double wj = a[j] * ip;
 #pragma unroll
@@ -1037,15 +1072,13 @@ __device__ void chol_inv_tile(double *A, double *X, double *dlog, int w, double 
       if (lane < 16) {
 #pragma unroll
         for (int c = 0; c < 16; ++c) A[(r0 + lane) * TLD + r0 + c] = a[c];
+        dlog[r0 + lane] = dg;   // logs taken once, at the end
       }
-      __builtin_amdgcn_wave_barrier();
-      // L_jj = piv_j / sqrt(piv_j) is NaN exactly when the pivot is not
-      // positive (or not a number): the first such row is the failure
-      const double dg = A[(r0 + lr16) * TLD + r0 + lr16];
+      // L_jj is NaN exactly when the pivot is not positive (or not a
+      // number): the first such row is the failure
       const bool ok = (dg > 0.0) || lane >= 16 || r0 + lane >= w;
       const unsigned long long badm = __ballot(!ok);
       if (badm && lane == 0) atomicMin(info, row_off + r0 + __ffsll(badm));
-      if (lane < 16) dlog[r0 + lane] = dg;   // logs taken once, at the end
       __builtin_amdgcn_wave_barrier();
       // X = L^{-1}: X_ic = (delta_ic - sum_{m<i} L_im X_mc) / L_ii; entries
       // above the diagonal come out zero because the right-hand side is e_c
@@ -1076,6 +1109,11 @@ __device__ void chol_inv_tile(double *A, double *X, double *dlog, int w, double 
 #pragma unroll
         for (int i = 0; i < 16; ++i) X[(r0 + i) * TLD + r0 + lane] = x[i];
       }
+    } else if (wv < k) {
+      // row block k-1 of X (block j = wv-1 < k-1): L_{k-1,m} (m < k-1), the
+      // rows of X above and X_{k-1,k-1} are final; the scratch is the unused
+      // block (0, wv) above the diagonal
+      inv_block(A, X, A + 16 * wv, k - 1, wv - 1);
     }
     __syncthreads();
     if (k + 1 >= nb) break;
@@ -1118,69 +1156,61 @@ __device__ void chol_inv_tile(double *A, double *X, double *dlog, int w, double 
     }
     __syncthreads();
   }
-  // block inverse below the diagonal, one block diagonal d at a time
-  for (int d = 1; d < nb; ++d) {
-    const int j = wv, i = wv + d;
-    double *P = A + 16 * (wv + 1);   // scratch: upper block (0, wv+1) of A is unused
-    const bool act = i < nb;
-    if (act) {
-      d4 acc = {0.0, 0.0, 0.0, 0.0};
-      for (int m = j; m < i; ++m) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const double av = A[(16 * i + lr) * TLD + 16 * m + 4 * q + lk];
-          const double bv = X[(16 * m + 4 * q + lk) * TLD + 16 * j + lr];
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) P[(lk + 4 * r) * TLD + lr] = acc[r];
-    }
-    __syncthreads();
-    if (act) {
-      d4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const double av = X[(16 * i + lr) * TLD + 16 * i + 4 * q + lk];
-        const double bv = P[(4 * q + lk) * TLD + lr];
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) X[(16 * i + lk + 4 * r) * TLD + 16 * j + lr] = -acc[r];
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < kTile * kTile; e += kThreads) {
-    const int r = e & (kTile - 1), c = e / kTile;
-    if (r < w && c < w) gst(Lout + r + (long long)c * ldl, (c <= r) ? X[r * TLD + c] : 0.0);
-  }
-  if (wv == 0) {
+  // the last row block of X (blocks j < nb-1 on waves j; scratch above the
+  // diagonal of block row 0) and, on wave 3, the sum of log L_jj
+  if (wv < nb - 1) {
+    inv_block(A, X, A + 16 * (wv + 1), nb - 1, wv);
+  } else if (wv == 3) {
     double v = (lane < w) ? log(dlog[lane]) : 0.0;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     if (lane == 0) *ldsum = v;
   }
+  __syncthreads();
+  {
+    // inv(L) (zeros above the diagonal) to Lout: every read is issued before the stores
+    double v[kTile * kTile / kThreads];
+#pragma unroll
+    for (int q = 0; q < kTile * kTile / kThreads; ++q) {
+      const int e = tid + q * kThreads;
+      const int r = e & (kTile - 1), c = e / kTile;
+      v[q] = (c <= r) ? X[r * TLD + c] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kTile * kTile / kThreads; ++q) {
+      const int e = tid + q * kThreads;
+      const int r = e & (kTile - 1), c = e / kTile;
+      if (r < w && c < w) gst(Lout + r + (long long)c * ldl, v[q]);
+    }
+  }
   if (Mout) {
-    // M_rc = sum_k X_kr X_kc; wave (wr, wc) computes the 32 x 32 block (wr, wc).
+    // M = X^T X = inv(A) is symmetric and M_rc = sum_{k >= max(r,c)} X_kr X_kc
+    // (X lower triangular), so of the 32 x 32 blocks only (0,0), (1,0) and
+    // (1,1) are computed, each wave over 32 values of k: wave 0 takes block
+    // (0,0) over k < 32 and wave 1 over k >= 32 (its sum reaches wave 0 through
+    // LDS), waves 2 and 3 take blocks (1,0) and (1,1), where only k >= 32
+    // contributes.  Block (0,1) is stored as the transpose of block (1,0).
     // Only the lower triangle of X in LDS is defined: entries above it are read as 0.
-    const int wr = wv >> 1, wc = wv & 1;
+    const int br = wv >> 1, bc = (wv == 3) ? 1 : 0;
+    const int k0 = (wv == 0) ? 0 : 32;
     d4 mac[2][2];
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
       for (int nj = 0; nj < 2; ++nj) mac[mi][nj] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int kk = 0; kk < kTile; kk += 4) {
-      const int kq = kk + lk;
+#pragma unroll
+    for (int kk = 0; kk < 32; kk += 4) {
+      const int kq = k0 + kk + lk;
       double av[2], bv[2];
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi) {
-        const int r = wr * 32 + mi * 16 + lr;
+        const int r = br * 32 + mi * 16 + lr;
         const double v = X[kq * TLD + r];
         av[mi] = (kq >= r) ? v : 0.0;
       }
 #pragma unroll
       for (int nj = 0; nj < 2; ++nj) {
-        const int c = wc * 32 + nj * 16 + lr;
+        const int c = bc * 32 + nj * 16 + lr;
         const double v = X[kq * TLD + c];
         bv[nj] = (kq >= c) ? v : 0.0;
       }
@@ -1190,14 +1220,30 @@ __device__ void chol_inv_tile(double *A, double *X, double *dlog, int w, double 
         for (int nj = 0; nj < 2; ++nj)
           mac[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mi], bv[nj], mac[mi][nj], 0, 0, 0);
     }
+    // the factor in A is no longer needed: wave 1's partial sums pass through it
+    if (wv == 1) {
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
+      for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-      for (int nj = 0; nj < 2; ++nj)
+        for (int nj = 0; nj < 2; ++nj)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          gst(Mout + (wr * 32 + mi * 16 + lk + 4 * r) + (long long)(wc * 32 + nj * 16 + lr) * kTile,
-              mac[mi][nj][r]);
+          for (int r = 0; r < 4; ++r) A[(mi * 16 + lk + 4 * r) * TLD + nj * 16 + lr] = mac[mi][nj][r];
+    }
+    __syncthreads();
+    if (wv != 1) {
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = br * 32 + mi * 16 + lk + 4 * r, col = bc * 32 + nj * 16 + lr;
+            double v = mac[mi][nj][r];
+            if (wv == 0) v += A[(mi * 16 + lk + 4 * r) * TLD + nj * 16 + lr];
+            gst(Mout + row + (long long)col * kTile, v);
+            if (wv == 2) gst(Mout + col + (long long)row * kTile, v);
+          }
+    }
   }
 }
 
@@ -1266,15 +1312,30 @@ __device__ __forceinline__ void left_chain_product(const Task &tk, double *smem,
 // TK_CHAIN on a 64 x 64 tile: acc = -(A0 B0) A1^T (+ seg[2]).  The intermediate T = A0 B0
 // (tk.m x 64, k = 64) comes from the regular product loop; it and A1 are then
 // staged in LDS (row-major, ld TLD) for the second product (k = 64).
-template <int KC>
+template <int KC, bool EARLY>
 __device__ __forceinline__ void chain_product(const Task &tk, double *smem, d4 (&acc)[2][2]) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = w >> 1, wc = w & 1;
+  // EARLY: the second product's right operand is loaded first, so that its
+  // latency overlaps the first product's loads (it holds 32 more registers)
+  const double *A1 = tk.seg[1].A;
+  const long long aks = tk.seg[1].aks;
+  double b1[kTile * kTile / kThreads];
+  auto load_b1 = [&]() {
+#pragma unroll
+    for (int q = 0; q < kTile * kTile / kThreads; ++q) {
+      const int e = tid + q * kThreads;
+      const int c = e & (kTile - 1), k = e / kTile;
+      b1[q] = gld(A1 + min(c, tk.n - 1) + (long long)k * aks);
+    }
+  };
+  if constexpr (EARLY) load_b1();
   Task t1 = tk;
   t1.n = kTile;
   t1.nseg = 1;
   run_product<KC, kTile, 2, 2, 2>(t1, smem, acc);   // ends with a barrier
   double *TA = smem, *TB = smem + kTile * TLD;
+  if constexpr (!EARLY) load_b1();
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
@@ -1282,13 +1343,11 @@ __device__ __forceinline__ void chain_product(const Task &tk, double *smem, d4 (
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         TA[acc_row(wr, mi, lane, r) * TLD + acc_col(wc, nj, lane)] = acc[mi][nj][r];
-  const double *A1 = tk.seg[1].A;
-  const long long aks = tk.seg[1].aks;
 #pragma unroll
   for (int q = 0; q < kTile * kTile / kThreads; ++q) {
     const int e = tid + q * kThreads;
     const int c = e & (kTile - 1), k = e / kTile;
-    TB[c * TLD + k] = gld(A1 + min(c, tk.n - 1) + (long long)k * aks);
+    TB[c * TLD + k] = b1[q];
   }
   __syncthreads();
 #pragma unroll
@@ -1398,7 +1457,21 @@ __global__ __launch_bounds__(kThreads, FAT ? 1 : 2) void tile_phase_kernel(const
 #pragma unroll
     for (int nj = 0; nj < 2; ++nj) acc[mi][nj] = d4{0.0, 0.0, 0.0, 0.0};
   constexpr int KC = FAT ? kFatKC : kLeanKC;
-  if (tk.kind == TK_CHAIN) chain_product<KC>(tk, smem, acc);
+  // C of the tile that is factored here is loaded (column by column, in
+  // full lines) before the products start, so that its latency overlaps theirs
+  constexpr int kPer = kTile * kTile / kThreads;
+  double cpre[FAT ? kPer : 1];
+  if constexpr (FAT) {
+    if (tk.chol) {
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const int e = tid + q * kThreads;
+        const int r = min(e & (kTile - 1), tk.m - 1), c = min(e / kTile, tk.n - 1);
+        cpre[q] = gld(tk.C + r + c * tk.ldc);
+      }
+    }
+  }
+  if (tk.kind == TK_CHAIN) chain_product<KC, FAT>(tk, smem, acc);
   else if (tk.kind == TK_LCHAIN) left_chain_product<KC>(tk, smem, acc);
   else run_product<KC, kTile, 2, 2, 2>(tk, smem, acc);
 
@@ -1407,8 +1480,15 @@ __global__ __launch_bounds__(kThreads, FAT ? 1 : 2) void tile_phase_kernel(const
       double *A = smem;
       double *X = smem + kTile * TLD;
       double *dlog = smem + 2 * kTile * TLD;
-      // the tile (identity padding beyond w) is written in full, without branches
-      double cold[2][2][4];
+      // beta C (identity padding beyond the tile) goes to LDS in full, then
+      // each lane adds its part of the product
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const int e = tid + q * kThreads;
+        const int r = e & (kTile - 1), c = e / kTile;
+        A[r * TLD + c] = (r < tk.m && c < tk.n) ? tk.beta * cpre[q] : ((r == c) ? 1.0 : 0.0);
+      }
+      __syncthreads();
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
@@ -1416,18 +1496,7 @@ __global__ __launch_bounds__(kThreads, FAT ? 1 : 2) void tile_phase_kernel(const
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int row = acc_row(wr, mi, lane, r), col = acc_col(wc, nj, lane);
-            cold[mi][nj][r] = gld(tk.C + min(row, tk.m - 1) + min(col, tk.n - 1) * tk.ldc);
-          }
-#pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-        for (int nj = 0; nj < 2; ++nj)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = acc_row(wr, mi, lane, r), col = acc_col(wc, nj, lane);
-            const double v = acc[mi][nj][r] + tk.beta * cold[mi][nj][r];
-            const double pad = (row == col) ? 1.0 : 0.0;
-            A[row * TLD + col] = (row < tk.m && col < tk.n) ? v : pad;
+            if (row < tk.m && col < tk.n) A[row * TLD + col] += acc[mi][nj][r];
           }
       __syncthreads();
       chol_inv_tile(A, X, dlog, tk.m, tk.Lout, tk.ldl, tk.ldsum, tk.row_off, it.info, tk.Mout);
