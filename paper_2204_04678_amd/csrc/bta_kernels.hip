@@ -240,16 +240,24 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
         return;
       }
       // column p+1 (and the diagonal tile of column p+2):
-      // A_{i,jc} -= L_{i,p-1} L_{jc,p-1}^T + (A_ip M_p) A_{jc,p}^T with
-      // M_p = inv(L_pp)^T inv(L_pp) = inv(A_pp); the diagonal tile factored in
-      // this step took its column p-1 term in the previous one
+      // A_{i,jc} -= L_{i,p-1} L_{jc,p-1}^T + L_{i,p} L_{jc,p}^T; the diagonal
+      // tile factored in this step took its column p-1 term in the previous one.
+      // The fused step forms L_{i,p} = A_ip X_pp^T and L_{jc,p} in the task
+      // (X_pp = inv(L_pp) is in place in D[t]); the batched one takes
+      // (A_ip M_p) A_{jc,p}^T with M_p = X_pp^T X_pp = inv(A_pp), which the
+      // diagonal task of the previous step leaves in Mp
       const bool fac = (i == p + 1 && jc == p + 1);
       tk.kind = TK_CHAIN;
       tk.m = tdim(b, i); tk.n = tdim(b, jc);
       tk.C = Dt + toff(b, i, jc); tk.ldc = b; tk.beta = 1.0;
-      set_seg(tk.seg[0], Dt + toff(b, i, p), 1, b, it.Mp + (long long)(p & 1) * kTile * kTile, kTile,
-              1, 0, kTile, 1.0);
-      set_seg(tk.seg[1], Dt + toff(b, jc, p), 1, b, nullptr, 0, 0, 0, kTile, -1.0);
+      if (phase == PH_STEPF) {
+        set_seg(tk.seg[0], Dt + toff(b, i, p), 1, b, Dt + toff(b, p, p), 1, b, 0, kTile, 1.0);
+        set_seg(tk.seg[1], Dt + toff(b, jc, p), 1, b, Dt + toff(b, p, p), 1, b, 0, kTile, -1.0);
+      } else {
+        set_seg(tk.seg[0], Dt + toff(b, i, p), 1, b, it.Mp + (long long)(p & 1) * kTile * kTile,
+                kTile, 1, 0, kTile, 1.0);
+        set_seg(tk.seg[1], Dt + toff(b, jc, p), 1, b, nullptr, 0, 0, 0, kTile, -1.0);
+      }
       if (p >= 1 && !fac)
         set_seg(tk.seg[2], it.W2 + toff(b, i, p - 1), 1, b, it.W2 + toff(b, jc, p - 1), 1, b, 0,
                 kTile, -1.0);
@@ -259,7 +267,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       if (fac) {
         tk.chol = 1; tk.Lout = Dt + toff(b, i, i); tk.ldl = b;
         tk.ldsum = it.ldpart + (long long)t * nP + i; tk.row_off = t * b + i * kTile;
-        tk.Mout = it.Mp + (long long)((p + 1) & 1) * kTile * kTile;
+        tk.Mout = (phase == PH_STEPF) ? nullptr : it.Mp + (long long)((p + 1) & 1) * kTile * kTile;
       }
       return;
     }
@@ -1309,14 +1317,18 @@ __device__ __forceinline__ void left_chain_product(const Task &tk, double *smem,
   __syncthreads();
 }
 
-// TK_CHAIN on a 64 x 64 tile: acc = -(A0 B0) A1^T (+ seg[2]).  The intermediate T = A0 B0
-// (tk.m x 64, k = 64) comes from the regular product loop; it and A1 are then
-// staged in LDS (row-major, ld TLD) for the second product (k = 64).
-template <int KC, bool EARLY>
+// TK_CHAIN on a 64 x 64 tile: acc = -T0 T1^T (+ seg[2]).  T0 = A0 B0^T (tk.m x 64,
+// k = 64) comes from the regular product loop.  T1 is A1 itself (seg[1].B null),
+// or, in the Cholesky-capable kernel (FATK), A1 B1^T formed here as well when
+// seg[1].B is set (T1 = T0 when A1 = A0).  Both are staged in LDS (row-major,
+// ld TLD) for the second product (k = 64).
+template <int KC, bool FATK>
 __device__ __forceinline__ void chain_product(const Task &tk, double *smem, d4 (&acc)[2][2]) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = w >> 1, wc = w & 1;
-  // EARLY: the second product's right operand is loaded first, so that its
+  const bool formed = FATK && tk.seg[1].B != nullptr;
+  const bool same = formed && tk.seg[1].A == tk.seg[0].A;
+  // A1 itself: the Cholesky-capable kernel loads it first, so that its
   // latency overlaps the first product's loads (it holds 32 more registers)
   const double *A1 = tk.seg[1].A;
   const long long aks = tk.seg[1].aks;
@@ -1329,25 +1341,52 @@ __device__ __forceinline__ void chain_product(const Task &tk, double *smem, d4 (
       b1[q] = gld(A1 + min(c, tk.n - 1) + (long long)k * aks);
     }
   };
-  if constexpr (EARLY) load_b1();
+  if (FATK && !formed) load_b1();
   Task t1 = tk;
   t1.n = kTile;
   t1.nseg = 1;
   run_product<KC, kTile, 2, 2, 2>(t1, smem, acc);   // ends with a barrier
   double *TA = smem, *TB = smem + kTile * TLD;
-  if constexpr (!EARLY) load_b1();
+  auto stage = [&](double *T, const d4 (&v)[2][2]) {
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+    for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-    for (int nj = 0; nj < 2; ++nj)
+      for (int nj = 0; nj < 2; ++nj)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        TA[acc_row(wr, mi, lane, r) * TLD + acc_col(wc, nj, lane)] = acc[mi][nj][r];
+        for (int r = 0; r < 4; ++r)
+          T[acc_row(wr, mi, lane, r) * TLD + acc_col(wc, nj, lane)] = v[mi][nj][r];
+  };
+  if (formed && !same) {
+    d4 t0[2][2];
 #pragma unroll
-  for (int q = 0; q < kTile * kTile / kThreads; ++q) {
-    const int e = tid + q * kThreads;
-    const int c = e & (kTile - 1), k = e / kTile;
-    TB[c * TLD + k] = b1[q];
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int nj = 0; nj < 2; ++nj) {
+        t0[mi][nj] = acc[mi][nj];
+        acc[mi][nj] = d4{0.0, 0.0, 0.0, 0.0};
+      }
+    Task t2 = tk;
+    t2.seg[0] = tk.seg[1];
+    t2.seg[0].alpha = 1.0;
+    t2.m = tk.n;
+    t2.n = kTile;
+    t2.nseg = 1;
+    run_product<KC, kTile, 2, 2, 2>(t2, smem, acc);   // ends with a barrier
+    stage(TA, t0);
+    stage(TB, acc);
+  } else {
+    stage(TA, acc);
+    if (formed) {
+      TB = TA;
+    } else {
+      if (!FATK) load_b1();
+#pragma unroll
+      for (int q = 0; q < kTile * kTile / kThreads; ++q) {
+        const int e = tid + q * kThreads;
+        const int c = e & (kTile - 1), k = e / kTile;
+        TB[c * TLD + k] = b1[q];
+      }
+    }
   }
   __syncthreads();
 #pragma unroll
