@@ -972,24 +972,38 @@ __device__ inline int acc_row(int wr, int mi, int lane, int r) {
 }
 __device__ inline int acc_col(int wc, int nj, int lane) { return wc * 32 + nj * 16 + (lane & 15); }
 
-// Value of x in lane m of the wave (m a compile-time constant), as a scalar.
-__device__ __forceinline__ double lane_value(double x, int m) {
-  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
-  const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, m);
-  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), m);
-  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+// Every lane takes the value of lane J of its own row of 16 lanes (DPP
+// row_newbcast, one 64-bit move; every lane is written, so the value the move
+// would keep in unwritten lanes is immaterial); row_bcast selects J from a
+// value that is a constant once the caller's loop is unrolled.
+template <int J>
+__device__ __forceinline__ double row_bcast_c(double x) {
+  return __builtin_amdgcn_update_dpp(x, x, 0x150 + J, 0xf, 0xf, true);
+}
+__device__ __forceinline__ double row_bcast(double x, int j) {
+  switch (j) {
+    case 0: return row_bcast_c<0>(x);
+    case 1: return row_bcast_c<1>(x);
+    case 2: return row_bcast_c<2>(x);
+    case 3: return row_bcast_c<3>(x);
+    case 4: return row_bcast_c<4>(x);
+    case 5: return row_bcast_c<5>(x);
+    case 6: return row_bcast_c<6>(x);
+    case 7: return row_bcast_c<7>(x);
+    case 8: return row_bcast_c<8>(x);
+    case 9: return row_bcast_c<9>(x);
+    case 10: return row_bcast_c<10>(x);
+    case 11: return row_bcast_c<11>(x);
+    case 12: return row_bcast_c<12>(x);
+    case 13: return row_bcast_c<13>(x);
+    case 14: return row_bcast_c<14>(x);
+    default: return row_bcast_c<15>(x);
+  }
 }
 
-// 1/x and 1/sqrt(x) from the hardware estimates, each refined by two Newton
-// steps (r <- r + r(1 - x r) and y <- y + y(1 - x y^2)/2), which take the
-// estimate to full double precision for the positive pivots of a Cholesky
-// factorization.
-__device__ __forceinline__ double recip_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(r, fma(-x, r, 1.0), r);
-  r = fma(r, fma(-x, r, 1.0), r);
-  return r;
-}
+// 1/sqrt(x) from the hardware estimate refined by two Newton steps
+// (y <- y + y(1 - x y^2)/2), which take it to full double precision for the
+// positive pivots of a Cholesky factorization.
 __device__ __forceinline__ double rsqrt_nr(double x) {
   double y = __builtin_amdgcn_rsq(x);
   y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
@@ -1045,14 +1059,15 @@ __device__ void chol_inv_tile(double *A, double *X, double *dlog, int w, double 
   const int lr = lane & 15, lk = lane >> 4;
   for (int k = 0; k < nb; ++k) {
     // (a) factor and invert the diagonal block (k,k) in wave 0.  Cholesky,
-    //     right-looking: lane i holds row i (lanes 16..63 hold copies); at
-    //     pivot j column j is read out of lanes j..15 into scalar registers
-    //     (v_readlane), so the only latency between pivots is the pivot's
-    //     reciprocal and one update.  Then the inverse by forward
-    //     substitution, lane c computing column c from the rows of L in LDS.
+    //     right-looking: lane i holds row i (every row of 16 lanes holds the
+    //     same copy); at pivot j column j (= row j of the symmetric trailing
+    //     block) reaches every lane by row broadcasts, so the only latency
+    //     between pivots is the pivot's reciprocal and one update.  Row j of
+    //     X = L^{-1} (lane c: column c) follows in the same pivot, by forward
+    //     substitution with row j of L, final on lane j once pivot j is done.
     if (wv == 0) {
       const int r0 = 16 * k;
-      double a[16], rinv[16];
+      double a[16], x[16];
       // Lane i computes row i of the factor; its entries above the diagonal
       // are scratch (they only ever feed other entries above the diagonal),
       // so the updates run on every lane without per-column lane masks.
@@ -1064,11 +1079,10 @@ __device__ void chol_inv_tile(double *A, double *X, double *dlog, int w, double 
       for (int j = 0; j < 16; ++j) {
         double cv[16];
 #pragma unroll
-        for (int m = j; m < 16; ++m) cv[m] = lane_value(a[j], m);
+        for (int m = j; m < 16; ++m) cv[m] = row_bcast(a[j], m);
         const double piv = cv[j];
-        const double ip = recip_nr(piv);
         const double rs = rsqrt_nr(piv);
-        rinv[j] = rs;
+        const double ip = rs * rs;   // 1/piv within a few ulp, without a second Newton chain
         // L_jj = piv / sqrt(piv), the same value on every lane
         dg = (lr16 == j) ? piv * rs : dg;
         // A_im -= L_ij L_mj = A_ij A_mj / piv for m > j; then L_ij = A_ij / sqrt(piv)
@@ -1076,10 +1090,22 @@ __device__ void chol_inv_tile(double *A, double *X, double *dlog, int w, double 
 #pragma unroll
         for (int m = j + 1; m < 16; ++m) a[m] = fma(-wj, cv[m], a[m]);
         a[j] *= rs;
+        // X_jc = (delta_jc - sum_{m<j} L_jm X_mc) / L_jj; entries above the
+        // diagonal come out zero because the right-hand side is e_c
+        double s0 = (j == lane) ? 1.0 : 0.0, s1 = 0.0;
+#pragma unroll
+        for (int m = 0; m < j; ++m) {
+          const double l = row_bcast(a[m], j);
+          if (m & 1) s1 = fma(-l, x[m], s1);
+          else s0 = fma(-l, x[m], s0);
+        }
+        x[j] = (s0 + s1) * rs;
       }
       if (lane < 16) {
 #pragma unroll
         for (int c = 0; c < 16; ++c) A[(r0 + lane) * TLD + r0 + c] = a[c];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) X[(r0 + i) * TLD + r0 + lane] = x[i];
         dlog[r0 + lane] = dg;   // logs taken once, at the end
       }
       // L_jj is NaN exactly when the pivot is not positive (or not a
@@ -1087,36 +1113,6 @@ __device__ void chol_inv_tile(double *A, double *X, double *dlog, int w, double 
       const bool ok = (dg > 0.0) || lane >= 16 || r0 + lane >= w;
       const unsigned long long badm = __ballot(!ok);
       if (badm && lane == 0) atomicMin(info, row_off + r0 + __ffsll(badm));
-      __builtin_amdgcn_wave_barrier();
-      // X = L^{-1}: X_ic = (delta_ic - sum_{m<i} L_im X_mc) / L_ii; entries
-      // above the diagonal come out zero because the right-hand side is e_c
-      // (row i + 1 of L is read while row i is computed; the scheduling
-      // barrier keeps the reads from running further ahead)
-      double x[16], lc[16];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        double ln[16];
-        if (i + 1 < 16) {
-#pragma unroll
-          for (int m = 0; m <= i; ++m) ln[m] = A[(r0 + i + 1) * TLD + r0 + m];
-        }
-        double s0 = (i == lane) ? 1.0 : 0.0, s1 = 0.0;
-#pragma unroll
-        for (int m = 0; m < i; ++m) {
-          if (m & 1) s1 = fma(-lc[m], x[m], s1);
-          else s0 = fma(-lc[m], x[m], s0);
-        }
-        x[i] = (s0 + s1) * rinv[i];
-        if (i + 1 < 16) {
-#pragma unroll
-          for (int m = 0; m <= i; ++m) lc[m] = ln[m];
-        }
-        __builtin_amdgcn_sched_barrier(0);
-      }
-      if (lane < 16) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) X[(r0 + i) * TLD + r0 + lane] = x[i];
-      }
     } else if (wv < k) {
       // row block k-1 of X (block j = wv-1 < k-1): L_{k-1,m} (m < k-1), the
       // rows of X above and X_{k-1,k-1} are final; the scratch is the unused
