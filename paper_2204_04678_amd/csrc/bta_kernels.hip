@@ -593,7 +593,7 @@ struct ChunkInfo {
 // issued while chunk c is multiplied and have two chunk-times to arrive.
 // Chunks are numbered across the segments; segment fields are only indexed by
 // constants so the task stays in registers.
-template <int KC, int ROWS, int WR, int WC, int DEPTH = 1>
+template <int KC, int ROWS, int WR, int WC, int DEPTH = 1, bool SHORT = false>
 __device__ __forceinline__ void run_product(const Task &tk, double *smem,
                                             d4 (&acc)[ROWS / WR / 16][ROWS / WC / 16],
                                             int part = 0, int nparts = 1) {
@@ -679,6 +679,18 @@ __device__ __forceinline__ void run_product(const Task &tk, double *smem,
     fetch(min(cb + 1, last), ra1, rb1, ci1);
     stage(buf0, ra0, rb0, ci0);
     __syncthreads();
+    if (SHORT && ce - cb <= 2) {
+      // one or two chunks: nothing more to fetch; chunk 0 is multiplied while
+      // chunk 1 lands (SHORT: only where the registers allow the extra path)
+      compute(buf0);
+      if (ce - cb == 2) {
+        stage(buf1, ra1, rb1, ci1);
+        __syncthreads();
+        compute(buf1);
+      }
+      __syncthreads();
+      return;
+    }
     // invariant at the top: buf0 holds chunk c, set 1 holds (or awaits) chunk c + 1
     for (int c = cb; c < ce; c += 2) {
       fetch(min(c + 2, last), ra0, rb0, ci0);
@@ -1253,13 +1265,13 @@ __device__ void chol_inv_tile(double *A, double *X, double *dlog, int w, double 
 
 // TK_LCHAIN on a 64 x 64 tile: acc = -A1 (A0 B0), A1 (tk.m x tk.m, lower, from
 // global memory) multiplying the intermediate T = A0 B0 (tk.m x 64) from the left.
-template <int KC>
+template <int KC, bool SHORT>
 __device__ __forceinline__ void left_chain_product(const Task &tk, double *smem, d4 (&acc)[2][2]) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = w >> 1, wc = w & 1;
   Task t1 = tk;
   t1.nseg = 1;
-  run_product<KC, kTile, 2, 2, 2>(t1, smem, acc);   // rows >= tk.m come out zero
+  run_product<KC, kTile, 2, 2, 2, SHORT>(t1, smem, acc);   // rows >= tk.m come out zero
   if (tk.src) {
     // plus the tile at src (ld = ldc): the running sum of the earlier terms
 #pragma unroll
@@ -1341,7 +1353,7 @@ __device__ __forceinline__ void chain_product(const Task &tk, double *smem, d4 (
   Task t1 = tk;
   t1.n = kTile;
   t1.nseg = 1;
-  run_product<KC, kTile, 2, 2, 2>(t1, smem, acc);   // ends with a barrier
+  run_product<KC, kTile, 2, 2, 2, FATK>(t1, smem, acc);   // ends with a barrier
   double *TA = smem, *TB = smem + kTile * TLD;
   auto stage = [&](double *T, const d4 (&v)[2][2]) {
 #pragma unroll
@@ -1367,7 +1379,7 @@ __device__ __forceinline__ void chain_product(const Task &tk, double *smem, d4 (
     t2.m = tk.n;
     t2.n = kTile;
     t2.nseg = 1;
-    run_product<KC, kTile, 2, 2, 2>(t2, smem, acc);   // ends with a barrier
+    run_product<KC, kTile, 2, 2, 2, FATK>(t2, smem, acc);   // ends with a barrier
     stage(TA, t0);
     stage(TB, acc);
   } else {
@@ -1407,7 +1419,7 @@ __device__ __forceinline__ void chain_product(const Task &tk, double *smem, d4 (
     Task t3 = tk;
     t3.seg[0] = tk.seg[2];
     t3.nseg = 1;
-    run_product<KC, kTile, 2, 2, 2>(t3, smem, acc);
+    run_product<KC, kTile, 2, 2, 2, FATK>(t3, smem, acc);
   }
 }
 
@@ -1507,8 +1519,8 @@ __global__ __launch_bounds__(kThreads, FAT ? 1 : 2) void tile_phase_kernel(const
     }
   }
   if (tk.kind == TK_CHAIN) chain_product<KC, FAT>(tk, smem, acc);
-  else if (tk.kind == TK_LCHAIN) left_chain_product<KC>(tk, smem, acc);
-  else run_product<KC, kTile, 2, 2, 2>(tk, smem, acc);
+  else if (tk.kind == TK_LCHAIN) left_chain_product<KC, FAT>(tk, smem, acc);
+  else run_product<KC, kTile, 2, 2, 2, FAT>(tk, smem, acc);
 
   if constexpr (FAT) {
     if (tk.chol) {
