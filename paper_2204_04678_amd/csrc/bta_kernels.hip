@@ -142,6 +142,16 @@ __device__ inline void set_seg(Seg &g, const double *A, int ars, int aks, const 
   g.k0 = k0; g.k1 = k1; g.alpha = alpha;
 }
 
+// V_t = L_{t+1,t} inv(L_tt) and U_t = L_{A,t} inv(L_tt) of step t of the
+// selected inversion: formed up front for every step (V, U) or step by step in
+// the workspace (W2, W3).  V has no slot for the last step, whose V is never read.
+__device__ inline const double *vmat(const ItemDev &it, int t) {
+  return (it.V && t < it.nt - 1) ? it.V + (long long)t * it.b * it.b : it.W2;
+}
+__device__ inline const double *umat(const ItemDev &it, int t) {
+  return it.U ? it.U + (long long)t * it.a * it.b : it.W3;
+}
+
 // Map (item, phase, t, p, local task q) to the work of one workgroup.
 __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int p, int q, Task &tk) {
   const int b = it.b, a = it.a, nP = it.nP;
@@ -382,17 +392,40 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       tk.nseg = 1;
       return;
     }
+    case PH_SI_VU_B: {
+      // as PH_SI_VU_X for every step tt < nt-1: q runs over (tt, tile)
+      const int per = nP * nP, tt = q / per, r = q - tt * per;
+      const int j = r / nP, i = r % nP;
+      const double *Dq = it.D + (long long)tt * bb, *Sq = it.S + (long long)tt * bb;
+      tk.m = tdim(b, i); tk.n = tdim(b, j);
+      tk.C = it.V + (long long)tt * bb + toff(b, i, j); tk.ldc = b;
+      set_seg(tk.seg[0], Sq + (long long)i * kTile, 1, b, Dq + (long long)j * kTile * b, b, 1,
+              j * kTile, b, 1.0);
+      tk.nseg = 1;
+      return;
+    }
+    case PH_SI_U_B: {
+      // as PH_SI_VU for every step tt
+      const int tt = q / nP, j = q % nP;
+      const double *Dq = it.D + (long long)tt * bb;
+      tk.m = a; tk.n = tdim(b, j);
+      tk.C = it.U + (long long)tt * a * b + (long long)j * kTile * a; tk.ldc = a;
+      set_seg(tk.seg[0], it.R + (long long)tt * a * b, 1, a, Dq + (long long)j * kTile * b, b, 1,
+              j * kTile, b, 1.0);
+      tk.nseg = 1;
+      return;
+    }
     case PH_SI_SR_X: {
       const int i = q / nP, j = q % nP;
       double *SDn = sig_D(it, t + 1);
       tk.m = tdim(b, i); tk.n = tdim(b, j);
       tk.C = sig_S(it, t) + toff(b, i, j); tk.ldc = b;
-      set_seg(tk.seg[0], SDn + (long long)i * kTile, 1, b, it.W2 + (long long)j * kTile * b, b, 1, 0,
-              b, -1.0);
+      set_seg(tk.seg[0], SDn + (long long)i * kTile, 1, b, vmat(it, t) + (long long)j * kTile * b, b,
+              1, 0, b, -1.0);
       tk.nseg = 1;
       if (arrow) {
         set_seg(tk.seg[1], sig_R(it, t + 1) + (long long)i * kTile * a, a, 1,
-                it.W3 + (long long)j * kTile * a, a, 1, 0, a, -1.0);
+                umat(it, t) + (long long)j * kTile * a, a, 1, 0, a, -1.0);
         tk.nseg = 2;
       }
       return;
@@ -403,8 +436,8 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       tk.C = sig_R(it, t) + (long long)j * kTile * a; tk.ldc = a;
       // every segment has a fixed slot (an empty one when absent), so that the
       // task never needs an indexed segment
-      set_seg(tk.seg[0], it.ST, 1, a, it.W3 + (long long)j * kTile * a, a, 1, 0, a, -1.0);
-      set_seg(tk.seg[1], sig_R(it, t + 1), 1, a, it.W2 + (long long)j * kTile * b, b, 1, 0,
+      set_seg(tk.seg[0], it.ST, 1, a, umat(it, t) + (long long)j * kTile * a, a, 1, 0, a, -1.0);
+      set_seg(tk.seg[1], sig_R(it, t + 1), 1, a, vmat(it, t) + (long long)j * kTile * b, b, 1, 0,
               last ? 0 : b, -1.0);
       tk.nseg = 2;
       return;
@@ -420,9 +453,9 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       set_seg(tk.seg[0], Dt + (long long)i * kTile * b, b, 1, Dt + (long long)j * kTile * b, b, 1,
               i * kTile, b, 1.0);
       set_seg(tk.seg[1], sig_S(it, t) + (long long)i * kTile * b, b, 1,
-              it.W2 + (long long)j * kTile * b, b, 1, 0, last ? 0 : b, -1.0);
+              vmat(it, t) + (long long)j * kTile * b, b, 1, 0, last ? 0 : b, -1.0);
       set_seg(tk.seg[2], sig_R(it, t) + (long long)i * kTile * a, a, 1,
-              it.W3 + (long long)j * kTile * a, a, 1, 0, a, -1.0);
+              umat(it, t) + (long long)j * kTile * a, a, 1, 0, a, -1.0);
       tk.nseg = 3;
       return;
     }
@@ -484,16 +517,28 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
               J * TS, b, 1.0);
       tk.nseg = 1;
       return;
+    case PH_SI_VU_B: {
+      // as PH_SI_VU_X for every step tt < nt-1: q runs over (tt, tile)
+      const int per = nQ * nQ, tt = q / per, r = q - tt * per;
+      J = r / nQ; I = r % nQ;
+      const double *Dq = it.D + (long long)tt * bb, *Sq = it.S + (long long)tt * bb;
+      tk.m = bdim<TS>(b, I); tk.n = bdim<TS>(b, J); tk.ti = I; tk.tj = J;
+      tk.C = it.V + (long long)tt * bb + boff<TS>(b, I, J); tk.ldc = b;
+      set_seg(tk.seg[0], Sq + (long long)I * TS, 1, b, Dq + (long long)J * TS * b, b, 1, J * TS, b,
+              1.0);
+      tk.nseg = 1;
+      return;
+    }
     case PH_SI_SR_X:
       I = q / nQ; J = q % nQ;
       tk.m = bdim<TS>(b, I); tk.n = bdim<TS>(b, J); tk.ti = I; tk.tj = J;
       tk.C = sig_S(it, t) + boff<TS>(b, I, J); tk.ldc = b;
       set_seg(tk.seg[0], sig_D(it, t + 1) + (long long)I * TS, 1, b,
-              it.W2 + (long long)J * TS * b, b, 1, 0, b, -1.0);
+              vmat(it, t) + (long long)J * TS * b, b, 1, 0, b, -1.0);
       tk.nseg = 1;
       if (arrow) {
         set_seg(tk.seg[1], sig_R(it, t + 1) + (long long)I * TS * a, a, 1,
-                it.W3 + (long long)J * TS * a, a, 1, 0, a, -1.0);
+                umat(it, t) + (long long)J * TS * a, a, 1, 0, a, -1.0);
         tk.nseg = 2;
       }
       return;
@@ -506,9 +551,9 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
       set_seg(tk.seg[0], Dt + (long long)I * TS * b, b, 1, Dt + (long long)J * TS * b, b, 1,
               I * TS, b, 1.0);
       set_seg(tk.seg[1], sig_S(it, t) + (long long)I * TS * b, b, 1,
-              it.W2 + (long long)J * TS * b, b, 1, 0, last ? 0 : b, -1.0);
+              vmat(it, t) + (long long)J * TS * b, b, 1, 0, last ? 0 : b, -1.0);
       set_seg(tk.seg[2], sig_R(it, t) + (long long)I * TS * a, a, 1,
-              it.W3 + (long long)J * TS * a, a, 1, 0, a, -1.0);
+              umat(it, t) + (long long)J * TS * a, a, 1, 0, a, -1.0);
       tk.nseg = 3;
       return;
     }
@@ -1799,7 +1844,7 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const ItemDev *__res
 // for the diagonal of Sigma.
 inline int big_layouts(int phase) {
   switch (phase) {
-    case PH_SI_VU_X: case PH_SI_SR_X: return 2;
+    case PH_SI_VU_X: case PH_SI_VU_B: case PH_SI_SR_X: return 2;
     case PH_SI_SD_X: return 3;
     default: return 0;
   }

@@ -140,6 +140,7 @@ struct Batch {
   int max_nt = 0, max_b = 0, max_a = 0;
   bool big = false;
   bool split = false;   // every item has split-k scratch
+  bool vb = false;      // selected inversion with V_t, U_t of every step formed up front
   void finalize() {
     big = use_big_tiles(host);
     split = !host.empty();
@@ -176,6 +177,8 @@ double phase_flops(const ItemDev &it, int phase, int t, int p) {
     case PH_SI_SR_X: return last ? 0.0 : 2.0 * b3 + 2.0 * a * b * b;
     case PH_SI_SR: return (last ? 0.0 : 2.0 * a * b * b) + 2.0 * a * a * b;
     case PH_SI_SD_X: return b3 / 3.0 + (last ? 0.0 : b3) + a * b * b;
+    case PH_SI_VU_B: return (it.nt - 1) * b3;
+    case PH_SI_U_B: return it.nt * a * b * b;
     default: return 0.0;
   }
 }
@@ -191,6 +194,9 @@ double phase_flops(const ItemDev &it, int phase, int t, int p) {
 // two matrices, b = 1600 with two), split or not; the autotuner and the tile
 // option can still ask for 128 (then split) there.
 constexpr long long kSplitTiles = 384;
+// Below this many 64-wide tiles per step (over the selected inversion's
+// matrices) the V_t, U_t of every step are formed up front, in one launch each.
+constexpr long long kVBatchTiles = 4096;
 // Below this many 64-tiles (summed nP^2 over the items of a factor launch)
 // each Cholesky step is one fused launch (see run_factor).  Measured on
 // b = 2025 with 2, 4 and 8 matrices (2048, 4096, 8192 tiles): fused 23%, 11%
@@ -200,6 +206,12 @@ constexpr long long kStepFusedTiles = 6144;
 int step_fused_override() {
   const char *e = getenv("INLA_STEP_FUSED");
   return (e && (e[0] == '0' || e[0] == '1')) ? e[0] - '0' : -1;
+}
+// INLA_SI_BATCH=0 keeps the selected inversion's V_t, U_t step by step; 1 (or
+// unset) forms them up front where the built-in rule wants it.
+bool si_batch_allowed() {
+  const char *e = getenv("INLA_SI_BATCH");
+  return !(e && e[0] == '0');
 }
 int g_tile_pref = 0;
 // The tile size asked for: INLA_TILE in the environment, else the engine's choice.
@@ -274,6 +286,8 @@ struct ProfScope {
 };
 
 inla_status run_phase(const Batch &B, int phase, int t, int p, hipStream_t s) {
+  // (the batched V_t use the tile width of the step-by-step ones, so that
+  // results do not depend on which of the two the workspace allowed)
   const bool big = B.big && phase_is_product_x(phase);
   long long total = 0;
   for (const auto &it : B.host) total += phase_tasks(it, phase, t, p, big);
@@ -282,8 +296,10 @@ inla_status run_phase(const Batch &B, int phase, int t, int p, hipStream_t s) {
   double flops = 0.0;
   if (g_prof.on)
     for (const auto &it : B.host) flops += phase_flops(it, phase, t, p);
-  const int ks = (big && B.split && total < kSplitTiles) ? kSplitK : 1;
-  const bool prod = phase_is_product_x(phase) && (B.big || small_variant() > 0);
+  // (the split-k scratch holds one b x b product per item: never the products
+  // of every step)
+  const int ks = (big && B.split && total < kSplitTiles && phase != PH_SI_VU_B) ? kSplitK : 1;
+  const bool prod = phase_is_product_x(phase) && (big || small_variant() > 0);
   ProfScope ps(phase, flops, s, prod ? PK_PROD : (phase_is_fat(phase) ? PK_FAT : PK_LEAN));
   HIP_TRY(launch_tile_phase(B.dev, (int)B.host.size(), (int)total, phase, -1, t, p, big, s, ks));
   return INLA_OK;
@@ -398,8 +414,13 @@ inla_status run_selinv(const Batch &B, bool traces, hipStream_t s) {
   const int n = (int)B.host.size();
   ST_TRY(run_phase(B, PH_SI_INIT, 0, 0, s));
   if (traces) HIP_TRY(launch_trace_step(B.dev, n, -1, s));
+  if (B.vb) {
+    // V_t and U_t need only the factor: every step's at once, paired as the
+    // step-by-step phases are (so that each is formed by the same code)
+    ST_TRY(run_pair(B, PH_SI_VU_B, PH_SI_U_B, 0, s));
+  }
   for (int t = B.max_nt - 1; t >= 0; --t) {
-    ST_TRY(run_pair(B, PH_SI_VU_X, PH_SI_VU, t, s));
+    if (!B.vb) ST_TRY(run_pair(B, PH_SI_VU_X, PH_SI_VU, t, s));
     ST_TRY(run_pair(B, PH_SI_SR_X, PH_SI_SR, t, s));
     ST_TRY(run_phase(B, PH_SI_SD_X, t, 0, s));
     if (traces) {
@@ -895,13 +916,15 @@ struct ThetaItemBufs {
 
 // Device bytes one (model, theta) item needs: two BTA matrices with their
 // workspaces, or one shared by Q_prior and Q_c when `seq` (the two are then
-// processed one after the other).
-size_t theta_item_bytes(const ModelDev &h, bool selinv, bool seq, bool split) {
+// processed one after the other); `vb`: the selected inversion keeps V_t and
+// U_t of every step.
+size_t theta_item_bytes(const ModelDev &h, bool selinv, bool seq, bool split, bool vb) {
   const size_t bb = (size_t)h.b * h.b, ab = (size_t)h.a * h.b;
   const int nP = ntile(h.b);
   size_t per = bta_doubles(h.b, h.nt, h.a) * 8 + (2 * bb + ab + 2 * kTile * kTile) * 8 +
                ((size_t)h.nt * nP + 1) * 8 + 5 * kAlign * 4;
   if (selinv) per += (2 * bb + 2 * ab + (size_t)h.a * h.a) * 8 + ((size_t)h.nt + 1) * kTraceBlocks * 32;
+  if (selinv && vb) per += ((size_t)(h.nt - 1) * bb + (size_t)h.nt * ab) * 8 + 2 * kAlign;
   if (split) per += (size_t)kSplitK * bb * 8 + kAlign;
   return (seq ? 1 : 2) * per + ((size_t)h.n + std::max(h.b, h.a) + kTermBlocks * 4) * 8 + 4096;
 }
@@ -912,7 +935,7 @@ size_t theta_item_bytes(const ModelDev &h, bool selinv, bool seq, bool split) {
 struct EvalGraph {
   bool valid = false;
   std::vector<const inla_model *> models;
-  bool grad = false, var = false, mu = false, prof = false, seq = false;
+  bool grad = false, var = false, mu = false, prof = false, seq = false, split = false, vb = false;
   int tile = 0, variant = 0, small = 0, step = -1;
   unsigned long long gen = 0;
   char *base = nullptr;
@@ -968,14 +991,20 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
   long long nb2 = 0;
   for (int i = 0; i < n_items; ++i) nb2 += 2LL * nbig(models[i]->host.b) * nbig(models[i]->host.b);
   const bool split_wanted = nb2 < kSplitTiles && tile_request() == 128;
+  // V_t and U_t of every step up front when the step-by-step launches of the
+  // selected inversion would have few tiles
+  long long nv = 0;
+  for (int i = 0; i < n_items; ++i) nv += 2LL * ntile(models[i]->host.b) * ntile(models[i]->host.b);
+  const bool vb_wanted = need_selinv && nv < kVBatchTiles && si_batch_allowed();
   // HBM admission: split the items into waves whose storage fits the budget
-  auto waves_for = [&](bool seq, bool split, std::vector<size_t> &bytes, double &all) -> int {
+  auto waves_for = [&](bool seq, bool split, bool vb, std::vector<size_t> &bytes,
+                       double &all) -> int {
     bytes.assign(n_items, 0);
     all = 0.0;
     int waves = 0;
     double acc = budget + 1.0;
     for (int i = 0; i < n_items; ++i) {
-      bytes[i] = theta_item_bytes(models[i]->host, need_selinv, seq, split);
+      bytes[i] = theta_item_bytes(models[i]->host, need_selinv, seq, split, vb);
       all += (double)bytes[i];
       if ((double)bytes[i] > budget) return INT_MAX;
       if (acc + (double)bytes[i] > budget) {
@@ -987,26 +1016,31 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
     return waves;
   };
   // layouts in order of preference; the first with the fewest waves wins
-  struct Plan { bool seq, split; };
+  struct Plan { bool seq, split, vb; };
   std::vector<Plan> plans;
   for (int sq = 0; sq < 2; ++sq) {
     const bool seq_c = sq == 1;
     if ((seq_mode == 1 && !seq_c) || (seq_mode == 2 && seq_c)) continue;
-    if (split_wanted) plans.push_back({seq_c, true});
-    plans.push_back({seq_c, false});
+    for (int v = 0; v < 2; ++v) {
+      const bool vb_c = v == 0;
+      if (vb_c && !vb_wanted) continue;
+      if (split_wanted) plans.push_back({seq_c, true, vb_c});
+      plans.push_back({seq_c, false, vb_c});
+    }
   }
   std::vector<size_t> bytes;
   double all = 0.0;
-  bool seq = false, split = false;
+  bool seq = false, split = false, vb = false;
   int waves = INT_MAX;
   for (const Plan &pl : plans) {
     std::vector<size_t> b1;
     double a1 = 0.0;
-    const int w1 = waves_for(pl.seq, pl.split, b1, a1);
+    const int w1 = waves_for(pl.seq, pl.split, pl.vb, b1, a1);
     if (w1 < waves) {
       waves = w1;
       seq = pl.seq;
       split = pl.split;
+      vb = pl.vb;
       bytes.swap(b1);
       all = a1;
     }
@@ -1014,7 +1048,7 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
   if (waves == INT_MAX) {
     const Plan pl = plans.back();   // the smallest layout
     for (int i = 0; i < n_items; ++i) {
-      const size_t need = theta_item_bytes(models[i]->host, need_selinv, pl.seq, pl.split);
+      const size_t need = theta_item_bytes(models[i]->host, need_selinv, pl.seq, pl.split, pl.vb);
       if ((double)need > budget)
         return fail(INLA_ERR_BUDGET, "item " + std::to_string(i) + " needs " + std::to_string(need) +
                                          " bytes, above the HBM budget");
@@ -1035,7 +1069,8 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
   std::vector<const inla_model *> key(models, models + n_items);
   if (graphable && g_graph.valid && g_graph.models == key && g_graph.grad == grad &&
       g_graph.var == (var_out != nullptr) && g_graph.mu == (mu_out != nullptr) &&
-      g_graph.prof == g_prof.on && g_graph.seq == seq && g_graph.tile == tile &&
+      g_graph.prof == g_prof.on && g_graph.seq == seq && g_graph.split == split &&
+      g_graph.vb == vb && g_graph.tile == tile &&
       g_graph.variant == variant && g_graph.small == small && g_graph.step == step &&
       g_graph.gen == g_arena.gen &&
       g_graph.base == g_arena.base) {
@@ -1084,6 +1119,10 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
         if (split) L.add(&it.P, (size_t)kSplitK * h.b * h.b);
         if (need_selinv) {
           layout_selinv_ws(L, it);
+          if (vb) {
+            if (h.nt > 1) L.add(&it.V, (size_t)(h.nt - 1) * h.b * h.b);
+            if (h.a > 0) L.add(&it.U, (size_t)h.nt * h.a * h.b);
+          }
           if (grad) L.add(&it.trpart, ((size_t)h.nt + 1) * kTraceBlocks * 4);
         }
       }
@@ -1112,7 +1151,7 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
         ItemDev &cv = tb[q].C;
         cv.W1 = pv.W1; cv.W2 = pv.W2; cv.W3 = pv.W3; cv.Mp = pv.Mp; cv.P = pv.P;
         cv.ldpart = pv.ldpart; cv.info = pv.info;
-        cv.SD = pv.SD; cv.SR = pv.SR; cv.ST = pv.ST;
+        cv.SD = pv.SD; cv.SR = pv.SR; cv.ST = pv.ST; cv.V = pv.V; cv.U = pv.U;
         Dbase[2 * q + 1] = Dbase[2 * q];
       }
     }
@@ -1191,6 +1230,8 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
     Fc.dev = fdev + k; Sic.dev = vdev + k;
     F.finalize(); Sv.finalize(); Si.finalize();
     if (seq) { Fc.finalize(); Sic.finalize(); }
+    Si.vb = vb;
+    Sic.vb = vb;
     ST_TRY(upload(fdev, F.host, s));
     if (seq) ST_TRY(upload(Fc.dev, Fc.host, s));
     ST_TRY(upload(sdev, Sv.host, s));
@@ -1269,6 +1310,8 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
       G.mu = mu_out != nullptr;
       G.prof = g_prof.on;
       G.seq = seq;
+      G.split = split;
+      G.vb = vb;
       G.tile = tile;
       G.variant = variant;
       G.small = small;

@@ -175,6 +175,38 @@ def test_step_paths_factor_and_selinv(P, monkeypatch, fused, b, nt, a):
         assert blk_err(g, e) < 1e-10, name
 
 
+@pytest.mark.parametrize("width", [64, 128], ids=["tile64", "tile128"])
+def test_selinv_batched_matches_stepwise(P, monkeypatch, width):
+    """The selected inversion with V_t = L_{t+1,t} inv(L_tt) and U_t of every
+    step formed up front (one launch each) against the step-by-step one: the
+    same f, gradient and variances, bitwise with 64-wide tiles (the same
+    products in the same order); with 128-wide tiles the step-by-step launches
+    of small models split k in two, so there they agree to rounding."""
+    print(f"selinv batched vs stepwise, tile {width}", flush=True)
+    mds = [make_model(5, 3, 2, 31), make_model(8, 4, 3, 32), make_model(6, 2, 0, 33),
+           make_model(4, 1, 2, 34)]
+    Ms = [P.Model.from_data(m) for m in mds]
+    th = np.array([[0.1, 0.8, 0.5, 2.0], [0.3, 1.1, 1.0, 3.0], [-0.2, 0.6, 0.2, 2.5],
+                   [0.0, 1.0, 1.5, 4.6]])
+    out = {}
+    for flag in ("0", "1"):
+        monkeypatch.setenv("INLA_SI_BATCH", flag)
+        out[flag] = P.eval_f_grad(Ms, th, want_var=True, tile=width)
+        torch.cuda.synchronize()
+    for key in ("f", "grad", "var", "status"):
+        a, b = out["0"][key], out["1"][key]
+        if width == 64 or key == "status":
+            assert torch.equal(a, b), key
+        else:
+            assert torch.allclose(a, b, rtol=1e-12, atol=0.0), key
+    for i, md in enumerate(mds):
+        assert rel(out["1"]["f"][i].item(), O.eval_f_dense(md, th[i])["f"]) < 1e-10
+        g = out["1"]["grad"][i].cpu().numpy()
+        gref = O.dense_gradient(md, th[i])
+        scale = np.maximum(grad_term_magnitudes(md, th[i]), 1e-3 * np.abs(gref).max())
+        assert np.max(np.abs(g - gref) / scale) < 1e-9
+
+
 def test_not_spd_reports_pivot(P):
     b, nt, a = 70, 3, 2
     Q = rand_spd_bta(b, nt, a, seed=5)
