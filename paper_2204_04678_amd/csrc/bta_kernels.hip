@@ -1374,9 +1374,12 @@ __device__ __forceinline__ void left_chain_product(const Task &tk, double *smem,
 // k = 64) comes from the regular product loop.  T1 is A1 itself (seg[1].B null),
 // or, in the Cholesky-capable kernel (FATK), A1 B1^T formed here as well when
 // seg[1].B is set (T1 = T0 when A1 = A0).  Both are staged in LDS (row-major,
-// ld TLD) for the second product (k = 64).
-template <int KC, bool FATK>
-__device__ __forceinline__ void chain_product(const Task &tk, double *smem, d4 (&acc)[2][2]) {
+// ld TLD) for the second product (k = 64).  When T1 = T0 the region of T1 is
+// free: stage_c(region) may put the caller's C there before the barrier ahead
+// of the second product; returns whether it did.
+template <int KC, bool FATK, class StageC>
+__device__ __forceinline__ bool chain_product(const Task &tk, double *smem, d4 (&acc)[2][2],
+                                              StageC stage_c) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = w >> 1, wc = w & 1;
   const bool formed = FATK && tk.seg[1].B != nullptr;
@@ -1409,6 +1412,7 @@ __device__ __forceinline__ void chain_product(const Task &tk, double *smem, d4 (
         for (int r = 0; r < 4; ++r)
           T[acc_row(wr, mi, lane, r) * TLD + acc_col(wc, nj, lane)] = v[mi][nj][r];
   };
+  bool c_staged = false;
   if (formed && !same) {
     d4 t0[2][2];
 #pragma unroll
@@ -1431,6 +1435,7 @@ __device__ __forceinline__ void chain_product(const Task &tk, double *smem, d4 (
     stage(TA, acc);
     if (formed) {
       TB = TA;
+      c_staged = stage_c(smem + kTile * TLD);
     } else {
       if (!FATK) load_b1();
 #pragma unroll
@@ -1466,6 +1471,7 @@ __device__ __forceinline__ void chain_product(const Task &tk, double *smem, d4 (
     t3.nseg = 1;
     run_product<KC, kTile, 2, 2, 2, FATK>(t3, smem, acc);
   }
+  return c_staged;
 }
 
 // Owner of workgroup task q in a launch over n_items items whose task counts
@@ -1563,7 +1569,24 @@ __global__ __launch_bounds__(kThreads, FAT ? 1 : 2) void tile_phase_kernel(const
       }
     }
   }
-  if (tk.kind == TK_CHAIN) chain_product<KC, FAT>(tk, smem, acc);
+  // the factored tile's beta C, identity-padded, in the layout of the tile in LDS
+  auto c_fill = [&](double *Tc) -> bool {
+    if constexpr (FAT) {
+      if (!tk.chol) return false;
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const int e = tid + q * kThreads;
+        const int r = e & (kTile - 1), c = e / kTile;
+        Tc[r * TLD + c] = (r < tk.m && c < tk.n) ? tk.beta * cpre[q] : ((r == c) ? 1.0 : 0.0);
+      }
+      return true;
+    } else {
+      (void)Tc;
+      return false;
+    }
+  };
+  bool c_staged = false;
+  if (tk.kind == TK_CHAIN) c_staged = chain_product<KC, FAT>(tk, smem, acc, c_fill);
   else if (tk.kind == TK_LCHAIN) left_chain_product<KC, FAT>(tk, smem, acc);
   else run_product<KC, kTile, 2, 2, 2, FAT>(tk, smem, acc);
 
@@ -1572,24 +1595,33 @@ __global__ __launch_bounds__(kThreads, FAT ? 1 : 2) void tile_phase_kernel(const
       double *A = smem;
       double *X = smem + kTile * TLD;
       double *dlog = smem + 2 * kTile * TLD;
-      // beta C (identity padding beyond the tile) goes to LDS in full, then
-      // each lane adds its part of the product
+      // beta C (identity padding beyond the tile) in LDS, then each lane adds
+      // its part of the product.  A chained task staged C in the region of X
+      // already (ahead of its second product): one pass from there into A.
+      if (c_staged) {
 #pragma unroll
-      for (int q = 0; q < kPer; ++q) {
-        const int e = tid + q * kThreads;
-        const int r = e & (kTile - 1), c = e / kTile;
-        A[r * TLD + c] = (r < tk.m && c < tk.n) ? tk.beta * cpre[q] : ((r == c) ? 1.0 : 0.0);
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+          for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = acc_row(wr, mi, lane, r), col = acc_col(wc, nj, lane);
+              const double v = X[row * TLD + col];
+              A[row * TLD + col] = (row < tk.m && col < tk.n) ? v + acc[mi][nj][r] : v;
+            }
+      } else {
+        c_fill(A);
+        __syncthreads();
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+          for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = acc_row(wr, mi, lane, r), col = acc_col(wc, nj, lane);
+              if (row < tk.m && col < tk.n) A[row * TLD + col] += acc[mi][nj][r];
+            }
       }
-      __syncthreads();
-#pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-        for (int nj = 0; nj < 2; ++nj)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = acc_row(wr, mi, lane, r), col = acc_col(wc, nj, lane);
-            if (row < tk.m && col < tk.n) A[row * TLD + col] += acc[mi][nj][r];
-          }
       __syncthreads();
       chol_inv_tile(A, X, dlog, tk.m, tk.Lout, tk.ldl, tk.ldsum, tk.row_off, it.info, tk.Mout);
       return;
