@@ -227,15 +227,15 @@ inla_status inla_eval_f_grad(const inla_model *const *models, int32_t n_items,
  * and writes, per profiling slot k < nslots, out[3k+0] = launches,
  * out[3k+1] = summed kernel time in milliseconds, out[3k+2] = algorithmic
  * FP64 flops of those launches (the dense-block operation counts of the
- * method, not the flops of padded tiles).  Slots 0..16 are the phases of the
+ * method, not the flops of padded tiles).  Slots 0..17 are the phases of the
  * tile kernels (Cholesky of the first diagonal tile, the steps that factor and
  * invert the diagonal block tile by tile and, beside them, the next diagonal
  * tile's Cholesky, or both fused in one launch, the b x b off-diagonal solve and its
  * arrow/copy remainder, the b x b Schur update and its remainder, arrow
  * Cholesky, the selected-inversion steps with their remainders, and the
- * selected inversion's V_t and U_t of every step formed in one launch each
- * (used instead of the step-by-step ones when those would have few tiles), in
- * that order); then substitution sweeps, trace
+ * selected inversion's V_t, U_t and inv(L_tt)^T inv(L_tt) of every step formed
+ * in one launch each (used instead of the step-by-step forms when those would
+ * have few tiles), in that order); then substitution sweeps, trace
  * reductions, assembly, the rest, and a last slot whose out[0] is the number
  * of evaluations the records cover (a replayed graph re-records its events,
  * so it counts once) and out[1] the number of unreadable records, then four

@@ -357,8 +357,9 @@ def profile_begin():
 
 PROFILE_SLOTS = ["diag0", "step", "diagc", "stepf", "offdiag_x", "offdiag", "schur_x", "schur", "arrow",
                  "si_init", "si_vu_x", "si_vu", "si_sr_x", "si_sr", "si_sd_x", "si_vu_b", "si_u_b",
-                 "solve", "trace", "assemble", "misc", "calls"]
-PRODUCT_X = ("offdiag_x", "schur_x", "si_vu_x", "si_sr_x", "si_sd_x", "si_vu_b")   # b x b products
+                 "si_g_b", "solve", "trace", "assemble", "misc", "calls"]
+PRODUCT_X = ("offdiag_x", "schur_x", "si_vu_x", "si_sr_x", "si_sd_x", "si_vu_b",
+             "si_g_b")   # b x b products
 FAT_PHASES = ("diag0", "diagc", "stepf", "arrow")   # run by the Cholesky-capable tile kernel
 
 

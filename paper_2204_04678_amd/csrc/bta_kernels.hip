@@ -115,6 +115,7 @@ struct Task {
   double *Mout;                   // Cholesky tasks: also M = inv(L)^T inv(L) here (or null)
   int ti, tj;                     // 128-wide tiles: block coordinates of C (split-k scratch)
   const double *src;              // copy source; TK_LCHAIN: running-sum tile (ld = ldc)
+  const double *init;             // TK_PRODUCT: the sum starts from this tile (ld = ldc), or 0
 };
 
 // Loads and stores through the global address space (global_load / global_store
@@ -161,7 +162,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
   tk.kind = TK_PRODUCT; tk.nseg = 0; tk.beta = 0.0; tk.mirror = 0; tk.diagtile = 0; tk.chol = 0;
   tk.Mout = nullptr;
   tk.Cm = nullptr; tk.Lout = nullptr; tk.ldsum = nullptr; tk.src = nullptr; tk.ldl = 0;
-  tk.row_off = 0;
+  tk.row_off = 0; tk.init = nullptr;
   double *Dt = it.D + (long long)t * bb;
   double *St = it.S ? it.S + (long long)t * bb : nullptr;
   double *Rt = arrow ? it.R + (long long)t * a * b : nullptr;
@@ -404,6 +405,20 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       tk.nseg = 1;
       return;
     }
+    case PH_SI_G_B: {
+      // inv(L_tt)^T inv(L_tt) of every step tt, lower tiles (the first term of
+      // PH_SI_SD_X, in full tiles: no mirror)
+      const int per = nP * (nP + 1) / 2, tt = q / per;
+      int i, j;
+      tri_decode(q - tt * per, i, j);
+      const double *Dq = it.D + (long long)tt * bb;
+      tk.m = tdim(b, i); tk.n = tdim(b, j);
+      tk.C = it.G + (long long)tt * bb + toff(b, i, j); tk.ldc = b;
+      set_seg(tk.seg[0], Dq + (long long)i * kTile * b, b, 1, Dq + (long long)j * kTile * b, b, 1,
+              i * kTile, b, 1.0);
+      tk.nseg = 1;
+      return;
+    }
     case PH_SI_U_B: {
       // as PH_SI_VU for every step tt
       const int tt = q / nP, j = q % nP;
@@ -449,9 +464,11 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       tk.m = tdim(b, i); tk.n = tdim(b, j);
       tk.C = SDt + toff(b, i, j); tk.ldc = b;
       tk.mirror = 1; tk.Cm = SDt + toff(b, j, i); tk.diagtile = (i == j);
-      // fixed slots: LinvT Linv, then - Sigma_S^T V, then - Sigma_R^T U (empty when absent)
+      // fixed slots: LinvT Linv, then - Sigma_S^T V, then - Sigma_R^T U (empty when absent);
+      // with G the first term is there already and the sum starts from it
       set_seg(tk.seg[0], Dt + (long long)i * kTile * b, b, 1, Dt + (long long)j * kTile * b, b, 1,
-              i * kTile, b, 1.0);
+              it.G ? 0 : i * kTile, it.G ? 0 : b, 1.0);
+      if (it.G) tk.init = it.G + (long long)t * bb + toff(b, i, j);
       set_seg(tk.seg[1], sig_S(it, t) + (long long)i * kTile * b, b, 1,
               vmat(it, t) + (long long)j * kTile * b, b, 1, 0, last ? 0 : b, -1.0);
       set_seg(tk.seg[2], sig_R(it, t) + (long long)i * kTile * a, a, 1,
@@ -485,7 +502,7 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
   tk.kind = TK_PRODUCT; tk.nseg = 0; tk.beta = 0.0; tk.mirror = 0; tk.diagtile = 0; tk.chol = 0;
   tk.Mout = nullptr;
   tk.Cm = nullptr; tk.Lout = nullptr; tk.ldsum = nullptr; tk.src = nullptr; tk.ldl = 0;
-  tk.row_off = 0;
+  tk.row_off = 0; tk.init = nullptr;
   double *Dt = it.D + (long long)t * bb;
   double *St = it.S ? it.S + (long long)t * bb : nullptr;
   int I, J;
@@ -542,6 +559,18 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
         tk.nseg = 2;
       }
       return;
+    case PH_SI_G_B: {
+      // inv(L_tt)^T inv(L_tt) of every step tt, lower tiles (full tiles: no mirror)
+      const int per = nQ * (nQ + 1) / 2, tt = q / per;
+      tri_decode(q - tt * per, I, J);
+      const double *Dq = it.D + (long long)tt * bb;
+      tk.m = bdim<TS>(b, I); tk.n = bdim<TS>(b, J); tk.ti = I; tk.tj = J;
+      tk.C = it.G + (long long)tt * bb + boff<TS>(b, I, J); tk.ldc = b;
+      set_seg(tk.seg[0], Dq + (long long)I * TS * b, b, 1, Dq + (long long)J * TS * b, b, 1, I * TS,
+              b, 1.0);
+      tk.nseg = 1;
+      return;
+    }
     case PH_SI_SD_X: {
       tri_decode(q, I, J);
       double *SDt = sig_D(it, t);
@@ -549,7 +578,8 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
       tk.C = SDt + boff<TS>(b, I, J); tk.ldc = b;
       tk.mirror = 1; tk.Cm = SDt + boff<TS>(b, J, I); tk.diagtile = (I == J);
       set_seg(tk.seg[0], Dt + (long long)I * TS * b, b, 1, Dt + (long long)J * TS * b, b, 1,
-              I * TS, b, 1.0);
+              it.G ? 0 : I * TS, it.G ? 0 : b, 1.0);
+      if (it.G) tk.init = it.G + (long long)t * bb + boff<TS>(b, I, J);
       set_seg(tk.seg[1], sig_S(it, t) + (long long)I * TS * b, b, 1,
               vmat(it, t) + (long long)J * TS * b, b, 1, 0, last ? 0 : b, -1.0);
       set_seg(tk.seg[2], sig_R(it, t) + (long long)I * TS * a, a, 1,
@@ -850,7 +880,8 @@ __device__ __forceinline__ void dma_operand(const double *X, int rs, int ks, int
 // step s of lane group g = lane / 16 takes k = 2g + s, which lets a Q row
 // deliver both steps' values with one 16-byte read.  The alphas are applied
 // to the accumulator: at a change of segment it is rescaled by
-// alpha_old / alpha_new (segment weights are nonzero), and once at the end.
+// alpha_old / alpha_new (segment weights are nonzero), and once at the end
+// (an accumulator that starts from a tile, tk.init, starts at weight 1).
 template <int KC, int WR, int WC, bool AQ, bool BQ, int TS, int S>
 __device__ __forceinline__ void run_product_dma(const Task &tk, double *buf0, double *buf1,
                                                 double *buf2, double *buf3,
@@ -940,6 +971,14 @@ __device__ __forceinline__ void run_product_dma(const Task &tk, double *buf0, do
     }
   };
   double cur = seg_alpha(cb);
+  if (tk.init && part == 0 && cur != 1.0) {
+    // the incoming sum (a tile formed earlier) carries weight 1
+    const double f = 1.0 / cur;
+#pragma unroll
+    for (int mi = 0; mi < MR; ++mi)
+#pragma unroll
+      for (int nj = 0; nj < MC; ++nj) acc[mi][nj] *= f;
+  }
   auto rescale = [&](int c) {
     const double al = seg_alpha(c);
     if (al != cur) {
@@ -1554,6 +1593,19 @@ __global__ __launch_bounds__(kThreads, FAT ? 1 : 2) void tile_phase_kernel(const
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
     for (int nj = 0; nj < 2; ++nj) acc[mi][nj] = d4{0.0, 0.0, 0.0, 0.0};
+  if (tk.kind == TK_PRODUCT && tk.init) {
+    // the sum starts from a tile formed earlier
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = min(acc_row(wr, mi, lane, r), tk.m - 1);
+          const int col = min(acc_col(wc, nj, lane), tk.n - 1);
+          acc[mi][nj][r] = gld(tk.init + row + (long long)col * tk.ldc);
+        }
+  }
   constexpr int KC = FAT ? kFatKC : kLeanKC;
   // C of the tile that is factored here is loaded (column by column, in
   // full lines) before the products start, so that its latency overlaps theirs
@@ -1742,6 +1794,19 @@ __global__ __launch_bounds__(big_threads<V>(), BigCfg<V>::OCC) void tile_product
   for (int mi = 0; mi < MR; ++mi)
 #pragma unroll
     for (int nj = 0; nj < MC; ++nj) acc[mi][nj] = d4{0.0, 0.0, 0.0, 0.0};
+  if (tk.init && part == 0) {
+    // the sum starts from a tile formed earlier (the one split-k part adds it)
+#pragma unroll
+    for (int mi = 0; mi < MR; ++mi)
+#pragma unroll
+      for (int nj = 0; nj < MC; ++nj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = min(wr * (TS / C::WR) + mi * 16 + (lane >> 4) + 4 * r, tk.m - 1);
+          const int col = min(wc * (TS / C::WC) + nj * 16 + (lane & 15), tk.n - 1);
+          acc[mi][nj][r] = gld(tk.init + row + (long long)col * tk.ldc);
+        }
+  }
   if constexpr (C::DMA && C::STAGES == 4) {
     __shared__ __attribute__((aligned(16))) double stage0[big_lds<V>() / 4];
     __shared__ __attribute__((aligned(16))) double stage1[big_lds<V>() / 4];
@@ -1877,7 +1942,7 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const ItemDev *__res
 inline int big_layouts(int phase) {
   switch (phase) {
     case PH_SI_VU_X: case PH_SI_VU_B: case PH_SI_SR_X: return 2;
-    case PH_SI_SD_X: return 3;
+    case PH_SI_SD_X: case PH_SI_G_B: return 3;
     default: return 0;
   }
 }

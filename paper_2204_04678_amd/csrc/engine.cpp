@@ -176,9 +176,10 @@ double phase_flops(const ItemDev &it, int phase, int t, int p) {
     case PH_SI_VU: return a * b * b;
     case PH_SI_SR_X: return last ? 0.0 : 2.0 * b3 + 2.0 * a * b * b;
     case PH_SI_SR: return (last ? 0.0 : 2.0 * a * b * b) + 2.0 * a * a * b;
-    case PH_SI_SD_X: return b3 / 3.0 + (last ? 0.0 : b3) + a * b * b;
+    case PH_SI_SD_X: return (it.G ? 0.0 : b3 / 3.0) + (last ? 0.0 : b3) + a * b * b;
     case PH_SI_VU_B: return (it.nt - 1) * b3;
     case PH_SI_U_B: return it.nt * a * b * b;
+    case PH_SI_G_B: return it.nt * b3 / 3.0;
     default: return 0.0;
   }
 }
@@ -298,7 +299,8 @@ inla_status run_phase(const Batch &B, int phase, int t, int p, hipStream_t s) {
     for (const auto &it : B.host) flops += phase_flops(it, phase, t, p);
   // (the split-k scratch holds one b x b product per item: never the products
   // of every step)
-  const int ks = (big && B.split && total < kSplitTiles && phase != PH_SI_VU_B) ? kSplitK : 1;
+  const bool every_step = phase == PH_SI_VU_B || phase == PH_SI_G_B;
+  const int ks = (big && B.split && total < kSplitTiles && !every_step) ? kSplitK : 1;
   const bool prod = phase_is_product_x(phase) && (big || small_variant() > 0);
   ProfScope ps(phase, flops, s, prod ? PK_PROD : (phase_is_fat(phase) ? PK_FAT : PK_LEAN));
   HIP_TRY(launch_tile_phase(B.dev, (int)B.host.size(), (int)total, phase, -1, t, p, big, s, ks));
@@ -415,9 +417,11 @@ inla_status run_selinv(const Batch &B, bool traces, hipStream_t s) {
   ST_TRY(run_phase(B, PH_SI_INIT, 0, 0, s));
   if (traces) HIP_TRY(launch_trace_step(B.dev, n, -1, s));
   if (B.vb) {
-    // V_t and U_t need only the factor: every step's at once, paired as the
-    // step-by-step phases are (so that each is formed by the same code)
+    // V_t, U_t and the first term of Sigma_D[t] need only the factor: every
+    // step's at once, paired as the step-by-step phases are (so that each is
+    // formed by the same code)
     ST_TRY(run_pair(B, PH_SI_VU_B, PH_SI_U_B, 0, s));
+    ST_TRY(run_phase(B, PH_SI_G_B, 0, 0, s));
   }
   for (int t = B.max_nt - 1; t >= 0; --t) {
     if (!B.vb) ST_TRY(run_pair(B, PH_SI_VU_X, PH_SI_VU, t, s));
@@ -924,7 +928,7 @@ size_t theta_item_bytes(const ModelDev &h, bool selinv, bool seq, bool split, bo
   size_t per = bta_doubles(h.b, h.nt, h.a) * 8 + (2 * bb + ab + 2 * kTile * kTile) * 8 +
                ((size_t)h.nt * nP + 1) * 8 + 5 * kAlign * 4;
   if (selinv) per += (2 * bb + 2 * ab + (size_t)h.a * h.a) * 8 + ((size_t)h.nt + 1) * kTraceBlocks * 32;
-  if (selinv && vb) per += ((size_t)(h.nt - 1) * bb + (size_t)h.nt * ab) * 8 + 2 * kAlign;
+  if (selinv && vb) per += ((size_t)(2 * h.nt - 1) * bb + (size_t)h.nt * ab) * 8 + 3 * kAlign;
   if (split) per += (size_t)kSplitK * bb * 8 + kAlign;
   return (seq ? 1 : 2) * per + ((size_t)h.n + std::max(h.b, h.a) + kTermBlocks * 4) * 8 + 4096;
 }
@@ -1122,6 +1126,7 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
           if (vb) {
             if (h.nt > 1) L.add(&it.V, (size_t)(h.nt - 1) * h.b * h.b);
             if (h.a > 0) L.add(&it.U, (size_t)h.nt * h.a * h.b);
+            L.add(&it.G, (size_t)h.nt * h.b * h.b);
           }
           if (grad) L.add(&it.trpart, ((size_t)h.nt + 1) * kTraceBlocks * 4);
         }
@@ -1151,7 +1156,7 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
         ItemDev &cv = tb[q].C;
         cv.W1 = pv.W1; cv.W2 = pv.W2; cv.W3 = pv.W3; cv.Mp = pv.Mp; cv.P = pv.P;
         cv.ldpart = pv.ldpart; cv.info = pv.info;
-        cv.SD = pv.SD; cv.SR = pv.SR; cv.ST = pv.ST; cv.V = pv.V; cv.U = pv.U;
+        cv.SD = pv.SD; cv.SR = pv.SR; cv.ST = pv.ST; cv.V = pv.V; cv.U = pv.U; cv.G = pv.G;
         Dbase[2 * q + 1] = Dbase[2 * q];
       }
     }

@@ -47,10 +47,11 @@ struct ItemDev {
                                  //   b*b (panels of L_tt, then S[t] Linv^T), a*b
   double *Mp;                    // 2 x 64 x 64: inverse of the current diagonal tile, by parity
   double *P;                     // kSplitK * b * b split-k partial products (or null: no split)
-  // Selected inversion with every step's V_t = L_{t+1,t} inv(L_tt) ((nt-1) b*b)
-  // and U_t = L_{A,t} inv(L_tt) (nt a*b) formed up front, in one launch each
-  // (null: V_t and U_t are formed step by step in W2 and W3).
-  double *V, *U;
+  // Selected inversion with every step's V_t = L_{t+1,t} inv(L_tt) ((nt-1) b*b),
+  // U_t = L_{A,t} inv(L_tt) (nt a*b) and G_t = inv(L_tt)^T inv(L_tt) (nt b*b,
+  // lower tiles) formed up front, in one launch each (null: V_t and U_t are
+  // formed step by step in W2 and W3, G_t inside the step's Sigma_D[t] launch).
+  double *V, *U, *G;
   // Selected inversion: Sigma blocks.  When sd_stride != 0 the blocks of step t
   // live at SD + t*sd_stride etc. (caller storage); otherwise Sigma_D and
   // Sigma_R ping-pong between two buffers by the parity of t and Sigma_S uses
@@ -105,7 +106,8 @@ enum Phase : int {
   PH_SI_SD_X = 14,   // Sigma_D[t] (lower tiles, mirrored)
   PH_SI_VU_B = 15,   // V_t for every t < nt-1 into V (one launch; V_t needs only the factor)
   PH_SI_U_B = 16,    // U_t for every t into U
-  PH_COUNT = 17
+  PH_SI_G_B = 17,    // G_t = inv(L_tt)^T inv(L_tt) for every t into G (lower tiles)
+  PH_COUNT = 18
 };
 
 constexpr int kTraceBlocks = 16;   // workgroups per item in a trace reduction step
@@ -113,7 +115,7 @@ constexpr int kBig = 128;        // edge of a big tile
 __host__ __device__ inline int nbig(int n) { return (n + kBig - 1) / kBig; }
 __host__ __device__ inline bool phase_is_product_x(int phase) {
   return phase == PH_OFFDIAG_X || phase == PH_SCHUR_X || phase == PH_SI_VU_X ||
-         phase == PH_SI_SR_X || phase == PH_SI_SD_X || phase == PH_SI_VU_B;
+         phase == PH_SI_SR_X || phase == PH_SI_SD_X || phase == PH_SI_VU_B || phase == PH_SI_G_B;
 }
 
 __host__ __device__ inline int ntile(int n) { return (n + kTile - 1) / kTile; }
@@ -156,6 +158,7 @@ __host__ __device__ inline int phase_tasks(const ItemDev &it, int phase, int t, 
     case PH_SI_SD_X: return nQ * (nQ + 1) / 2;
     case PH_SI_VU_B: return (it.nt - 1) * nQ * nQ;   // every step, from the launch's t = 0
     case PH_SI_U_B: return arrow ? it.nt * nP : 0;
+    case PH_SI_G_B: return it.nt * (nQ * (nQ + 1) / 2);
     default: return 0;
   }
 }
