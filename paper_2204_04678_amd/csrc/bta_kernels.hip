@@ -154,6 +154,18 @@ __device__ inline const double *umat(const ItemDev &it, int t) {
 }
 
 // Map (item, phase, t, p, local task q) to the work of one workgroup.
+// SIDE >= 0: decode only the side phases that ride in a product-kernel launch
+// of operand layout SIDE (0: the factorization's remainders, 2: the selected
+// inversion's U and Sigma_R rows), or, SIDE = kFatOnly / kLeanOnly, only the
+// phases of the Cholesky-capable / the lean tile kernel; the other cases
+// compile to no code.
+constexpr int kFatOnly = 100, kLeanOnly = 101;
+#define SIDE_ONLY(keep)                                   \
+  if constexpr (SIDE >= 0 && !(keep)) {                   \
+    tk.kind = TK_NONE;                                    \
+    return;                                               \
+  }
+template <int SIDE = -1>
 __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int p, int q, Task &tk) {
   const int b = it.b, a = it.a, nP = it.nP;
   const long long bb = (long long)b * b;
@@ -168,6 +180,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
   double *Rt = arrow ? it.R + (long long)t * a * b : nullptr;
   switch (phase) {
     case PH_DIAG0: {
+      SIDE_ONLY(SIDE == kFatOnly)
       tk.m = tk.n = tdim(b, 0);
       tk.C = Dt; tk.ldc = b; tk.beta = 1.0;
       tk.chol = 1; tk.Lout = Dt; tk.ldl = b;
@@ -178,6 +191,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
     case PH_STEP:
     case PH_DIAGC:
     case PH_STEPF: {
+      SIDE_ONLY(SIDE == kFatOnly || SIDE == kLeanOnly)
       // Tiles p-1 and p are full wherever they are used here (they precede a tile).
       const int npan = nP - 1 - p;
       const int ncol = max(nP - 2 - p, 0);
@@ -283,6 +297,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       return;
     }
     case PH_OFFDIAG_X: {
+      SIDE_ONLY(SIDE == kLeanOnly)
       // k runs to the end of tile column j: the longest tiles first
       const int j = nP - 1 - q / nP, i = q % nP;
       tk.m = tdim(b, i); tk.n = tdim(b, j);
@@ -293,6 +308,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       return;
     }
     case PH_OFFDIAG: {
+      SIDE_ONLY(SIDE == 0 || SIDE == kLeanOnly)
       int idx = q;
       if (arrow) {
         if (idx < nP) {
@@ -310,6 +326,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       return;
     }
     case PH_SCHUR_X: {
+      SIDE_ONLY(SIDE == kLeanOnly)
       int i, j;
       tri_decode(q, i, j);
       tk.m = tdim(b, i); tk.n = tdim(b, j);
@@ -320,6 +337,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       return;
     }
     case PH_SCHUR: {
+      SIDE_ONLY(SIDE == 0 || SIDE == kLeanOnly)
       int idx = q;
       if (!last) {
         if (idx < nP * nP) {
@@ -362,6 +380,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       return;
     }
     case PH_ARROW: {
+      SIDE_ONLY(SIDE == kFatOnly)
       tk.m = tk.n = a;
       tk.C = it.T; tk.ldc = a; tk.beta = 1.0;
       tk.chol = 1; tk.Lout = it.T; tk.ldl = a;
@@ -369,6 +388,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       return;
     }
     case PH_SI_INIT: {
+      SIDE_ONLY(SIDE == kLeanOnly)
       tk.m = tk.n = a;
       tk.C = it.ST; tk.ldc = a;
       set_seg(tk.seg[0], it.T, a, 1, it.T, a, 1, 0, a, 1.0);
@@ -376,6 +396,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       return;
     }
     case PH_SI_VU_X: {
+      SIDE_ONLY(SIDE == kLeanOnly)
       // k starts at tile column j: the longest tiles first
       const int j = q / nP, i = q % nP;
       tk.m = tdim(b, i); tk.n = tdim(b, j);
@@ -386,6 +407,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       return;
     }
     case PH_SI_VU: {
+      SIDE_ONLY(SIDE == 2 || SIDE == kLeanOnly)
       const int j = q;
       tk.m = a; tk.n = tdim(b, j);
       tk.C = it.W3 + (long long)j * kTile * a; tk.ldc = a;
@@ -394,6 +416,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       return;
     }
     case PH_SI_VU_B: {
+      SIDE_ONLY(SIDE == kLeanOnly)
       // as PH_SI_VU_X for every step tt < nt-1: q runs over (tt, tile)
       const int per = nP * nP, tt = q / per, r = q - tt * per;
       const int j = r / nP, i = r % nP;
@@ -406,6 +429,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       return;
     }
     case PH_SI_G_B: {
+      SIDE_ONLY(SIDE == kLeanOnly)
       // inv(L_tt)^T inv(L_tt) of every step tt, lower tiles (the first term of
       // PH_SI_SD_X, in full tiles: no mirror)
       const int per = nP * (nP + 1) / 2, tt = q / per;
@@ -420,6 +444,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       return;
     }
     case PH_SI_U_B: {
+      SIDE_ONLY(SIDE == 2 || SIDE == kLeanOnly)
       // as PH_SI_VU for every step tt
       const int tt = q / nP, j = q % nP;
       const double *Dq = it.D + (long long)tt * bb;
@@ -431,6 +456,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       return;
     }
     case PH_SI_SR_X: {
+      SIDE_ONLY(SIDE == kLeanOnly)
       const int i = q / nP, j = q % nP;
       double *SDn = sig_D(it, t + 1);
       tk.m = tdim(b, i); tk.n = tdim(b, j);
@@ -446,6 +472,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       return;
     }
     case PH_SI_SR: {
+      SIDE_ONLY(SIDE == 2 || SIDE == kLeanOnly)
       const int j = q;
       tk.m = a; tk.n = tdim(b, j);
       tk.C = sig_R(it, t) + (long long)j * kTile * a; tk.ldc = a;
@@ -458,6 +485,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       return;
     }
     case PH_SI_SD_X: {
+      SIDE_ONLY(SIDE == kLeanOnly)
       int i, j;
       tri_decode(q, i, j);
       double *SDt = sig_D(it, t);
@@ -481,6 +509,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       return;
   }
 }
+#undef SIDE_ONLY
 
 // Map (item, product phase, t, local task q) to one TS x TS output tile (TS =
 // 64 or 128).  For 128 the k ranges are those of the 64-tile form widened to
@@ -493,7 +522,16 @@ __device__ __forceinline__ long long boff(int b, int I, int J) {
 template <int TS>
 __device__ __forceinline__ int bdim(int n, int I) { return min(TS, n - I * TS); }
 
-template <int TS>
+// A launch of the product kernel decodes only the phases of its operand
+// layout (LAY, as big_layouts assigns them): the other cases compile to no
+// code, which keeps the kernel's registers to what its own phases need.
+// LAY < 0 (the split-k reduction) decodes every phase.
+#define LAY_ONLY(l)                                       \
+  if constexpr (!(LAY < 0 || LAY == (l))) {               \
+    tk.kind = TK_NONE;                                    \
+    return;                                               \
+  }
+template <int TS, int LAY = -1>
 __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, int q, Task &tk) {
   const int b = it.b, a = it.a, nQ = (it.b + TS - 1) / TS;
   const long long bb = (long long)b * b;
@@ -508,6 +546,7 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
   int I, J;
   switch (phase) {
     case PH_OFFDIAG_X:
+      LAY_ONLY(0)
       // k runs to the end of tile column J: tiles of the last columns (the
       // longest) first, so that the short ones fill the end of the launch
       J = nQ - 1 - q / nQ; I = q % nQ;
@@ -518,6 +557,7 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
       tk.nseg = 1;
       return;
     case PH_SCHUR_X:
+      LAY_ONLY(0)
       tri_decode(q, I, J);
       tk.m = bdim<TS>(b, I); tk.n = bdim<TS>(b, J); tk.ti = I; tk.tj = J;
       tk.C = it.D + (long long)(t + 1) * bb + boff<TS>(b, I, J); tk.ldc = b; tk.beta = 1.0;
@@ -526,6 +566,7 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
       tk.nseg = 1;
       return;
     case PH_SI_VU_X:
+      LAY_ONLY(2)
       // k starts at tile column J: the first columns (the longest) first
       J = q / nQ; I = q % nQ;
       tk.m = bdim<TS>(b, I); tk.n = bdim<TS>(b, J); tk.ti = I; tk.tj = J;
@@ -535,6 +576,7 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
       tk.nseg = 1;
       return;
     case PH_SI_VU_B: {
+      LAY_ONLY(2)
       // as PH_SI_VU_X for every step tt < nt-1: q runs over (tt, tile)
       const int per = nQ * nQ, tt = q / per, r = q - tt * per;
       J = r / nQ; I = r % nQ;
@@ -547,6 +589,7 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
       return;
     }
     case PH_SI_SR_X:
+      LAY_ONLY(2)
       I = q / nQ; J = q % nQ;
       tk.m = bdim<TS>(b, I); tk.n = bdim<TS>(b, J); tk.ti = I; tk.tj = J;
       tk.C = sig_S(it, t) + boff<TS>(b, I, J); tk.ldc = b;
@@ -560,6 +603,7 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
       }
       return;
     case PH_SI_G_B: {
+      LAY_ONLY(3)
       // inv(L_tt)^T inv(L_tt) of every step tt, lower tiles (full tiles: no mirror)
       const int per = nQ * (nQ + 1) / 2, tt = q / per;
       tri_decode(q - tt * per, I, J);
@@ -572,6 +616,7 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
       return;
     }
     case PH_SI_SD_X: {
+      LAY_ONLY(3)
       tri_decode(q, I, J);
       double *SDt = sig_D(it, t);
       tk.m = bdim<TS>(b, I); tk.n = bdim<TS>(b, J); tk.ti = I; tk.tj = J;
@@ -592,6 +637,7 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
       return;
   }
 }
+#undef LAY_ONLY
 
 // Global -> register staging of rows [0, rows) x k in [kc, min(kc+KC, k1)) of op(X)
 // for a panel of ROWS rows, NT threads.  Addresses are clamped into range so
@@ -1567,7 +1613,7 @@ __global__ __launch_bounds__(kThreads, FAT ? 1 : 2) void tile_phase_kernel(const
     }
   }
   Task tk;
-  decode(it, ph, t, p, q, tk);
+  decode<FAT ? kFatOnly : kLeanOnly>(it, ph, t, p, q, tk);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = w >> 1, wc = w & 1;
   if (tk.kind == TK_NONE) return;
@@ -1777,8 +1823,11 @@ __global__ __launch_bounds__(big_threads<V>(), BigCfg<V>::OCC) void tile_product
   if (ii >= n_items) return;
   const ItemDev it = items[ii];
   Task tk;
-  if (side) decode(it, phase2, t, 0, q, tk);
-  else decode_big<TS>(it, phase, t, q, tk);
+  // LAY names the phases of a direct-load launch (big_layouts); the
+  // register-staged layouts run every phase
+  constexpr int kOnly = C::DMA ? LAY : -1;
+  if (side) decode<kOnly>(it, phase2, t, 0, q, tk);
+  else decode_big<TS, kOnly>(it, phase, t, q, tk);
   if (tk.kind == TK_COPY) {
     for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
       const int r = e & (kTile - 1), c = e / kTile;
@@ -2019,6 +2068,8 @@ hipError_t launch_tile_phase(const ItemDev *items_dev, int n_items, int total, i
                          phase, t, ks);
     }
   } else if (phase_is_fat(phase) || (phase2 >= 0 && phase_is_fat(phase2))) {
+    // the Cholesky-capable kernel decodes its own phases only
+    if (!phase_is_fat(phase) || (phase2 >= 0 && !phase_is_fat(phase2))) return hipErrorInvalidValue;
     hipLaunchKernelGGL(tile_phase_kernel<true>, dim3(total), dim3(kThreads), 0, s, items_dev, n_items,
                        phase, phase2, t, p);
   } else {
