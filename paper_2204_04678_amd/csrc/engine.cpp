@@ -310,6 +310,11 @@ inla_status run_phase(const Batch &B, int phase, int t, int p, hipStream_t s) {
 // Side stream (default priority) for phases that run beside another launch.
 hipStream_t g_side = nullptr;
 hipEvent_t g_fork = nullptr, g_join = nullptr;
+// A second side stream (default priority) for the mode solve beside the
+// selected inversion, with events of its own: the selected inversion forks to
+// g_side itself.
+hipStream_t g_solve = nullptr;
+hipEvent_t g_solve_fork = nullptr, g_solve_join = nullptr;
 
 // Runs phase pm on s and the independent phase ps of the same step on the side
 // stream, joined back into s (in a captured graph: two parallel nodes).
@@ -968,6 +973,11 @@ inla_status ensure_streams() {
     HIP_TRY(hipEventCreateWithFlags(&g_join, hipEventDisableTiming));
   }
   if (!g_cap) HIP_TRY(hipStreamCreateWithFlags(&g_cap, hipStreamNonBlocking));
+  if (!g_solve) {
+    HIP_TRY(hipStreamCreateWithFlags(&g_solve, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&g_solve_fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&g_solve_join, hipEventDisableTiming));
+  }
   return INLA_OK;
 }
 
@@ -1274,9 +1284,20 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
         ST_TRY(assemble(1));
         ST_TRY(run_factor(F, ls));
         HIP_TRY(launch_logdet_finish(fdev, 2 * k, logdet, info, ls));
-        ST_TRY(run_solve(Sv, xs, tmps, ls));
-        HIP_TRY(launch_terms(tdev, k, ls));
-        if (need_selinv) ST_TRY(run_selinv(Si, true, ls));
+        if (need_selinv) {
+          // the mode solve (and its terms) beside the selected inversion: both
+          // only read the factor, and they write disjoint buffers
+          HIP_TRY(hipEventRecord(g_solve_fork, ls));
+          HIP_TRY(hipStreamWaitEvent(g_solve, g_solve_fork, 0));
+          ST_TRY(run_solve(Sv, xs, tmps, g_solve));
+          HIP_TRY(launch_terms(tdev, k, g_solve));
+          HIP_TRY(hipEventRecord(g_solve_join, g_solve));
+          ST_TRY(run_selinv(Si, true, ls));
+          HIP_TRY(hipStreamWaitEvent(ls, g_solve_join, 0));
+        } else {
+          ST_TRY(run_solve(Sv, xs, tmps, ls));
+          HIP_TRY(launch_terms(tdev, k, ls));
+        }
       } else {
         // Q_prior first (factor, log-determinant, gradient traces), then Q_c
         // in the same storage
