@@ -115,6 +115,11 @@ typedef struct {
  *                      needs fewer admission waves.  Selected-inverse blocks
  *                      are never stored in either mode: each is recomputed
  *                      from the stored factor and consumed as it is produced.
+ *                      When the selected inversion's per-step launches would
+ *                      have few tiles, its factor-only parts of every step
+ *                      (V_t, U_t, inv(L_tt)^T inv(L_tt); about one more BTA
+ *                      matrix of memory) are formed up front if that needs
+ *                      no more admission waves; results are the same.
  *   keep_sigma       : reserved, must be 0
  *   tile             : 64 or 128 forces the tile of the b x b products;
  *                      0 = the autotuner's entry for this call signature if
