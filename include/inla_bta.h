@@ -119,7 +119,8 @@ typedef struct {
  *                      have few tiles, its factor-only parts of every step
  *                      (V_t, U_t, inv(L_tt)^T inv(L_tt); about one more BTA
  *                      matrix of memory) are formed up front if that needs
- *                      no more admission waves; results are the same.
+ *                      no more admission waves (the results agree bitwise
+ *                      with 64-wide tiles, to rounding with 128-wide ones).
  *   keep_sigma       : reserved, must be 0
  *   tile             : 64 or 128 forces the tile of the b x b products;
  *                      0 = the autotuner's entry for this call signature if
