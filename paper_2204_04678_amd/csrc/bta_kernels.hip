@@ -216,7 +216,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       } else if (q < npan + ncol + ndef) {
         // the rest of panel p-1's update: A_ij -= L_{i,p-1} L_{j,p-1}^T, p+1 < j <= i;
         // the diagonal tile of column p+2 also takes column p's term here (a
-        // chained product through M_p), one step before it is factored
+        // chained product), one step before it is factored
         int ii, jj;
         tri_decode(q - npan - ncol, ii, jj);
         const int id = p + 2 + ii, jd = p + 2 + jj;

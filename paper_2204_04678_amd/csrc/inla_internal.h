@@ -45,7 +45,8 @@ struct ItemDev {
   double *W1, *W2, *W3;          // workspace: b*b (running sums of inv(L_tt) rows in the
                                  // factorization, Sigma_S in the selected inversion),
                                  //   b*b (panels of L_tt, then S[t] Linv^T), a*b
-  double *Mp;                    // 2 x 64 x 64: inverse of the current diagonal tile, by parity
+  double *Mp;                    // 2 x 64 x 64: M_p = inv(A_pp) of the current diagonal tile,
+                                 // by parity (the batched Cholesky step reads it)
   double *P;                     // kSplitK * b * b split-k partial products (or null: no split)
   // Selected inversion with every step's V_t = L_{t+1,t} inv(L_tt) ((nt-1) b*b),
   // U_t = L_{A,t} inv(L_tt) (nt a*b) and G_t = inv(L_tt)^T inv(L_tt) (nt b*b,
@@ -92,7 +93,9 @@ enum Phase : int {
   PH_DIAGC = 2,      // beside STEP(p): tile (p+1,p+1) updated as its column, then its
                      //   Cholesky + inverse and M_{p+1}
   PH_STEPF = 3,      // DIAGC(p) and STEP(p) as one launch of the Cholesky-capable kernel
-                     //   (few tasks per step: the launch latency dominates)
+                     //   (few tasks per step: the launch latency dominates); the column-p
+                     //   term of column p+1 is L[i,p] L[p+1,p]^T formed in the task from
+                     //   X_pp, so no M_p is needed
   PH_OFFDIAG_X = 4,  // X = S[t] Linv^T
   PH_OFFDIAG = 5,    // R' = R[t] Linv^T
   PH_SCHUR_X = 6,    // D[t+1] -= X X^T
