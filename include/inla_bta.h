@@ -262,6 +262,14 @@ const char *inla_status_string(inla_status s);
 /* Thread-local text of the last synchronous error ("" if none). */
 const char *inla_last_error(void);
 
+/*
+ * Build id: the first 16 hex digits of the SHA-256 of the library's source
+ * files (kernels, engine, internal headers and this header) it was compiled
+ * from, or "unknown".  Bindings compare it with the sources beside them so
+ * that a library left over from older sources is refused, not run.
+ */
+const char *inla_build_id(void);
+
 #ifdef __cplusplus
 }
 #endif

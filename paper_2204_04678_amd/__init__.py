@@ -11,6 +11,7 @@ from .binding import (  # noqa: F401
     InlaObjective,
     Model,
     assemble,
+    build_id,
     eval_f,
     eval_f_grad,
     factor_logdet,

@@ -13,7 +13,7 @@ import re
 import numpy as np
 import torch
 
-from ._build import LIB, ROOT
+from ._build import LIB, ROOT, source_hash
 
 INLA_OK = 0
 STATUS = {0: "ok", -1: "invalid argument", -2: "not positive definite", -3: "over HBM budget",
@@ -69,6 +69,7 @@ _SIGS = {
     "inla_profile_slots": (C.c_int32, []),
     "inla_status_string": (C.c_char_p, [C.c_int]),
     "inla_last_error": (C.c_char_p, []),
+    "inla_build_id": (C.c_char_p, []),
 }
 
 
@@ -81,7 +82,8 @@ def header_functions() -> list[str]:
 
 
 def lib(path: str = LIB):
-    """Load the HIP library (raises if it has not been built)."""
+    """Load the HIP library (raises if it has not been built, or if it was
+    built from other sources than the ones beside this package)."""
     global _LIB
     if _LIB is None:
         if not os.path.exists(path):
@@ -91,8 +93,17 @@ def lib(path: str = LIB):
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
+        built, want = L.inla_build_id().decode(), source_hash()
+        if built != want:
+            raise RuntimeError(f"{path} was built from other sources (build id {built}, sources "
+                               f"{want}): rebuild it with __graft_entry__.build()")
         _LIB = L
     return _LIB
+
+
+def build_id() -> str:
+    """The source hash the loaded library was built from."""
+    return lib().inla_build_id().decode()
 
 
 def _check(code: int):

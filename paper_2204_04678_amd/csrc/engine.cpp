@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -31,6 +32,7 @@
 #include <vector>
 
 #include "../../include/inla_bta.h"
+#include "graph_key.h"
 #include "inla_internal.h"
 
 using namespace inla;
@@ -512,6 +514,33 @@ size_t bta_doubles(int b, int nt, int a) {
   return (size_t)(2 * nt - 1) * b * b + (size_t)nt * a * b + (size_t)a * a;
 }
 
+// The launch sequence of one batched evaluation, captured once per call
+// signature and replayed.  Inputs and outputs pass through library buffers so
+// the captured graph only ever touches library memory.
+struct EvalGraph {
+  bool valid = false;
+  GraphKey key;
+  hipGraphExec_t exec = nullptr;
+  double *th = nullptr, *f = nullptr, *g = nullptr, *mu_buf = nullptr, *var_buf = nullptr;
+  int *st = nullptr;
+};
+EvalGraph g_graph;
+hipStream_t g_cap = nullptr;
+
+bool graphs_enabled() {
+  const char *e = getenv("INLA_GRAPH");
+  return !(e && e[0] == '0');
+}
+
+void drop_graph() {
+  if (g_graph.exec) (void)hipGraphExecDestroy(g_graph.exec);
+  g_graph = EvalGraph();
+}
+
+void drop_graph_of_model(uint64_t id) {
+  if (g_graph.valid && key_uses_model(g_graph.key, id)) drop_graph();
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -523,9 +552,12 @@ struct inla_model {
   void *mem = nullptr;
   int device = 0;
   long long n = 0, m = 0;
+  uint64_t id = 0;    // unique over the process lifetime (captured graphs key on it)
 };
 
 namespace {
+
+std::atomic<uint64_t> g_next_model_id{1};
 
 struct HostModel {
   int N, nt, a, b;
@@ -681,6 +713,11 @@ const char *inla_status_string(inla_status s) {
 
 const char *inla_last_error(void) { return g_last_error.c_str(); }
 
+#ifndef INLA_SOURCE_HASH
+#define INLA_SOURCE_HASH "unknown"
+#endif
+const char *inla_build_id(void) { return INLA_SOURCE_HASH; }
+
 inla_status inla_model_create(const inla_model_desc *desc, void *hip_stream, inla_model **out) {
   g_last_error.clear();
   if (!desc || !out) return fail(INLA_ERR_ARG, "desc and out must be non-NULL");
@@ -775,6 +812,7 @@ inla_status inla_model_create(const inla_model_desc *desc, void *hip_stream, inl
     return fail(INLA_ERR_HIP, std::string("model upload: ") + hipGetErrorString(e));
   }
   M->dev = mdev;
+  M->id = g_next_model_id.fetch_add(1);
   *out = M;
   return INLA_OK;
 }
@@ -784,6 +822,8 @@ void inla_model_destroy(inla_model *model) {
   {
     std::lock_guard<std::mutex> lk(g_mutex);
     if (g_arena.last) (void)hipEventSynchronize(g_arena.last);
+    // a captured graph that reads this model's data must never run again
+    drop_graph_of_model(model->id);
   }
   if (model->mem) (void)hipFree(model->mem);
   delete model;
@@ -938,34 +978,6 @@ size_t theta_item_bytes(const ModelDev &h, bool selinv, bool seq, bool split, bo
   return (seq ? 1 : 2) * per + ((size_t)h.n + std::max(h.b, h.a) + kTermBlocks * 4) * 8 + 4096;
 }
 
-// The launch sequence of one batched evaluation, captured once per call
-// signature and replayed.  Inputs and outputs pass through library buffers so
-// the captured graph only ever touches library memory.
-struct EvalGraph {
-  bool valid = false;
-  std::vector<const inla_model *> models;
-  bool grad = false, var = false, mu = false, prof = false, seq = false, split = false, vb = false;
-  int tile = 0, variant = 0, small = 0, step = -1;
-  unsigned long long gen = 0;
-  char *base = nullptr;
-  hipGraphExec_t exec = nullptr;
-  double *th = nullptr, *f = nullptr, *g = nullptr, *mu_buf = nullptr, *var_buf = nullptr;
-  int *st = nullptr;
-  long long ntot = 0;
-};
-EvalGraph g_graph;
-hipStream_t g_cap = nullptr;
-
-bool graphs_enabled() {
-  const char *e = getenv("INLA_GRAPH");
-  return !(e && e[0] == '0');
-}
-
-void drop_graph() {
-  if (g_graph.exec) (void)hipGraphExecDestroy(g_graph.exec);
-  g_graph = EvalGraph();
-}
-
 inla_status ensure_streams() {
   if (!g_side) {
     HIP_TRY(hipStreamCreateWithFlags(&g_side, hipStreamNonBlocking));
@@ -981,14 +993,17 @@ inla_status ensure_streams() {
   return INLA_OK;
 }
 
-inla_status copy_outputs(const EvalGraph &G, int n, double *f_dev, double *grad_dev, double *mu_out,
-                         double *var_out, int32_t *status_dev, hipStream_t s) {
+// Copies a replayed graph's outputs to the caller; ntot is this call's total
+// length of mu / var (equal to the graph's: it is part of the key).
+inla_status copy_outputs(const EvalGraph &G, int n, long long ntot, double *f_dev, double *grad_dev,
+                         double *mu_out, double *var_out, int32_t *status_dev, hipStream_t s) {
   const auto D2D = hipMemcpyDeviceToDevice;
   HIP_TRY(hipMemcpyAsync(f_dev, G.f, (size_t)n * 8, D2D, s));
   if (grad_dev) HIP_TRY(hipMemcpyAsync(grad_dev, G.g, (size_t)n * 32, D2D, s));
   if (status_dev) HIP_TRY(hipMemcpyAsync(status_dev, G.st, (size_t)n * 4, D2D, s));
-  if (mu_out) HIP_TRY(hipMemcpyAsync(mu_out, G.mu_buf, (size_t)G.ntot * 8, D2D, s));
-  if (var_out) HIP_TRY(hipMemcpyAsync(var_out, G.var_buf, (size_t)G.ntot * 8, D2D, s));
+  if (G.key.ntot != ntot) return fail(INLA_ERR_STATE, "internal: replayed graph has another output size");
+  if (mu_out) HIP_TRY(hipMemcpyAsync(mu_out, G.mu_buf, (size_t)ntot * 8, D2D, s));
+  if (var_out) HIP_TRY(hipMemcpyAsync(var_out, G.var_buf, (size_t)ntot * 8, D2D, s));
   return INLA_OK;
 }
 
@@ -1080,18 +1095,22 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
   // laid out the workspace since
   // (events recorded during capture cannot be timed, so profiling runs eagerly)
   const bool graphable = allow_graph && graphs_enabled() && !g_prof.on && all <= budget;
-  std::vector<const inla_model *> key(models, models + n_items);
-  if (graphable && g_graph.valid && g_graph.models == key && g_graph.grad == grad &&
-      g_graph.var == (var_out != nullptr) && g_graph.mu == (mu_out != nullptr) &&
-      g_graph.prof == g_prof.on && g_graph.seq == seq && g_graph.split == split &&
-      g_graph.vb == vb && g_graph.tile == tile &&
-      g_graph.variant == variant && g_graph.small == small && g_graph.step == step &&
-      g_graph.gen == g_arena.gen &&
-      g_graph.base == g_arena.base) {
+  GraphKey key;
+  for (int i = 0; i < n_items; ++i) {
+    const ModelDev &h = models[i]->host;
+    key.model_ids.push_back(models[i]->id);
+    for (int64_t v : {(int64_t)h.b, (int64_t)h.nt, (int64_t)h.a, (int64_t)models[i]->n})
+      key.shapes.push_back(v);
+  }
+  key.grad = grad; key.var = var_out != nullptr; key.mu = mu_out != nullptr; key.prof = g_prof.on;
+  key.seq = seq; key.split = split; key.vb = vb;
+  key.tile = tile; key.variant = variant; key.small = small; key.step = step;
+  key.gen = g_arena.gen; key.base = g_arena.base; key.ntot = ntot;
+  if (graphable && g_graph.valid && same_signature(g_graph.key, key)) {
     if (g_arena.last && g_arena.last_stream != s) HIP_TRY(hipStreamWaitEvent(s, g_arena.last, 0));
     HIP_TRY(hipMemcpyAsync(g_graph.th, theta_dev, (size_t)n_items * 32, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipGraphLaunch(g_graph.exec, s));
-    ST_TRY(copy_outputs(g_graph, n_items, f_dev, grad_dev, mu_out, var_out, status_dev, s));
+    ST_TRY(copy_outputs(g_graph, n_items, ntot, f_dev, grad_dev, mu_out, var_out, status_dev, s));
     return arena_done(s);
   }
   if (graphable) drop_graph();
@@ -1330,25 +1349,14 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
       (void)hipGraphDestroy(graph);
       if (e != hipSuccess) return fail(INLA_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
       G.valid = true;
-      G.models = key;
-      G.grad = grad;
-      G.var = var_out != nullptr;
-      G.mu = mu_out != nullptr;
-      G.prof = g_prof.on;
-      G.seq = seq;
-      G.split = split;
-      G.vb = vb;
-      G.tile = tile;
-      G.variant = variant;
-      G.small = small;
-      G.step = step;
-      G.gen = g_arena.gen;
-      G.base = g_arena.base;
       G.exec = exec;
-      G.ntot = ntot;
+      G.key = key;
+      // the arena was laid out afresh for this call: the key takes its new state
+      G.key.gen = g_arena.gen;
+      G.key.base = g_arena.base;
       g_graph = G;
       HIP_TRY(hipGraphLaunch(g_graph.exec, s));
-      ST_TRY(copy_outputs(g_graph, n_items, f_dev, grad_dev, mu_out, var_out, status_dev, s));
+      ST_TRY(copy_outputs(g_graph, n_items, ntot, f_dev, grad_dev, mu_out, var_out, status_dev, s));
     } else if (st != INLA_OK) {
       return st;
     }

@@ -123,10 +123,6 @@ __host__ __device__ inline bool phase_is_product_x(int phase) {
 
 __host__ __device__ inline int ntile(int n) { return (n + kTile - 1) / kTile; }
 
-// Recursive-doubling inverse of a block lower-triangular matrix with nP tiles:
-// at level L (block size s = 2^(L-1) tiles) each pair of adjacent diagonal
-// blocks U = [u0, u0+s), V = [u0+s, min(u0+2s, nP)) gets
-//   X_VU = -X_VV (L_VU X_UU)   (stage 0: T = L_VU X_UU; stage 1: X_VU = -X_VV T).
 // Number of workgroup tasks of one item in (phase, t, p); big selects 128-tiles
 // for the _X phases.
 __host__ __device__ inline int phase_tasks(const ItemDev &it, int phase, int t, int p,

@@ -84,3 +84,15 @@ def test_batch_and_shape_errors_are_synchronous(libpath):
     assert L.inla_assemble(None, dummy, 0, ctypes.byref(Lq), None, None) == -1
     assert L.inla_assemble(dummy, dummy, 2, ctypes.byref(Lq), None, None) == -1
     assert b"which" in L.inla_last_error()
+
+
+def test_build_id_ties_the_library_to_its_sources(libpath, monkeypatch):
+    """The library reports the hash of the sources it was built from, and the
+    binding refuses a library whose hash differs from the sources beside it."""
+    L = ctypes.CDLL(libpath)
+    L.inla_build_id.restype = ctypes.c_char_p
+    assert L.inla_build_id().decode() == _build.source_hash()
+    monkeypatch.setattr(binding, "_LIB", None)
+    monkeypatch.setattr(binding, "source_hash", lambda: "0" * 16)
+    with pytest.raises(RuntimeError, match="other sources"):
+        binding.lib(libpath)

@@ -310,6 +310,40 @@ def test_eval_f_grad_degenerate_models(P, N, nt, nb):
     assert np.max(np.abs(out["var"].cpu().numpy() - var_ref) / var_ref) < 1e-9
 
 
+def test_new_model_is_not_served_a_destroyed_models_graph(P, monkeypatch):
+    """Regression: a captured evaluation graph bakes in the device data of its
+    models.  A model created after another was destroyed (possibly at the same
+    host address, possibly with the same shape) must get its own results, never
+    a replay of the destroyed model's graph."""
+    import gc
+    monkeypatch.setenv("INLA_GRAPH", "1")
+    mdA = make_model(4, 3, 2, 41)
+    A = P.Model.from_data(mdA)
+    for _ in range(2):   # capture, then replay
+        outA = P.eval_f_grad(A, THETA0, want_mu=True, want_var=True)
+        torch.cuda.synchronize()
+    assert rel(outA["f"].item(), O.eval_f_dense(mdA, THETA0)["f"]) < 1e-10
+    del A
+    gc.collect()
+    # a different shape (no fixed effects), then the destroyed model's shape
+    # with other data: each must match its own oracle value
+    for shape, seed in (((5, 3, 0), 42), ((4, 3, 2), 43), ((5, 3, 0), 44)):
+        print(f"model after destroy: shape={shape} seed={seed}", flush=True)
+        md = make_model(*shape, seed)
+        M = P.Model.from_data(md)
+        for _ in range(2):
+            out = P.eval_f_grad(M, THETA0, want_mu=True, want_var=True)
+            torch.cuda.synchronize()
+            ref = O.eval_f_dense(md, THETA0)
+            assert int(out["status"].item()) == 0
+            assert out["mu"].numel() == md.n and out["var"].numel() == md.n
+            assert rel(out["f"].item(), ref["f"]) < 1e-10
+            mu = out["mu"].cpu().numpy()
+            assert np.abs(mu - ref["mu"]).max() / np.abs(ref["mu"]).max() < 1e-9
+        del M
+        gc.collect()
+
+
 def test_batched_uneven_matches_single(P):
     mds = [make_model(4, 3, 2, 1), make_model(6, 2, 3, 2), make_model(9, 4, 1, 3)]
     Ms = [P.Model.from_data(m) for m in mds]
@@ -418,3 +452,99 @@ def test_objective_autograd(P):
     with torch.no_grad():
         f2 = P.objective(th, [M, M])
     assert torch.equal(f2, f.detach())
+
+
+MULTI_TILE = [(9, 3, 0), (9, 3, 3), (12, 3, 0), (12, 3, 3)]
+
+
+def check_against_dense_oracle(out, i, md, theta, voff=0):
+    """f, grad f, mu and the variances of item i against the dense oracle."""
+    ref = O.eval_f_dense(md, theta)
+    assert int(out["status"][i].item()) == 0
+    assert rel(out["f"][i].item(), ref["f"]) < 1e-10
+    g = out["grad"][i].cpu().numpy()
+    gref = O.dense_gradient(md, theta)
+    scale = np.maximum(grad_term_magnitudes(md, theta), 1e-3 * np.abs(gref).max())
+    assert np.max(np.abs(g - gref) / scale) < 1e-9, (g, gref)
+    if "mu" in out:
+        mu = out["mu"].cpu().numpy()[voff:voff + md.n]
+        assert np.abs(mu - ref["mu"]).max() / np.abs(ref["mu"]).max() < 1e-9
+    if "var" in out:
+        var = out["var"].cpu().numpy()[voff:voff + md.n]
+        vref = O.marginal_variances_dense(md, theta)
+        assert np.max(np.abs(var - vref) / vref) < 1e-9
+
+
+@pytest.mark.parametrize("N,nt,nb", MULTI_TILE)
+def test_eval_f_grad_multi_tile(P, tile, N, nt, nb):
+    """The adjoint where the kernels tile: b = 81 (two 64-wide tiles, one
+    128-wide) and b = 144 (three 64-wide tiles, two 128-wide), with and without
+    fixed effects, under every product form, against the oracle's
+    dense-inverse gradient (and f, mu, variances)."""
+    print(f"multi-tile adjoint N={N} nt={nt} nb={nb} tile={tile}", flush=True)
+    md = make_model(N, nt, nb, 50 + N + nb)
+    M = P.Model.from_data(md)
+    theta = np.array([0.3, 0.9, 1.1, 3.5])
+    out = P.eval_f_grad(M, theta, want_mu=True, want_var=True)
+    torch.cuda.synchronize()
+    check_against_dense_oracle(out, 0, md, theta)
+
+
+@pytest.mark.parametrize("fused", ["0", "1"], ids=["batched_step", "fused_step"])
+@pytest.mark.parametrize("width", [64, 128], ids=["tile64", "tile128"])
+def test_eval_f_grad_multi_tile_step_forms(P, monkeypatch, fused, width):
+    """Both forms of the Cholesky step, with 64- and 128-wide products, on a
+    multi-tile model (b = 144, nt = 3, nb = 3) against the dense oracle."""
+    print(f"multi-tile step forms fused={fused} width={width}", flush=True)
+    monkeypatch.setenv("INLA_STEP_FUSED", fused)
+    md = make_model(12, 3, 3, 65)
+    M = P.Model.from_data(md)
+    theta = np.array([-0.1, 0.7, 0.6, 4.0])
+    out = P.eval_f_grad(M, theta, want_mu=True, want_var=True, tile=width)
+    torch.cuda.synchronize()
+    check_against_dense_oracle(out, 0, md, theta)
+
+
+@pytest.mark.parametrize("N,nt,nb", [(5, 3, 2), (12, 3, 3), (9, 4, 0)])
+def test_eval_f_grad_rho_zero(P, N, nt, nb):
+    """theta_3 = 0 (rho = 0): the time blocks decouple in the prior and the
+    theta_3 derivative of Q_AR1 reduces to its off-diagonal term."""
+    print(f"rho = 0: N={N} nt={nt} nb={nb}", flush=True)
+    md = make_model(N, nt, nb, 70 + N)
+    M = P.Model.from_data(md)
+    theta = np.array([0.2, 1.0, 0.0, 3.0])
+    out = P.eval_f_grad(M, theta, want_mu=True, want_var=True)
+    torch.cuda.synchronize()
+    check_against_dense_oracle(out, 0, md, theta)
+
+
+def test_eval_status_not_positive_definite(P):
+    """Items whose matrices are not numerically positive definite get status 1
+    (Q_prior: tau = e^-500 makes tau^2 underflow to 0, so the space-time part of
+    Q_prior is zero) or 2 (Q_c: tau_y = e^800 overflows to infinity), NaN f and
+    gradient; the other items of the same batched call are unaffected."""
+    md1, md2 = make_model(9, 3, 2, 81), make_model(6, 2, 0, 82)
+    M1, M2 = P.Model.from_data(md1), P.Model.from_data(md2)
+    th = np.array([THETA0, [-500.0, 1.0, 1.5, 4.6], [0.0, 1.0, 1.5, 800.0], THETA0])
+    for fn in ("eval_f_grad", "eval_f"):
+        print(f"status batch via {fn}", flush=True)
+        out = getattr(P, fn)([M1, M1, M2, M2], th, want_mu=True, want_var=True)
+        torch.cuda.synchronize()
+        assert out["status"].cpu().tolist() == [0, 1, 2, 0]
+        f = out["f"].cpu().numpy()
+        assert np.isnan(f[1]) and np.isnan(f[2])
+        if fn == "eval_f_grad":
+            g = out["grad"].cpu().numpy()
+            assert np.isnan(g[1]).all() and np.isnan(g[2]).all()
+            voff = np.cumsum([0, md1.n, md1.n, md2.n])
+            check_against_dense_oracle(out, 0, md1, THETA0, voff[0])
+            check_against_dense_oracle(out, 3, md2, THETA0, voff[3])
+            # the good items equal their single evaluations
+            for i, M in ((0, M1), (3, M2)):
+                one = P.eval_f_grad(M, THETA0)
+                torch.cuda.synchronize()
+                assert out["f"][i].item() == one["f"][0].item()
+                assert torch.equal(out["grad"][i], one["grad"][0])
+        else:
+            assert rel(f[0], O.eval_f_dense(md1, THETA0)["f"]) < 1e-10
+            assert rel(f[3], O.eval_f_dense(md2, THETA0)["f"]) < 1e-10

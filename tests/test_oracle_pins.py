@@ -142,7 +142,33 @@ def marginal_likelihood_f(model, theta):
     sign, ld = np.linalg.slogdet(S)
     assert sign > 0
     quad = float(model.y @ np.linalg.solve(S, model.y))
-    return -O.log_hyperprior(model, theta) + 0.5 * ld + 0.5 * quad + 0.5 * model.m * O.LOG2PI
+    return -scipy_log_hyperprior(model, theta) + 0.5 * ld + 0.5 * quad + 0.5 * model.m * O.LOG2PI
+
+
+def scipy_log_hyperprior(model, theta):
+    """Independent Gaussian hyperprior N(m_k, 1/p_k) through scipy's own normal density."""
+    from scipy.stats import norm
+    sd = 1.0 / np.sqrt(np.asarray(model.theta_prior_prec, dtype=np.float64))
+    return math.fsum(norm.logpdf(np.asarray(theta, dtype=np.float64),
+                                 loc=np.asarray(model.theta_prior_mean, dtype=np.float64),
+                                 scale=sd))
+
+
+@pytest.mark.parametrize("mean,prec,theta", [
+    (np.zeros(4), np.full(4, 0.01), THETA0),
+    (np.array([0.5, -1.0, 2.0, 3.0]), np.array([1.0, 4.0, 0.25, 9.0]),
+     np.array([0.3, -0.2, -0.7, 2.0])),
+    (np.array([-3.0, 0.0, 0.1, 10.0]), np.array([100.0, 1e-4, 2.0, 0.5]),
+     np.array([-2.5, 7.0, 0.0, -1.0])),
+])
+def test_log_hyperprior_is_the_gaussian_density(mean, prec, theta):
+    """log pi(theta), constants included (the Gaussian hyperprior reading of
+    Sec. "Latent Gaussian Models"), against scipy.stats.norm.logpdf summed over
+    the four components."""
+    model = small()
+    model.theta_prior_mean = mean
+    model.theta_prior_prec = prec
+    assert rel(O.log_hyperprior(model, theta), scipy_log_hyperprior(model, theta)) < 1e-14
 
 
 @pytest.mark.parametrize("shape,tol", [((4, 3, 2), 1e-10), ((3, 2, 0), 1e-10), ((2, 4, 1), 1e-10)])
@@ -356,3 +382,26 @@ def test_pins_detect_planted_mistakes(monkeypatch):
     monkeypatch.undo()
     fd = O.fd_gradient(model, theta, h=1e-5)
     assert np.max(np.abs(g - fd) / np.maximum(np.abs(fd), 1e-3)) > 1e-4
+
+    # (6) hyperprior without its 2 pi (log p instead of log(p / 2 pi)): both the
+    #     density pin and the marginal-likelihood identity must fail
+    def bad_prior(model_, theta_):
+        t = np.asarray(theta_, dtype=np.float64)
+        m = np.asarray(model_.theta_prior_mean, dtype=np.float64)
+        p = np.asarray(model_.theta_prior_prec, dtype=np.float64)
+        return float(np.sum(0.5 * np.log(p) - 0.5 * p * (t - m) ** 2))
+    monkeypatch.setattr(O.inla_oracle, "log_hyperprior", bad_prior)
+    monkeypatch.setattr(O, "log_hyperprior", bad_prior)
+    assert rel(O.log_hyperprior(model, theta), scipy_log_hyperprior(model, theta)) > 1e-6
+    assert rel(O.eval_f_dense(model, theta)["f"], good_ml) > 1e-6
+    monkeypatch.undo()
+
+    # (7) half the normalising constant dropped (1/2 log p taken as log p)
+    def bad_prior2(model_, theta_):
+        t = np.asarray(theta_, dtype=np.float64)
+        m = np.asarray(model_.theta_prior_mean, dtype=np.float64)
+        p = np.asarray(model_.theta_prior_prec, dtype=np.float64)
+        return float(np.sum(np.log(p) - 0.5 * math.log(2.0 * math.pi) - 0.5 * p * (t - m) ** 2))
+    monkeypatch.setattr(O.inla_oracle, "log_hyperprior", bad_prior2)
+    assert rel(O.eval_f_dense(model, theta)["f"], good_ml) > 1e-6
+    monkeypatch.undo()
