@@ -176,6 +176,26 @@ inla_status inla_assemble(const inla_model *model, const double *theta_dev, int3
 inla_status inla_factor_logdet(inla_bta *QL, double *logdet_dev, int32_t *info_dev, void *hip_stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * factorization as inla_factor_logdet, with the same results bit for bit, but
+ * its workspace (two b x b panels, the arrow panel, the diagonal-tile scratch,
+ * the log-determinant partial sums and the item descriptor) lives in one
+ * fixed device array of INLA_NOALLOC_SCRATCH_BYTES per GPU instead of the
+ * library's growable workspace.  The array is set up on the first call on a
+ * device (with that device current) and held until the process ends; no
+ * call allocates or frees device memory, and none stages data in host memory.
+ * A matrix whose workspace does not fit (about 2 b^2 + a b + nt ceil(b/64)
+ * doubles; b up to about 2048) is rejected with INLA_ERR_BUDGET before
+ * anything is enqueued.  Every call on one GPU shares that GPU's array: calls
+ * that overlap on one GPU (on different streams without ordering between
+ * them) race.  Not profiled by inla_profile_begin/end.
+ */
+#define INLA_NOALLOC_SCRATCH_BYTES (64u << 20)
+inla_status inla_factor_logdet_noalloc(inla_bta *QL, double *logdet_dev, int32_t *info_dev,
+                                       void *hip_stream);
+
+/*
  * Solve Q X = RHS with the factor from inla_factor_logdet by forward then
  * backward substitution (Sec. "Sparse Linear Algebra").  rhs_dev, x_dev:
  * n x nrhs column-major (n = b*nt + a); they may alias.

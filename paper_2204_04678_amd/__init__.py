@@ -15,6 +15,7 @@ from .binding import (  # noqa: F401
     eval_f,
     eval_f_grad,
     factor_logdet,
+    factor_logdet_noalloc,
     header_functions,
     lib,
     objective,

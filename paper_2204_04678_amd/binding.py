@@ -56,6 +56,8 @@ _SIGS = {
     "inla_assemble": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(Bta), C.c_void_p,
                                 C.c_void_p]),
     "inla_factor_logdet": (C.c_int, [C.POINTER(Bta), C.c_void_p, C.c_void_p, C.c_void_p]),
+    "inla_factor_logdet_noalloc": (C.c_int, [C.POINTER(Bta), C.c_void_p, C.c_void_p,
+                                             C.c_void_p]),
     "inla_solve": (C.c_int, [C.POINTER(Bta), C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "inla_selinv": (C.c_int, [C.POINTER(Bta), C.POINTER(Bta), C.c_void_p, C.c_void_p]),
     "inla_eval_f": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.c_void_p,
@@ -239,6 +241,16 @@ def factor_logdet(Q: BtaTensors):
     st = Q.struct()
     _check(lib().inla_factor_logdet(C.byref(st), _ptr(ld), _ptr(info), _stream()))
     return ld, info
+
+
+def factor_logdet_noalloc(Q: BtaTensors, logdet=None, info=None):
+    """inla_factor_logdet_noalloc: the same factorization with the library's
+    fixed per-GPU workspace; logdet / info may be caller tensors (1 element)."""
+    ld = logdet if logdet is not None else torch.empty(1, dtype=torch.float64, device="cuda")
+    inf = info if info is not None else torch.empty(1, dtype=torch.int32, device="cuda")
+    st = Q.struct()
+    _check(lib().inla_factor_logdet_noalloc(C.byref(st), _ptr(ld), _ptr(inf), _stream()))
+    return ld, inf
 
 
 def solve(L: BtaTensors, rhs):

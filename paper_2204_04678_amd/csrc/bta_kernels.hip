@@ -2107,6 +2107,18 @@ hipError_t launch_fill_int(int *ptr, long long n, int v, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Stores one item descriptor, passed by value as a kernel argument, into
+// device memory (no host staging buffer: nothing is read from host memory
+// when the copy runs).
+__global__ void put_item_kernel(ItemDev it, ItemDev *dst) {
+  if (threadIdx.x == 0) *dst = it;
+}
+
+hipError_t launch_put_item(const ItemDev &it, ItemDev *dst, hipStream_t s) {
+  hipLaunchKernelGGL(put_item_kernel, dim3(1), dim3(64), 0, s, it, dst);
+  return hipGetLastError();
+}
+
 // log|Q| = 2 sum of the per-tile partial sums of log L_jj, in a fixed tree order.
 // Item i writes logdet_out[i * stride] and info_out[i * stride].
 __global__ void logdet_finish_kernel(const ItemDev *items, double *logdet_out, int *info_out,

@@ -541,6 +541,37 @@ void drop_graph_of_model(uint64_t id) {
   if (g_graph.valid && key_uses_model(g_graph.key, id)) drop_graph();
 }
 
+// ---------------------------------------------------------------------------
+// workspace of the allocation-free factorization: one fixed device array per
+// GPU, held from the first call on that GPU until the process ends
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchBytes = INLA_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+// Device address of `scratch` on each GPU (host code must never pass the
+// array's name itself to a kernel: on the host it is only a stand-in).
+char *g_scratch_ptr[kMaxDevices] = {};
+
+inla_status ensure_streams();
+
+// Set-up on the first call on the current device: the array's device address
+// and the library's side streams (so that later calls create nothing).
+// Called with g_mutex held.
+inla_status noalloc_scratch(char **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(INLA_ERR_STATE, "device index out of range");
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(INLA_ERR_STATE, "no device address for the fixed workspace");
+    ST_TRY_INNER(ensure_streams());
+    g_scratch_ptr[dev] = static_cast<char *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return INLA_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -878,6 +909,52 @@ inla_status inla_factor_logdet(inla_bta *QL, double *logdet_dev, int32_t *info_d
   HIP_TRY(launch_logdet_finish(B.dev, 1, logdet_dev ? logdet_dev : ld_tmp,
                                info_dev ? info_dev : info_tmp, s));
   return arena_done(s);
+}
+
+inla_status inla_factor_logdet_noalloc(inla_bta *QL, double *logdet_dev, int32_t *info_dev,
+                                       void *hip_stream) {
+  g_last_error.clear();
+  ST_TRY(check_bta(QL, "QL"));
+  std::lock_guard<std::mutex> lk(g_mutex);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  char *base = nullptr;
+  ST_TRY(noalloc_scratch(&base));
+  Batch B;
+  B.host.push_back(item_from_bta(*QL));
+  Layout L;
+  layout_factor_ws(L, B.host[0]);
+  L.add(&B.dev, 1);
+  double *ld_tmp;
+  int *info_tmp;
+  L.add(&ld_tmp, 1);
+  L.add(&info_tmp, 1);
+  if (L.total > kNoAllocScratchBytes)
+    return fail(INLA_ERR_BUDGET, "the factorization needs " + std::to_string(L.total) +
+                                     " bytes of workspace, above the " +
+                                     std::to_string(kNoAllocScratchBytes) +
+                                     " bytes of inla_factor_logdet_noalloc");
+  size_t off = 0;
+  for (auto &r : L.reqs) {
+    *r.slot = base + off;
+    off += align_up(std::max<size_t>(r.bytes, 1));
+  }
+  B.finalize();
+  // no event pool growth and no records: this entry point is never profiled
+  const bool prof = g_prof.on;
+  g_prof.on = false;
+  auto body = [&]() -> inla_status {
+    // the first failing pivot starts at "none"; the descriptor travels as a
+    // kernel argument (nothing is staged in host memory)
+    HIP_TRY(launch_fill_int(B.host[0].info, 1, kInfoNone, s));
+    HIP_TRY(launch_put_item(B.host[0], B.dev, s));
+    ST_TRY(run_factor(B, s));
+    HIP_TRY(launch_logdet_finish(B.dev, 1, logdet_dev ? logdet_dev : ld_tmp,
+                                 info_dev ? info_dev : info_tmp, s));
+    return INLA_OK;
+  };
+  const inla_status st = body();
+  g_prof.on = prof;
+  return st;
 }
 
 inla_status inla_solve(const inla_bta *L_, const double *rhs_dev, double *x_dev, int32_t nrhs,

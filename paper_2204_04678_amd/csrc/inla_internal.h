@@ -177,6 +177,8 @@ hipError_t launch_tile_phase(const ItemDev *items_dev, int n_items, int total, i
 constexpr int kSplitK = 2;        // k-split of 128-tile launches with too few tiles
 hipError_t launch_fill(double *ptr, long long n, double v, hipStream_t s);
 hipError_t launch_fill_int(int *ptr, long long n, int v, hipStream_t s);
+// Writes *dst = it on the stream (the descriptor travels as a kernel argument).
+hipError_t launch_put_item(const ItemDev &it, ItemDev *dst, hipStream_t s);
 hipError_t launch_logdet_finish(const ItemDev *items_dev, int n_items, double *logdet_out,
                                 int *info_out, hipStream_t s, int stride = 1);
 // Layout of the 128-wide tile kernel (0: 8 waves of 64 x 32, k-chunk 16, two
