@@ -12,7 +12,14 @@ Also measured in the same run (reported beside the headline, not as it):
   * the plain finite-difference baseline on the same GPU: 2*dim(theta)+1 = 9
     f-only evaluations one after another per gradient;
   * the same 9 points as one batched call;
-  * the CPU oracle on the host (bounded sample), as the cpu_baseline.
+  * the largest block size (45x45 grid, b = 2025, nt = 200, nb = 10): the 8
+    line-search theta points in one batched call, with its own step count, as
+    the "largest_block" record (evaluations/s, whole-step FP64 rate and the
+    product kernel's roofline);
+  * the CPU oracle on the host (bounded samples), as the cpu_baseline: all
+    cores through threaded LAPACK, one thread, and the level-1 form of the
+    paper's parallel scheme (the 9 central-difference points in 9 concurrent
+    processes), run before anything touches the GPU.
 
 Prints one JSON line.
 """
@@ -72,104 +79,167 @@ def hbm_traffic(config, kernel):
     return sum(v["hbm_bytes_per_dispatch"] * v["dispatches"] for v in ks) / nd
 
 
-def cpu_baseline(md, theta, budget_s=20.0):
-    """Oracle f(theta) on the host; the oracle's gradient is 2d+1 = 9 f evaluations."""
+def host_facts():
+    """Host CPU facts for the CPU baseline: logical CPUs, the CPUs this process
+    may run on, the thread count the box asks for, the CPU model and the BLAS
+    libraries numpy / scipy use with their thread counts."""
+    facts = {"nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
+             "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+    try:
+        with open("/proc/cpuinfo") as fh:
+            models = [ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")]
+        facts["cpu_model"] = models[0] if models else None
+    except OSError:
+        facts["cpu_model"] = None
+    try:
+        from threadpoolctl import threadpool_info
+        facts["blas"] = [{"api": p.get("internal_api"), "version": p.get("version"),
+                          "threads": p.get("num_threads"),
+                          "library": os.path.basename(p.get("filepath", ""))}
+                         for p in threadpool_info()]
+    except Exception:  # pragma: no cover
+        facts["blas"] = None
+    return facts
+
+
+_LEVEL1_CHILD = """
+import json, os, sys, time
+sys.path.insert(0, {root!r})
+import numpy as np
+import oracle
+from inla_synth import config_model, fd_stencil, THETA0
+md = config_model({config!r})
+pt = fd_stencil(THETA0, 1e-3)[{k}]
+t0 = time.time()
+f = oracle.eval_f_banded(md, pt)["f"]
+t1 = time.time()
+print(json.dumps({{"start": t0, "end": t1, "f": f}}))
+"""
+
+
+def cpu_baseline(config, budget_s=30.0):
+    """The oracle on the host's cores, in three modes (a baseline only, never
+    the target): threaded LAPACK on all cores, one thread, and the paper's
+    level-1 parallelism -- the 2d+1 = 9 central-difference points of one
+    gradient as 9 concurrent processes with cores // 9 threads each.  f+grad
+    by central differences costs 9 f evaluations."""
+    import subprocess
+
     import numpy as np
 
     import oracle
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:  # pragma: no cover
-        threads = os.cpu_count() or 1
+    from inla_synth import THETA0, config_model
+    facts = host_facts()
+    cores = int(facts["omp_num_threads"] or facts["affinity_cpus"] or 1)
+    md = config_model(config)
+    theta = np.asarray(THETA0)
+    modes = {}
+    # (1) all cores through threaded LAPACK
     t0 = time.perf_counter()
     n = 0
-    while True:
-        oracle.eval_f_banded(md, np.asarray(theta))
+    while n < 2 and time.perf_counter() - t0 < budget_s / 3:
+        oracle.eval_f_banded(md, theta)
         n += 1
-        if time.perf_counter() - t0 > budget_s / 2 or n >= 3:
-            break
     dt = (time.perf_counter() - t0) / n
-    return {"value": 1.0 / (9.0 * dt), "unit": "f+grad evals/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"{n} oracle f evaluation(s) (bordered-banded LAPACK Cholesky of Q_p and Q_c + "
-                      f"solve) at the workload size, {dt:.2f} s each; f+grad by central "
-                      f"differences = 9 f evaluations"}
+    modes["threaded"] = {"threads": cores, "f_evals": n, "s_per_f": round(dt, 3),
+                         "f_grad_evals_per_s": 1.0 / (9.0 * dt)}
+    # (2) one thread
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            oracle.eval_f_banded(md, theta)
+            dt1 = time.perf_counter() - t0
+        modes["single_thread"] = {"threads": 1, "f_evals": 1, "s_per_f": round(dt1, 3),
+                                  "f_grad_evals_per_s": 1.0 / (9.0 * dt1)}
+    except ImportError:  # pragma: no cover
+        pass
+    # (3) level 1: the 9 stencil points in 9 concurrent processes
+    per = max(1, cores // 9)
+    env = dict(os.environ, OMP_NUM_THREADS=str(per), OPENBLAS_NUM_THREADS=str(per),
+               MKL_NUM_THREADS=str(per))
+    procs = [subprocess.Popen([sys.executable, "-c",
+                               _LEVEL1_CHILD.format(root=ROOT, config=config, k=k)],
+                              stdout=subprocess.PIPE, stderr=subprocess.PIPE, env=env, text=True)
+             for k in range(9)]
+    recs = []
+    for p in procs:
+        out, err = p.communicate(timeout=600)
+        if p.returncode != 0:
+            raise RuntimeError("level-1 oracle process failed: " + err[-2000:])
+        recs.append(json.loads(out.strip().splitlines()[-1]))
+    wall = max(r["end"] for r in recs) - min(r["start"] for r in recs)
+    fv = [r["f"] for r in recs]
+    modes["level1_9_processes"] = {
+        "threads": 9 * per, "processes": 9, "threads_per_process": per,
+        "fd_gradient_wall_s": round(wall, 3), "f_grad_evals_per_s": 1.0 / wall,
+        "fd_grad_h1e-3": [(fv[1 + 2 * k] - fv[2 + 2 * k]) / 2e-3 for k in range(4)]}
+    best = max(modes, key=lambda k: modes[k]["f_grad_evals_per_s"])
+    for m in modes.values():
+        m["f_grad_evals_per_s"] = round(m["f_grad_evals_per_s"], 5)
+    return {"value": modes[best]["f_grad_evals_per_s"], "unit": "f+grad evals/s",
+            "cores": modes[best]["threads"], "kind": "oracle",
+            "sample": (f"oracle f (bordered-banded LAPACK Cholesky of Q_p and Q_c + solve) at "
+                       f"{md.N}x{md.N}x{md.nt} (n={md.n}); f+grad = 9 f evaluations by central "
+                       f"differences; value = fastest of the modes ({best}); threaded: {n} f "
+                       f"evaluation(s), single thread: 1, level 1: one gradient"),
+            "modes": modes, "host": facts}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
-                    help="c2 (default, the headline): 32x32x50, one theta; c3: 64 uneven models, "
-                         "one batched call; c4: 40x40x100, one theta; c5: 45x45x200, the 8 "
-                         "line-search points in one batched call")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-fd", action="store_true", help="skip the finite-difference baseline")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
-              f"batched items would shard across GPUs by theta point, which is not built.",
-              file=sys.stderr)
-        sys.exit(2)
-
+def load_workload(P, config):
+    """Models, theta batch (device) and per-item model data of a named workload."""
     import numpy as np
     import torch
 
-    import paper_2204_04678_amd as P
-    from inla_synth import THETA0, config_model, config_theta_batch, fd_stencil, uneven_batch
-
-    if not os.path.exists(P.binding.LIB):
-        from paper_2204_04678_amd import _build
-        _build.build()
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
-
-    if args.config == "c3":
+    from inla_synth import THETA0, config_model, config_theta_batch, uneven_batch
+    if config == "c3":
         items = uneven_batch(64)
         mds = [m for m, _ in items]
         model = [P.Model.from_data(m) for m in mds]
         theta = torch.tensor(np.stack([t for _, t in items]), dtype=torch.float64, device="cuda")
-        md = mds[0]
         workload = "64 models of uneven (N in {16,24,32}, nt in [20,100], nb in [2,6]), each " \
                    "with its own theta, f+grad via adjoint, one batched call"
-    else:
-        md = config_model(args.config)
-        mds = [md]
-        model = P.Model.from_data(md)
-        th = config_theta_batch(args.config) if args.config == "c5" else THETA0[None, :]
-        theta = torch.tensor(th, dtype=torch.float64, device="cuda")
-        mds = mds * theta.shape[0]
-        workload = (f"N={md.N} (b={md.ns}), nt={md.nt}, nb={md.nb}, n={md.n}, m={md.m}, "
-                    f"{theta.shape[0]} theta point(s), f+grad via adjoint")
-    n_items = theta.shape[0]
-    b, nt, a = md.ns, md.nt, md.nb
-    F_alg = sum(2 * flops_chol(m.ns, m.nt, m.nb) + 2 * flops_selinv(m.ns, m.nt, m.nb) for m in mds)
+        return model, theta, mds, workload
+    md = config_model(config)
+    model = P.Model.from_data(md)
+    th = config_theta_batch(config) if config == "c5" else THETA0[None, :]
+    theta = torch.tensor(th, dtype=torch.float64, device="cuda")
+    mds = [md] * theta.shape[0]
+    workload = (f"N={md.N} (b={md.ns}), nt={md.nt}, nb={md.nb}, n={md.n}, m={md.m}, "
+                f"{theta.shape[0]} theta point(s), f+grad via adjoint"
+                + (", one batched call" if theta.shape[0] > 1 else ""))
+    return model, theta, mds, workload
 
+
+def measure(P, config, model, theta, mds, steps, warmup, timing_steps):
+    """Time `steps` evaluations (graph replay) after `warmup`, then an eager
+    pass of `timing_steps` evaluations with HIP events around every launch;
+    returns the throughput record and the roofline of the dominant tile kernel."""
+    import torch
+    n_items = theta.shape[0]
+    F_alg = sum(2 * flops_chol(m.ns, m.nt, m.nb) + 2 * flops_selinv(m.ns, m.nt, m.nb) for m in mds)
     # Timed region: the evaluation replays its captured hipGraph (one launch of
-    # the whole ~2.5k-kernel sequence per step).
-    for _ in range(max(args.warmup, 1)):
+    # the whole kernel sequence per step).
+    for _ in range(max(warmup, 1)):
         P.eval_f_grad(model, theta)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         out = P.eval_f_grad(model, theta)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    step_s = (t1 - t0) / args.steps
+    step_s = (t1 - t0) / steps
     value = n_items / step_s
 
-    # Kernel timing pass: the same steps launched eagerly with HIP events around
-    # every kernel on its stream (events recorded inside a captured graph cannot
-    # be timed), in the same process right after the timed region.
+    # Kernel timing pass: the same evaluations launched eagerly with HIP events
+    # around every kernel on its stream (events recorded inside a captured
+    # graph cannot be timed), in the same process right after the timed region.
     prev_graph = os.environ.get("INLA_GRAPH")
     os.environ["INLA_GRAPH"] = "0"
     P.profile_begin()
     torch.cuda.synchronize()
     tp0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(timing_steps):
         P.eval_f_grad(model, theta)
     torch.cuda.synchronize()
     tp1 = time.perf_counter()
@@ -178,13 +248,7 @@ def main():
         os.environ.pop("INLA_GRAPH", None)
     else:
         os.environ["INLA_GRAPH"] = prev_graph
-    eager_step_s = (tp1 - tp0) / args.steps
-    f_val = out["f"].cpu().numpy().tolist()
-    grad = out["grad"].cpu().numpy().tolist()
-    if n_items == 1:
-        f_val, grad = f_val[0], grad[0]
-    elif n_items > 8:
-        f_val, grad = f_val[:8], grad[:8]
+    eager_step_s = (tp1 - tp0) / timing_steps
 
     calls = max(prof["calls"], 1)
     slots, kernels = prof["slots"], prof["kernels"]
@@ -196,7 +260,7 @@ def main():
     roofline = {"bound": "mfma", "kernel": dom,
                 "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                "traffic": hbm_traffic(args.config, "inla::" + dom),
+                "traffic": hbm_traffic(config, "inla::" + dom),
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
                 "launches_per_step": pk["launches"] / calls,
                 "avg_launch_us": round(pk["ms"] * 1e3 / max(pk["launches"], 1), 3),
@@ -212,6 +276,61 @@ def main():
                                for k, v in kernels.items() if v["launches"]},
                 "per_phase_ms_per_step": {k: round(v["ms"] / calls, 3)
                                           for k, v in slots.items() if v["launches"]}}
+    f_val = out["f"].cpu().numpy().tolist()
+    grad = out["grad"].cpu().numpy().tolist()
+    return {"value": value, "step_s": step_s, "F_alg": F_alg, "f": f_val, "grad": grad,
+            "roofline": roofline, "status": out["status"].cpu().numpy().tolist()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
+                    help="c2 (default, the headline): 32x32x50, one theta; c3: 64 uneven models, "
+                         "one batched call; c4: 40x40x100, one theta; c5: 45x45x200, the 8 "
+                         "line-search points in one batched call")
+    ap.add_argument("--largest-steps", type=int, default=3,
+                    help="timed steps of the largest-block record (0: skip it)")
+    ap.add_argument("--largest-warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fd", action="store_true", help="skip the finite-difference baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
+              f"batched items would shard across GPUs by theta point, which is not built.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    # the CPU baseline first: its level-1 mode starts processes, which must
+    # not come from a process that has touched the GPU
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline("c2" if args.config == "c3" else args.config)
+
+    import numpy as np
+    import torch
+
+    import paper_2204_04678_amd as P
+    from inla_synth import THETA0, fd_stencil
+
+    if not os.path.exists(P.binding.LIB):
+        from paper_2204_04678_amd import _build
+        _build.build()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    model, theta, mds, workload = load_workload(P, args.config)
+    md = mds[0]
+    n_items = theta.shape[0]
+    r = measure(P, args.config, model, theta, mds, args.steps, args.warmup, args.steps)
+    value, step_s = r["value"], r["step_s"]
+    f_val, grad = r["f"], r["grad"]
+    if n_items == 1:
+        f_val, grad = f_val[0], grad[0]
+    elif n_items > 8:
+        f_val, grad = f_val[:8], grad[:8]
 
     extra = {}
     if not args.no_fd and args.config in ("c2", "c4"):
@@ -242,9 +361,29 @@ def main():
             "fd_grad_h1e-3": g_fd,
         }
 
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(md, theta[0].cpu().numpy())
+    if args.largest_steps > 0 and args.config != "c5":
+        # the largest block size: free this workload's device memory first
+        del model
+        P.release_workspace()
+        torch.cuda.empty_cache()
+        t_load = time.perf_counter()
+        m5, th5, mds5, wl5 = load_workload(P, "c5")
+        t_load = time.perf_counter() - t_load
+        r5 = measure(P, "c5", m5, th5, mds5, args.largest_steps, args.largest_warmup, 1)
+        extra["largest_block"] = {
+            "config": {"workload": wl5, "b": mds5[0].ns, "nt": mds5[0].nt, "a": mds5[0].nb,
+                       "n": mds5[0].n, "items": th5.shape[0]},
+            "steps": args.largest_steps, "warmup": args.largest_warmup,
+            "value": round(r5["value"], 4), "unit": "evals/s",
+            "ms_per_step": round(r5["step_s"] * 1e3, 3),
+            "alg_flops_per_step": r5["F_alg"],
+            "pct_fp64_peak_whole_step": round(100 * r5["F_alg"] / r5["step_s"]
+                                              / (PEAK_FP64_TFLOPS * 1e12), 3),
+            "status": r5["status"], "f": r5["f"],
+            "model_setup_s": round(t_load, 2),
+            "roofline": r5["roofline"]}
+        del m5
+        P.release_workspace()
 
     rec = {
         "metric": "f(theta)+grad f evaluations/s (BTA Cholesky + selected-inversion adjoint, FP64)",
@@ -259,12 +398,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded grid model; no dataset)",
-        "config": {"workload": workload, "b": b, "nt": nt, "a": a, "n": md.n, "items": n_items},
-        "pct_fp64_peak_whole_step": round(100 * F_alg / step_s / (PEAK_FP64_TFLOPS * 1e12), 3),
-        "alg_flops_per_step": F_alg,
+        "config": {"workload": workload, "b": md.ns, "nt": md.nt, "a": md.nb, "n": md.n,
+                   "items": n_items},
+        "build_id": P.build_id(),
+        "pct_fp64_peak_whole_step": round(100 * r["F_alg"] / step_s / (PEAK_FP64_TFLOPS * 1e12), 3),
+        "alg_flops_per_step": r["F_alg"],
         "f": f_val,
         "grad": grad,
-        "roofline": roofline,
+        "roofline": r["roofline"],
         "cpu_baseline": cpu,
         **extra,
     }
