@@ -121,7 +121,14 @@ typedef struct {
  *                      matrix of memory) are formed up front if that needs
  *                      no more admission waves (the results agree bitwise
  *                      with 64-wide tiles, to rounding with 128-wide ones).
- *   keep_sigma       : reserved, must be 0
+ *   keep_sigma       : 1 = also keep the selected inverse of Q_c: item i's
+ *                      Sigma blocks on the BTA pattern (D[t] full symmetric
+ *                      blocks, S[t] = block (t+1,t), R[t], T) are written to
+ *                      the caller's storage sigma_out[i] (a host array of
+ *                      n_items descriptors of device storage, each of the
+ *                      item's model shape; Sec. "Partial Inversion"); no
+ *                      graph is captured for such a call.  0 = not kept.
+ *   sigma_out        : see keep_sigma (ignored when keep_sigma = 0)
  *   tile             : 64 or 128 forces the tile of the b x b products;
  *                      0 = the autotuner's entry for this call signature if
  *                      autotune_cache is set, else a built-in rule
@@ -141,6 +148,7 @@ typedef struct {
   int32_t tile;
   int32_t reserved;
   const char *autotune_cache;
+  const inla_bta *sigma_out;
 } inla_opts;
 
 /*
@@ -245,6 +253,33 @@ inla_status inla_eval_f_grad(const inla_model *const *models, int32_t n_items,
                              const double *theta_dev, double *f_dev, double *grad_dev,
                              double *mu_or_null, double *var_or_null, int32_t *status_dev,
                              const inla_opts *opts, void *hip_stream);
+
+/*
+ * f now, its gradient later (the backward pass of an automatic-differentiation
+ * framework, or the one accepted point of a line search).  inla_eval_f_keep
+ * computes f (and mu) for the batch like inla_eval_f and, when the batch's two
+ * factors per item fit the HBM budget in one wave, keeps them in a device
+ * allocation owned by the returned state; inla_eval_grad_kept then runs only
+ * the selected inversions of the kept factors with their trace reductions
+ * (the selected-inverse blocks are recomputed from the stored factors,
+ * Sec. "Partial Inversion") and returns f, grad f, the status and optionally
+ * the marginal variances -- the same values, bit for bit, as inla_eval_f_grad
+ * under the same options.  When the factors do not fit (or recompute = 1 asks
+ * for shared storage) the state keeps only theta, and inla_eval_grad_kept runs
+ * the whole evaluation again (inla_eval_state_kept tells which).  The models
+ * must outlive the state; inla_eval_grad_kept may be called more than once;
+ * inla_eval_state_destroy waits for the state's last call and frees it.
+ * keep_sigma is not accepted here.
+ */
+typedef struct inla_eval_state inla_eval_state;
+inla_status inla_eval_f_keep(const inla_model *const *models, int32_t n_items,
+                             const double *theta_dev, double *f_dev, double *mu_or_null,
+                             int32_t *status_dev, const inla_opts *opts, void *hip_stream,
+                             inla_eval_state **state_out);
+inla_status inla_eval_grad_kept(inla_eval_state *state, double *f_dev, double *grad_dev,
+                                double *var_or_null, int32_t *status_dev, void *hip_stream);
+int32_t inla_eval_state_kept(const inla_eval_state *state);
+void inla_eval_state_destroy(inla_eval_state *state);
 
 /*
  * Instrumentation for benchmarks.  Between inla_profile_begin() and

@@ -7,6 +7,7 @@ this package only marshals arguments.
 from .binding import (  # noqa: F401
     Bta,
     BtaTensors,
+    EvalState,
     InlaError,
     InlaObjective,
     Model,

@@ -42,7 +42,7 @@ class ModelDesc(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_double), ("recompute", C.c_int32),
                 ("keep_sigma", C.c_int32), ("tile", C.c_int32), ("reserved", C.c_int32),
-                ("autotune_cache", C.c_char_p)]
+                ("autotune_cache", C.c_char_p), ("sigma_out", C.POINTER(Bta))]
 
 
 _LIB = None
@@ -65,6 +65,13 @@ _SIGS = {
     "inla_eval_f_grad": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.c_void_p,
                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.POINTER(Opts), C.c_void_p]),
+    "inla_eval_f_keep": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.POINTER(Opts), C.c_void_p,
+                                   C.POINTER(C.c_void_p)]),
+    "inla_eval_grad_kept": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p]),
+    "inla_eval_state_kept": (C.c_int32, [C.c_void_p]),
+    "inla_eval_state_destroy": (None, [C.c_void_p]),
     "inla_release_workspace": (None, []),
     "inla_profile_begin": (C.c_int, []),
     "inla_profile_end": (C.c_int, [C.POINTER(C.c_double), C.c_int32]),
@@ -280,13 +287,20 @@ def _models_array(models):
     return arr
 
 
-def _opts(budget=0.0, recompute=0, tile=0, autotune_cache=None):
+def _opts(budget=0.0, recompute=0, tile=0, autotune_cache=None, sigma=None):
     """inla_opts: HBM budget in bytes (0 = free memory minus a reserve);
     recompute 0 auto / 1 always / 2 never share one matrix's storage between
     Q_prior and Q_c; tile 0 (built-in rule or autotuner), 64 or 128;
-    autotune_cache: JSON file the autotuner reads and extends (None: off)."""
+    autotune_cache: JSON file the autotuner reads and extends (None: off);
+    sigma: list of BtaTensors, one per item, receiving Sigma of Q_c (keep_sigma)."""
     path = None if autotune_cache is None else os.fsencode(os.fspath(autotune_cache))
-    return Opts(float(budget), int(recompute), 0, int(tile), 0, path)
+    o = Opts(float(budget), int(recompute), 0, int(tile), 0, path, None)
+    if sigma is not None:
+        arr = (Bta * len(sigma))(*[x.struct() for x in sigma])
+        o.keep_sigma = 1
+        o.sigma_out = C.cast(arr, C.POINTER(Bta))
+        o._keep = arr   # keeps the descriptor array alive with the options
+    return o
 
 
 def eval_f(models, thetas, want_mu=False, want_var=False, budget=0.0, recompute=0, tile=0,
@@ -315,8 +329,10 @@ def eval_f(models, thetas, want_mu=False, want_var=False, budget=0.0, recompute=
 
 
 def eval_f_grad(models, thetas, want_mu=False, want_var=False, budget=0.0, recompute=0, tile=0,
-                autotune_cache=None):
-    """Batched f(theta) and its exact gradient.  Returns dict(f, grad, status, [mu], [var])."""
+                autotune_cache=None, sigma=None):
+    """Batched f(theta) and its exact gradient.  Returns dict(f, grad, status, [mu], [var]).
+    sigma: optional list of BtaTensors (one per item, the item's model shape)
+    that receive the selected inverse of Q_c (keep_sigma)."""
     if isinstance(models, Model):
         models = [models]
     th = thetas if torch.is_tensor(thetas) else _dev_f64(np.atleast_2d(thetas))
@@ -330,7 +346,7 @@ def eval_f_grad(models, thetas, want_mu=False, want_var=False, budget=0.0, recom
     status = torch.empty(k, dtype=torch.int32, device="cuda")
     mu = torch.empty(ntot, dtype=torch.float64, device="cuda") if want_mu else None
     var = torch.empty(ntot, dtype=torch.float64, device="cuda") if want_var else None
-    o = _opts(budget, recompute, tile, autotune_cache)
+    o = _opts(budget, recompute, tile, autotune_cache, sigma)
     _check(lib().inla_eval_f_grad(_models_array(models), k, _ptr(th), _ptr(f), _ptr(g), _ptr(mu),
                                   _ptr(var), _ptr(status), C.byref(o), _stream()))
     out = dict(f=f, grad=g, status=status)
@@ -341,18 +357,82 @@ def eval_f_grad(models, thetas, want_mu=False, want_var=False, budget=0.0, recom
     return out
 
 
+class EvalState:
+    """f now, the gradient later (inla_eval_f_keep / inla_eval_grad_kept):
+    the forward evaluation keeps the factors of the batch when they fit the
+    HBM budget, and grad() runs only the selected inversions from them (or the
+    whole evaluation again when they were not kept)."""
+
+    def __init__(self, models, thetas, want_mu=False, budget=0.0, recompute=0, tile=0,
+                 autotune_cache=None):
+        if isinstance(models, Model):
+            models = [models]
+        th = thetas if torch.is_tensor(thetas) else _dev_f64(np.atleast_2d(thetas))
+        th = th.contiguous()
+        k = th.shape[0]
+        if len(models) == 1 and k > 1:
+            models = models * k
+        self.models = list(models)   # the models must outlive the state
+        self.k = k
+        self.ntot = sum(m.n for m in models)
+        self.f = torch.empty(k, dtype=torch.float64, device="cuda")
+        self.status = torch.empty(k, dtype=torch.int32, device="cuda")
+        self.mu = torch.empty(self.ntot, dtype=torch.float64, device="cuda") if want_mu else None
+        o = _opts(budget, recompute, tile, autotune_cache)
+        h = C.c_void_p()
+        _check(lib().inla_eval_f_keep(_models_array(models), k, _ptr(th), _ptr(self.f),
+                                      _ptr(self.mu), _ptr(self.status), C.byref(o), _stream(),
+                                      C.byref(h)))
+        self.handle = h
+
+    @property
+    def kept(self) -> bool:
+        return bool(lib().inla_eval_state_kept(self.handle))
+
+    def grad(self, want_var=False):
+        """dict(f, grad, status, [var]) of the batch."""
+        f = torch.empty(self.k, dtype=torch.float64, device="cuda")
+        g = torch.empty(self.k, 4, dtype=torch.float64, device="cuda")
+        st = torch.empty(self.k, dtype=torch.int32, device="cuda")
+        var = torch.empty(self.ntot, dtype=torch.float64, device="cuda") if want_var else None
+        _check(lib().inla_eval_grad_kept(self.handle, _ptr(f), _ptr(g), _ptr(var), _ptr(st),
+                                         _stream()))
+        out = dict(f=f, grad=g, status=st)
+        if want_var:
+            out["var"] = var
+        return out
+
+    def close(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _LIB is not None:
+            _LIB.inla_eval_state_destroy(h)
+        self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
 class InlaObjective(torch.autograd.Function):
     """f(theta) with the exact gradient from the selected-inversion adjoint.
 
     theta: (k, 4) float64 CUDA tensor; returns f (k,).  When theta requires a
     gradient the forward pass runs inla_eval_f_grad once and keeps grad f for
-    the backward pass; otherwise it runs inla_eval_f.
+    the backward pass (opts defer_grad=False, the default), or runs f only and
+    keeps the factors, and the backward pass recomputes the selected inverse
+    from them (defer_grad=True: inla_eval_f_keep / inla_eval_grad_kept; the
+    same gradient bit for bit).  Without a gradient it runs inla_eval_f.
     """
 
     @staticmethod
     def forward(ctx, theta, models, opts):
         th = theta.detach().contiguous()
+        opts = dict(opts)
+        defer = opts.pop("defer_grad", False)
+        ctx.state = None
         if ctx.needs_input_grad[0]:
+            if defer:
+                ctx.state = EvalState(models, th, **opts)
+                return ctx.state.f
             out = eval_f_grad(models, th, **opts)
             ctx.save_for_backward(out["grad"])
         else:
@@ -361,12 +441,18 @@ class InlaObjective(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, gout):
-        (g,) = ctx.saved_tensors
+        if ctx.state is not None:
+            g = ctx.state.grad()["grad"]
+            ctx.state.close()
+            ctx.state = None
+        else:
+            (g,) = ctx.saved_tensors
         return gout[:, None] * g, None, None
 
 
 def objective(theta, models, **opts):
-    """f(theta) as a differentiable function of theta (k x 4); opts as eval_f."""
+    """f(theta) as a differentiable function of theta (k x 4); opts as eval_f,
+    plus defer_grad (see InlaObjective)."""
     return InlaObjective.apply(theta, models, opts)
 
 

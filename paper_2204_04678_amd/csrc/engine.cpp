@@ -1084,15 +1084,22 @@ inla_status copy_outputs(const EvalGraph &G, int n, long long ntot, double *f_de
   return INLA_OK;
 }
 
-// One batched evaluation with a fixed tile choice.  `seq_mode`: 2 never,
-// 1 always, 0 when the two-matrix layout needs more admission waves than the
-// one-matrix layout.
-inla_status eval_run(const inla_model *const *models, int32_t n_items, const double *theta_dev,
-                     double *f_dev, double *grad_dev, double *mu_out, double *var_out,
-                     int32_t *status_dev, double budget, int seq_mode, bool allow_graph,
-                     hipStream_t s) {
-  const bool grad = grad_dev != nullptr;
-  const bool need_selinv = grad || var_out != nullptr;
+// Layout choices of one batched evaluation and the bytes each item needs.
+struct EvalPlan {
+  bool grad = false, need_selinv = false;
+  bool seq = false, split = false, vb = false;
+  int waves = 0;
+  std::vector<size_t> bytes;   // per item
+  double all = 0.0;            // summed over the items
+};
+
+// HBM admission: the layout with the fewest waves whose storage fits the
+// budget.  `seq_mode`: 2 never, 1 always, 0 when the two-matrix layout needs
+// more admission waves than the one-matrix layout.
+inla_status plan_eval(const inla_model *const *models, int32_t n_items, bool grad, bool need_selinv,
+                      double budget, int seq_mode, EvalPlan &P) {
+  P.grad = grad;
+  P.need_selinv = need_selinv;
   // split-k scratch when the whole call has few 128-wide tiles per launch
   long long nb2 = 0;
   for (int i = 0; i < n_items; ++i) nb2 += 2LL * nbig(models[i]->host.b) * nbig(models[i]->host.b);
@@ -1102,7 +1109,6 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
   long long nv = 0;
   for (int i = 0; i < n_items; ++i) nv += 2LL * ntile(models[i]->host.b) * ntile(models[i]->host.b);
   const bool vb_wanted = need_selinv && nv < kVBatchTiles && si_batch_allowed();
-  // HBM admission: split the items into waves whose storage fits the budget
   auto waves_for = [&](bool seq, bool split, bool vb, std::vector<size_t> &bytes,
                        double &all) -> int {
     bytes.assign(n_items, 0);
@@ -1122,45 +1128,319 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
     return waves;
   };
   // layouts in order of preference; the first with the fewest waves wins
-  struct Plan { bool seq, split, vb; };
-  std::vector<Plan> plans;
+  struct Cand { bool seq, split, vb; };
+  std::vector<Cand> cands;
   for (int sq = 0; sq < 2; ++sq) {
     const bool seq_c = sq == 1;
     if ((seq_mode == 1 && !seq_c) || (seq_mode == 2 && seq_c)) continue;
     for (int v = 0; v < 2; ++v) {
       const bool vb_c = v == 0;
       if (vb_c && !vb_wanted) continue;
-      if (split_wanted) plans.push_back({seq_c, true, vb_c});
-      plans.push_back({seq_c, false, vb_c});
+      if (split_wanted) cands.push_back({seq_c, true, vb_c});
+      cands.push_back({seq_c, false, vb_c});
     }
   }
-  std::vector<size_t> bytes;
-  double all = 0.0;
-  bool seq = false, split = false, vb = false;
-  int waves = INT_MAX;
-  for (const Plan &pl : plans) {
+  P.waves = INT_MAX;
+  for (const Cand &c : cands) {
     std::vector<size_t> b1;
     double a1 = 0.0;
-    const int w1 = waves_for(pl.seq, pl.split, pl.vb, b1, a1);
-    if (w1 < waves) {
-      waves = w1;
-      seq = pl.seq;
-      split = pl.split;
-      vb = pl.vb;
-      bytes.swap(b1);
-      all = a1;
+    const int w1 = waves_for(c.seq, c.split, c.vb, b1, a1);
+    if (w1 < P.waves) {
+      P.waves = w1;
+      P.seq = c.seq;
+      P.split = c.split;
+      P.vb = c.vb;
+      P.bytes.swap(b1);
+      P.all = a1;
     }
   }
-  if (waves == INT_MAX) {
-    const Plan pl = plans.back();   // the smallest layout
+  if (P.waves == INT_MAX) {
+    const Cand c = cands.back();   // the smallest layout
     for (int i = 0; i < n_items; ++i) {
-      const size_t need = theta_item_bytes(models[i]->host, need_selinv, pl.seq, pl.split, pl.vb);
+      const size_t need = theta_item_bytes(models[i]->host, need_selinv, c.seq, c.split, c.vb);
       if ((double)need > budget)
         return fail(INLA_ERR_BUDGET, "item " + std::to_string(i) + " needs " + std::to_string(need) +
                                          " bytes, above the HBM budget");
     }
     return fail(INLA_ERR_BUDGET, "no layout fits the HBM budget");
   }
+  return INLA_OK;
+}
+
+// One admission wave of a batched evaluation: the descriptors of every item's
+// matrices, workspaces and outputs, laid out in one block of device memory
+// (the library arena, or a block of its own when the factors are kept for a
+// gradient asked for later).
+struct Wave {
+  int start = 0, k = 0;
+  bool grad = false, need_selinv = false, seq = false, split = false, vb = false;
+  bool io = false;       // theta and outputs in buffers of the wave (graph capture, kept factors)
+  bool two_combines = false;   // also an f-only combination (gradient asked for later)
+  bool want_var = false;
+  std::vector<ThetaItemBufs> tb;
+  std::vector<double *> Dbase;
+  Batch F, Sv, Si, Fc, Sic;
+  ItemDev *fdev = nullptr, *sdev = nullptr, *vdev = nullptr;
+  double **xs = nullptr, **tmps = nullptr, *logdet = nullptr;
+  int *info = nullptr;
+  TermItem *tdev = nullptr;
+  CombineItem *cdev = nullptr;     // f, and the gradient when grad
+  CombineItem *cdev_f = nullptr;   // f only (two_combines)
+  EvalGraph G;                     // theta and outputs when io
+  long long ntot = 0;              // length of the wave's mu / var outputs
+};
+
+// Adds the wave's device buffers to L (the pointers are set once L is placed).
+void wave_layout(Wave &W, const inla_model *const *models, bool mu_in_caller, Layout &L) {
+  const int k = W.k;
+  W.tb.assign(k, ThetaItemBufs());
+  W.Dbase.assign(2 * k, nullptr);
+  W.ntot = 0;
+  for (int q = 0; q < k; ++q) W.ntot += models[W.start + q]->n;
+  if (W.io) {
+    L.add(&W.G.th, (size_t)4 * k);
+    L.add(&W.G.f, (size_t)k);
+    L.add(&W.G.g, (size_t)4 * k);
+    L.add(&W.G.st, (size_t)k);
+    L.add(&W.G.mu_buf, (size_t)W.ntot);
+    if (W.want_var) L.add(&W.G.var_buf, (size_t)W.ntot);
+  }
+  for (int q = 0; q < k; ++q) {
+    const ModelDev &h = models[W.start + q]->host;
+    for (int w = 0; w < 2; ++w) {
+      ItemDev &it = w ? W.tb[q].C : W.tb[q].P;
+      std::memset(&it, 0, sizeof(it));
+      it.b = h.b; it.nt = h.nt; it.a = h.a; it.nP = ntile(h.b);
+      it.which = w;
+      it.model = models[W.start + q]->dev;
+      if (w == 1 && W.seq) {
+        // Q_c reuses the storage and workspaces of Q_prior (aliased in
+        // wave_bind, once the memory is placed); only its trace partials are its own
+        if (W.grad) L.add(&it.trpart, ((size_t)h.nt + 1) * kTraceBlocks * 4);
+        continue;
+      }
+      L.add(&W.Dbase[2 * q + w], bta_doubles(h.b, h.nt, h.a));
+      layout_factor_ws(L, it);
+      if (W.split) L.add(&it.P, (size_t)kSplitK * h.b * h.b);
+      if (W.need_selinv) {
+        layout_selinv_ws(L, it);
+        if (W.vb) {
+          if (h.nt > 1) L.add(&it.V, (size_t)(h.nt - 1) * h.b * h.b);
+          if (h.a > 0) L.add(&it.U, (size_t)h.nt * h.a * h.b);
+          L.add(&it.G, (size_t)h.nt * h.b * h.b);
+        }
+        if (W.grad) L.add(&it.trpart, ((size_t)h.nt + 1) * kTraceBlocks * 4);
+      }
+    }
+    if (!mu_in_caller && !W.io) L.add(&W.tb[q].x, (size_t)h.n);
+    L.add(&W.tb[q].tmp, (size_t)std::max(h.b, std::max(h.a, 1)));
+    L.add(&W.tb[q].term, (size_t)kTermBlocks * 4);
+  }
+  L.add(&W.fdev, 2 * k);
+  L.add(&W.sdev, k);
+  L.add(&W.vdev, 2 * k);
+  L.add(&W.xs, k);
+  L.add(&W.tmps, k);
+  L.add(&W.logdet, 2 * k);
+  L.add(&W.info, 2 * k);
+  L.add(&W.tdev, k);
+  L.add(&W.cdev, k);
+  if (W.two_combines) L.add(&W.cdev_f, k);
+}
+
+// Finishes the descriptors once the wave's memory is placed and uploads them.
+// Without io the wave reads theta from theta_w and writes f, grad, status, mu
+// and var straight to the caller's buffers (already offset to the wave).
+// sigma (n = k, or null): caller storage that receives Sigma of Q_c.
+inla_status wave_bind(Wave &W, const inla_model *const *models, const double *theta_w,
+                      double *f_w, double *g_w, int *st_w, double *mu_w, double *var_w,
+                      const inla_bta *sigma, hipStream_t s) {
+  const int k = W.k;
+  if (W.seq) {
+    for (int q = 0; q < k; ++q) {
+      const ItemDev &pv = W.tb[q].P;
+      ItemDev &cv = W.tb[q].C;
+      cv.W1 = pv.W1; cv.W2 = pv.W2; cv.W3 = pv.W3; cv.Mp = pv.Mp; cv.P = pv.P;
+      cv.ldpart = pv.ldpart; cv.info = pv.info;
+      cv.SD = pv.SD; cv.SR = pv.SR; cv.ST = pv.ST; cv.V = pv.V; cv.U = pv.U; cv.G = pv.G;
+      W.Dbase[2 * q + 1] = W.Dbase[2 * q];
+    }
+  }
+  const double *th = W.io ? W.G.th : theta_w;
+  double *fo = W.io ? W.G.f : f_w;
+  double *go = W.io ? W.G.g : g_w;
+  int *so = W.io ? W.G.st : st_w;
+  double *muo = W.io ? W.G.mu_buf : mu_w;
+  double *vo = W.io ? W.G.var_buf : var_w;
+  W.F = Batch(); W.Sv = Batch(); W.Si = Batch(); W.Fc = Batch(); W.Sic = Batch();
+  std::vector<double *> hx(k), ht(k);
+  std::vector<TermItem> thv(k);
+  std::vector<CombineItem> ch(k), chf(k);
+  long long off = 0;
+  for (int q = 0; q < k; ++q) {
+    const int i = W.start + q;
+    const ModelDev &h = models[i]->host;
+    const size_t bb = (size_t)h.b * h.b;
+    for (int w = 0; w < 2; ++w) {
+      ItemDev &it = w ? W.tb[q].C : W.tb[q].P;
+      double *base = W.Dbase[2 * q + w];
+      it.D = base;
+      it.S = h.nt > 1 ? base + (size_t)h.nt * bb : nullptr;
+      it.R = h.a > 0 ? base + (size_t)(2 * h.nt - 1) * bb : nullptr;
+      it.T = h.a > 0 ? it.R + (size_t)h.nt * h.a * h.b : nullptr;
+      it.theta = th + 4 * q;
+      if (W.need_selinv) it.SS = it.W1;
+      if (w == 1 && vo) it.diag = vo + off;
+      if (w == 1 && sigma) {
+        // Sigma of Q_c into the caller's storage, every step's blocks kept
+        const inla_bta &sg = sigma[q];
+        it.SD = sg.D; it.sd_stride = (long long)bb;
+        it.SS = sg.S; it.ss_stride = (long long)bb;
+        it.SR = sg.R; it.sr_stride = (long long)h.a * h.b;
+        it.ST = sg.T;
+      }
+    }
+    if (muo) W.tb[q].x = muo + off;
+    hx[q] = W.tb[q].x;
+    ht[q] = W.tb[q].tmp;
+    if (W.seq) {
+      W.F.host.push_back(W.tb[q].P);
+      W.Fc.host.push_back(W.tb[q].C);
+      if (W.grad) W.Si.host.push_back(W.tb[q].P);
+      if (W.need_selinv) W.Sic.host.push_back(W.tb[q].C);
+    } else {
+      W.F.host.push_back(W.tb[q].P);
+      W.F.host.push_back(W.tb[q].C);
+      if (W.grad) W.Si.host.push_back(W.tb[q].P);
+      if (W.need_selinv) W.Si.host.push_back(W.tb[q].C);
+    }
+    W.Sv.host.push_back(W.tb[q].C);
+    thv[q] = TermItem{models[i]->dev, th + 4 * q, W.tb[q].x, W.tb[q].term};
+    CombineItem c;
+    std::memset(&c, 0, sizeof(c));
+    c.model = models[i]->dev;
+    c.theta = th + 4 * q;
+    c.term_part = W.tb[q].term;
+    c.mu = W.tb[q].x;
+    c.logdet = W.logdet + 2 * q;
+    c.info = W.info + 2 * q;
+    c.f = fo + q;
+    c.status = so ? so + q : nullptr;
+    chf[q] = c;
+    c.trp = W.grad ? W.tb[q].P.trpart : nullptr;
+    c.trc = W.grad ? W.tb[q].C.trpart : nullptr;
+    c.grad = (W.grad && go) ? go + 4 * q : nullptr;
+    ch[q] = c;
+    off += h.n;
+  }
+  // every descriptor must point into placed memory before anything is launched
+  for (int q = 0; q < k; ++q)
+    for (const ItemDev *it : {&W.tb[q].P, &W.tb[q].C}) {
+      const bool ok = it->D && it->W1 && it->W2 && it->W3 && it->Mp && it->ldpart && it->info &&
+                      (!W.need_selinv || (it->SD && (it->a == 0 || (it->SR && it->ST)))) &&
+                      (!W.grad || it->trpart) && W.tb[q].x && W.tb[q].tmp && W.tb[q].term;
+      if (!ok) return fail(INLA_ERR_STATE, "internal: workspace of item " +
+                                               std::to_string(W.start + q) + " not placed");
+    }
+  // descriptor arrays: the sequential layout splits fdev / vdev in halves
+  W.F.dev = W.fdev; W.Sv.dev = W.sdev; W.Si.dev = W.vdev;
+  W.Fc.dev = W.fdev + k; W.Sic.dev = W.vdev + k;
+  W.F.finalize(); W.Sv.finalize(); W.Si.finalize();
+  if (W.seq) { W.Fc.finalize(); W.Sic.finalize(); }
+  W.Si.vb = W.vb;
+  W.Sic.vb = W.vb;
+  ST_TRY(upload(W.fdev, W.F.host, s));
+  if (W.seq) ST_TRY(upload(W.Fc.dev, W.Fc.host, s));
+  ST_TRY(upload(W.sdev, W.Sv.host, s));
+  if (W.need_selinv && !W.Si.host.empty()) ST_TRY(upload(W.vdev, W.Si.host, s));
+  if (W.seq && W.need_selinv) ST_TRY(upload(W.Sic.dev, W.Sic.host, s));
+  ST_TRY(upload(W.xs, hx, s));
+  ST_TRY(upload(W.tmps, ht, s));
+  ST_TRY(upload(W.tdev, thv, s));
+  ST_TRY(upload(W.cdev, ch, s));
+  if (W.two_combines) ST_TRY(upload(W.cdev_f, chf, s));
+  return INLA_OK;
+}
+
+inla_status wave_assemble(Wave &W, const inla_model *const *models, int w, hipStream_t ls) {
+  for (int q = 0; q < W.k; ++q) {
+    const int i = W.start + q;
+    const ModelDev &h = models[i]->host;
+    ItemDev &it = w ? W.tb[q].C : W.tb[q].P;
+    {
+      ProfScope ps(PS_ASSEMBLE, 0.0, ls);
+      HIP_TRY(launch_assemble(models[i]->dev, h.b, h.nt, h.a, it.theta, w, it.D, it.S, it.R, it.T,
+                              w ? W.tb[q].x : nullptr, ls));
+    }
+    HIP_TRY(launch_fill_int(it.info, 1, kInfoNone, ls));
+  }
+  return INLA_OK;
+}
+
+// The wave's launches.  defer_grad: the two-matrix layout runs everything but
+// the selected inversions, and combines f only (wave_gradient runs the rest).
+inla_status wave_forward(Wave &W, const inla_model *const *models, bool defer_grad, hipStream_t ls) {
+  const int k = W.k;
+  if (!W.seq) {
+    // assemble Q_prior, Q_c and b = tau_y A^T y (into x, solved in place)
+    ST_TRY(wave_assemble(W, models, 0, ls));
+    ST_TRY(wave_assemble(W, models, 1, ls));
+    ST_TRY(run_factor(W.F, ls));
+    HIP_TRY(launch_logdet_finish(W.fdev, 2 * k, W.logdet, W.info, ls));
+    if (W.need_selinv && !defer_grad) {
+      // the mode solve (and its terms) beside the selected inversion: both
+      // only read the factor, and they write disjoint buffers
+      HIP_TRY(hipEventRecord(g_solve_fork, ls));
+      HIP_TRY(hipStreamWaitEvent(g_solve, g_solve_fork, 0));
+      ST_TRY(run_solve(W.Sv, W.xs, W.tmps, g_solve));
+      HIP_TRY(launch_terms(W.tdev, k, g_solve));
+      HIP_TRY(hipEventRecord(g_solve_join, g_solve));
+      ST_TRY(run_selinv(W.Si, true, ls));
+      HIP_TRY(hipStreamWaitEvent(ls, g_solve_join, 0));
+    } else {
+      ST_TRY(run_solve(W.Sv, W.xs, W.tmps, ls));
+      HIP_TRY(launch_terms(W.tdev, k, ls));
+    }
+  } else {
+    if (defer_grad) return fail(INLA_ERR_STATE, "internal: shared storage cannot keep both factors");
+    // Q_prior first (factor, log-determinant, gradient traces), then Q_c
+    // in the same storage
+    ST_TRY(wave_assemble(W, models, 0, ls));
+    ST_TRY(run_factor(W.F, ls));
+    HIP_TRY(launch_logdet_finish(W.fdev, k, W.logdet, W.info, ls, 2));
+    if (W.grad) ST_TRY(run_selinv(W.Si, true, ls));
+    ST_TRY(wave_assemble(W, models, 1, ls));
+    ST_TRY(run_factor(W.Fc, ls));
+    HIP_TRY(launch_logdet_finish(W.Fc.dev, k, W.logdet + 1, W.info + 1, ls, 2));
+    ST_TRY(run_solve(W.Sv, W.xs, W.tmps, ls));
+    HIP_TRY(launch_terms(W.tdev, k, ls));
+    if (W.need_selinv) ST_TRY(run_selinv(W.Sic, true, ls));
+  }
+  HIP_TRY(launch_combine(defer_grad ? W.cdev_f : W.cdev, k, ls));
+  return INLA_OK;
+}
+
+// The deferred half of a two-matrix wave: both selected inversions with their
+// traces, then f and the gradient combined (the same launches, in the same
+// order per matrix, as the one-pass evaluation).
+inla_status wave_gradient(Wave &W, hipStream_t ls) {
+  ST_TRY(run_selinv(W.Si, true, ls));
+  HIP_TRY(launch_combine(W.cdev, W.k, ls));
+  return INLA_OK;
+}
+
+// One batched evaluation with a fixed tile choice.  `seq_mode`: 2 never,
+// 1 always, 0 when the two-matrix layout needs more admission waves than the
+// one-matrix layout.  sigma (n_items, or null): Sigma of each item's Q_c into
+// caller storage (then nothing is captured in a graph).
+inla_status eval_run(const inla_model *const *models, int32_t n_items, const double *theta_dev,
+                     double *f_dev, double *grad_dev, double *mu_out, double *var_out,
+                     int32_t *status_dev, const inla_bta *sigma, double budget, int seq_mode,
+                     bool allow_graph, hipStream_t s) {
+  const bool grad = grad_dev != nullptr;
+  const bool need_selinv = grad || var_out != nullptr || sigma != nullptr;
+  EvalPlan plan;
+  ST_TRY(plan_eval(models, n_items, grad, need_selinv, budget, seq_mode, plan));
   // per-item output offsets into the concatenated mu / var buffers
   std::vector<long long> voff(n_items + 1, 0);
   for (int i = 0; i < n_items; ++i) voff[i + 1] = voff[i] + models[i]->n;
@@ -1171,7 +1451,8 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
   // replay a captured graph when the call matches it and nothing else has
   // laid out the workspace since
   // (events recorded during capture cannot be timed, so profiling runs eagerly)
-  const bool graphable = allow_graph && graphs_enabled() && !g_prof.on && all <= budget;
+  const bool graphable = allow_graph && graphs_enabled() && !g_prof.on && plan.all <= budget &&
+                         sigma == nullptr;
   GraphKey key;
   for (int i = 0; i < n_items; ++i) {
     const ModelDev &h = models[i]->host;
@@ -1180,7 +1461,7 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
       key.shapes.push_back(v);
   }
   key.grad = grad; key.var = var_out != nullptr; key.mu = mu_out != nullptr; key.prof = g_prof.on;
-  key.seq = seq; key.split = split; key.vb = vb;
+  key.seq = plan.seq; key.split = plan.split; key.vb = plan.vb;
   key.tile = tile; key.variant = variant; key.small = small; key.step = step;
   key.gen = g_arena.gen; key.base = g_arena.base; key.ntot = ntot;
   if (graphable && g_graph.valid && same_signature(g_graph.key, key)) {
@@ -1196,223 +1477,30 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
   while (start < n_items) {
     int end = start;
     double acc = 0.0;
-    while (end < n_items && acc + (double)bytes[end] <= budget) acc += (double)bytes[end++];
-    const int k = end - start;
-    std::vector<ThetaItemBufs> tb(k);
+    while (end < n_items && acc + (double)plan.bytes[end] <= budget) acc += (double)plan.bytes[end++];
+    Wave W;
+    W.start = start;
+    W.k = end - start;
+    W.grad = grad; W.need_selinv = need_selinv;
+    W.seq = plan.seq; W.split = plan.split; W.vb = plan.vb;
+    W.io = graphable;
+    W.want_var = var_out != nullptr;
     Layout L;
-    std::vector<double *> Dbase(2 * k);
-    EvalGraph G;
-    if (graphable) {
-      L.add(&G.th, (size_t)4 * k);
-      L.add(&G.f, (size_t)k);
-      L.add(&G.g, (size_t)4 * k);
-      L.add(&G.st, (size_t)k);
-      L.add(&G.mu_buf, (size_t)ntot);
-      if (var_out) L.add(&G.var_buf, (size_t)ntot);
-    }
-    for (int q = 0; q < k; ++q) {
-      const ModelDev &h = models[start + q]->host;
-      for (int w = 0; w < 2; ++w) {
-        ItemDev &it = w ? tb[q].C : tb[q].P;
-        std::memset(&it, 0, sizeof(it));
-        it.b = h.b; it.nt = h.nt; it.a = h.a; it.nP = ntile(h.b);
-        it.which = w;
-        it.model = models[start + q]->dev;
-        if (w == 1 && seq) {
-          // Q_c reuses the storage and workspaces of Q_prior (aliased below,
-          // once the arena has placed them); only its trace partials are its own
-          if (grad) L.add(&it.trpart, ((size_t)h.nt + 1) * kTraceBlocks * 4);
-          continue;
-        }
-        L.add(&Dbase[2 * q + w], bta_doubles(h.b, h.nt, h.a));
-        layout_factor_ws(L, it);
-        if (split) L.add(&it.P, (size_t)kSplitK * h.b * h.b);
-        if (need_selinv) {
-          layout_selinv_ws(L, it);
-          if (vb) {
-            if (h.nt > 1) L.add(&it.V, (size_t)(h.nt - 1) * h.b * h.b);
-            if (h.a > 0) L.add(&it.U, (size_t)h.nt * h.a * h.b);
-            L.add(&it.G, (size_t)h.nt * h.b * h.b);
-          }
-          if (grad) L.add(&it.trpart, ((size_t)h.nt + 1) * kTraceBlocks * 4);
-        }
-      }
-      if (!mu_out && !graphable) L.add(&tb[q].x, (size_t)h.n);
-      L.add(&tb[q].tmp, (size_t)std::max(h.b, std::max(h.a, 1)));
-      L.add(&tb[q].term, (size_t)kTermBlocks * 4);
-    }
-    ItemDev *fdev, *sdev, *vdev;
-    double **xs, **tmps, *logdet;
-    int *info;
-    TermItem *tdev;
-    CombineItem *cdev;
-    L.add(&fdev, 2 * k);
-    L.add(&sdev, k);
-    L.add(&vdev, 2 * k);
-    L.add(&xs, k);
-    L.add(&tmps, k);
-    L.add(&logdet, 2 * k);
-    L.add(&info, 2 * k);
-    L.add(&tdev, k);
-    L.add(&cdev, k);
+    wave_layout(W, models, mu_out != nullptr, L);
     ST_TRY(arena_bind(L, s));
-    if (seq) {
-      for (int q = 0; q < k; ++q) {
-        const ItemDev &pv = tb[q].P;
-        ItemDev &cv = tb[q].C;
-        cv.W1 = pv.W1; cv.W2 = pv.W2; cv.W3 = pv.W3; cv.Mp = pv.Mp; cv.P = pv.P;
-        cv.ldpart = pv.ldpart; cv.info = pv.info;
-        cv.SD = pv.SD; cv.SR = pv.SR; cv.ST = pv.ST; cv.V = pv.V; cv.U = pv.U; cv.G = pv.G;
-        Dbase[2 * q + 1] = Dbase[2 * q];
-      }
-    }
-    // where this wave reads theta and writes its outputs
-    const double *th = graphable ? G.th : theta_dev + 4 * start;
-    double *fo = graphable ? G.f : f_dev + start;
-    double *go = graphable ? G.g : (grad ? grad_dev + 4 * start : nullptr);
-    int *so = graphable ? G.st : (status_dev ? status_dev + start : nullptr);
-    double *muo = graphable ? G.mu_buf : (mu_out ? mu_out + voff[start] : nullptr);
-    double *vo = graphable ? G.var_buf : (var_out ? var_out + voff[start] : nullptr);
-    // carve BTA storage and finish descriptors.  Two-matrix layout: one
-    // factor batch over (P_0, C_0, P_1, ...), one selinv batch likewise.
-    // Sequential layout: a P batch and a C batch of each kind.
-    Batch F, Sv, Si, Fc, Sic;
-    std::vector<double *> hx(k), ht(k);
-    std::vector<TermItem> thv(k);
-    std::vector<CombineItem> ch(k);
-    for (int q = 0; q < k; ++q) {
-      const int i = start + q;
-      const ModelDev &h = models[i]->host;
-      const size_t bb = (size_t)h.b * h.b;
-      const long long off = voff[i] - voff[start];
-      for (int w = 0; w < 2; ++w) {
-        ItemDev &it = w ? tb[q].C : tb[q].P;
-        double *base = Dbase[2 * q + w];
-        it.D = base;
-        it.S = h.nt > 1 ? base + (size_t)h.nt * bb : nullptr;
-        it.R = h.a > 0 ? base + (size_t)(2 * h.nt - 1) * bb : nullptr;
-        it.T = h.a > 0 ? it.R + (size_t)h.nt * h.a * h.b : nullptr;
-        it.theta = th + 4 * q;
-        if (need_selinv) it.SS = it.W1;
-        if (w == 1 && vo) it.diag = vo + off;
-      }
-      if (muo) tb[q].x = muo + off;
-      hx[q] = tb[q].x;
-      ht[q] = tb[q].tmp;
-      if (seq) {
-        F.host.push_back(tb[q].P);
-        Fc.host.push_back(tb[q].C);
-        if (grad) Si.host.push_back(tb[q].P);
-        if (need_selinv) Sic.host.push_back(tb[q].C);
-      } else {
-        F.host.push_back(tb[q].P);
-        F.host.push_back(tb[q].C);
-        if (grad) Si.host.push_back(tb[q].P);
-        if (need_selinv) Si.host.push_back(tb[q].C);
-      }
-      Sv.host.push_back(tb[q].C);
-      thv[q] = TermItem{models[i]->dev, th + 4 * q, tb[q].x, tb[q].term};
-      CombineItem c;
-      std::memset(&c, 0, sizeof(c));
-      c.model = models[i]->dev;
-      c.theta = th + 4 * q;
-      c.term_part = tb[q].term;
-      c.mu = tb[q].x;
-      c.logdet = logdet + 2 * q;
-      c.trp = grad ? tb[q].P.trpart : nullptr;
-      c.trc = grad ? tb[q].C.trpart : nullptr;
-      c.info = info + 2 * q;
-      c.f = fo + q;
-      c.grad = go ? go + 4 * q : nullptr;
-      c.status = so ? so + q : nullptr;
-      ch[q] = c;
-    }
-    // every descriptor must point into the arena before anything is launched
-    for (int q = 0; q < k; ++q)
-      for (const ItemDev *it : {&tb[q].P, &tb[q].C}) {
-        const bool ok = it->D && it->W1 && it->W2 && it->W3 && it->Mp && it->ldpart && it->info &&
-                        (!need_selinv || (it->SD && it->SR && it->ST)) &&
-                        (!grad || it->trpart) && tb[q].x && tb[q].tmp && tb[q].term;
-        if (!ok) return fail(INLA_ERR_STATE, "internal: workspace of item " +
-                                                 std::to_string(start + q) + " not placed");
-      }
-    // descriptor arrays: the sequential layout splits fdev / vdev in halves
-    F.dev = fdev; Sv.dev = sdev; Si.dev = vdev;
-    Fc.dev = fdev + k; Sic.dev = vdev + k;
-    F.finalize(); Sv.finalize(); Si.finalize();
-    if (seq) { Fc.finalize(); Sic.finalize(); }
-    Si.vb = vb;
-    Sic.vb = vb;
-    ST_TRY(upload(fdev, F.host, s));
-    if (seq) ST_TRY(upload(Fc.dev, Fc.host, s));
-    ST_TRY(upload(sdev, Sv.host, s));
-    if (need_selinv && !Si.host.empty()) ST_TRY(upload(vdev, Si.host, s));
-    if (seq && need_selinv) ST_TRY(upload(Sic.dev, Sic.host, s));
-    ST_TRY(upload(xs, hx, s));
-    ST_TRY(upload(tmps, ht, s));
-    ST_TRY(upload(tdev, thv, s));
-    ST_TRY(upload(cdev, ch, s));
+    ST_TRY(wave_bind(W, models, theta_dev + 4 * start, f_dev + start,
+                     grad ? grad_dev + 4 * start : nullptr, status_dev ? status_dev + start : nullptr,
+                     mu_out ? mu_out + voff[start] : nullptr, var_out ? var_out + voff[start] : nullptr,
+                     sigma ? sigma + start : nullptr, s));
     if (graphable)
-      HIP_TRY(hipMemcpyAsync(G.th, theta_dev, (size_t)k * 32, hipMemcpyDeviceToDevice, s));
+      HIP_TRY(hipMemcpyAsync(W.G.th, theta_dev, (size_t)W.k * 32, hipMemcpyDeviceToDevice, s));
     hipStream_t ls = s;
     if (graphable) {
       ls = g_cap;
       HIP_TRY(hipStreamBeginCapture(ls, hipStreamCaptureModeThreadLocal));
     }
-    auto assemble = [&](int w) -> inla_status {
-      for (int q = 0; q < k; ++q) {
-        const int i = start + q;
-        const ModelDev &h = models[i]->host;
-        ItemDev &it = w ? tb[q].C : tb[q].P;
-        {
-          ProfScope ps(PS_ASSEMBLE, 0.0, ls);
-          HIP_TRY(launch_assemble(models[i]->dev, h.b, h.nt, h.a, th + 4 * q, w, it.D, it.S, it.R,
-                                  it.T, w ? tb[q].x : nullptr, ls));
-        }
-        HIP_TRY(launch_fill_int(it.info, 1, kInfoNone, ls));
-      }
-      return INLA_OK;
-    };
-    auto body = [&]() -> inla_status {
-      if (!seq) {
-        // assemble Q_prior, Q_c and b = tau_y A^T y (into x, solved in place)
-        ST_TRY(assemble(0));
-        ST_TRY(assemble(1));
-        ST_TRY(run_factor(F, ls));
-        HIP_TRY(launch_logdet_finish(fdev, 2 * k, logdet, info, ls));
-        if (need_selinv) {
-          // the mode solve (and its terms) beside the selected inversion: both
-          // only read the factor, and they write disjoint buffers
-          HIP_TRY(hipEventRecord(g_solve_fork, ls));
-          HIP_TRY(hipStreamWaitEvent(g_solve, g_solve_fork, 0));
-          ST_TRY(run_solve(Sv, xs, tmps, g_solve));
-          HIP_TRY(launch_terms(tdev, k, g_solve));
-          HIP_TRY(hipEventRecord(g_solve_join, g_solve));
-          ST_TRY(run_selinv(Si, true, ls));
-          HIP_TRY(hipStreamWaitEvent(ls, g_solve_join, 0));
-        } else {
-          ST_TRY(run_solve(Sv, xs, tmps, ls));
-          HIP_TRY(launch_terms(tdev, k, ls));
-        }
-      } else {
-        // Q_prior first (factor, log-determinant, gradient traces), then Q_c
-        // in the same storage
-        ST_TRY(assemble(0));
-        ST_TRY(run_factor(F, ls));
-        HIP_TRY(launch_logdet_finish(fdev, k, logdet, info, ls, 2));
-        if (grad) ST_TRY(run_selinv(Si, true, ls));
-        ST_TRY(assemble(1));
-        ST_TRY(run_factor(Fc, ls));
-        HIP_TRY(launch_logdet_finish(Fc.dev, k, logdet + 1, info + 1, ls, 2));
-        ST_TRY(run_solve(Sv, xs, tmps, ls));
-        HIP_TRY(launch_terms(tdev, k, ls));
-        if (need_selinv) ST_TRY(run_selinv(Sic, true, ls));
-      }
-      HIP_TRY(launch_combine(cdev, k, ls));
-      return INLA_OK;
-    };
     if (g_prof.on) ++g_prof.calls;
-    inla_status st = body();
+    inla_status st = wave_forward(W, models, false, ls);
     if (graphable) {
       hipGraph_t graph = nullptr;
       hipError_t e = hipStreamEndCapture(ls, &graph);
@@ -1425,6 +1513,7 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
       e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
       if (e != hipSuccess) return fail(INLA_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+      EvalGraph G = W.G;
       G.valid = true;
       G.exec = exec;
       G.key = key;
@@ -1510,6 +1599,28 @@ void tune_save(const std::string &path) {
   (void)rename(tmp.c_str(), path.c_str());
 }
 
+inla_status check_opts(const inla_opts *opts) {
+  if (!opts) return INLA_OK;
+  if (opts->keep_sigma != 0 && opts->keep_sigma != 1) return fail(INLA_ERR_ARG, "keep_sigma must be 0 or 1");
+  if (opts->tile != 0 && opts->tile != 64 && opts->tile != 128)
+    return fail(INLA_ERR_ARG, "tile must be 0, 64 or 128");
+  if (opts->recompute < 0 || opts->recompute > 2)
+    return fail(INLA_ERR_ARG, "recompute must be 0, 1 or 2");
+  return INLA_OK;
+}
+
+// The HBM budget of a call: the caller's, else free memory plus the arena
+// minus a 4 GiB reserve.
+inla_status call_budget(const inla_opts *opts, double *budget) {
+  *budget = opts ? opts->hbm_budget_bytes : 0.0;
+  if (!(*budget > 0.0)) {
+    size_t fr = 0, tot = 0;
+    HIP_TRY(hipMemGetInfo(&fr, &tot));
+    *budget = (double)fr + (double)g_arena.cap - 4.0 * (1ULL << 30);
+  }
+  return INLA_OK;
+}
+
 inla_status eval_impl(const inla_model *const *models, int32_t n_items, const double *theta_dev,
                       double *f_dev, double *grad_dev, double *mu_out, double *var_out,
                       int32_t *status_dev, const inla_opts *opts, hipStream_t s) {
@@ -1517,25 +1628,28 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
     return fail(INLA_ERR_ARG, "need models, n_items >= 1, theta and f");
   for (int i = 0; i < n_items; ++i)
     if (!models[i]) return fail(INLA_ERR_ARG, "NULL model in batch");
-  if (opts && opts->keep_sigma != 0) return fail(INLA_ERR_ARG, "keep_sigma is reserved (must be 0)");
-  if (opts && opts->tile != 0 && opts->tile != 64 && opts->tile != 128)
-    return fail(INLA_ERR_ARG, "tile must be 0, 64 or 128");
-  if (opts && (opts->recompute < 0 || opts->recompute > 2))
-    return fail(INLA_ERR_ARG, "recompute must be 0, 1 or 2");
-  ST_TRY(ensure_streams());
-  double budget = opts ? opts->hbm_budget_bytes : 0.0;
-  if (!(budget > 0.0)) {
-    size_t fr = 0, tot = 0;
-    HIP_TRY(hipMemGetInfo(&fr, &tot));
-    budget = (double)fr + (double)g_arena.cap - 4.0 * (1ULL << 30);
+  ST_TRY(check_opts(opts));
+  const inla_bta *sigma = nullptr;
+  if (opts && opts->keep_sigma == 1) {
+    if (!opts->sigma_out) return fail(INLA_ERR_ARG, "keep_sigma = 1 needs sigma_out");
+    for (int i = 0; i < n_items; ++i) {
+      ST_TRY(check_bta(&opts->sigma_out[i], "sigma_out"));
+      const ModelDev &h = models[i]->host;
+      if (opts->sigma_out[i].b != h.b || opts->sigma_out[i].nt != h.nt || opts->sigma_out[i].a != h.a)
+        return fail(INLA_ERR_ARG, "sigma_out[" + std::to_string(i) + "] shape does not match the model");
+    }
+    sigma = opts->sigma_out;
   }
+  ST_TRY(ensure_streams());
+  double budget = 0.0;
+  ST_TRY(call_budget(opts, &budget));
   const int seq_mode = opts ? opts->recompute : 0;
   auto run = [&](const TileChoice &c, bool allow_graph) -> inla_status {
     g_tile_pref = c.tile;
     set_big_variant(c.variant);
     set_small_variant(c.small);
     const inla_status st = eval_run(models, n_items, theta_dev, f_dev, grad_dev, mu_out, var_out,
-                                    status_dev, budget, seq_mode, allow_graph, s);
+                                    status_dev, sigma, budget, seq_mode, allow_graph, s);
     g_tile_pref = 0;
     set_big_variant(kDefaultBigVariant);
     set_small_variant(kDefaultSmallVariant);
@@ -1596,6 +1710,197 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
   return run(choice, true);
 }
 
+
+// Tile choice of a call: the caller's tile, else the autotuner's stored entry
+// for the call's signature, else the built-in rule (nothing is timed here).
+TileChoice stored_choice(const inla_model *const *models, int n, const inla_opts *opts, bool grad,
+                         bool var) {
+  TileChoice c;
+  if (opts && opts->tile != 0) {
+    c.tile = opts->tile;
+  } else if (opts && opts->autotune_cache && opts->autotune_cache[0]) {
+    tune_load(opts->autotune_cache);
+    auto it = g_tune.find(tune_key(models, n, grad, var));
+    if (it != g_tune.end()) c = it->second;
+  }
+  return c;
+}
+
+struct ChoiceScope {
+  explicit ChoiceScope(const TileChoice &c) {
+    g_tile_pref = c.tile;
+    set_big_variant(c.variant);
+    set_small_variant(c.small);
+  }
+  ~ChoiceScope() {
+    g_tile_pref = 0;
+    set_big_variant(kDefaultBigVariant);
+    set_small_variant(kDefaultSmallVariant);
+  }
+};
+
+}  // namespace
+
+// f now, its gradient later: the factors of a batch kept between the two.
+struct inla_eval_state {
+  std::vector<const inla_model *> models;
+  int n = 0;
+  bool kept = false;           // factors kept (else the gradient recomputes everything)
+  void *mem = nullptr;         // device block: the kept wave, or the theta copy
+  double *theta = nullptr;     // the theta batch (device copy)
+  Wave W;
+  TileChoice choice;
+  inla_opts opts{};
+  std::string cache;
+  int device = 0;
+  hipEvent_t done = nullptr;   // completion of the last call on the state
+};
+
+namespace {
+
+inla_status state_record(inla_eval_state *st, hipStream_t s) {
+  if (!st->done) HIP_TRY(hipEventCreateWithFlags(&st->done, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(st->done, s));
+  return INLA_OK;
+}
+
+inla_status eval_f_keep_impl(const inla_model *const *models, int32_t n_items,
+                             const double *theta_dev, double *f_dev, double *mu_out,
+                             int32_t *status_dev, const inla_opts *opts, hipStream_t s,
+                             inla_eval_state **out) {
+  if (!out) return fail(INLA_ERR_ARG, "state_out must be non-NULL");
+  *out = nullptr;
+  if (!models || n_items < 1 || !theta_dev || !f_dev)
+    return fail(INLA_ERR_ARG, "need models, n_items >= 1, theta and f");
+  for (int i = 0; i < n_items; ++i)
+    if (!models[i]) return fail(INLA_ERR_ARG, "NULL model in batch");
+  ST_TRY(check_opts(opts));
+  if (opts && opts->keep_sigma) return fail(INLA_ERR_ARG, "keep_sigma is for inla_eval_f_grad");
+  ST_TRY(ensure_streams());
+  double budget = 0.0;
+  ST_TRY(call_budget(opts, &budget));
+  auto *st = new inla_eval_state();
+  st->models.assign(models, models + n_items);
+  st->n = n_items;
+  if (opts) {
+    st->opts = *opts;
+    if (opts->autotune_cache) {
+      st->cache = opts->autotune_cache;
+      st->opts.autotune_cache = st->cache.c_str();
+    }
+    st->opts.sigma_out = nullptr;
+  }
+  HIP_TRY(hipGetDevice(&st->device));
+  st->choice = stored_choice(models, n_items, opts, true, false);
+  inla_status rc = INLA_OK;
+  {
+    ChoiceScope cs(st->choice);
+    // the gradient's layout, both matrices in storage of their own, one wave
+    EvalPlan plan;
+    if ((!opts || opts->recompute != 1) &&
+        plan_eval(models, n_items, true, true, budget, 2, plan) == INLA_OK && plan.waves == 1) {
+      Wave &W = st->W;
+      W.start = 0;
+      W.k = n_items;
+      W.grad = true; W.need_selinv = true;
+      W.seq = false; W.split = plan.split; W.vb = plan.vb;
+      W.io = true;
+      W.want_var = true;
+      W.two_combines = true;
+      Layout L;
+      wave_layout(W, models, false, L);
+      void *p = nullptr;
+      if (hipMalloc(&p, align_up(L.total)) == hipSuccess) {
+        st->mem = p;
+        size_t off = 0;
+        for (auto &r : L.reqs) {
+          *r.slot = static_cast<char *>(p) + off;
+          off += align_up(std::max<size_t>(r.bytes, 1));
+        }
+        st->kept = true;
+      } else {
+        (void)hipGetLastError();
+      }
+    }
+    g_last_error.clear();
+    if (st->kept) {
+      Wave &W = st->W;
+      st->theta = W.G.th;
+      rc = wave_bind(W, models, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, s);
+      if (rc == INLA_OK) {
+        const auto D2D = hipMemcpyDeviceToDevice;
+        hipError_t e = hipMemcpyAsync(W.G.th, theta_dev, (size_t)n_items * 32, D2D, s);
+        if (e != hipSuccess) rc = fail(INLA_ERR_HIP, std::string("theta copy: ") + hipGetErrorString(e));
+        if (rc == INLA_OK) {
+          if (g_prof.on) ++g_prof.calls;
+          rc = wave_forward(W, models, true, s);
+        }
+        if (rc == INLA_OK) {
+          e = hipMemcpyAsync(f_dev, W.G.f, (size_t)n_items * 8, D2D, s);
+          if (!e && status_dev) e = hipMemcpyAsync(status_dev, W.G.st, (size_t)n_items * 4, D2D, s);
+          if (!e && mu_out) e = hipMemcpyAsync(mu_out, W.G.mu_buf, (size_t)W.ntot * 8, D2D, s);
+          if (e != hipSuccess) rc = fail(INLA_ERR_HIP, std::string("output copy: ") + hipGetErrorString(e));
+        }
+      }
+    }
+  }
+  if (rc == INLA_OK && !st->kept) {
+    // not kept: f as usual now, everything again for the gradient
+    void *p = nullptr;
+    if (hipMalloc(&p, (size_t)n_items * 32) != hipSuccess) {
+      (void)hipGetLastError();
+      delete st;
+      return fail(INLA_ERR_NOMEM, "theta copy allocation failed");
+    }
+    st->mem = p;
+    st->theta = static_cast<double *>(p);
+    hipError_t e = hipMemcpyAsync(st->theta, theta_dev, (size_t)n_items * 32,
+                                  hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) rc = fail(INLA_ERR_HIP, std::string("theta copy: ") + hipGetErrorString(e));
+    if (rc == INLA_OK)
+      rc = eval_impl(models, n_items, theta_dev, f_dev, nullptr, mu_out, nullptr, status_dev, opts, s);
+  }
+  if (rc == INLA_OK) rc = state_record(st, s);
+  if (rc != INLA_OK) {
+    (void)hipDeviceSynchronize();
+    if (st->mem) (void)hipFree(st->mem);
+    delete st;
+    return rc;
+  }
+  *out = st;
+  return INLA_OK;
+}
+
+inla_status eval_grad_kept_impl(inla_eval_state *st, double *f_dev, double *grad_dev,
+                                double *var_out, int32_t *status_dev, hipStream_t s) {
+  if (!st) return fail(INLA_ERR_ARG, "state is NULL");
+  if (!f_dev || !grad_dev) return fail(INLA_ERR_ARG, "f_dev and grad_dev must be non-NULL");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != st->device) return fail(INLA_ERR_STATE, "state belongs to another device");
+  if (st->done) HIP_TRY(hipStreamWaitEvent(s, st->done, 0));
+  if (!st->kept) {
+    // the factors were not kept: the whole evaluation again
+    ST_TRY(eval_impl(st->models.data(), st->n, st->theta, f_dev, grad_dev, nullptr, var_out,
+                     status_dev, &st->opts, s));
+    return state_record(st, s);
+  }
+  ST_TRY(ensure_streams());
+  Wave &W = st->W;
+  {
+    ChoiceScope cs(st->choice);
+    if (g_prof.on) ++g_prof.calls;
+    ST_TRY(wave_gradient(W, s));
+  }
+  const auto D2D = hipMemcpyDeviceToDevice;
+  const int n = st->n;
+  HIP_TRY(hipMemcpyAsync(f_dev, W.G.f, (size_t)n * 8, D2D, s));
+  HIP_TRY(hipMemcpyAsync(grad_dev, W.G.g, (size_t)n * 32, D2D, s));
+  if (status_dev) HIP_TRY(hipMemcpyAsync(status_dev, W.G.st, (size_t)n * 4, D2D, s));
+  if (var_out) HIP_TRY(hipMemcpyAsync(var_out, W.G.var_buf, (size_t)W.ntot * 8, D2D, s));
+  return state_record(st, s);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1618,6 +1923,36 @@ inla_status inla_eval_f_grad(const inla_model *const *models, int32_t n_items,
   std::lock_guard<std::mutex> lk(g_mutex);
   return eval_impl(models, n_items, theta_dev, f_dev, grad_dev, mu_or_null, var_or_null,
                    status_dev, opts, static_cast<hipStream_t>(hip_stream));
+}
+
+inla_status inla_eval_f_keep(const inla_model *const *models, int32_t n_items,
+                             const double *theta_dev, double *f_dev, double *mu_or_null,
+                             int32_t *status_dev, const inla_opts *opts, void *hip_stream,
+                             inla_eval_state **state_out) {
+  g_last_error.clear();
+  std::lock_guard<std::mutex> lk(g_mutex);
+  return eval_f_keep_impl(models, n_items, theta_dev, f_dev, mu_or_null, status_dev, opts,
+                          static_cast<hipStream_t>(hip_stream), state_out);
+}
+
+inla_status inla_eval_grad_kept(inla_eval_state *state, double *f_dev, double *grad_dev,
+                                double *var_or_null, int32_t *status_dev, void *hip_stream) {
+  g_last_error.clear();
+  std::lock_guard<std::mutex> lk(g_mutex);
+  return eval_grad_kept_impl(state, f_dev, grad_dev, var_or_null, status_dev,
+                             static_cast<hipStream_t>(hip_stream));
+}
+
+int32_t inla_eval_state_kept(const inla_eval_state *state) { return state && state->kept ? 1 : 0; }
+
+void inla_eval_state_destroy(inla_eval_state *state) {
+  if (!state) return;
+  if (state->done) {
+    (void)hipEventSynchronize(state->done);
+    (void)hipEventDestroy(state->done);
+  }
+  if (state->mem) (void)hipFree(state->mem);
+  delete state;
 }
 
 inla_status inla_profile_begin(void) {

@@ -96,3 +96,23 @@ def test_build_id_ties_the_library_to_its_sources(libpath, monkeypatch):
     monkeypatch.setattr(binding, "source_hash", lambda: "0" * 16)
     with pytest.raises(RuntimeError, match="other sources"):
         binding.lib(libpath)
+
+
+def test_state_and_sigma_argument_errors(libpath):
+    """The kept-state calls and keep_sigma reject bad arguments on the host."""
+    L = binding.lib(libpath)
+    dummy = ctypes.c_void_p(64)
+    one = (ctypes.c_void_p * 1)(dummy.value)
+    o = binding.Opts()
+    o.keep_sigma = 2
+    assert L.inla_eval_f(one, 1, dummy, dummy, None, None, None, ctypes.byref(o), None) == -1
+    assert b"keep_sigma" in L.inla_last_error()
+    st = ctypes.c_void_p()
+    assert L.inla_eval_f_keep(one, 1, dummy, dummy, None, None, None, None, None) == -1
+    assert b"state_out" in L.inla_last_error()
+    assert L.inla_eval_f_keep(one, 0, dummy, dummy, None, None, None, None, ctypes.byref(st)) == -1
+    assert st.value is None
+    assert L.inla_eval_grad_kept(None, dummy, dummy, None, None, None) == -1
+    assert b"state is NULL" in L.inla_last_error()
+    assert L.inla_eval_state_kept(None) == 0
+    L.inla_eval_state_destroy(None)

@@ -548,3 +548,78 @@ def test_eval_status_not_positive_definite(P):
         else:
             assert rel(f[0], O.eval_f_dense(md1, THETA0)["f"]) < 1e-10
             assert rel(f[3], O.eval_f_dense(md2, THETA0)["f"]) < 1e-10
+
+
+@pytest.mark.parametrize("si_batch", ["0", "1"], ids=["si_stepwise", "si_every_step"])
+@pytest.mark.parametrize("width", [64, 128], ids=["tile64", "tile128"])
+def test_keep_sigma_stores_selected_inverse(P, monkeypatch, si_batch, width):
+    """keep_sigma: the selected inverse of each item's Q_c lands in caller
+    storage, block by block equal to the dense inverse (Sec. "Partial
+    Inversion"), and f / grad f are those of the call without it."""
+    print(f"keep_sigma width={width} si_batch={si_batch}", flush=True)
+    monkeypatch.setenv("INLA_SI_BATCH", si_batch)
+    mds = [make_model(9, 3, 2, 91), make_model(5, 1, 3, 92), make_model(6, 4, 0, 93)]
+    Ms = [P.Model.from_data(m) for m in mds]
+    th = np.array([[0.1, 0.8, 0.5, 2.0], [0.3, 1.1, 1.0, 3.0], [-0.2, 0.6, 0.2, 2.5]])
+    sig = [P.BtaTensors(M.b, M.nt, M.a) for M in Ms]
+    out = P.eval_f_grad(Ms, th, want_var=True, tile=width, sigma=sig)
+    ref = P.eval_f_grad(Ms, th, want_var=True, tile=width)
+    torch.cuda.synchronize()
+    for key in ("f", "grad", "var", "status"):
+        assert torch.equal(out[key], ref[key]), key
+    for i, (md, S) in enumerate(zip(mds, sig)):
+        _, Qc, _ = O.conditional_precision(md, th[i])
+        Sinv = np.linalg.inv(Qc.toarray())
+        for g, e, name in zip(S.to_blocks(), O.bta_blocks(Sinv, md.ns, md.nt, md.nb), "DSRT"):
+            assert blk_err(g, e) < 1e-10, (i, name)
+
+
+@pytest.mark.parametrize("width", [64, 128], ids=["tile64", "tile128"])
+def test_deferred_gradient_matches_one_pass(P, width):
+    """f now and the gradient later from the kept factors (the selected
+    inversions recomputed from them) equals the one-pass adjoint bit for bit;
+    without room for the factors the gradient recomputes everything and still
+    agrees."""
+    print(f"deferred gradient width={width}", flush=True)
+    mds = [make_model(9, 3, 2, 95), make_model(12, 2, 3, 96), make_model(4, 1, 0, 97)]
+    Ms = [P.Model.from_data(m) for m in mds]
+    th = np.array([[0.1, 0.8, 0.5, 2.0], [0.3, 1.1, 1.0, 3.0], [-0.2, 0.6, 0.2, 2.5]])
+    one = P.eval_f_grad(Ms, th, want_mu=True, want_var=True, tile=width)
+    st = P.EvalState(Ms, th, want_mu=True, tile=width)
+    torch.cuda.synchronize()
+    assert st.kept
+    assert torch.equal(st.f, one["f"]) and torch.equal(st.mu, one["mu"])
+    for _ in range(2):   # the kept factors serve more than one gradient
+        g = st.grad(want_var=True)
+        torch.cuda.synchronize()
+        for key in ("f", "grad", "var", "status"):
+            assert torch.equal(g[key], one[key]), key
+    st.close()
+    # shared storage (recompute = 1) cannot keep both factors: recomputed
+    st2 = P.EvalState(Ms, th, tile=width, recompute=1)
+    g2 = st2.grad()
+    ref2 = P.eval_f_grad(Ms, th, tile=width, recompute=1)
+    torch.cuda.synchronize()
+    assert not st2.kept
+    assert torch.equal(g2["grad"], ref2["grad"]) and torch.equal(g2["f"], ref2["f"])
+    st2.close()
+    for i, md in enumerate(mds):
+        assert rel(one["f"][i].item(), O.eval_f_dense(md, th[i])["f"]) < 1e-10
+
+
+def test_objective_deferred_backward(P):
+    """autograd through the objective with the gradient deferred to the
+    backward pass equals the forward-adjoint gradient bit for bit."""
+    md = make_model(9, 3, 2, 98)
+    M = P.Model.from_data(md)
+    th0 = np.stack([THETA0, THETA0 + 0.1])
+    a = torch.tensor(th0, dtype=torch.float64, device="cuda", requires_grad=True)
+    b = torch.tensor(th0, dtype=torch.float64, device="cuda", requires_grad=True)
+    fa = P.objective(a, [M, M])
+    fb = P.objective(b, [M, M], defer_grad=True)
+    assert torch.equal(fa.detach(), fb.detach())
+    (2.0 * fa[0] + 3.0 * fa[1]).backward()
+    (2.0 * fb[0] + 3.0 * fb[1]).backward()
+    assert torch.equal(a.grad, b.grad)
+    g = O.dense_gradient(md, THETA0)
+    assert np.max(np.abs(b.grad[0].cpu().numpy() / 2.0 - g) / np.abs(g).max()) < 1e-9
