@@ -282,6 +282,70 @@ int32_t inla_eval_state_kept(const inla_eval_state *state);
 void inla_eval_state_destroy(inla_eval_state *state);
 
 /*
+ * Robust quadratic fit (Sec. "Parallel Line Search": the second-order
+ * polynomial through the line-search points by robust regression with
+ * bisquare weights).  Host-only: x, y are n >= 3 host doubles (finite, x not
+ * all equal); coef[3] receives q(x) = coef[0] + coef[1] x + coef[2] x^2.
+ * Iteratively reweighted least squares from the ordinary fit: residual scale
+ * s = median |r_i| / 0.6745, weights w_i = (1 - (r_i / (4.685 s))^2)^2 for
+ * |r_i| < 4.685 s, else 0, until the weights change by less than 1e-12 (at
+ * most 200 rounds); with s = 0 the points off the fit get weight 0.
+ * weights_or_null receives the final weights (n doubles).  INLA_ERR_ARG for
+ * bad input or fewer than three usable points.
+ */
+inla_status inla_robust_quadratic_fit(const double *x, const double *y, int32_t n, double *coef,
+                                      double *weights_or_null);
+
+/*
+ * Options of inla_bfgs_minimize (NULL = defaults; a field <= 0 = its default).
+ *   max_iter  : BFGS iterations (100)
+ *   n_points  : candidate points on the search interval per iteration (6);
+ *               two stabilising points are added on the other side of theta
+ *   gamma     : upper bound of the step length along -p (1: the quasi-Newton step)
+ *   gtol      : stop when max_k |df/dtheta_k| <= gtol (1e-6)
+ *   ftol      : stop when an iteration lowers f by <= ftol max(1, |f|) (1e-13)
+ *   eval_opts : options of the evaluations (NULL = defaults)
+ */
+typedef struct {
+  int32_t max_iter;
+  int32_t n_points;
+  double gamma;
+  double gtol;
+  double ftol;
+  const inla_opts *eval_opts;
+} inla_bfgs_opts;
+
+/* reason: 0 gradient below gtol, 1 decrease of f below ftol, 2 max_iter,
+ * 3 no point of the search interval (shrunk 8 times by 4) lowered f. */
+typedef struct {
+  double theta[4], f, grad[4];
+  int32_t iterations, f_evals, grad_evals, reason;
+} inla_bfgs_result;
+
+/*
+ * Minimise f(theta) for one model from theta0 (4 host doubles): BFGS
+ * (eq. bfgs_update) with the exact adjoint gradient at every accepted iterate,
+ * and the parallel line search of Sec. "Parallel Line Search" (Fig.
+ * parallel_linsearch): with p = H grad f (H the inverse-Hessian approximation,
+ * the first direction of unit length) the n_points candidates
+ * theta - alpha p, alpha = gamma i / n_points, and the two stabilising points
+ * alpha = -gamma/8, -gamma/4 are evaluated in ONE batched inla_eval_f call; a
+ * robust quadratic (inla_robust_quadratic_fit) through them and f(theta) is
+ * minimised on (0, gamma] and that point becomes the next iterate (if an
+ * evaluated candidate is lower than f there, that candidate; if nothing
+ * lowers f, the interval shrinks by 4; the next iteration's interval is
+ * max(gamma, 2 alpha) for the step alpha just taken).  The inverse Hessian is scaled by
+ * s^T y / y^T y at the first update and updated only when s^T y > 0.
+ * Synchronises hip_stream once per evaluation (the decisions are on the host).
+ * history_or_null: host buffer of (max_iter + 1) x 8 doubles, row l =
+ * (f, max |grad f|, alpha, theta[4], f evaluations so far) after iteration l.
+ * Returns INLA_ERR_NOT_SPD if f cannot be evaluated at theta0.
+ */
+inla_status inla_bfgs_minimize(const inla_model *model, const double *theta0,
+                               const inla_bfgs_opts *opts, inla_bfgs_result *res,
+                               double *history_or_null, void *hip_stream);
+
+/*
  * Instrumentation for benchmarks.  Between inla_profile_begin() and
  * inla_profile_end() every kernel launch of the library is bracketed by HIP
  * events on the stream it runs on.  inla_profile_end waits for those events

@@ -19,6 +19,7 @@ from .binding import (  # noqa: F401
     factor_logdet_noalloc,
     header_functions,
     lib,
+    minimize,
     objective,
     profile_begin,
     profile_end,

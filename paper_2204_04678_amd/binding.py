@@ -45,6 +45,17 @@ class Opts(C.Structure):
                 ("autotune_cache", C.c_char_p), ("sigma_out", C.POINTER(Bta))]
 
 
+class BfgsOpts(C.Structure):
+    _fields_ = [("max_iter", C.c_int32), ("n_points", C.c_int32), ("gamma", C.c_double),
+                ("gtol", C.c_double), ("ftol", C.c_double), ("eval_opts", C.POINTER(Opts))]
+
+
+class BfgsResult(C.Structure):
+    _fields_ = [("theta", C.c_double * 4), ("f", C.c_double), ("grad", C.c_double * 4),
+                ("iterations", C.c_int32), ("f_evals", C.c_int32), ("grad_evals", C.c_int32),
+                ("reason", C.c_int32)]
+
+
 _LIB = None
 
 _SIGS = {
@@ -72,6 +83,11 @@ _SIGS = {
                                       C.c_void_p]),
     "inla_eval_state_kept": (C.c_int32, [C.c_void_p]),
     "inla_eval_state_destroy": (None, [C.c_void_p]),
+    "inla_robust_quadratic_fit": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                            C.c_int32, C.POINTER(C.c_double),
+                                            C.POINTER(C.c_double)]),
+    "inla_bfgs_minimize": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(BfgsOpts),
+                                     C.POINTER(BfgsResult), C.POINTER(C.c_double), C.c_void_p]),
     "inla_release_workspace": (None, []),
     "inla_profile_begin": (C.c_int, []),
     "inla_profile_end": (C.c_int, [C.POINTER(C.c_double), C.c_int32]),
@@ -454,6 +470,28 @@ def objective(theta, models, **opts):
     """f(theta) as a differentiable function of theta (k x 4); opts as eval_f,
     plus defer_grad (see InlaObjective)."""
     return InlaObjective.apply(theta, models, opts)
+
+
+BFGS_REASONS = {0: "gradient below gtol", 1: "decrease of f below ftol", 2: "max_iter reached",
+                3: "no point of the search interval lowered f"}
+
+
+def minimize(model: Model, theta0, max_iter=100, n_points=6, gamma=1.0, gtol=1e-6, ftol=1e-13,
+             **eval_opts):
+    """BFGS with the parallel line search (inla_bfgs_minimize) from theta0 (4 values).
+    Returns dict(theta, f, grad, iterations, f_evals, grad_evals, reason, history)
+    with history one row (f, max |grad|, alpha, theta[4], f evaluations) per iteration."""
+    th0 = (C.c_double * 4)(*[float(v) for v in np.asarray(theta0, dtype=np.float64)])
+    eo = _opts(**eval_opts) if eval_opts else None
+    o = BfgsOpts(int(max_iter), int(n_points), float(gamma), float(gtol), float(ftol),
+                 C.pointer(eo) if eo is not None else None)
+    res = BfgsResult()
+    hist = (C.c_double * ((max_iter + 1) * 8))()
+    _check(lib().inla_bfgs_minimize(model.handle, th0, C.byref(o), C.byref(res), hist, _stream()))
+    h = np.array(hist[:(res.iterations + 1) * 8]).reshape(-1, 8)
+    return dict(theta=np.array(res.theta[:]), f=res.f, grad=np.array(res.grad[:]),
+                iterations=res.iterations, f_evals=res.f_evals, grad_evals=res.grad_evals,
+                reason=res.reason, history=h)
 
 
 def release_workspace():

@@ -46,6 +46,17 @@ inla_status fail(inla_status st, const std::string &msg) {
   return st;
 }
 
+}  // namespace
+
+namespace inla {
+inla_status set_last_error(inla_status st, const char *msg) {
+  g_last_error = msg ? msg : "";
+  return st;
+}
+}  // namespace inla
+
+namespace {
+
 #define HIP_TRY(expr)                                                                        \
   do {                                                                                       \
     hipError_t e_ = (expr);                                                                  \

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "../../include/inla_bta.h"
+
 namespace inla {
 
 constexpr int kTile = 64;        // tile edge of the block kernels (rows = cols)
@@ -167,6 +169,8 @@ __host__ __device__ inline bool phase_is_fat(int phase) {
   return phase == PH_DIAG0 || phase == PH_DIAGC || phase == PH_STEPF || phase == PH_ARROW;
 }
 
+// Sets the calling thread's inla_last_error() text and returns st.
+inla_status set_last_error(inla_status st, const char *msg);
 // ---- launch wrappers (bta_kernels.hip) ----
 // total counts the tasks of both phases; with the product kernel (big, or a
 // direct-load 64-wide form) and phase2 >= 0, nside of them are phase2's and
