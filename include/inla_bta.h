@@ -127,7 +127,9 @@ typedef struct {
  *                      the caller's storage sigma_out[i] (a host array of
  *                      n_items descriptors of device storage, each of the
  *                      item's model shape; Sec. "Partial Inversion"); no
- *                      graph is captured for such a call.  0 = not kept.
+ *                      graph is captured for such a call, and its matrices
+ *                      are eliminated from the first time block on (see
+ *                      below).  0 = not kept.
  *   sigma_out        : see keep_sigma (ignored when keep_sigma = 0)
  *   tile             : 64 or 128 forces the tile of the b x b products;
  *                      0 = the autotuner's entry for this call signature if
@@ -140,6 +142,18 @@ typedef struct {
  *                      stored; later calls and processes read it back.
  * Results with different tile layouts agree to rounding (about 1e-15
  * relative), not bitwise.
+ *
+ * Elimination order: a matrix with four or more time blocks is eliminated
+ * from both ends at once -- time blocks 0, 1, .. up to the middle block
+ * m = ceil(nt/2) and nt-1, nt-2, .. down to m+1 in the same launches, the
+ * middle block last before the arrow -- which halves the sequential chain of
+ * the factorization, the substitution and the selected inversion (every
+ * elimination order of the blocks gives the same determinant, mode and
+ * inverse; rounding differs, about 1e-15 relative).  It reads each coupling
+ * block of the backward half as the transpose of the stored one, which the
+ * assembled precision matrices satisfy (each is a multiple of the symmetric
+ * spatial precision).  INLA_TWIST=0 in the environment keeps the one-sided
+ * order.
  */
 typedef struct {
   double hbm_budget_bytes;

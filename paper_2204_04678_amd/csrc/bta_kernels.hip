@@ -175,16 +175,16 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
   tk.Mout = nullptr;
   tk.Cm = nullptr; tk.Lout = nullptr; tk.ldsum = nullptr; tk.src = nullptr; tk.ldl = 0;
   tk.row_off = 0; tk.init = nullptr;
-  double *Dt = it.D + (long long)t * bb;
-  double *St = it.S ? it.S + (long long)t * bb : nullptr;
-  double *Rt = arrow ? it.R + (long long)t * a * b : nullptr;
+  double *Dt = dblk(it, t);
+  double *St = it.S ? sblk(it, t) : nullptr;
+  double *Rt = arrow ? rblk(it, t) : nullptr;
   switch (phase) {
     case PH_DIAG0: {
       SIDE_ONLY(SIDE == kFatOnly)
       tk.m = tk.n = tdim(b, 0);
       tk.C = Dt; tk.ldc = b; tk.beta = 1.0;
       tk.chol = 1; tk.Lout = Dt; tk.ldl = b;
-      tk.ldsum = it.ldpart + (long long)t * nP; tk.row_off = t * b;
+      tk.ldsum = it.ldpart + (long long)t * nP; tk.row_off = tmap(it, t) * b;
       tk.Mout = it.Mp;
       return;
     }
@@ -291,7 +291,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       tk.nseg = 1;
       if (fac) {
         tk.chol = 1; tk.Lout = Dt + toff(b, i, i); tk.ldl = b;
-        tk.ldsum = it.ldpart + (long long)t * nP + i; tk.row_off = t * b + i * kTile;
+        tk.ldsum = it.ldpart + (long long)t * nP + i; tk.row_off = tmap(it, t) * b + i * kTile;
         tk.Mout = (phase == PH_STEPF) ? nullptr : it.Mp + (long long)((p + 1) & 1) * kTile * kTile;
       }
       return;
@@ -330,7 +330,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       int i, j;
       tri_decode(q, i, j);
       tk.m = tdim(b, i); tk.n = tdim(b, j);
-      tk.C = it.D + (long long)(t + 1) * bb + toff(b, i, j); tk.ldc = b; tk.beta = 1.0;
+      tk.C = dblk(it, t + 1) + toff(b, i, j); tk.ldc = b; tk.beta = 1.0;
       set_seg(tk.seg[0], it.W2 + (long long)i * kTile, 1, b, it.W2 + (long long)j * kTile, 1, b, 0, b,
               -1.0);
       tk.nseg = 1;
@@ -354,7 +354,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
           if (idx < nP) {
             const int j = idx;
             tk.m = a; tk.n = tdim(b, j);
-            tk.C = it.R + (long long)(t + 1) * a * b + (long long)j * kTile * a; tk.ldc = a;
+            tk.C = rblk(it, t + 1) + (long long)j * kTile * a; tk.ldc = a;
             tk.beta = 1.0;
             set_seg(tk.seg[0], it.W3, 1, a, it.W2 + (long long)j * kTile, 1, b, 0, b, -1.0);
             tk.nseg = 1;
@@ -420,7 +420,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       // as PH_SI_VU_X for every step tt < nt-1: q runs over (tt, tile)
       const int per = nP * nP, tt = q / per, r = q - tt * per;
       const int j = r / nP, i = r % nP;
-      const double *Dq = it.D + (long long)tt * bb, *Sq = it.S + (long long)tt * bb;
+      const double *Dq = dblk(it, tt), *Sq = sblk(it, tt);
       tk.m = tdim(b, i); tk.n = tdim(b, j);
       tk.C = it.V + (long long)tt * bb + toff(b, i, j); tk.ldc = b;
       set_seg(tk.seg[0], Sq + (long long)i * kTile, 1, b, Dq + (long long)j * kTile * b, b, 1,
@@ -435,7 +435,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       const int per = nP * (nP + 1) / 2, tt = q / per;
       int i, j;
       tri_decode(q - tt * per, i, j);
-      const double *Dq = it.D + (long long)tt * bb;
+      const double *Dq = dblk(it, tt);
       tk.m = tdim(b, i); tk.n = tdim(b, j);
       tk.C = it.G + (long long)tt * bb + toff(b, i, j); tk.ldc = b;
       set_seg(tk.seg[0], Dq + (long long)i * kTile * b, b, 1, Dq + (long long)j * kTile * b, b, 1,
@@ -447,10 +447,10 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       SIDE_ONLY(SIDE == 2 || SIDE == kLeanOnly)
       // as PH_SI_VU for every step tt
       const int tt = q / nP, j = q % nP;
-      const double *Dq = it.D + (long long)tt * bb;
+      const double *Dq = dblk(it, tt);
       tk.m = a; tk.n = tdim(b, j);
       tk.C = it.U + (long long)tt * a * b + (long long)j * kTile * a; tk.ldc = a;
-      set_seg(tk.seg[0], it.R + (long long)tt * a * b, 1, a, Dq + (long long)j * kTile * b, b, 1,
+      set_seg(tk.seg[0], rblk(it, tt), 1, a, Dq + (long long)j * kTile * b, b, 1,
               j * kTile, b, 1.0);
       tk.nseg = 1;
       return;
@@ -541,8 +541,8 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
   tk.Mout = nullptr;
   tk.Cm = nullptr; tk.Lout = nullptr; tk.ldsum = nullptr; tk.src = nullptr; tk.ldl = 0;
   tk.row_off = 0; tk.init = nullptr;
-  double *Dt = it.D + (long long)t * bb;
-  double *St = it.S ? it.S + (long long)t * bb : nullptr;
+  double *Dt = dblk(it, t);
+  double *St = it.S ? sblk(it, t) : nullptr;
   int I, J;
   switch (phase) {
     case PH_OFFDIAG_X:
@@ -560,7 +560,7 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
       LAY_ONLY(0)
       tri_decode(q, I, J);
       tk.m = bdim<TS>(b, I); tk.n = bdim<TS>(b, J); tk.ti = I; tk.tj = J;
-      tk.C = it.D + (long long)(t + 1) * bb + boff<TS>(b, I, J); tk.ldc = b; tk.beta = 1.0;
+      tk.C = dblk(it, t + 1) + boff<TS>(b, I, J); tk.ldc = b; tk.beta = 1.0;
       set_seg(tk.seg[0], it.W2 + (long long)I * TS, 1, b, it.W2 + (long long)J * TS, 1, b, 0, b,
               -1.0);
       tk.nseg = 1;
@@ -580,7 +580,7 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
       // as PH_SI_VU_X for every step tt < nt-1: q runs over (tt, tile)
       const int per = nQ * nQ, tt = q / per, r = q - tt * per;
       J = r / nQ; I = r % nQ;
-      const double *Dq = it.D + (long long)tt * bb, *Sq = it.S + (long long)tt * bb;
+      const double *Dq = dblk(it, tt), *Sq = sblk(it, tt);
       tk.m = bdim<TS>(b, I); tk.n = bdim<TS>(b, J); tk.ti = I; tk.tj = J;
       tk.C = it.V + (long long)tt * bb + boff<TS>(b, I, J); tk.ldc = b;
       set_seg(tk.seg[0], Sq + (long long)I * TS, 1, b, Dq + (long long)J * TS * b, b, 1, J * TS, b,
@@ -607,7 +607,7 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
       // inv(L_tt)^T inv(L_tt) of every step tt, lower tiles (full tiles: no mirror)
       const int per = nQ * (nQ + 1) / 2, tt = q / per;
       tri_decode(q - tt * per, I, J);
-      const double *Dq = it.D + (long long)tt * bb;
+      const double *Dq = dblk(it, tt);
       tk.m = bdim<TS>(b, I); tk.n = bdim<TS>(b, J); tk.ti = I; tk.tj = J;
       tk.C = it.G + (long long)tt * bb + boff<TS>(b, I, J); tk.ldc = b;
       set_seg(tk.seg[0], Dq + (long long)I * TS * b, b, 1, Dq + (long long)J * TS * b, b, 1, I * TS,

@@ -405,79 +405,105 @@ inla_status run_pair(const Batch &B, int px, int pr, int t, hipStream_t s) {
     if (st_ != INLA_OK) return st_;      \
   } while (0)
 
-inla_status run_factor(const Batch &B, hipStream_t s) {
-  for (int t = 0; t < B.max_nt; ++t) {
-    ST_TRY(run_phase(B, PH_DIAG0, t, 0, s));
+// The matrices of a batch eliminated from both ends: one pair of chains each.
+struct Twist {
+  std::vector<TwistPair> host;
+  TwistPair *dev = nullptr;
+  int max_a = 0, max_b = 0;
+  int n() const { return (int)host.size(); }
+  bool middle_at(int t) const {
+    for (const auto &p : host)
+      if (p.m == t) return true;
+    return false;
+  }
+};
+const Twist kNoTwist;
+
+// Block Cholesky of the batch.  C holds the chains (a whole matrix is one
+// chain; a matrix eliminated from both ends is two), F the whole matrices,
+// which factor the arrow block once both chains have added their updates.
+inla_status run_factor(const Batch &C, const Batch &F, const Twist &tw, hipStream_t s) {
+  if (tw.n()) HIP_TRY(launch_twist_arrow(tw.dev, tw.n(), tw.max_a, 0, s));
+  for (int t = 0; t < C.max_nt; ++t) {
+    ST_TRY(run_phase(C, PH_DIAG0, t, 0, s));
     int mp = 0;
-    for (const auto &it : B.host)
-      if (t < it.nt) mp = std::max(mp, it.nP);
+    for (const auto &it : C.host)
+      if (t < it.nrun) mp = std::max(mp, it.nP);
     // Few tiles per step: one launch of the Cholesky-capable kernel per step (its
     // latency is the cost).  Many: the lean kernel for the step and the next
     // diagonal tile beside it.
     long long tiles2 = 0;
-    for (const auto &it : B.host)
-      if (t < it.nt) tiles2 += (long long)it.nP * it.nP;
+    for (const auto &it : C.host)
+      if (t < it.nrun) tiles2 += (long long)it.nP * it.nP;
     const int fo = step_fused_override();
     const bool fused = fo < 0 ? tiles2 < kStepFusedTiles : fo == 1;
     for (int p = 0; p < mp; ++p) {
-      if (fused) ST_TRY(run_phase(B, PH_STEPF, t, p, s));
-      else ST_TRY(run_beside(B, PH_STEP, PH_DIAGC, t, p, s));
+      if (fused) ST_TRY(run_phase(C, PH_STEPF, t, p, s));
+      else ST_TRY(run_beside(C, PH_STEP, PH_DIAGC, t, p, s));
     }
-    ST_TRY(run_pair(B, PH_OFFDIAG_X, PH_OFFDIAG, t, s));
-    ST_TRY(run_pair(B, PH_SCHUR_X, PH_SCHUR, t, s));
+    ST_TRY(run_pair(C, PH_OFFDIAG_X, PH_OFFDIAG, t, s));
+    ST_TRY(run_pair(C, PH_SCHUR_X, PH_SCHUR, t, s));
   }
-  ST_TRY(run_phase(B, PH_ARROW, 0, 0, s));
+  if (tw.n()) HIP_TRY(launch_twist_arrow(tw.dev, tw.n(), tw.max_a, 1, s));
+  ST_TRY(run_phase(F, PH_ARROW, 0, 0, s));
   return INLA_OK;
 }
 
-inla_status run_selinv(const Batch &B, bool traces, hipStream_t s) {
-  const int n = (int)B.host.size();
-  ST_TRY(run_phase(B, PH_SI_INIT, 0, 0, s));
-  if (traces) HIP_TRY(launch_trace_step(B.dev, n, -1, s));
-  if (B.vb) {
+// Selected inversion: the arrow block by the whole matrices (F), then the
+// block recursion down every chain (C); a backward chain starts from the
+// middle block's Sigma, handed over once the forward chain has formed it.
+inla_status run_selinv(const Batch &C, const Batch &F, const Twist &tw, bool traces, hipStream_t s) {
+  ST_TRY(run_phase(F, PH_SI_INIT, 0, 0, s));
+  if (traces) HIP_TRY(launch_trace_step(F.dev, (int)F.host.size(), -1, s));
+  const int n = (int)C.host.size();
+  if (C.vb) {
     // V_t, U_t and the first term of Sigma_D[t] need only the factor: every
     // step's at once, paired as the step-by-step phases are (so that each is
     // formed by the same code)
-    ST_TRY(run_pair(B, PH_SI_VU_B, PH_SI_U_B, 0, s));
-    ST_TRY(run_phase(B, PH_SI_G_B, 0, 0, s));
+    ST_TRY(run_pair(C, PH_SI_VU_B, PH_SI_U_B, 0, s));
+    ST_TRY(run_phase(C, PH_SI_G_B, 0, 0, s));
   }
-  for (int t = B.max_nt - 1; t >= 0; --t) {
-    if (!B.vb) ST_TRY(run_pair(B, PH_SI_VU_X, PH_SI_VU, t, s));
-    ST_TRY(run_pair(B, PH_SI_SR_X, PH_SI_SR, t, s));
-    ST_TRY(run_phase(B, PH_SI_SD_X, t, 0, s));
+  for (int t = C.max_nt - 1; t >= 0; --t) {
+    if (!C.vb) ST_TRY(run_pair(C, PH_SI_VU_X, PH_SI_VU, t, s));
+    ST_TRY(run_pair(C, PH_SI_SR_X, PH_SI_SR, t, s));
+    ST_TRY(run_phase(C, PH_SI_SD_X, t, 0, s));
     if (traces) {
       ProfScope ps(PS_TRACE, 0.0, s);
-      HIP_TRY(launch_trace_step(B.dev, n, t, s));
+      HIP_TRY(launch_trace_step(C.dev, n, t, s));
     }
+    if (tw.middle_at(t)) HIP_TRY(launch_twist_middle(tw.dev, tw.n(), tw.max_b, tw.max_a, t, s));
   }
   return INLA_OK;
 }
 
-inla_status run_solve(const Batch &B, double *const *xs_dev, double *const *tmps_dev, hipStream_t s) {
-  const int n = (int)B.host.size();
-  for (int t = 0; t < B.max_nt; ++t) {
+// Forward and backward substitution: the time blocks chain by chain (C, with
+// per-chain vectors and scratch), the arrow block by the whole matrices (F).
+inla_status run_solve(const Batch &C, const Batch &F, double *const *xs_c, double *const *tmps_c,
+                      double *const *xs_f, double *const *tmps_f, hipStream_t s) {
+  const int n = (int)C.host.size(), nf = (int)F.host.size();
+  for (int t = 0; t < C.max_nt; ++t) {
     {
       ProfScope ps(PS_SOLVE, 0.0, s);
-      HIP_TRY(launch_solve_stage(B.dev, n, B.max_b, B.max_a, t, SV_F1, xs_dev, tmps_dev, s));
+      HIP_TRY(launch_solve_stage(C.dev, n, C.max_b, C.max_a, t, SV_F1, xs_c, tmps_c, s));
     }
     {
       ProfScope ps(PS_SOLVE, 0.0, s);
-      HIP_TRY(launch_solve_stage(B.dev, n, B.max_b, B.max_a, t, SV_F2, xs_dev, tmps_dev, s));
+      HIP_TRY(launch_solve_stage(C.dev, n, C.max_b, C.max_a, t, SV_F2, xs_c, tmps_c, s));
     }
   }
-  if (B.max_a > 0) {
-    HIP_TRY(launch_solve_stage(B.dev, n, B.max_b, B.max_a, 0, SV_FA1, xs_dev, tmps_dev, s));
-    HIP_TRY(launch_solve_stage(B.dev, n, B.max_b, B.max_a, 0, SV_FA2, xs_dev, tmps_dev, s));
-    HIP_TRY(launch_solve_stage(B.dev, n, B.max_b, B.max_a, 0, SV_BA, xs_dev, tmps_dev, s));
+  if (F.max_a > 0) {
+    HIP_TRY(launch_solve_stage(F.dev, nf, F.max_b, F.max_a, 0, SV_FA1, xs_f, tmps_f, s));
+    HIP_TRY(launch_solve_stage(F.dev, nf, F.max_b, F.max_a, 0, SV_FA2, xs_f, tmps_f, s));
+    HIP_TRY(launch_solve_stage(F.dev, nf, F.max_b, F.max_a, 0, SV_BA, xs_f, tmps_f, s));
   }
-  for (int t = B.max_nt - 1; t >= 0; --t) {
+  for (int t = C.max_nt - 1; t >= 0; --t) {
     {
       ProfScope ps(PS_SOLVE, 0.0, s);
-      HIP_TRY(launch_solve_stage(B.dev, n, B.max_b, B.max_a, t, SV_B1, xs_dev, tmps_dev, s));
+      HIP_TRY(launch_solve_stage(C.dev, n, C.max_b, C.max_a, t, SV_B1, xs_c, tmps_c, s));
     }
     {
       ProfScope ps(PS_SOLVE, 0.0, s);
-      HIP_TRY(launch_solve_stage(B.dev, n, B.max_b, B.max_a, t, SV_B2, xs_dev, tmps_dev, s));
+      HIP_TRY(launch_solve_stage(C.dev, n, C.max_b, C.max_a, t, SV_B2, xs_c, tmps_c, s));
     }
   }
   return INLA_OK;
@@ -498,6 +524,7 @@ ItemDev item_from_bta(const inla_bta &q) {
   ItemDev it;
   std::memset(&it, 0, sizeof(it));
   it.b = q.b; it.nt = q.nt; it.a = q.a; it.nP = ntile(q.b);
+  it.ntf = q.nt; it.trev = 0; it.nrun = q.nt; it.own_arrow = 1;
   it.D = q.D; it.S = q.S; it.R = q.R; it.T = q.T;
   return it;
 }
@@ -916,7 +943,7 @@ inla_status inla_factor_logdet(inla_bta *QL, double *logdet_dev, int32_t *info_d
   B.finalize();
   HIP_TRY(launch_fill_int(B.host[0].info, 1, kInfoNone, s));
   ST_TRY(upload(B.dev, B.host, s));
-  ST_TRY(run_factor(B, s));
+  ST_TRY(run_factor(B, B, kNoTwist, s));
   HIP_TRY(launch_logdet_finish(B.dev, 1, logdet_dev ? logdet_dev : ld_tmp,
                                info_dev ? info_dev : info_tmp, s));
   return arena_done(s);
@@ -958,7 +985,7 @@ inla_status inla_factor_logdet_noalloc(inla_bta *QL, double *logdet_dev, int32_t
     // kernel argument (nothing is staged in host memory)
     HIP_TRY(launch_fill_int(B.host[0].info, 1, kInfoNone, s));
     HIP_TRY(launch_put_item(B.host[0], B.dev, s));
-    ST_TRY(run_factor(B, s));
+    ST_TRY(run_factor(B, B, kNoTwist, s));
     HIP_TRY(launch_logdet_finish(B.dev, 1, logdet_dev ? logdet_dev : ld_tmp,
                                  info_dev ? info_dev : info_tmp, s));
     return INLA_OK;
@@ -998,7 +1025,7 @@ inla_status inla_solve(const inla_bta *L_, const double *rhs_dev, double *x_dev,
   ST_TRY(upload(B.dev, B.host, s));
   ST_TRY(upload(xs, hx, s));
   ST_TRY(upload(tmps, ht, s));
-  ST_TRY(run_solve(B, xs, tmps, s));
+  ST_TRY(run_solve(B, B, xs, tmps, xs, tmps, s));
   return arena_done(s);
 }
 
@@ -1035,7 +1062,7 @@ inla_status inla_selinv(const inla_bta *L_, inla_bta *sigma_or_null, double *dia
   ST_TRY(arena_bind(L, s));
   B.finalize();
   ST_TRY(upload(B.dev, B.host, s));
-  ST_TRY(run_selinv(B, diag_or_null != nullptr, s));
+  ST_TRY(run_selinv(B, B, kNoTwist, diag_or_null != nullptr, s));
   return arena_done(s);
 }
 
@@ -1047,15 +1074,28 @@ inla_status inla_selinv(const inla_bta *L_, inla_bta *sigma_or_null, double *dia
 namespace {
 
 struct ThetaItemBufs {
-  ItemDev P, C;
-  double *x = nullptr, *tmp = nullptr, *term = nullptr;
+  ItemDev P, C;        // the whole matrices
+  ItemDev Pb, Cb;      // their backward chains (two-sided elimination)
+  bool tw = false;     // the matrices are eliminated from both ends
+  double *x = nullptr, *tmp = nullptr, *tmpb = nullptr, *term = nullptr;
+  double *TBp = nullptr, *TBc = nullptr;   // arrow accumulators of the backward chains
 };
+
+// Whether a matrix of nt time blocks is eliminated from both ends: from four
+// blocks on (two steps in each direction), unless INLA_TWIST=0 in the
+// environment or the call keeps the selected inverse in caller storage.
+bool twist_env() {
+  const char *e = getenv("INLA_TWIST");
+  return !(e && e[0] == '0');
+}
+bool twisted(const ModelDev &h, bool allowed) { return allowed && h.nt >= 4; }
 
 // Device bytes one (model, theta) item needs: two BTA matrices with their
 // workspaces, or one shared by Q_prior and Q_c when `seq` (the two are then
 // processed one after the other); `vb`: the selected inversion keeps V_t and
-// U_t of every step.
-size_t theta_item_bytes(const ModelDev &h, bool selinv, bool seq, bool split, bool vb) {
+// U_t of every step; `tw`: the matrices are eliminated from both ends (the
+// backward chains have workspaces of their own).
+size_t theta_item_bytes(const ModelDev &h, bool selinv, bool seq, bool split, bool vb, bool tw) {
   const size_t bb = (size_t)h.b * h.b, ab = (size_t)h.a * h.b;
   const int nP = ntile(h.b);
   size_t per = bta_doubles(h.b, h.nt, h.a) * 8 + (2 * bb + ab + 2 * kTile * kTile) * 8 +
@@ -1063,7 +1103,12 @@ size_t theta_item_bytes(const ModelDev &h, bool selinv, bool seq, bool split, bo
   if (selinv) per += (2 * bb + 2 * ab + (size_t)h.a * h.a) * 8 + ((size_t)h.nt + 1) * kTraceBlocks * 32;
   if (selinv && vb) per += ((size_t)(2 * h.nt - 1) * bb + (size_t)h.nt * ab) * 8 + 3 * kAlign;
   if (split) per += (size_t)kSplitK * bb * 8 + kAlign;
-  return (seq ? 1 : 2) * per + ((size_t)h.n + std::max(h.b, h.a) + kTermBlocks * 4) * 8 + 4096;
+  if (tw) {
+    per += (2 * bb + ab + 2 * kTile * kTile + (size_t)h.a * h.a) * 8 + 5 * kAlign;
+    if (split) per += (size_t)kSplitK * bb * 8 + kAlign;
+    if (selinv) per += (2 * bb + 2 * ab) * 8 + 2 * kAlign;
+  }
+  return (seq ? 1 : 2) * per + ((size_t)h.n + 2 * std::max(h.b, h.a) + kTermBlocks * 4) * 8 + 4096;
 }
 
 inla_status ensure_streams() {
@@ -1097,7 +1142,7 @@ inla_status copy_outputs(const EvalGraph &G, int n, long long ntot, double *f_de
 
 // Layout choices of one batched evaluation and the bytes each item needs.
 struct EvalPlan {
-  bool grad = false, need_selinv = false;
+  bool grad = false, need_selinv = false, twist_ok = false;
   bool seq = false, split = false, vb = false;
   int waves = 0;
   std::vector<size_t> bytes;   // per item
@@ -1108,9 +1153,10 @@ struct EvalPlan {
 // budget.  `seq_mode`: 2 never, 1 always, 0 when the two-matrix layout needs
 // more admission waves than the one-matrix layout.
 inla_status plan_eval(const inla_model *const *models, int32_t n_items, bool grad, bool need_selinv,
-                      double budget, int seq_mode, EvalPlan &P) {
+                      double budget, int seq_mode, bool twist_ok, EvalPlan &P) {
   P.grad = grad;
   P.need_selinv = need_selinv;
+  P.twist_ok = twist_ok;
   // split-k scratch when the whole call has few 128-wide tiles per launch
   long long nb2 = 0;
   for (int i = 0; i < n_items; ++i) nb2 += 2LL * nbig(models[i]->host.b) * nbig(models[i]->host.b);
@@ -1127,7 +1173,8 @@ inla_status plan_eval(const inla_model *const *models, int32_t n_items, bool gra
     int waves = 0;
     double acc = budget + 1.0;
     for (int i = 0; i < n_items; ++i) {
-      bytes[i] = theta_item_bytes(models[i]->host, need_selinv, seq, split, vb);
+      bytes[i] = theta_item_bytes(models[i]->host, need_selinv, seq, split, vb,
+                                  twisted(models[i]->host, twist_ok));
       all += (double)bytes[i];
       if ((double)bytes[i] > budget) return INT_MAX;
       if (acc + (double)bytes[i] > budget) {
@@ -1168,7 +1215,8 @@ inla_status plan_eval(const inla_model *const *models, int32_t n_items, bool gra
   if (P.waves == INT_MAX) {
     const Cand c = cands.back();   // the smallest layout
     for (int i = 0; i < n_items; ++i) {
-      const size_t need = theta_item_bytes(models[i]->host, need_selinv, c.seq, c.split, c.vb);
+      const size_t need = theta_item_bytes(models[i]->host, need_selinv, c.seq, c.split, c.vb,
+                                           twisted(models[i]->host, twist_ok));
       if ((double)need > budget)
         return fail(INLA_ERR_BUDGET, "item " + std::to_string(i) + " needs " + std::to_string(need) +
                                          " bytes, above the HBM budget");
@@ -1181,18 +1229,27 @@ inla_status plan_eval(const inla_model *const *models, int32_t n_items, bool gra
 // One admission wave of a batched evaluation: the descriptors of every item's
 // matrices, workspaces and outputs, laid out in one block of device memory
 // (the library arena, or a block of its own when the factors are kept for a
-// gradient asked for later).
+// gradient asked for later).  Each matrix is one chain of time blocks, or two
+// (a forward and a backward chain meeting at a middle block) when it is
+// eliminated from both ends; the per-step phases run over the chains (*h
+// batches), the arrow block, log-determinant and combination over the whole
+// matrices.
 struct Wave {
   int start = 0, k = 0;
   bool grad = false, need_selinv = false, seq = false, split = false, vb = false;
+  bool twist_ok = false;   // matrices of four or more time blocks are eliminated from both ends
   bool io = false;       // theta and outputs in buffers of the wave (graph capture, kept factors)
   bool two_combines = false;   // also an f-only combination (gradient asked for later)
   bool want_var = false;
   std::vector<ThetaItemBufs> tb;
   std::vector<double *> Dbase;
-  Batch F, Sv, Si, Fc, Sic;
+  Batch F, Sv, Si, Fc, Sic;            // whole matrices
+  Batch Fh, Svh, Sih, Fch, Sich;       // their chains
+  Twist twf, twfc, twsi, twsic;        // matrices eliminated from both ends, per batch
   ItemDev *fdev = nullptr, *sdev = nullptr, *vdev = nullptr;
-  double **xs = nullptr, **tmps = nullptr, *logdet = nullptr;
+  ItemDev *fhdev = nullptr, *shdev = nullptr, *vhdev = nullptr;
+  TwistPair *tpf = nullptr, *tpsi = nullptr;
+  double **xs = nullptr, **tmps = nullptr, **xsh = nullptr, **tmpsh = nullptr, *logdet = nullptr;
   int *info = nullptr;
   TermItem *tdev = nullptr;
   CombineItem *cdev = nullptr;     // f, and the gradient when grad
@@ -1200,6 +1257,20 @@ struct Wave {
   EvalGraph G;                     // theta and outputs when io
   long long ntot = 0;              // length of the wave's mu / var outputs
 };
+
+// Workspace of a backward chain (its factor storage is the matrix's own).
+void layout_back_ws(Layout &L, ItemDev &it, bool split, bool selinv) {
+  const size_t bb = (size_t)it.b * it.b;
+  L.add(&it.W1, bb);
+  L.add(&it.W2, bb);
+  L.add(&it.W3, std::max<size_t>((size_t)it.a * it.b, 1));
+  L.add(&it.Mp, 2 * (size_t)kTile * kTile);
+  if (split) L.add(&it.P, (size_t)kSplitK * bb);
+  if (selinv) {
+    L.add(&it.SD, 2 * bb);
+    L.add(&it.SR, std::max<size_t>(2 * (size_t)it.a * it.b, 1));
+  }
+}
 
 // Adds the wave's device buffers to L (the pointers are set once L is placed).
 void wave_layout(Wave &W, const inla_model *const *models, bool mu_in_caller, Layout &L) {
@@ -1218,12 +1289,18 @@ void wave_layout(Wave &W, const inla_model *const *models, bool mu_in_caller, La
   }
   for (int q = 0; q < k; ++q) {
     const ModelDev &h = models[W.start + q]->host;
+    ThetaItemBufs &T = W.tb[q];
+    T.tw = twisted(h, W.twist_ok);
     for (int w = 0; w < 2; ++w) {
-      ItemDev &it = w ? W.tb[q].C : W.tb[q].P;
+      ItemDev &it = w ? T.C : T.P;
+      ItemDev &bk = w ? T.Cb : T.Pb;
       std::memset(&it, 0, sizeof(it));
+      std::memset(&bk, 0, sizeof(bk));
       it.b = h.b; it.nt = h.nt; it.a = h.a; it.nP = ntile(h.b);
+      it.ntf = h.nt; it.nrun = h.nt; it.own_arrow = 1;
       it.which = w;
       it.model = models[W.start + q]->dev;
+      bk.b = h.b; bk.a = h.a; bk.nP = it.nP;
       if (w == 1 && W.seq) {
         // Q_c reuses the storage and workspaces of Q_prior (aliased in
         // wave_bind, once the memory is placed); only its trace partials are its own
@@ -1242,21 +1319,65 @@ void wave_layout(Wave &W, const inla_model *const *models, bool mu_in_caller, La
         }
         if (W.grad) L.add(&it.trpart, ((size_t)h.nt + 1) * kTraceBlocks * 4);
       }
+      if (T.tw) {
+        layout_back_ws(L, bk, W.split, W.need_selinv);
+        if (h.a > 0) L.add(w ? &T.TBc : &T.TBp, (size_t)h.a * h.a);
+      }
     }
-    if (!mu_in_caller && !W.io) L.add(&W.tb[q].x, (size_t)h.n);
-    L.add(&W.tb[q].tmp, (size_t)std::max(h.b, std::max(h.a, 1)));
-    L.add(&W.tb[q].term, (size_t)kTermBlocks * 4);
+    if (!mu_in_caller && !W.io) L.add(&T.x, (size_t)h.n);
+    L.add(&T.tmp, (size_t)std::max(h.b, std::max(h.a, 1)));
+    if (T.tw) L.add(&T.tmpb, (size_t)std::max(h.b, std::max(h.a, 1)));
+    L.add(&T.term, (size_t)kTermBlocks * 4);
   }
   L.add(&W.fdev, 2 * k);
   L.add(&W.sdev, k);
   L.add(&W.vdev, 2 * k);
+  L.add(&W.fhdev, 4 * k);
+  L.add(&W.shdev, 2 * k);
+  L.add(&W.vhdev, 4 * k);
+  L.add(&W.tpf, 2 * k);
+  L.add(&W.tpsi, 2 * k);
   L.add(&W.xs, k);
   L.add(&W.tmps, k);
+  L.add(&W.xsh, 2 * k);
+  L.add(&W.tmpsh, 2 * k);
   L.add(&W.logdet, 2 * k);
   L.add(&W.info, 2 * k);
   L.add(&W.tdev, k);
   L.add(&W.cdev, k);
   if (W.two_combines) L.add(&W.cdev_f, k);
+}
+
+// The forward chain (time blocks 0..m, m = ceil(nt/2)) of a whole matrix and
+// its backward chain (blocks nt-1 down to m+1, whose last block is the
+// middle one), completing bk, whose workspace is already placed; TB: its
+// arrow accumulator.  The backward chain's last step updates the middle
+// block in an earlier lockstep step than the forward chain's (nt-m-2 < m-1),
+// so the two never touch it in one launch.
+void make_chains(const ItemDev &full, ItemDev &fw, ItemDev &bk, double *TB, TwistPair &tp) {
+  const int nt = full.nt, m = (nt + 1) / 2;
+  const long long bb = (long long)full.b * full.b, ab = (long long)full.a * full.b;
+  fw = full;
+  fw.nt = m + 1; fw.nrun = m + 1; fw.own_arrow = 0;
+  ItemDev w = bk;   // its workspace pointers
+  bk = full;
+  bk.W1 = w.W1; bk.W2 = w.W2; bk.W3 = w.W3; bk.Mp = w.Mp; bk.P = w.P;
+  bk.SD = w.SD; bk.SR = w.SR;
+  bk.SS = full.SS ? bk.W1 : nullptr;
+  bk.nt = nt - m; bk.nrun = nt - m - 1; bk.ntf = nt; bk.trev = 1; bk.own_arrow = 0;
+  bk.T = TB;
+  bk.ldpart = full.ldpart + (long long)(m + 1) * full.nP;
+  bk.trpart = full.trpart ? full.trpart + (long long)(m + 1) * kTraceBlocks * 4 : nullptr;
+  bk.V = full.V ? full.V + (long long)m * bb : nullptr;
+  bk.U = full.U ? full.U + (long long)(m + 1) * ab : nullptr;
+  bk.G = full.G ? full.G + (long long)(m + 1) * bb : nullptr;
+  std::memset(&tp, 0, sizeof(tp));
+  tp.T = full.T; tp.TB = TB;
+  if (full.SD) {
+    tp.SDf = sig_D(fw, m); tp.SDb = sig_D(bk, bk.nt - 1);
+    tp.SRf = sig_R(fw, m); tp.SRb = sig_R(bk, bk.nt - 1);
+  }
+  tp.a = full.a; tp.b = full.b; tp.m = m;
 }
 
 // Finishes the descriptors once the wave's memory is placed and uploads them.
@@ -1269,12 +1390,18 @@ inla_status wave_bind(Wave &W, const inla_model *const *models, const double *th
   const int k = W.k;
   if (W.seq) {
     for (int q = 0; q < k; ++q) {
-      const ItemDev &pv = W.tb[q].P;
-      ItemDev &cv = W.tb[q].C;
+      ThetaItemBufs &T = W.tb[q];
+      const ItemDev &pv = T.P;
+      ItemDev &cv = T.C;
       cv.W1 = pv.W1; cv.W2 = pv.W2; cv.W3 = pv.W3; cv.Mp = pv.Mp; cv.P = pv.P;
       cv.ldpart = pv.ldpart; cv.info = pv.info;
       cv.SD = pv.SD; cv.SR = pv.SR; cv.ST = pv.ST; cv.V = pv.V; cv.U = pv.U; cv.G = pv.G;
       W.Dbase[2 * q + 1] = W.Dbase[2 * q];
+      const ItemDev &pb = T.Pb;
+      ItemDev &cb = T.Cb;
+      cb.W1 = pb.W1; cb.W2 = pb.W2; cb.W3 = pb.W3; cb.Mp = pb.Mp; cb.P = pb.P;
+      cb.SD = pb.SD; cb.SR = pb.SR;
+      T.TBc = T.TBp;
     }
   }
   const double *th = W.io ? W.G.th : theta_w;
@@ -1284,16 +1411,24 @@ inla_status wave_bind(Wave &W, const inla_model *const *models, const double *th
   double *muo = W.io ? W.G.mu_buf : mu_w;
   double *vo = W.io ? W.G.var_buf : var_w;
   W.F = Batch(); W.Sv = Batch(); W.Si = Batch(); W.Fc = Batch(); W.Sic = Batch();
-  std::vector<double *> hx(k), ht(k);
+  W.Fh = Batch(); W.Svh = Batch(); W.Sih = Batch(); W.Fch = Batch(); W.Sich = Batch();
+  W.twf = Twist(); W.twfc = Twist(); W.twsi = Twist(); W.twsic = Twist();
+  std::vector<double *> hx(k), ht(k), hxh, hth;
   std::vector<TermItem> thv(k);
   std::vector<CombineItem> ch(k), chf(k);
+  auto add_twist = [](Twist &tw, const TwistPair &tp) {
+    tw.host.push_back(tp);
+    tw.max_a = std::max(tw.max_a, tp.a);
+    tw.max_b = std::max(tw.max_b, tp.b);
+  };
   long long off = 0;
   for (int q = 0; q < k; ++q) {
     const int i = W.start + q;
     const ModelDev &h = models[i]->host;
+    ThetaItemBufs &T = W.tb[q];
     const size_t bb = (size_t)h.b * h.b;
     for (int w = 0; w < 2; ++w) {
-      ItemDev &it = w ? W.tb[q].C : W.tb[q].P;
+      ItemDev &it = w ? T.C : T.P;
       double *base = W.Dbase[2 * q + w];
       it.D = base;
       it.S = h.nt > 1 ? base + (size_t)h.nt * bb : nullptr;
@@ -1311,62 +1446,143 @@ inla_status wave_bind(Wave &W, const inla_model *const *models, const double *th
         it.ST = sg.T;
       }
     }
-    if (muo) W.tb[q].x = muo + off;
-    hx[q] = W.tb[q].x;
-    ht[q] = W.tb[q].tmp;
-    if (W.seq) {
-      W.F.host.push_back(W.tb[q].P);
-      W.Fc.host.push_back(W.tb[q].C);
-      if (W.grad) W.Si.host.push_back(W.tb[q].P);
-      if (W.need_selinv) W.Sic.host.push_back(W.tb[q].C);
-    } else {
-      W.F.host.push_back(W.tb[q].P);
-      W.F.host.push_back(W.tb[q].C);
-      if (W.grad) W.Si.host.push_back(W.tb[q].P);
-      if (W.need_selinv) W.Si.host.push_back(W.tb[q].C);
+    if (muo) T.x = muo + off;
+    hx[q] = T.x;
+    ht[q] = T.tmp;
+    // the chains of each matrix
+    ItemDev pf = T.P, pb, cf = T.C, cb;
+    TwistPair tpp, tpc;
+    if (T.tw) {
+      pb = T.Pb;
+      cb = T.Cb;
+      make_chains(T.P, pf, pb, T.TBp, tpp);
+      make_chains(T.C, cf, cb, T.TBc, tpc);
     }
-    W.Sv.host.push_back(W.tb[q].C);
-    thv[q] = TermItem{models[i]->dev, th + 4 * q, W.tb[q].x, W.tb[q].term};
+    auto chains = [&](Batch &B, const ItemDev &f, const ItemDev &bk) {
+      B.host.push_back(f);
+      if (T.tw) B.host.push_back(bk);
+    };
+    if (W.seq) {
+      W.F.host.push_back(T.P);
+      W.Fc.host.push_back(T.C);
+      chains(W.Fh, pf, pb);
+      chains(W.Fch, cf, cb);
+      if (T.tw) {
+        add_twist(W.twf, tpp);
+        add_twist(W.twfc, tpc);
+      }
+      if (W.grad) {
+        W.Si.host.push_back(T.P);
+        chains(W.Sih, pf, pb);
+        if (T.tw) add_twist(W.twsi, tpp);
+      }
+      if (W.need_selinv) {
+        W.Sic.host.push_back(T.C);
+        chains(W.Sich, cf, cb);
+        if (T.tw) add_twist(W.twsic, tpc);
+      }
+    } else {
+      W.F.host.push_back(T.P);
+      W.F.host.push_back(T.C);
+      chains(W.Fh, pf, pb);
+      chains(W.Fh, cf, cb);
+      if (T.tw) {
+        add_twist(W.twf, tpp);
+        add_twist(W.twf, tpc);
+      }
+      if (W.grad) {
+        W.Si.host.push_back(T.P);
+        chains(W.Sih, pf, pb);
+        if (T.tw) add_twist(W.twsi, tpp);
+      }
+      if (W.need_selinv) {
+        W.Si.host.push_back(T.C);
+        chains(W.Sih, cf, cb);
+        if (T.tw) add_twist(W.twsi, tpc);
+      }
+    }
+    W.Sv.host.push_back(T.C);
+    chains(W.Svh, cf, cb);
+    hxh.push_back(T.x);
+    hth.push_back(T.tmp);
+    if (T.tw) {
+      hxh.push_back(T.x);
+      hth.push_back(T.tmpb);
+    }
+    thv[q] = TermItem{models[i]->dev, th + 4 * q, T.x, T.term};
     CombineItem c;
     std::memset(&c, 0, sizeof(c));
     c.model = models[i]->dev;
     c.theta = th + 4 * q;
-    c.term_part = W.tb[q].term;
-    c.mu = W.tb[q].x;
+    c.term_part = T.term;
+    c.mu = T.x;
     c.logdet = W.logdet + 2 * q;
     c.info = W.info + 2 * q;
     c.f = fo + q;
     c.status = so ? so + q : nullptr;
     chf[q] = c;
-    c.trp = W.grad ? W.tb[q].P.trpart : nullptr;
-    c.trc = W.grad ? W.tb[q].C.trpart : nullptr;
+    c.trp = W.grad ? T.P.trpart : nullptr;
+    c.trc = W.grad ? T.C.trpart : nullptr;
     c.grad = (W.grad && go) ? go + 4 * q : nullptr;
     ch[q] = c;
     off += h.n;
   }
   // every descriptor must point into placed memory before anything is launched
-  for (int q = 0; q < k; ++q)
-    for (const ItemDev *it : {&W.tb[q].P, &W.tb[q].C}) {
+  for (int q = 0; q < k; ++q) {
+    const ThetaItemBufs &T = W.tb[q];
+    for (const ItemDev *it : {&T.P, &T.C}) {
       const bool ok = it->D && it->W1 && it->W2 && it->W3 && it->Mp && it->ldpart && it->info &&
                       (!W.need_selinv || (it->SD && (it->a == 0 || (it->SR && it->ST)))) &&
-                      (!W.grad || it->trpart) && W.tb[q].x && W.tb[q].tmp && W.tb[q].term;
+                      (!W.grad || it->trpart) && T.x && T.tmp && T.term;
       if (!ok) return fail(INLA_ERR_STATE, "internal: workspace of item " +
                                                std::to_string(W.start + q) + " not placed");
     }
-  // descriptor arrays: the sequential layout splits fdev / vdev in halves
+    if (T.tw) {
+      const bool ok = T.Pb.W1 && T.Pb.W2 && T.Pb.W3 && T.Pb.Mp && T.tmpb &&
+                      (!W.need_selinv || T.Pb.SD) && (T.P.a == 0 || T.TBp);
+      if (!ok) return fail(INLA_ERR_STATE, "internal: chain workspace of item " +
+                                               std::to_string(W.start + q) + " not placed");
+    }
+  }
+  // descriptor arrays: the sequential layout splits them in halves
   W.F.dev = W.fdev; W.Sv.dev = W.sdev; W.Si.dev = W.vdev;
   W.Fc.dev = W.fdev + k; W.Sic.dev = W.vdev + k;
-  W.F.finalize(); W.Sv.finalize(); W.Si.finalize();
-  if (W.seq) { W.Fc.finalize(); W.Sic.finalize(); }
-  W.Si.vb = W.vb;
-  W.Sic.vb = W.vb;
+  W.Fh.dev = W.fhdev; W.Svh.dev = W.shdev; W.Sih.dev = W.vhdev;
+  W.Fch.dev = W.fhdev + 2 * k; W.Sich.dev = W.vhdev + 2 * k;
+  W.twf.dev = W.tpf; W.twsi.dev = W.tpsi;
+  W.twfc.dev = W.tpf + k; W.twsic.dev = W.tpsi + k;
+  for (Batch *B : {&W.F, &W.Sv, &W.Si, &W.Fh, &W.Svh, &W.Sih}) B->finalize();
+  if (W.seq)
+    for (Batch *B : {&W.Fc, &W.Sic, &W.Fch, &W.Sich}) B->finalize();
+  for (Batch *B : {&W.Si, &W.Sic, &W.Sih, &W.Sich}) B->vb = W.vb;
+  // the chains of a matrix use the tile choice of the whole matrices
+  for (Batch *B : {&W.Fh, &W.Svh, &W.Sih, &W.Fch, &W.Sich}) B->big = W.F.big;
   ST_TRY(upload(W.fdev, W.F.host, s));
-  if (W.seq) ST_TRY(upload(W.Fc.dev, W.Fc.host, s));
+  ST_TRY(upload(W.fhdev, W.Fh.host, s));
+  if (W.seq) {
+    ST_TRY(upload(W.Fc.dev, W.Fc.host, s));
+    ST_TRY(upload(W.Fch.dev, W.Fch.host, s));
+  }
   ST_TRY(upload(W.sdev, W.Sv.host, s));
-  if (W.need_selinv && !W.Si.host.empty()) ST_TRY(upload(W.vdev, W.Si.host, s));
-  if (W.seq && W.need_selinv) ST_TRY(upload(W.Sic.dev, W.Sic.host, s));
+  ST_TRY(upload(W.shdev, W.Svh.host, s));
+  if (W.need_selinv && !W.Si.host.empty()) {
+    ST_TRY(upload(W.vdev, W.Si.host, s));
+    ST_TRY(upload(W.vhdev, W.Sih.host, s));
+  }
+  if (W.seq && W.need_selinv) {
+    ST_TRY(upload(W.Sic.dev, W.Sic.host, s));
+    ST_TRY(upload(W.Sich.dev, W.Sich.host, s));
+  }
+  ST_TRY(upload(W.tpf, W.twf.host, s));
+  ST_TRY(upload(W.tpsi, W.twsi.host, s));
+  if (W.seq) {
+    ST_TRY(upload(W.twfc.dev, W.twfc.host, s));
+    ST_TRY(upload(W.twsic.dev, W.twsic.host, s));
+  }
   ST_TRY(upload(W.xs, hx, s));
   ST_TRY(upload(W.tmps, ht, s));
+  ST_TRY(upload(W.xsh, hxh, s));
+  ST_TRY(upload(W.tmpsh, hth, s));
   ST_TRY(upload(W.tdev, thv, s));
   ST_TRY(upload(W.cdev, ch, s));
   if (W.two_combines) ST_TRY(upload(W.cdev_f, chf, s));
@@ -1396,20 +1612,20 @@ inla_status wave_forward(Wave &W, const inla_model *const *models, bool defer_gr
     // assemble Q_prior, Q_c and b = tau_y A^T y (into x, solved in place)
     ST_TRY(wave_assemble(W, models, 0, ls));
     ST_TRY(wave_assemble(W, models, 1, ls));
-    ST_TRY(run_factor(W.F, ls));
+    ST_TRY(run_factor(W.Fh, W.F, W.twf, ls));
     HIP_TRY(launch_logdet_finish(W.fdev, 2 * k, W.logdet, W.info, ls));
     if (W.need_selinv && !defer_grad) {
       // the mode solve (and its terms) beside the selected inversion: both
       // only read the factor, and they write disjoint buffers
       HIP_TRY(hipEventRecord(g_solve_fork, ls));
       HIP_TRY(hipStreamWaitEvent(g_solve, g_solve_fork, 0));
-      ST_TRY(run_solve(W.Sv, W.xs, W.tmps, g_solve));
+      ST_TRY(run_solve(W.Svh, W.Sv, W.xsh, W.tmpsh, W.xs, W.tmps, g_solve));
       HIP_TRY(launch_terms(W.tdev, k, g_solve));
       HIP_TRY(hipEventRecord(g_solve_join, g_solve));
-      ST_TRY(run_selinv(W.Si, true, ls));
+      ST_TRY(run_selinv(W.Sih, W.Si, W.twsi, true, ls));
       HIP_TRY(hipStreamWaitEvent(ls, g_solve_join, 0));
     } else {
-      ST_TRY(run_solve(W.Sv, W.xs, W.tmps, ls));
+      ST_TRY(run_solve(W.Svh, W.Sv, W.xsh, W.tmpsh, W.xs, W.tmps, ls));
       HIP_TRY(launch_terms(W.tdev, k, ls));
     }
   } else {
@@ -1417,15 +1633,15 @@ inla_status wave_forward(Wave &W, const inla_model *const *models, bool defer_gr
     // Q_prior first (factor, log-determinant, gradient traces), then Q_c
     // in the same storage
     ST_TRY(wave_assemble(W, models, 0, ls));
-    ST_TRY(run_factor(W.F, ls));
+    ST_TRY(run_factor(W.Fh, W.F, W.twf, ls));
     HIP_TRY(launch_logdet_finish(W.fdev, k, W.logdet, W.info, ls, 2));
-    if (W.grad) ST_TRY(run_selinv(W.Si, true, ls));
+    if (W.grad) ST_TRY(run_selinv(W.Sih, W.Si, W.twsi, true, ls));
     ST_TRY(wave_assemble(W, models, 1, ls));
-    ST_TRY(run_factor(W.Fc, ls));
+    ST_TRY(run_factor(W.Fch, W.Fc, W.twfc, ls));
     HIP_TRY(launch_logdet_finish(W.Fc.dev, k, W.logdet + 1, W.info + 1, ls, 2));
-    ST_TRY(run_solve(W.Sv, W.xs, W.tmps, ls));
+    ST_TRY(run_solve(W.Svh, W.Sv, W.xsh, W.tmpsh, W.xs, W.tmps, ls));
     HIP_TRY(launch_terms(W.tdev, k, ls));
-    if (W.need_selinv) ST_TRY(run_selinv(W.Sic, true, ls));
+    if (W.need_selinv) ST_TRY(run_selinv(W.Sich, W.Sic, W.twsic, true, ls));
   }
   HIP_TRY(launch_combine(defer_grad ? W.cdev_f : W.cdev, k, ls));
   return INLA_OK;
@@ -1435,7 +1651,7 @@ inla_status wave_forward(Wave &W, const inla_model *const *models, bool defer_gr
 // traces, then f and the gradient combined (the same launches, in the same
 // order per matrix, as the one-pass evaluation).
 inla_status wave_gradient(Wave &W, hipStream_t ls) {
-  ST_TRY(run_selinv(W.Si, true, ls));
+  ST_TRY(run_selinv(W.Sih, W.Si, W.twsi, true, ls));
   HIP_TRY(launch_combine(W.cdev, W.k, ls));
   return INLA_OK;
 }
@@ -1450,8 +1666,9 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
                      bool allow_graph, hipStream_t s) {
   const bool grad = grad_dev != nullptr;
   const bool need_selinv = grad || var_out != nullptr || sigma != nullptr;
+  const bool twist_ok = twist_env() && sigma == nullptr;
   EvalPlan plan;
-  ST_TRY(plan_eval(models, n_items, grad, need_selinv, budget, seq_mode, plan));
+  ST_TRY(plan_eval(models, n_items, grad, need_selinv, budget, seq_mode, twist_ok, plan));
   // per-item output offsets into the concatenated mu / var buffers
   std::vector<long long> voff(n_items + 1, 0);
   for (int i = 0; i < n_items; ++i) voff[i + 1] = voff[i] + models[i]->n;
@@ -1472,7 +1689,7 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
       key.shapes.push_back(v);
   }
   key.grad = grad; key.var = var_out != nullptr; key.mu = mu_out != nullptr; key.prof = g_prof.on;
-  key.seq = plan.seq; key.split = plan.split; key.vb = plan.vb;
+  key.seq = plan.seq; key.split = plan.split; key.vb = plan.vb; key.twist = twist_ok;
   key.tile = tile; key.variant = variant; key.small = small; key.step = step;
   key.gen = g_arena.gen; key.base = g_arena.base; key.ntot = ntot;
   if (graphable && g_graph.valid && same_signature(g_graph.key, key)) {
@@ -1494,6 +1711,7 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
     W.k = end - start;
     W.grad = grad; W.need_selinv = need_selinv;
     W.seq = plan.seq; W.split = plan.split; W.vb = plan.vb;
+    W.twist_ok = twist_ok;
     W.io = graphable;
     W.want_var = var_out != nullptr;
     Layout L;
@@ -1809,12 +2027,14 @@ inla_status eval_f_keep_impl(const inla_model *const *models, int32_t n_items,
     // the gradient's layout, both matrices in storage of their own, one wave
     EvalPlan plan;
     if ((!opts || opts->recompute != 1) &&
-        plan_eval(models, n_items, true, true, budget, 2, plan) == INLA_OK && plan.waves == 1) {
+        plan_eval(models, n_items, true, true, budget, 2, twist_env(), plan) == INLA_OK &&
+        plan.waves == 1) {
       Wave &W = st->W;
       W.start = 0;
       W.k = n_items;
       W.grad = true; W.need_selinv = true;
       W.seq = false; W.split = plan.split; W.vb = plan.vb;
+      W.twist_ok = plan.twist_ok;
       W.io = true;
       W.want_var = true;
       W.two_combines = true;

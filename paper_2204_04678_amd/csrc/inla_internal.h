@@ -69,8 +69,29 @@ struct ItemDev {
   const ModelDev *model;         // model whose derivative blocks the traces use (or null)
   const double *theta;           // 4 hyperparameters of this item (device)
   int which;                     // 0: Q_prior, 1: Q_c
-  int pad_;
+  // Two-sided elimination.  An item is a chain of nt time blocks of a matrix
+  // with ntf blocks: step t of the chain is time block tmap(t) = t (trev = 0)
+  // or ntf - 1 - t (trev = 1: the chain runs from the last block backwards,
+  // reading each coupling block as its transpose).  The chain runs steps
+  // t < nrun (nrun = nt, or nt - 1 for a backward chain whose last block is
+  // the middle block, factored by the forward chain).  own_arrow: the item
+  // factors / inverts the arrow block itself (a whole matrix); a half never does.
+  int ntf, trev, nrun, own_arrow;
 };
+
+// Time block of chain step t, and the storage of the chain's blocks.  The
+// coupling of backward-chain steps t and t+1 (times tau and tau - 1) is stored
+// in the forward slot of block (tau, tau - 1), which holds its transpose.
+__host__ __device__ inline int tmap(const ItemDev &it, int t) { return it.trev ? it.ntf - 1 - t : t; }
+__host__ __device__ inline double *dblk(const ItemDev &it, int t) {
+  return it.D + (long long)tmap(it, t) * it.b * it.b;
+}
+__host__ __device__ inline double *sblk(const ItemDev &it, int t) {
+  return it.S + (long long)(tmap(it, t) - it.trev) * it.b * it.b;
+}
+__host__ __device__ inline double *rblk(const ItemDev &it, int t) {
+  return it.R + (long long)tmap(it, t) * it.a * it.b;
+}
 
 __host__ __device__ inline double *sig_D(const ItemDev &it, int t) {
   return it.sd_stride ? it.SD + (long long)t * it.sd_stride : it.SD + (long long)(t & 1) * it.b * it.b;
@@ -132,8 +153,12 @@ __host__ __device__ inline int phase_tasks(const ItemDev &it, int phase, int t, 
   const int nP = it.nP;
   const int nQ = big ? nbig(it.b) : nP;
   const bool arrow = it.a > 0;
-  if (phase == PH_ARROW || phase == PH_SI_INIT) return arrow ? 1 : 0;
-  if (t >= it.nt) return 0;
+  if (phase == PH_ARROW || phase == PH_SI_INIT) return (arrow && it.own_arrow) ? 1 : 0;
+  // the every-step phases count from the launch's t = 0 over the chain's steps
+  if (phase == PH_SI_VU_B) return (it.nrun < it.nt ? it.nrun : it.nt - 1) * nQ * nQ;
+  if (phase == PH_SI_U_B) return arrow ? it.nrun * nP : 0;
+  if (phase == PH_SI_G_B) return it.nrun * (nQ * (nQ + 1) / 2);
+  if (t >= it.nrun) return 0;
   const bool last = (t == it.nt - 1);
   switch (phase) {
     case PH_DIAG0: return 1;
@@ -157,9 +182,6 @@ __host__ __device__ inline int phase_tasks(const ItemDev &it, int phase, int t, 
     case PH_SI_SR_X: return last ? 0 : nQ * nQ;
     case PH_SI_SR: return arrow ? nP : 0;
     case PH_SI_SD_X: return nQ * (nQ + 1) / 2;
-    case PH_SI_VU_B: return (it.nt - 1) * nQ * nQ;   // every step, from the launch's t = 0
-    case PH_SI_U_B: return arrow ? it.nt * nP : 0;
-    case PH_SI_G_B: return it.nt * (nQ * (nQ + 1) / 2);
     default: return 0;
   }
 }
@@ -244,5 +266,24 @@ struct CombineItem {
   int pad_;
 };
 hipError_t launch_combine(const CombineItem *items_dev, int n_items, hipStream_t s);
+// A matrix eliminated from both ends (a forward chain over time blocks 0..m,
+// a backward chain from block nt-1 down to m+1): the backward chain's arrow
+// updates collect in TB, and the middle block's selected-inverse blocks are
+// handed from the forward chain's buffers to the backward chain's.
+struct TwistPair {
+  double *T, *TB;          // arrow block (a x a) and the backward chain's accumulator
+  const double *SDf;       // Sigma of the middle block in the forward chain's buffer (b x b)
+  double *SDb;             // ... and where the backward chain reads it
+  const double *SRf;       // Sigma_{A,m} (a x b), likewise
+  double *SRb;
+  int a, b, m;             // arrow width, block size, middle block
+  int pad_;
+};
+// mode 0: TB = 0; mode 1: T += TB.
+hipError_t launch_twist_arrow(const TwistPair *pairs_dev, int n_pairs, int max_a, int mode,
+                              hipStream_t s);
+// For the pairs whose middle block is m == t: SDb = SDf, SRb = SRf.
+hipError_t launch_twist_middle(const TwistPair *pairs_dev, int n_pairs, int max_b, int max_a, int t,
+                               hipStream_t s);
 
 }  // namespace inla

@@ -10,6 +10,7 @@
 //   Q_AR1 = T(rho) / (1 - rho^2)  (stationary AR1, unit marginal variance),
 // observations y = A x + e, e ~ N(0, tau_y^{-1} I), so that
 //   Q_c = Q_prior + tau_y A^T A and the mode solves Q_c mu = tau_y A^T y.
+#include <algorithm>
 #include <cmath>
 
 #include "inla_internal.h"
@@ -186,12 +187,14 @@ __global__ void solve_stage_kernel(const ItemDev *__restrict__ items, int t, int
     case SV_F2: {
       // 8 rows per workgroup, 32 column lanes per row (columns cl, cl + 32, ...);
       // the 32 partial sums of a row are added in a fixed order
-      if (t >= nt) return;
+      // (a backward chain runs its first stage at its last block, the middle
+      // block of the matrix, which the forward chain factors: there it only
+      // subtracts its coupling term from the middle block's right-hand side)
+      if (t >= nt || (stage == SV_F2 && t >= it.nrun)) return;
       const int rr = tid & 7, cl = tid >> 3;
       const int r = blockIdx.x * 8 + rr;
-      const double *M = (stage == SV_F1) ? (t > 0 ? it.S + (long long)(t - 1) * bb : nullptr)
-                                         : it.D + (long long)t * bb;
-      const double *v = (stage == SV_F1) ? x + (long long)(t - 1) * b : tmp;
+      const double *M = (stage == SV_F1) ? (t > 0 ? sblk(it, t - 1) : nullptr) : dblk(it, t);
+      const double *v = (stage == SV_F1) ? (t > 0 ? x + (long long)tmap(it, t - 1) * b : nullptr) : tmp;
       const int jend = (stage == SV_F1) ? b : min(b, blockIdx.x * 8 + 8);
       // four independent partial sums per lane keep four loads in flight
       double acc = 0.0;
@@ -211,8 +214,13 @@ __global__ void solve_stage_kernel(const ItemDev *__restrict__ items, int t, int
       if (cl == 0 && r < b) {
         double sum = 0.0;
         for (int c = 0; c < 32; ++c) sum += red8[c * 8 + rr];
-        if (stage == SV_F1) tmp[r] = x[(long long)t * b + r] - sum;
-        else x[(long long)t * b + r] = sum;
+        double *xt = x + (long long)tmap(it, t) * b;
+        if (stage == SV_F1) {
+          if (t == it.nrun) xt[r] -= sum;
+          else tmp[r] = xt[r] - sum;
+        } else {
+          xt[r] = sum;
+        }
       }
       return;
     }
@@ -254,14 +262,14 @@ __global__ void solve_stage_kernel(const ItemDev *__restrict__ items, int t, int
     }
     case SV_B1:
     case SV_B2: {
-      if (t >= nt) return;
+      if (t >= it.nrun) return;
       const int j = blockIdx.x * 4 + w;
       if (j >= b) return;
       double acc = 0.0;
       if (stage == SV_B1) {
         if (t < nt - 1) {
-          const double *X = it.S + (long long)t * bb + (long long)j * b;
-          const double *xn = x + (long long)(t + 1) * b;
+          const double *X = sblk(it, t) + (long long)j * b;
+          const double *xn = x + (long long)tmap(it, t + 1) * b;
           // four independent partial sums keep four loads in flight
           double a4[4] = {0.0, 0.0, 0.0, 0.0};
           int i = lane;
@@ -273,12 +281,12 @@ __global__ void solve_stage_kernel(const ItemDev *__restrict__ items, int t, int
           acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
         }
         if (a > 0) {
-          const double *Rt = it.R + (long long)t * a * b + (long long)j * a;
-          const double *xA = x + (long long)nt * b;
+          const double *Rt = rblk(it, t) + (long long)j * a;
+          const double *xA = x + (long long)it.ntf * b;
           for (int c = lane; c < a; c += 64) acc += Rt[c] * xA[c];
         }
       } else {
-        const double *L = it.D + (long long)t * bb + (long long)j * b;
+        const double *L = dblk(it, t) + (long long)j * b;
         double a4[4] = {0.0, 0.0, 0.0, 0.0};
         int i = j + lane;
         for (; i + 192 < b; i += 256) {
@@ -291,8 +299,9 @@ __global__ void solve_stage_kernel(const ItemDev *__restrict__ items, int t, int
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
       if (lane == 0) {
-        if (stage == SV_B1) tmp[j] = x[(long long)t * b + j] - acc;
-        else x[(long long)t * b + j] = acc;
+        double *xt = x + (long long)tmap(it, t) * b;
+        if (stage == SV_B1) tmp[j] = xt[j] - acc;
+        else xt[j] = acc;
       }
       return;
     }
@@ -334,7 +343,8 @@ __global__ __launch_bounds__(256) void trace_step_kernel(const ItemDev *__restri
   __shared__ double red[4 * 256];
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   if (t < 0) {
-    // arrow block: Sigma_T
+    // arrow block: Sigma_T (a whole matrix only)
+    if (!it.own_arrow) return;
     if (a > 0) {
       if (it.diag && blk == 0 && tid < a) it.diag[(long long)nt * b + tid] = it.ST[tid + (long long)tid * a];
       if (it.trpart && it.which == 1 && it.model) {
@@ -350,16 +360,17 @@ __global__ __launch_bounds__(256) void trace_step_kernel(const ItemDev *__restri
     }
     return;
   }
-  if (t >= nt) return;
+  if (t >= it.nrun) return;
+  const int tau = tmap(it, t);   // the time block of chain step t
   const double *SD = sig_D(it, t);
   if (it.diag) {
-    for (int s = g0; s < b; s += gs) it.diag[(long long)t * b + s] = SD[s + (long long)s * b];
+    for (int s = g0; s < b; s += gs) it.diag[(long long)tau * b + s] = SD[s + (long long)s * b];
   }
   if (!it.trpart) return;
   const ModelDev &M = *it.model;
   const Coef c = make_coef(M, it.theta);
-  const double cD = ar1_diag(c, t, nt), cS = ar1_off(c);
-  const double dcD = ar1_ddiag(c, t, nt), dcS = ar1_doff(c);
+  const double cD = ar1_diag(c, tau, it.ntf), cS = ar1_off(c);
+  const double dcD = ar1_ddiag(c, tau, it.ntf), dcS = ar1_doff(c);
   const bool hasS = t < nt - 1;
   const double *SS = hasS ? sig_S(it, t) : nullptr;
   for (int e = g0; e < M.nnz; e += gs) {
@@ -369,7 +380,7 @@ __global__ __launch_bounds__(256) void trace_step_kernel(const ItemDev *__restri
     v[0] += 2.0 * cD * q * sd;
     v[1] += cD * dq * sd;
     v[2] += dcD * q * sd;
-    if (it.which == 1) v[3] += c.tauy * M.AtA[(long long)t * M.nnz + e] * sd;
+    if (it.which == 1) v[3] += c.tauy * M.AtA[(long long)tau * M.nnz + e] * sd;
     if (hasS) {
       const double ss = SS[i + (long long)s * b];
       v[0] += 4.0 * cS * q * ss;
@@ -379,7 +390,7 @@ __global__ __launch_bounds__(256) void trace_step_kernel(const ItemDev *__restri
   }
   if (it.which == 1 && a > 0) {
     const double *SR = sig_R(it, t);
-    const double *Z = M.ZtA + (long long)t * a * b;
+    const double *Z = M.ZtA + (long long)tau * a * b;
     for (int k = g0; k < a * b; k += gs) v[3] += 2.0 * c.tauy * Z[k] * SR[k];
   }
   block_reduce<256>(v, red);
@@ -523,6 +534,46 @@ __global__ __launch_bounds__(256) void combine_kernel(const CombineItem *__restr
       ci.grad[k] = st ? NAN : g;
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// two-sided elimination: arrow accumulator and the middle block's hand-over
+// ---------------------------------------------------------------------------
+
+__global__ void twist_arrow_kernel(const TwistPair *__restrict__ pairs, int mode) {
+  const TwistPair P = pairs[blockIdx.y];
+  const int n = P.a * P.a;
+  for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+    if (mode == 0) P.TB[k] = 0.0;
+    else P.T[k] += P.TB[k];
+  }
+}
+
+hipError_t launch_twist_arrow(const TwistPair *pairs_dev, int n_pairs, int max_a, int mode,
+                              hipStream_t s) {
+  if (n_pairs <= 0 || max_a <= 0) return hipSuccess;
+  const int gx = std::min((max_a * max_a + 255) / 256, 16);
+  hipLaunchKernelGGL(twist_arrow_kernel, dim3(gx, n_pairs), dim3(256), 0, s, pairs_dev, mode);
+  return hipGetLastError();
+}
+
+__global__ void twist_middle_kernel(const TwistPair *__restrict__ pairs, int t) {
+  const TwistPair P = pairs[blockIdx.y];
+  if (P.m != t) return;
+  const long long nd = (long long)P.b * P.b, nr = (long long)P.a * P.b;
+  for (long long k = blockIdx.x * 256LL + threadIdx.x; k < nd + nr; k += (long long)gridDim.x * 256) {
+    if (k < nd) P.SDb[k] = P.SDf[k];
+    else P.SRb[k - nd] = P.SRf[k - nd];
+  }
+}
+
+hipError_t launch_twist_middle(const TwistPair *pairs_dev, int n_pairs, int max_b, int max_a, int t,
+                               hipStream_t s) {
+  if (n_pairs <= 0) return hipSuccess;
+  const long long n = (long long)max_b * max_b + (long long)max_a * max_b;
+  const int gx = (int)std::min<long long>((n + 255) / 256, 512);
+  hipLaunchKernelGGL(twist_middle_kernel, dim3(gx, n_pairs), dim3(256), 0, s, pairs_dev, t);
+  return hipGetLastError();
 }
 
 hipError_t launch_combine(const CombineItem *items_dev, int n_items, hipStream_t s) {

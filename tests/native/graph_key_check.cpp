@@ -56,6 +56,8 @@ int main() {
   check(!inla::same_signature(a, c), "storage mode");
   c = a; c.vb = true;
   check(!inla::same_signature(a, c), "selected-inversion form");
+  c = a; c.twist = true;
+  check(!inla::same_signature(a, c), "elimination order");
   c = a; c.tile = 128;
   check(!inla::same_signature(a, c), "tile");
   c = a; c.step = 1;

@@ -386,7 +386,7 @@ def test_hbm_admission_waves_match_single_wave(P, monkeypatch):
     th = np.array([[0.1, 0.8, 0.5, 2.0], [0.3, 1.1, 1.0, 3.0], [-0.2, 0.6, 0.2, 2.5]])
     one = P.eval_f_grad(Ms, th)
     torch.cuda.synchronize()
-    waves = P.eval_f_grad(Ms, th, budget=1.8e5)
+    waves = P.eval_f_grad(Ms, th, budget=2.0e5)
     torch.cuda.synchronize()
     assert torch.equal(one["f"], waves["f"]) and torch.equal(one["grad"], waves["grad"])
     with pytest.raises(P.InlaError):
@@ -563,6 +563,9 @@ def test_keep_sigma_stores_selected_inverse(P, monkeypatch, si_batch, width):
     th = np.array([[0.1, 0.8, 0.5, 2.0], [0.3, 1.1, 1.0, 3.0], [-0.2, 0.6, 0.2, 2.5]])
     sig = [P.BtaTensors(M.b, M.nt, M.a) for M in Ms]
     out = P.eval_f_grad(Ms, th, want_var=True, tile=width, sigma=sig)
+    # (keeping Sigma in caller storage eliminates every matrix from its first
+    # time block on: the bitwise reference does the same)
+    monkeypatch.setenv("INLA_TWIST", "0")
     ref = P.eval_f_grad(Ms, th, want_var=True, tile=width)
     torch.cuda.synchronize()
     for key in ("f", "grad", "var", "status"):
@@ -651,3 +654,30 @@ def test_bfgs_parallel_line_search_reaches_the_mode(P, name):
     assert f_at <= ref.fun + 1e-10 * abs(ref.fun)
     assert rel(res["f"], f_at) < 1e-10
     assert np.abs(res["theta"] - ref.x).max() < 1e-3
+
+
+@pytest.mark.parametrize("N,nt,nb", [(6, 4, 2), (5, 5, 0), (9, 7, 3), (12, 6, 1), (4, 9, 2)])
+def test_two_sided_elimination_matches_one_sided(P, monkeypatch, N, nt, nb):
+    """Eliminating the time blocks from both ends at once (a forward chain up
+    to the middle block and a backward chain down to it, the default from four
+    time blocks on) gives the one-sided results to rounding, and both match
+    the oracle: f, grad f, mu and the variances."""
+    print(f"two-sided elimination N={N} nt={nt} nb={nb}", flush=True)
+    md = make_model(N, nt, nb, 100 + N + nt)
+    M = P.Model.from_data(md)
+    theta = np.array([0.2, 0.8, 0.9, 3.2])
+    out = {}
+    for flag in ("1", "0"):
+        monkeypatch.setenv("INLA_TWIST", flag)
+        out[flag] = P.eval_f_grad(M, theta, want_mu=True, want_var=True)
+        torch.cuda.synchronize()
+    for flag in ("1", "0"):
+        check_against_dense_oracle(out[flag], 0, md, theta)
+    a, b = out["1"], out["0"]
+    assert rel(a["f"].item(), b["f"].item()) < 1e-12
+    scale = np.maximum(grad_term_magnitudes(md, theta), 1e-3 * np.abs(b["grad"].cpu().numpy()).max())
+    assert np.max(np.abs(a["grad"].cpu().numpy() - b["grad"].cpu().numpy()) / scale) < 1e-11
+    va, vb = a["var"].cpu().numpy(), b["var"].cpu().numpy()
+    assert np.max(np.abs(va - vb) / vb) < 1e-11
+    ma, mb = a["mu"].cpu().numpy(), b["mu"].cpu().numpy()
+    assert np.abs(ma - mb).max() / np.abs(mb).max() < 1e-11
