@@ -1587,6 +1587,7 @@ __device__ __forceinline__ int find_item(const ItemDev *items, int n_items, int 
     }
     base += tot;
   }
+  q -= base;   // past the last task: q counts on from the end
   return n_items;
 }
 
@@ -1597,21 +1598,35 @@ __global__ __launch_bounds__(kThreads, FAT ? 1 : 2) void tile_phase_kernel(const
                                                               int n_items, int phase, int phase2,
                                                               int t, int p) {
   __shared__ double smem[FAT ? kFatLds : kLeanLds];
-  // tasks are ordered item by item, the item's `phase` tasks before its `phase2` ones
   int q = blockIdx.x;
-  const int ii = find_item(items, n_items, q, [&](const ItemDev &x) {
-    return phase_tasks(x, phase, t, p) + (phase2 >= 0 ? phase_tasks(x, phase2, t, p) : 0);
-  });
-  if (ii >= n_items) return;
-  const ItemDev it = items[ii];
+  int ii;
   int ph = phase;
-  {
-    const int c1 = phase_tasks(it, phase, t, p);
+  if ((phase == PH_STEP || phase == PH_STEPF) && phase2 < 0) {
+    // a Cholesky step: the long tasks of every item take the first
+    // workgroups, so that none of them waits for a second round behind short ones
+    ii = find_item(items, n_items, q, [&](const ItemDev &x) {
+      return step_split(x.nP, phase, t, p, x.nrun).nlong();
+    });
+    const bool is_long = ii < n_items;
+    if (!is_long)
+      ii = find_item(items, n_items, q, [&](const ItemDev &x) {
+        return step_split(x.nP, phase, t, p, x.nrun).nshort();
+      });
+    if (ii >= n_items) return;
+    q = step_task_local(step_split(items[ii].nP, phase, t, p, items[ii].nrun), is_long, q);
+  } else {
+    // tasks are ordered item by item, the item's `phase` tasks before its `phase2` ones
+    ii = find_item(items, n_items, q, [&](const ItemDev &x) {
+      return phase_tasks(x, phase, t, p) + (phase2 >= 0 ? phase_tasks(x, phase2, t, p) : 0);
+    });
+    if (ii >= n_items) return;
+    const int c1 = phase_tasks(items[ii], phase, t, p);
     if (q >= c1) {
       q -= c1;
       ph = phase2;
     }
   }
+  const ItemDev it = items[ii];
   Task tk;
   decode<FAT ? kFatOnly : kLeanOnly>(it, ph, t, p, q, tk);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;

@@ -146,6 +146,47 @@ __host__ __device__ inline bool phase_is_product_x(int phase) {
 
 __host__ __device__ inline int ntile(int n) { return (n + kTile - 1) / kTile; }
 
+// The tasks of a Cholesky step launch (PH_STEP, PH_STEPF) of one item in two
+// classes: long ones (the diagonal tile, the chained tasks of column p+1 and
+// of the diagonal tile of column p+2, row p of inv(L_tt)) and short ones
+// (single products: panels, the rest of panel p-1's update, running sums).
+// step_task_local maps an index within a class to the item's task index in
+// the decoder's order (diagonal tile, panels, chained tasks, deferred
+// updates, rows, running sums).
+struct StepSplit {
+  int ndiag, npan, ncol, ndef, nrow, nsum;
+  __host__ __device__ int nlong() const { return ndiag + ncol + (ndef > 0 ? 1 : 0) + nrow; }
+  __host__ __device__ int nshort() const { return npan + ndef - (ndef > 0 ? 1 : 0) + nsum; }
+};
+__host__ __device__ inline StepSplit step_split(int nP, int phase, int t, int p, int nrun) {
+  StepSplit z{0, 0, 0, 0, 0, 0};
+  if (t >= nrun || p >= nP) return z;
+  z.npan = nP - 1 - p;
+  z.ncol = (nP - 2 - p > 0) ? nP - 2 - p : 0;
+  z.ndef = (p >= 1) ? z.ncol * (z.ncol + 1) / 2 : (z.ncol > 0 ? 1 : 0);
+  z.nrow = p;
+  z.nsum = (phase == PH_STEPF) ? (nP - 1 - p) * p : 0;
+  z.ndiag = (phase == PH_STEPF && p < nP - 1) ? 1 : 0;
+  return z;
+}
+__host__ __device__ inline int step_task_local(const StepSplit &z, bool is_long, int c) {
+  const int d1 = z.ndef > 0 ? 1 : 0;
+  if (is_long) {
+    if (c < z.ndiag) return 0;
+    c -= z.ndiag;
+    if (c < z.ncol) return z.ndiag + z.npan + c;
+    c -= z.ncol;
+    if (c < d1) return z.ndiag + z.npan + z.ncol;   // deferred task 0: the chained diagonal tile
+    c -= d1;
+    return z.ndiag + z.npan + z.ncol + z.ndef + c;
+  }
+  if (c < z.npan) return z.ndiag + c;
+  c -= z.npan;
+  if (c < z.ndef - d1) return z.ndiag + z.npan + z.ncol + d1 + c;
+  c -= z.ndef - d1;
+  return z.ndiag + z.npan + z.ncol + z.ndef + z.nrow + c;
+}
+
 // Number of workgroup tasks of one item in (phase, t, p); big selects 128-tiles
 // for the _X phases.
 __host__ __device__ inline int phase_tasks(const ItemDev &it, int phase, int t, int p,
