@@ -360,6 +360,79 @@ inla_status inla_bfgs_minimize(const inla_model *model, const double *theta0,
                                double *history_or_null, void *hip_stream);
 
 /*
+ * Options of inla_integrate (NULL = defaults; a field <= 0 = its default).
+ *   h         : step of the central differences of the gradient (1e-3)
+ *   dz        : grid step in standardised coordinates (1)
+ *   dpi       : keep a point when f(theta) - f(theta*) < dpi (2.5)
+ *   max_steps : steps per direction of the axis exploration (6)
+ *   max_box   : the box of grid points may hold at most this many (20000)
+ *   eval_opts : options of the evaluations (NULL = defaults)
+ */
+typedef struct {
+  double h;
+  double dz;
+  double dpi;
+  int32_t max_steps;
+  int32_t max_box;
+  const inla_opts *eval_opts;
+} inla_integrate_opts;
+
+/* Result of inla_integrate.  Matrices are row-major; eigvec[4 i + j] is entry
+ * i of eigenvector j.  lo[j] / hi[j]: the axis ranges, in grid steps, on the
+ * negative / positive side of direction j.  n_points: the points kept (K);
+ * n_box: the candidates evaluated. */
+typedef struct {
+  double f_mode, grad_mode[4];
+  double hessian[16];
+  double eigval[4], eigvec[16];
+  double theta_mean[4], theta_cov[16];
+  double log_evidence;
+  int32_t lo[4], hi[4];
+  int32_t n_box, n_points, f_evals, grad_evals;
+} inla_integrate_result;
+
+/*
+ * The integration step after the mode search for one model (Sec. "Latent
+ * Gaussian Models": points around theta* at which pi~(theta | y) is evaluated
+ * for the numerical integration of the hyperparameter marginals; Sec.
+ * "Approximating pi(x_i | y)", eq. LatParam: the latent marginals integrated
+ * over those points, one partial inversion per point; Sec. "Parallelization
+ * of Function Evaluations": the points and their partial inversions are
+ * independent and evaluated in batched calls).  The paper fixes no design of
+ * the points; this one is the standardised grid of Rue, Martino and Chopin
+ * (2009):
+ *   1. H = Hessian of f at theta_mode by central differences of the adjoint
+ *      gradient (theta_mode and theta_mode +- h e_k in ONE batched
+ *      inla_eval_f_grad call), symmetrised;
+ *   2. H = V diag(lambda) V^T, lambda ascending, each eigenvector's
+ *      largest-magnitude entry positive (INLA_ERR_NOT_SPD if some
+ *      lambda <= 0); theta(z) = theta_mode + V diag(lambda^{-1/2}) z;
+ *   3. along each direction +-e_j in z, steps s = 1..max_steps of length dz
+ *      while f(theta(s dz e_j)) - f* < dpi (all 2 x 4 x max_steps points in one
+ *      batched inla_eval_f call): the ranges lo[j], hi[j];
+ *   4. every z = dz s, s integer in the box [-lo, hi], evaluated in batched
+ *      calls (INLA_ERR_ARG if the box holds more than max_box points) and kept
+ *      when f - f* < dpi (f* = f(theta_mode) of step 1; an item whose Q is not
+ *      positive definite counts as f = +inf);
+ *   5. w_k = exp(-(f_k - f*)) / sum; E[theta|y], Cov[theta|y] the weighted
+ *      sums; log pi(y) = -f* + log sum exp(-(f_k - f*)) + 4 log dz
+ *      - sum_j log(lambda_j) / 2;
+ *   6. if x_mean_dev or x_var_dev is non-NULL (device, n doubles each): the
+ *      mean and variance of the mixture sum_k w_k N(mu(theta^k),
+ *      diag Q_c(theta^k)^{-1}) (eq. LatParam with the Gaussian conditionals),
+ *      mu and the marginal variances at the K points from batched inla_eval_f
+ *      calls (K selected inversions).
+ * points_or_null: host, up to points_cap rows of 10 doubles, one per kept
+ * point in lexicographic order of s: s[4], theta[4], f, w.
+ * Synchronises hip_stream (the decisions are on the host); allocates device
+ * buffers for the batches (at most about 1 GiB for the latent step).
+ */
+inla_status inla_integrate(const inla_model *model, const double *theta_mode,
+                           const inla_integrate_opts *opts, inla_integrate_result *res,
+                           double *points_or_null, int32_t points_cap, double *x_mean_dev,
+                           double *x_var_dev, void *hip_stream);
+
+/*
  * Instrumentation for benchmarks.  Between inla_profile_begin() and
  * inla_profile_end() every kernel launch of the library is bracketed by HIP
  * events on the stream it runs on.  inla_profile_end waits for those events

@@ -18,6 +18,7 @@ from .binding import (  # noqa: F401
     factor_logdet,
     factor_logdet_noalloc,
     header_functions,
+    integrate,
     lib,
     minimize,
     objective,

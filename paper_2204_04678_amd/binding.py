@@ -56,6 +56,20 @@ class BfgsResult(C.Structure):
                 ("reason", C.c_int32)]
 
 
+class IntegrateOpts(C.Structure):
+    _fields_ = [("h", C.c_double), ("dz", C.c_double), ("dpi", C.c_double),
+                ("max_steps", C.c_int32), ("max_box", C.c_int32), ("eval_opts", C.POINTER(Opts))]
+
+
+class IntegrateResult(C.Structure):
+    _fields_ = [("f_mode", C.c_double), ("grad_mode", C.c_double * 4),
+                ("hessian", C.c_double * 16), ("eigval", C.c_double * 4),
+                ("eigvec", C.c_double * 16), ("theta_mean", C.c_double * 4),
+                ("theta_cov", C.c_double * 16), ("log_evidence", C.c_double),
+                ("lo", C.c_int32 * 4), ("hi", C.c_int32 * 4), ("n_box", C.c_int32),
+                ("n_points", C.c_int32), ("f_evals", C.c_int32), ("grad_evals", C.c_int32)]
+
+
 _LIB = None
 
 _SIGS = {
@@ -88,6 +102,9 @@ _SIGS = {
                                             C.POINTER(C.c_double)]),
     "inla_bfgs_minimize": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(BfgsOpts),
                                      C.POINTER(BfgsResult), C.POINTER(C.c_double), C.c_void_p]),
+    "inla_integrate": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(IntegrateOpts),
+                                 C.POINTER(IntegrateResult), C.POINTER(C.c_double), C.c_int32,
+                                 C.c_void_p, C.c_void_p, C.c_void_p]),
     "inla_release_workspace": (None, []),
     "inla_profile_begin": (C.c_int, []),
     "inla_profile_end": (C.c_int, [C.POINTER(C.c_double), C.c_int32]),
@@ -492,6 +509,40 @@ def minimize(model: Model, theta0, max_iter=100, n_points=6, gamma=1.0, gtol=1e-
     return dict(theta=np.array(res.theta[:]), f=res.f, grad=np.array(res.grad[:]),
                 iterations=res.iterations, f_evals=res.f_evals, grad_evals=res.grad_evals,
                 reason=res.reason, history=h)
+
+
+def integrate(model: Model, theta_mode, h=1e-3, dz=1.0, dpi=2.5, max_steps=6, max_box=20000,
+              latent=True, points_cap=4096, **eval_opts):
+    """The integration step at the mode (inla_integrate): the FD Hessian of the
+    adjoint gradient, the standardised grid, the quadrature over theta and, if
+    latent, the mixture mean and variance of the latent field (device tensors).
+    Returns a dict of the result fields, 'points' (K x 10: s[4], theta[4], f, w)
+    and 'x_mean' / 'x_var'."""
+    th = (C.c_double * 4)(*[float(v) for v in np.asarray(theta_mode, dtype=np.float64)])
+    eo = _opts(**eval_opts) if eval_opts else None
+    o = IntegrateOpts(float(h), float(dz), float(dpi), int(max_steps), int(max_box),
+                      C.pointer(eo) if eo is not None else None)
+    res = IntegrateResult()
+    pts = (C.c_double * (10 * points_cap))()
+    xm = xv = None
+    if latent:
+        n = model.n
+        xm = torch.empty(n, dtype=torch.float64, device="cuda")
+        xv = torch.empty(n, dtype=torch.float64, device="cuda")
+    _check(lib().inla_integrate(model.handle, th, C.byref(o), C.byref(res), pts, points_cap,
+                                _ptr(xm), _ptr(xv), _stream()))
+    K = res.n_points
+    out = dict(f_mode=res.f_mode, grad_mode=np.array(res.grad_mode[:]),
+               hessian=np.array(res.hessian[:]).reshape(4, 4), eigval=np.array(res.eigval[:]),
+               eigvec=np.array(res.eigvec[:]).reshape(4, 4),
+               theta_mean=np.array(res.theta_mean[:]),
+               theta_cov=np.array(res.theta_cov[:]).reshape(4, 4),
+               log_evidence=res.log_evidence, lo=np.array(res.lo[:]), hi=np.array(res.hi[:]),
+               n_box=res.n_box, n_points=K, f_evals=res.f_evals, grad_evals=res.grad_evals,
+               points=np.array(pts[:10 * min(K, points_cap)]).reshape(-1, 10))
+    if latent:
+        out["x_mean"], out["x_var"] = xm, xv
+    return out
 
 
 def release_workspace():

@@ -320,6 +320,15 @@ struct TwistPair {
   int a, b, m;             // arrow width, block size, middle block
   int pad_;
 };
+// Mixture of K Gaussians N(mu^k, v^k) with weights w (device, K doubles; mu, var:
+// K x n point-major).  With d = mu^k - shift: acc_m (+)= sum_k w_k d,
+// acc_s (+)= sum_k w_k (v^k + d^2) (init = 1 starts from zero).  The finish
+// writes mean = shift + acc_m and var = acc_s - acc_m^2 (weights summing to 1).
+hipError_t launch_mixture_accumulate(const double *mu, const double *var, const double *w, int K,
+                                     long long n, const double *shift, double *acc_m, double *acc_s,
+                                     int init, hipStream_t s);
+hipError_t launch_mixture_finish(const double *shift, const double *acc_m, const double *acc_s,
+                                 long long n, double *mean_out, double *var_out, hipStream_t s);
 // mode 0: TB = 0; mode 1: T += TB.
 hipError_t launch_twist_arrow(const TwistPair *pairs_dev, int n_pairs, int max_a, int mode,
                               hipStream_t s);

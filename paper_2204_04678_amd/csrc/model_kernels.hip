@@ -576,6 +576,59 @@ hipError_t launch_twist_middle(const TwistPair *pairs_dev, int n_pairs, int max_
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// latent marginals over integration points: the mixture of the Gaussians
+// N(mu^k, v^k) with weights w_k (the numerical integral of eq. LatParam),
+// accumulated chunk by chunk about a shift (the mode's mu) so that the
+// variance is not a difference of two large second moments
+// ---------------------------------------------------------------------------
+
+__global__ void mixture_accumulate_kernel(const double *__restrict__ mu, const double *__restrict__ var,
+                                          const double *__restrict__ w, int K, long long n,
+                                          const double *__restrict__ shift, double *acc_m,
+                                          double *acc_s, int init) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    double m = init ? 0.0 : acc_m[i], s2 = init ? 0.0 : acc_s[i];
+    const double c = shift[i];
+    for (int k = 0; k < K; ++k) {
+      const double d = mu[(long long)k * n + i] - c;
+      m = fma(w[k], d, m);
+      s2 = fma(w[k], fma(d, d, var[(long long)k * n + i]), s2);
+    }
+    acc_m[i] = m;
+    acc_s[i] = s2;
+  }
+}
+
+__global__ void mixture_finish_kernel(const double *__restrict__ shift, const double *__restrict__ acc_m,
+                                      const double *__restrict__ acc_s, long long n, double *mean_out,
+                                      double *var_out) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    const double m = acc_m[i];
+    if (mean_out) mean_out[i] = shift[i] + m;
+    if (var_out) var_out[i] = acc_s[i] - m * m;
+  }
+}
+
+hipError_t launch_mixture_accumulate(const double *mu, const double *var, const double *w, int K,
+                                     long long n, const double *shift, double *acc_m, double *acc_s,
+                                     int init, hipStream_t s) {
+  if (n <= 0 || K <= 0) return hipSuccess;
+  const int gx = (int)std::min<long long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(mixture_accumulate_kernel, dim3(gx), dim3(256), 0, s, mu, var, w, K, n, shift,
+                     acc_m, acc_s, init);
+  return hipGetLastError();
+}
+
+hipError_t launch_mixture_finish(const double *shift, const double *acc_m, const double *acc_s,
+                                 long long n, double *mean_out, double *var_out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int gx = (int)std::min<long long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(mixture_finish_kernel, dim3(gx), dim3(256), 0, s, shift, acc_m, acc_s, n,
+                     mean_out, var_out);
+  return hipGetLastError();
+}
+
 hipError_t launch_combine(const CombineItem *items_dev, int n_items, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   hipLaunchKernelGGL(combine_kernel, dim3(n_items), dim3(256), 0, s, items_dev);

@@ -116,3 +116,20 @@ def test_state_and_sigma_argument_errors(libpath):
     assert b"state is NULL" in L.inla_last_error()
     assert L.inla_eval_state_kept(None) == 0
     L.inla_eval_state_destroy(None)
+
+
+def test_integrate_argument_errors(libpath):
+    """inla_integrate rejects bad arguments on the host before any device call."""
+    L = binding.lib(libpath)
+    res = binding.IntegrateResult()
+    th = (ctypes.c_double * 4)(0.0, 0.0, 0.0, 0.0)
+    assert L.inla_integrate(None, th, None, ctypes.byref(res), None, 0, None, None, None) == -1
+    assert b"need model" in L.inla_last_error()
+    bad = (ctypes.c_double * 4)(0.0, float("nan"), 0.0, 0.0)
+    dummy = ctypes.c_void_p(64)
+    assert L.inla_integrate(dummy, bad, None, ctypes.byref(res), None, 0, None, None, None) == -1
+    assert b"not finite" in L.inla_last_error()
+    o = binding.IntegrateOpts(0.0, 0.0, 0.0, 65, 0, None)
+    assert L.inla_integrate(dummy, th, ctypes.byref(o), ctypes.byref(res), None, 0, None, None,
+                            None) == -1
+    assert b"max_steps" in L.inla_last_error()

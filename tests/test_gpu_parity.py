@@ -681,3 +681,50 @@ def test_two_sided_elimination_matches_one_sided(P, monkeypatch, N, nt, nb):
     assert np.max(np.abs(va - vb) / vb) < 1e-11
     ma, mb = a["mu"].cpu().numpy(), b["mu"].cpu().numpy()
     assert np.abs(ma - mb).max() / np.abs(mb).max() < 1e-11
+
+
+@pytest.mark.parametrize("N,nt,nb,seed", [(4, 3, 2, 5), (9, 4, 3, 31)])
+def test_integrate_matches_oracle(P, N, nt, nb, seed):
+    """The integration step at the mode (Sec. "Latent Gaussian Models", eq.
+    LatParam) against the oracle's: the Hessian from differences of the
+    adjoint gradient, the eigen-decomposition, the axis ranges, the kept grid
+    points (the same integer coordinates), their f and weights, the theta
+    moments, the log evidence and the latent mixture mean and variance.  The
+    second model has 64-wide tiles in two columns and four time blocks (the
+    two-sided elimination).  The mode comes from scipy's BFGS on the oracle."""
+    from scipy.optimize import minimize as sp_minimize
+    from oracle import integrate as OI
+    print(f"integrate N={N} nt={nt} nb={nb}", flush=True)
+    md = make_model(N, nt, nb, seed)
+    g0 = O.dense_gradient(md, THETA0)
+    mode = sp_minimize(lambda th: O.eval_f_dense(md, th)["f"], THETA0,
+                       jac=lambda th: O.dense_gradient(md, th), method="BFGS",
+                       options=dict(gtol=1e-9, maxiter=400,
+                                    hess_inv0=np.eye(4) / np.abs(g0).max())).x
+    ref = OI.integrate_model(md, mode)
+    # no candidate's drop is within rounding of the threshold (both sides
+    # decide keep / drop in FP64 from f values that agree to ~1e-9)
+    assert np.abs(ref["drops"] - 2.5).min() > 1e-4
+    M = P.Model.from_data(md)
+    r = P.integrate(M, mode)
+    Hs = np.abs(ref["hessian"]).max()
+    assert np.abs(r["hessian"] - ref["hessian"]).max() < 1e-7 * Hs
+    np.testing.assert_allclose(r["eigval"], ref["eigval"], rtol=1e-6)
+    np.testing.assert_allclose(r["eigvec"], ref["eigvec"], atol=1e-5)
+    assert list(r["lo"]) == list(ref["lo"]) and list(r["hi"]) == list(ref["hi"])
+    assert r["n_box"] == ref["n_box"] and r["n_points"] == len(ref["f"])
+    pts = r["points"]
+    assert np.array_equal(pts[:, :4].astype(int), ref["s"])
+    np.testing.assert_allclose(pts[:, 4:8], ref["theta"], rtol=0, atol=1e-6)
+    assert rel(r["f_mode"], ref["f_mode"]) < 1e-10
+    assert np.abs(pts[:, 8] - ref["f"]).max() < 1e-6 * max(1.0, abs(ref["f_mode"]))
+    np.testing.assert_allclose(pts[:, 9], ref["weights"], rtol=1e-5)
+    np.testing.assert_allclose(r["theta_mean"], ref["theta_mean"], rtol=0, atol=1e-6)
+    np.testing.assert_allclose(r["theta_cov"], ref["theta_cov"], rtol=1e-5,
+                               atol=1e-7 * np.abs(ref["theta_cov"]).max())
+    assert abs(r["log_evidence"] - ref["log_evidence"]) < 1e-5
+    xm = r["x_mean"].cpu().numpy()
+    xv = r["x_var"].cpu().numpy()
+    assert np.abs(xm - ref["x_mean"]).max() < 1e-8 * np.abs(ref["x_mean"]).max()
+    np.testing.assert_allclose(xv, ref["x_var"], rtol=1e-7)
+    assert r["grad_evals"] == 9 and r["f_evals"] == 8 * 6 + r["n_box"] + 1 + r["n_points"]
