@@ -32,21 +32,66 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6  # MI355X, dense FP64 matrix (and vector) peak, published
 
 
-def flops_chol(b, nt, a):
-    """Dense-block BTA Cholesky: POTRF per block, TRSM/SYRK/GEMM couplings, arrow."""
-    return (nt * b ** 3 / 3 + (nt - 1) * (2 * b ** 3 + 2 * a * b * b) + nt * (a * b * b + a * a * b)
-            + a ** 3 / 3)
+def coupling_halfbandwidth(N):
+    """Half-bandwidth of the coupling blocks c(rho) Q_s of an N x N grid: Q_s
+    couples nodes up to grid distance 2 (|dx| + |dy| <= 2), which in the
+    row-major order is an index offset of at most 2N (N + 1 on a 2 x 2 grid)."""
+    b = N * N
+    if N == 1:
+        return 0
+    return min(2 * N, b - 1) if N >= 3 else N + 1
 
 
-def flops_selinv(b, nt, a):
-    """Block selected inversion: per step POTRI (2/3 b^3), V (b^3), Sigma_S (2 b^3), Sigma_D (b^3)."""
-    return nt * (2.0 / 3.0) * b ** 3 + (nt - 1) * 4 * b ** 3 + nt * (4 * a * b * b + 2 * a * a * b)
+def band_macs(b, w):
+    """Multiply-adds of the band-aware b x b products (entry by entry): X = S
+    inv(L)^T with S of half-bandwidth w, the lower half of X X^T, V = X inv(L),
+    and one arrow row times X^T.  With w >= b - 1 these are the dense counts."""
+    r = np.arange(b, dtype=np.float64)
+    lo = np.maximum(0.0, r - w)
+    hi = np.minimum(b - 1.0, r + w)
+    L = hi - lo + 1
+    x = float(np.sum(0.5 * L * (L + 1) + (b - 1 - hi) * L))
+    syrk = float(np.sum((r + 1) * (b - lo)))
+    v = float(np.sum(lo * (b - lo) + 0.5 * (b - lo) * (b - lo + 1)))
+    arrow = float(np.sum(b - lo))
+    return x, syrk, v, arrow
+
+
+def flops_chol(b, nt, a, w=None):
+    """BTA Cholesky: POTRF and TRTRI per block, the coupling X = S inv(L)^T
+    (TRMM), the Schur update (SYRK), the arrow couplings, the arrow block.
+    w: the coupling blocks' half-bandwidth (None: dense)."""
+    if w is None or w >= b - 1:
+        cpl = 2 * b ** 3 + 2 * a * b * b
+    else:
+        x, syrk, _, arrow = band_macs(b, w)
+        cpl = 2 * x + 2 * syrk + 2 * a * arrow
+    return nt * b ** 3 / 3 + (nt - 1) * cpl + nt * (a * b * b + a * a * b) + a ** 3 / 3
+
+
+def flops_selinv(b, nt, a, w=None):
+    """Block selected inversion: per step POTRI (2/3 b^3), V = L_{t+1,t} inv(L_tt)
+    (b^3 dense; band-aware with w), Sigma_S (2 b^3), Sigma_D (b^3)."""
+    if w is None or w >= b - 1:
+        vv = b ** 3
+    else:
+        vv = 2 * band_macs(b, w)[2]
+    return nt * (2.0 / 3.0) * b ** 3 + (nt - 1) * (vv + 3 * b ** 3) + nt * (4 * a * b * b + 2 * a * a * b)
+
+
+def band_of(md):
+    """The half-bandwidth the library uses for this model (None with INLA_BAND=0)."""
+    if os.environ.get("INLA_BAND", "1").startswith("0"):
+        return None
+    return coupling_halfbandwidth(md.N)
 
 
 def kernel_sources_sha256():
@@ -217,7 +262,8 @@ def measure(P, config, model, theta, mds, steps, warmup, timing_steps):
     returns the throughput record and the roofline of the dominant tile kernel."""
     import torch
     n_items = theta.shape[0]
-    F_alg = sum(2 * flops_chol(m.ns, m.nt, m.nb) + 2 * flops_selinv(m.ns, m.nt, m.nb) for m in mds)
+    F_alg = sum(2 * flops_chol(m.ns, m.nt, m.nb, band_of(m)) + 2 * flops_selinv(m.ns, m.nt, m.nb, band_of(m))
+                for m in mds)
     # Timed region: the evaluation replays its captured hipGraph (one launch of
     # the whole kernel sequence per step).
     for _ in range(max(warmup, 1)):
@@ -372,7 +418,8 @@ def main():
         r5 = measure(P, "c5", m5, th5, mds5, args.largest_steps, args.largest_warmup, 1)
         extra["largest_block"] = {
             "config": {"workload": wl5, "b": mds5[0].ns, "nt": mds5[0].nt, "a": mds5[0].nb,
-                       "n": mds5[0].n, "items": th5.shape[0]},
+                       "n": mds5[0].n, "items": th5.shape[0],
+                       "coupling_halfbandwidth": band_of(mds5[0])},
             "steps": args.largest_steps, "warmup": args.largest_warmup,
             "value": round(r5["value"], 4), "unit": "evals/s",
             "ms_per_step": round(r5["step_s"] * 1e3, 3),
@@ -399,7 +446,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded grid model; no dataset)",
         "config": {"workload": workload, "b": md.ns, "nt": md.nt, "a": md.nb, "n": md.n,
-                   "items": n_items},
+                   "items": n_items,
+                   "coupling_halfbandwidth": (band_of(md) if len({m.N for m in mds}) == 1
+                                              else "2N per model")},
         "build_id": P.build_id(),
         "pct_fp64_peak_whole_step": round(100 * r["F_alg"] / step_s / (PEAK_FP64_TFLOPS * 1e12), 3),
         "alg_flops_per_step": r["F_alg"],

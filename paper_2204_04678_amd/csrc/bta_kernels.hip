@@ -143,6 +143,19 @@ __device__ inline void set_seg(Seg &g, const double *A, int ars, int aks, const 
   g.k0 = k0; g.k1 = k1; g.alpha = alpha;
 }
 
+// Band of the coupling blocks (ItemDev::sbw).  Rows r >= r0 of S[t] and of
+// X = S[t] inv(L_tt)^T are zero at k < r0 - sbw: band_lo is that bound
+// rounded down to a multiple of 64 (0 when S is dense).  Rows r < r1 of S[t]
+// are zero at k > r1 - 1 + sbw: band_hi is the exclusive bound rounded up to
+// a multiple of 64, at most b.  Skipping those k ranges leaves out exact
+// zeros only.
+__device__ inline int band_lo(const ItemDev &it, int r0) {
+  return it.sbw >= it.b ? 0 : (max(0, r0 - it.sbw) & ~(kTile - 1));
+}
+__device__ inline int band_hi(const ItemDev &it, int r1) {
+  return it.sbw >= it.b ? it.b : min(it.b, ((r1 - 1 + it.sbw) / kTile + 1) * kTile);
+}
+
 // V_t = L_{t+1,t} inv(L_tt) and U_t = L_{A,t} inv(L_tt) of step t of the
 // selected inversion: formed up front for every step (V, U) or step by step in
 // the workspace (W2, W3).  V has no slot for the last step, whose V is never read.
@@ -299,11 +312,13 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
     case PH_OFFDIAG_X: {
       SIDE_ONLY(SIDE == kLeanOnly)
       // k runs to the end of tile column j: the longest tiles first
+      // (X = S[t] inv(L_tt)^T: k <= the last column of tile j, and within S's band)
       const int j = nP - 1 - q / nP, i = q % nP;
       tk.m = tdim(b, i); tk.n = tdim(b, j);
       tk.C = it.W2 + toff(b, i, j); tk.ldc = b;
-      set_seg(tk.seg[0], St + (long long)i * kTile, 1, b, Dt + (long long)j * kTile, 1, b, 0,
-              min(b, (j + 1) * kTile), 1.0);
+      set_seg(tk.seg[0], St + (long long)i * kTile, 1, b, Dt + (long long)j * kTile, 1, b,
+              band_lo(it, i * kTile), min(min(b, (j + 1) * kTile), band_hi(it, i * kTile + tk.m)),
+              1.0);
       tk.nseg = 1;
       return;
     }
@@ -328,11 +343,11 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
     case PH_SCHUR_X: {
       SIDE_ONLY(SIDE == kLeanOnly)
       int i, j;
-      tri_decode(q, i, j);
+      tri_decode(q, i, j);   // i >= j: the rows of tile i bound the nonzero k of both
       tk.m = tdim(b, i); tk.n = tdim(b, j);
       tk.C = dblk(it, t + 1) + toff(b, i, j); tk.ldc = b; tk.beta = 1.0;
-      set_seg(tk.seg[0], it.W2 + (long long)i * kTile, 1, b, it.W2 + (long long)j * kTile, 1, b, 0, b,
-              -1.0);
+      set_seg(tk.seg[0], it.W2 + (long long)i * kTile, 1, b, it.W2 + (long long)j * kTile, 1, b,
+              band_lo(it, i * kTile), b, -1.0);
       tk.nseg = 1;
       return;
     }
@@ -356,7 +371,8 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
             tk.m = a; tk.n = tdim(b, j);
             tk.C = rblk(it, t + 1) + (long long)j * kTile * a; tk.ldc = a;
             tk.beta = 1.0;
-            set_seg(tk.seg[0], it.W3, 1, a, it.W2 + (long long)j * kTile, 1, b, 0, b, -1.0);
+            set_seg(tk.seg[0], it.W3, 1, a, it.W2 + (long long)j * kTile, 1, b,
+                    band_lo(it, j * kTile), b, -1.0);
             tk.nseg = 1;
             return;
           }
@@ -402,7 +418,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       tk.m = tdim(b, i); tk.n = tdim(b, j);
       tk.C = it.W2 + toff(b, i, j); tk.ldc = b;
       set_seg(tk.seg[0], St + (long long)i * kTile, 1, b, Dt + (long long)j * kTile * b, b, 1,
-              j * kTile, b, 1.0);
+              max(j * kTile, band_lo(it, i * kTile)), b, 1.0);
       tk.nseg = 1;
       return;
     }
@@ -424,7 +440,7 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
       tk.m = tdim(b, i); tk.n = tdim(b, j);
       tk.C = it.V + (long long)tt * bb + toff(b, i, j); tk.ldc = b;
       set_seg(tk.seg[0], Sq + (long long)i * kTile, 1, b, Dq + (long long)j * kTile * b, b, 1,
-              j * kTile, b, 1.0);
+              max(j * kTile, band_lo(it, i * kTile)), b, 1.0);
       tk.nseg = 1;
       return;
     }
@@ -552,8 +568,8 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
       J = nQ - 1 - q / nQ; I = q % nQ;
       tk.m = bdim<TS>(b, I); tk.n = bdim<TS>(b, J); tk.ti = I; tk.tj = J;
       tk.C = it.W2 + boff<TS>(b, I, J); tk.ldc = b;
-      set_seg(tk.seg[0], St + (long long)I * TS, 1, b, Dt + (long long)J * TS, 1, b, 0,
-              min(b, (J + 1) * TS), 1.0);
+      set_seg(tk.seg[0], St + (long long)I * TS, 1, b, Dt + (long long)J * TS, 1, b,
+              band_lo(it, I * TS), min(min(b, (J + 1) * TS), band_hi(it, I * TS + tk.m)), 1.0);
       tk.nseg = 1;
       return;
     case PH_SCHUR_X:
@@ -561,8 +577,8 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
       tri_decode(q, I, J);
       tk.m = bdim<TS>(b, I); tk.n = bdim<TS>(b, J); tk.ti = I; tk.tj = J;
       tk.C = dblk(it, t + 1) + boff<TS>(b, I, J); tk.ldc = b; tk.beta = 1.0;
-      set_seg(tk.seg[0], it.W2 + (long long)I * TS, 1, b, it.W2 + (long long)J * TS, 1, b, 0, b,
-              -1.0);
+      set_seg(tk.seg[0], it.W2 + (long long)I * TS, 1, b, it.W2 + (long long)J * TS, 1, b,
+              band_lo(it, I * TS), b, -1.0);
       tk.nseg = 1;
       return;
     case PH_SI_VU_X:
@@ -572,7 +588,7 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
       tk.m = bdim<TS>(b, I); tk.n = bdim<TS>(b, J); tk.ti = I; tk.tj = J;
       tk.C = it.W2 + boff<TS>(b, I, J); tk.ldc = b;
       set_seg(tk.seg[0], St + (long long)I * TS, 1, b, Dt + (long long)J * TS * b, b, 1,
-              J * TS, b, 1.0);
+              max(J * TS, band_lo(it, I * TS)), b, 1.0);
       tk.nseg = 1;
       return;
     case PH_SI_VU_B: {
@@ -583,8 +599,8 @@ __device__ __forceinline__ void decode_big(const ItemDev &it, int phase, int t, 
       const double *Dq = dblk(it, tt), *Sq = sblk(it, tt);
       tk.m = bdim<TS>(b, I); tk.n = bdim<TS>(b, J); tk.ti = I; tk.tj = J;
       tk.C = it.V + (long long)tt * bb + boff<TS>(b, I, J); tk.ldc = b;
-      set_seg(tk.seg[0], Sq + (long long)I * TS, 1, b, Dq + (long long)J * TS * b, b, 1, J * TS, b,
-              1.0);
+      set_seg(tk.seg[0], Sq + (long long)I * TS, 1, b, Dq + (long long)J * TS * b, b, 1,
+              max(J * TS, band_lo(it, I * TS)), b, 1.0);
       tk.nseg = 1;
       return;
     }

@@ -166,6 +166,36 @@ struct Batch {
   }
 };
 
+// The products that read the coupling blocks skip the zeros outside their band
+// (ItemDev::sbw); INLA_BAND=0 in the environment treats the blocks as dense.
+bool band_aware() {
+  const char *e = getenv("INLA_BAND");
+  return !(e && e[0] == '0');
+}
+
+// Multiply-adds of the band-aware b x b products with coupling half-bandwidth
+// w (X = S inv(L)^T with S banded and inv(L) lower; the lower half of X X^T;
+// V = X inv(L); the arrow rows times X^T), entry by entry:
+//   X(r, c):    k from max(0, r - w) to min(c, r + w)
+//   XX^T(r, c): k from max(0, r - w) to b - 1 (r >= c)
+//   V(r, c):    k from max(c, r - w) to b - 1
+//   W X^T(., c): k from max(0, c - w) to b - 1 (per arrow row)
+struct BandMacs {
+  double x = 0, syrk = 0, v = 0, arrow = 0;
+};
+BandMacs band_macs(long long b, long long w) {
+  BandMacs m;
+  for (long long r = 0; r < b; ++r) {
+    const long long lo = std::max(0LL, r - w), hi = std::min(b - 1, r + w);
+    const long long L = hi - lo + 1;
+    m.x += 0.5 * (double)L * (L + 1) + (double)(b - 1 - hi) * L;   // c from lo to b - 1
+    m.syrk += (double)(r + 1) * (b - lo);
+    m.v += (double)lo * (b - lo) + 0.5 * (double)(b - lo) * (b - lo + 1);
+    m.arrow += (double)(b - lo);
+  }
+  return m;
+}
+
 // Algorithmic FP64 flops of one item in one phase (dense-block counts:
 // POTRF(b) = b^3/3, TRTRI(b) = b^3/3, TRSM/TRMM(m x b) = m b^2, SYRK(n, k) = n^2 k,
 // GEMM(m, n, k) = 2 m n k, LAUUM(b) = b^3/3).
@@ -173,6 +203,18 @@ double phase_flops(const ItemDev &it, int phase, int t, int p) {
   if (phase_tasks(it, phase, t, p) == 0) return 0.0;
   const double b = it.b, a = it.a, b3 = b * b * b;
   const bool last = (t == it.nt - 1);
+  if (it.sbw < it.b) {
+    // the products that meet the band: their band-aware counts
+    const BandMacs m = band_macs(it.b, it.sbw);
+    switch (phase) {
+      case PH_OFFDIAG_X: return last ? 0.0 : 2.0 * m.x;
+      case PH_SCHUR_X: return last ? 0.0 : 2.0 * m.syrk;
+      case PH_SCHUR: return (last ? 0.0 : 2.0 * a * m.arrow) + a * a * b;
+      case PH_SI_VU_X: return last ? 0.0 : 2.0 * m.v;
+      case PH_SI_VU_B: return (it.nt - 1) * 2.0 * m.v;
+      default: break;
+    }
+  }
   switch (phase) {
     // POTRF and TRTRI of the block (2 b^3 / 3) spread over its launches: the
     // first diagonal tile, then every tile step equally
@@ -525,6 +567,7 @@ ItemDev item_from_bta(const inla_bta &q) {
   std::memset(&it, 0, sizeof(it));
   it.b = q.b; it.nt = q.nt; it.a = q.a; it.nP = ntile(q.b);
   it.ntf = q.nt; it.trev = 0; it.nrun = q.nt; it.own_arrow = 1;
+  it.sbw = q.b;   // a caller's coupling blocks are taken as dense
   it.D = q.D; it.S = q.S; it.R = q.R; it.T = q.T;
   return it;
 }
@@ -630,6 +673,7 @@ std::atomic<uint64_t> g_next_model_id{1};
 
 struct HostModel {
   int N, nt, a, b;
+  int sbw = 0;   // half-bandwidth of Q_s (the largest |i - s| of a nonzero entry)
   std::vector<int> colptr, rowidx, colidx;
   std::vector<double> pdelta, pg1, pg2, AtA, ZtA, ZtZ, Aty;
 };
@@ -730,6 +774,7 @@ inla_status build_host_model(const inla_model_desc &d, HostModel &hm) {
         g2 += Gval(i, u) * Gval(u, s);
       }
       hm.pg2[e] = g2;
+      if (hm.pdelta[e] != 0.0 || hm.pg1[e] != 0.0 || g2 != 0.0) hm.sbw = std::max(hm.sbw, std::abs(i - s));
     }
   }
   // A^T A per time block, Z^T A_t, Z^T Z, A^T y (row order: deterministic sums)
@@ -821,6 +866,7 @@ inla_status inla_model_create(const inla_model_desc *desc, void *hip_stream, inl
     h.prior_prec[k] = d.theta_prior_prec[k];
   }
   h.nnz = hm.colptr[b];
+  h.sbw = std::min(hm.sbw, b);
   Layout L;
   int *colptr, *rowidx, *colidx, *A_col;
   double *pdelta, *pg1, *pg2, *AtA, *ZtA, *ZtZ, *Aty, *A_val, *y;
@@ -1298,6 +1344,7 @@ void wave_layout(Wave &W, const inla_model *const *models, bool mu_in_caller, La
       std::memset(&bk, 0, sizeof(bk));
       it.b = h.b; it.nt = h.nt; it.a = h.a; it.nP = ntile(h.b);
       it.ntf = h.nt; it.nrun = h.nt; it.own_arrow = 1;
+      it.sbw = band_aware() ? h.sbw : h.b;
       it.which = w;
       it.model = models[W.start + q]->dev;
       bk.b = h.b; bk.a = h.a; bk.nP = it.nP;
@@ -1690,6 +1737,7 @@ inla_status eval_run(const inla_model *const *models, int32_t n_items, const dou
   }
   key.grad = grad; key.var = var_out != nullptr; key.mu = mu_out != nullptr; key.prof = g_prof.on;
   key.seq = plan.seq; key.split = plan.split; key.vb = plan.vb; key.twist = twist_ok;
+  key.band = band_aware();
   key.tile = tile; key.variant = variant; key.small = small; key.step = step;
   key.gen = g_arena.gen; key.base = g_arena.base; key.ntot = ntot;
   if (graphable && g_graph.valid && same_signature(g_graph.key, key)) {

@@ -19,7 +19,7 @@ struct GraphKey {
   std::vector<uint64_t> model_ids;   // per item: the model's creation id (never reused)
   std::vector<int64_t> shapes;       // per item: b, nt, a, n
   bool grad = false, var = false, mu = false, prof = false;
-  bool seq = false, split = false, vb = false, twist = false;
+  bool seq = false, split = false, vb = false, twist = false, band = false;
   int tile = 0, variant = 0, small = 0, step = -1;
   uint64_t gen = 0;                  // workspace layout generation
   const void *base = nullptr;        // workspace base address
@@ -29,7 +29,8 @@ struct GraphKey {
 inline bool same_signature(const GraphKey &x, const GraphKey &y) {
   return x.model_ids == y.model_ids && x.shapes == y.shapes && x.grad == y.grad &&
          x.var == y.var && x.mu == y.mu && x.prof == y.prof && x.seq == y.seq &&
-         x.split == y.split && x.vb == y.vb && x.twist == y.twist && x.tile == y.tile && x.variant == y.variant &&
+         x.split == y.split && x.vb == y.vb && x.twist == y.twist && x.band == y.band && x.tile == y.tile &&
+         x.variant == y.variant &&
          x.small == y.small && x.step == y.step && x.gen == y.gen && x.base == y.base &&
          x.ntot == y.ntot;
 }

@@ -23,7 +23,7 @@ struct ModelDev {
   double prior_mean[4], prior_prec[4];
   // union pattern of Q_s and of every A_t^T A_t, column-compressed over b x b
   int nnz;
-  int pad_;
+  int sbw;                       // half-bandwidth of Q_s: entries with |r - c| > sbw are zero
   const int *colptr;             // b + 1
   const int *rowidx;             // nnz
   const int *colidx;             // nnz: column of each pattern entry
@@ -77,6 +77,11 @@ struct ItemDev {
   // the middle block, factored by the forward chain).  own_arrow: the item
   // factors / inverts the arrow block itself (a whole matrix); a half never does.
   int ntf, trev, nrun, own_arrow;
+  // Half-bandwidth of the coupling blocks S[t] (entries with |r - c| > sbw
+  // are zero; b when they are dense).  Then X = S[t] inv(L_tt)^T = L_{t+1,t}
+  // has zeros left of column r - sbw in row r (upper trapezoidal), and the
+  // products that read S[t] or X skip the k ranges of those zeros.
+  int sbw;
 };
 
 // Time block of chain step t, and the storage of the chain's blocks.  The

@@ -58,6 +58,8 @@ int main() {
   check(!inla::same_signature(a, c), "selected-inversion form");
   c = a; c.twist = true;
   check(!inla::same_signature(a, c), "elimination order");
+  c = a; c.band = true;
+  check(!inla::same_signature(a, c), "band-aware products");
   c = a; c.tile = 128;
   check(!inla::same_signature(a, c), "tile");
   c = a; c.step = 1;

@@ -728,3 +728,36 @@ def test_integrate_matches_oracle(P, N, nt, nb, seed):
     assert np.abs(xm - ref["x_mean"]).max() < 1e-8 * np.abs(ref["x_mean"]).max()
     np.testing.assert_allclose(xv, ref["x_var"], rtol=1e-7)
     assert r["grad_evals"] == 9 and r["f_evals"] == 8 * 6 + r["n_box"] + 1 + r["n_points"]
+
+
+@pytest.mark.parametrize("N,nt,nb,tile", [(12, 5, 2, "64"), (20, 4, 3, "64"), (20, 4, 3, "128"),
+                                          (17, 3, 0, "128"), (9, 6, 1, "64")])
+def test_band_aware_products_match_dense(P, monkeypatch, N, nt, nb, tile):
+    """The products that skip the zeros outside the coupling blocks' band (the
+    default) give the dense products' f, grad f, mu and variances to rounding,
+    and both match the oracle; 64- and 128-wide tiles, one- and two-sided
+    elimination."""
+    print(f"band N={N} nt={nt} nb={nb} tile={tile}", flush=True)
+    monkeypatch.setenv("INLA_TILE", tile)
+    md = make_model(N, nt, nb, 300 + N + nt)
+    M = P.Model.from_data(md)
+    theta = np.array([0.3, 1.1, 0.7, 2.9])
+    out = {}
+    for flag in ("1", "0"):
+        monkeypatch.setenv("INLA_BAND", flag)
+        out[flag] = P.eval_f_grad(M, theta, want_mu=True, want_var=True)
+    bd, dn = out["1"], out["0"]
+    assert int(bd["status"].cpu()[0]) == 0
+    fb, fd = float(bd["f"].cpu()[0]), float(dn["f"].cpu()[0])
+    assert rel(fb, fd) < 1e-13
+    gb, gd = bd["grad"].cpu().numpy()[0], dn["grad"].cpu().numpy()[0]
+    assert np.abs(gb - gd).max() < 1e-11 * np.abs(gd).max()
+    for key in ("mu", "var"):
+        x, y = bd[key].cpu().numpy(), dn[key].cpu().numpy()
+        assert np.abs(x - y).max() < 1e-12 * np.abs(y).max()
+    ref = O.eval_f_dense(md, theta)
+    assert rel(fb, ref["f"]) < 1e-10
+    g_ref = O.dense_gradient(md, theta)
+    assert np.abs(gb - g_ref).max() < 1e-9 * np.abs(g_ref).max()
+    v_ref = O.marginal_variances_dense(md, theta)
+    np.testing.assert_allclose(bd["var"].cpu().numpy(), v_ref, rtol=1e-9)
