@@ -12,6 +12,7 @@ from .generate import (  # noqa: F401
     config_model,
     config_theta_batch,
     make_model,
+    poisson_counts,
     uneven_batch,
     line_search_points,
     fd_stencil,

@@ -20,7 +20,7 @@ library for that.
 """
 from __future__ import annotations
 
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 
@@ -116,6 +116,19 @@ def make_model(N: int, nt: int, nb: int, seed: int, obs_per_node: int = 2,
     y = Ax + noise_sd * eps
     return ModelData(N=N, nt=nt, nb=nb, h=h, m=m, A_rowptr=rowptr, A_col=col, A_val=val,
                      y=y, seed=seed)
+
+
+def poisson_counts(md: ModelData, seed: int = 0, level: float = 0.5, spread: float = 0.3) -> ModelData:
+    """The same design with count responses for a Poisson likelihood: the log
+    rate of observation i is level + spread * (standardised y_i), clipped to
+    [-2, 2.5] (rates between 0.14 and 12), and the count is a seeded Poisson
+    draw with that rate.  Returns a copy of md with y replaced by the counts
+    (as float64)."""
+    rng = np.random.default_rng(10_000 + seed)
+    z = (md.y - md.y.mean()) / max(md.y.std(), 1e-300)
+    log_rate = np.clip(level + spread * z, -2.0, 2.5)
+    counts = rng.poisson(np.exp(log_rate)).astype(np.float64)
+    return replace(md, y=counts)
 
 
 def config_model(name: str) -> ModelData:
