@@ -432,6 +432,50 @@ inla_status inla_integrate(const inla_model *model, const double *theta_mode,
                            double *points_or_null, int32_t points_cap, double *x_mean_dev,
                            double *x_var_dev, void *hip_stream);
 
+/* Options of inla_eval_f_grad_poisson (NULL = defaults; a field <= 0 = its default). */
+typedef struct {
+  int32_t max_iter;   /* Newton iterations (100) */
+  int32_t warm;       /* 1: start from x_mode_dev as given; 0: from x = 0 */
+  double tol;         /* stop when max |x_new - x| <= tol (1 + max |x|) (1e-12) */
+} inla_newton_opts;
+
+/* status: 0 ok; 1 Q_prior, 2 Q_c(x) not positive definite; 4 Newton's method
+ * did not converge in max_iter iterations (f and grad are NaN unless 0).
+ * log_lik = log pi(y | x*) with its log y! terms; quad = x*^T Q_prior x*. */
+typedef struct {
+  double f, grad[4];
+  double logdet_p, logdet_c, log_lik, quad;
+  int32_t iterations, halvings, status, pad_;
+} inla_newton_result;
+
+/*
+ * f(theta) and its exact gradient for one model with a Poisson likelihood,
+ * y_i ~ Poisson(exp(eta_i)), eta = A x, the model's responses taken as counts
+ * (INLA_ERR_ARG if some y_i is not a non-negative integer); theta_4 enters only
+ * through its prior.  Sec. "Latent Gaussian Models": a non-Gaussian likelihood
+ * makes the Gaussian approximation an inner optimisation whose mode and
+ * normalising constant are recomputed in every iteration.  Newton's method on
+ * the mode x* from x = 0 (or from x_mode_dev with opts->warm): per iteration
+ * Q_c(x) = Q_prior + A^T diag(exp(A x)) A is assembled and factored
+ * (inla_assemble, the observation terms, inla_factor_logdet) and
+ * Q_c(x) x_new = A^T (y + e (eta - 1)) solved; the step is halved (at most 60
+ * times) until log pi(x | theta) + log pi(y | x) does not decrease.  Then
+ *   f = -log pi(theta) - 1/2 log|Q_prior| + 1/2 x*^T Q_prior x* - log pi(y | x*)
+ *       + 1/2 log|Q_c(x*)|
+ *   df/dtheta_k = p_k (theta_k - m_k) - 1/2 tr(Q_prior^{-1} dQ_k) + 1/2 x*^T dQ_k x*
+ *       + 1/2 tr(Q_c^{-1} dQ_k) - z^T dQ_k x*,  z = Q_c^{-1} A^T c,
+ *       c_i = 1/2 exp(eta*_i) (A Q_c^{-1} A^T)_ii
+ * (dQ_k = dQ_prior/dtheta_k, zero for k = 4; the last term is the implicit
+ * one of the moving mode) from the selected inverses of both factors.
+ * theta: 4 host doubles.  x_mode_dev (n, device, may be NULL): receives x*
+ * (and gives the start with warm).  var_dev (n, device, may be NULL):
+ * receives diag Q_c(x*)^{-1}.  Allocates three BTA matrices and O(n + m)
+ * vectors per call; synchronises hip_stream once per Newton step.
+ */
+inla_status inla_eval_f_grad_poisson(const inla_model *model, const double *theta,
+                                     const inla_newton_opts *opts, inla_newton_result *res,
+                                     double *x_mode_dev, double *var_dev, void *hip_stream);
+
 /*
  * Instrumentation for benchmarks.  Between inla_profile_begin() and
  * inla_profile_end() every kernel launch of the library is bracketed by HIP

@@ -15,6 +15,7 @@ from .binding import (  # noqa: F401
     build_id,
     eval_f,
     eval_f_grad,
+    eval_f_grad_poisson,
     factor_logdet,
     factor_logdet_noalloc,
     header_functions,

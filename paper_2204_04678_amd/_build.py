@@ -11,7 +11,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libinla_bta.so")
-SOURCES = ["bta_kernels.hip", "model_kernels.hip", "engine.cpp", "optimizer.cpp", "integrate.cpp"]
+SOURCES = ["bta_kernels.hip", "model_kernels.hip", "engine.cpp", "optimizer.cpp", "integrate.cpp", "nongauss.cpp"]
 ARCH = os.environ.get("INLA_OFFLOAD_ARCH", "gfx950")
 
 

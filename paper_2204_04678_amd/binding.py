@@ -70,6 +70,17 @@ class IntegrateResult(C.Structure):
                 ("n_points", C.c_int32), ("f_evals", C.c_int32), ("grad_evals", C.c_int32)]
 
 
+class NewtonOpts(C.Structure):
+    _fields_ = [("max_iter", C.c_int32), ("warm", C.c_int32), ("tol", C.c_double)]
+
+
+class NewtonResult(C.Structure):
+    _fields_ = [("f", C.c_double), ("grad", C.c_double * 4), ("logdet_p", C.c_double),
+                ("logdet_c", C.c_double), ("log_lik", C.c_double), ("quad", C.c_double),
+                ("iterations", C.c_int32), ("halvings", C.c_int32), ("status", C.c_int32),
+                ("pad_", C.c_int32)]
+
+
 _LIB = None
 
 _SIGS = {
@@ -105,6 +116,9 @@ _SIGS = {
     "inla_integrate": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(IntegrateOpts),
                                  C.POINTER(IntegrateResult), C.POINTER(C.c_double), C.c_int32,
                                  C.c_void_p, C.c_void_p, C.c_void_p]),
+    "inla_eval_f_grad_poisson": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(NewtonOpts),
+                                           C.POINTER(NewtonResult), C.c_void_p, C.c_void_p,
+                                           C.c_void_p]),
     "inla_release_workspace": (None, []),
     "inla_profile_begin": (C.c_int, []),
     "inla_profile_end": (C.c_int, [C.POINTER(C.c_double), C.c_int32]),
@@ -542,6 +556,28 @@ def integrate(model: Model, theta_mode, h=1e-3, dz=1.0, dpi=2.5, max_steps=6, ma
                points=np.array(pts[:10 * min(K, points_cap)]).reshape(-1, 10))
     if latent:
         out["x_mean"], out["x_var"] = xm, xv
+    return out
+
+
+def eval_f_grad_poisson(model: Model, theta, max_iter=100, tol=1e-12, x0=None, want_var=False):
+    """f(theta) and its exact gradient with a Poisson likelihood on the model's
+    count responses (inla_eval_f_grad_poisson).  x0: optional device tensor
+    (n) to start Newton's method from.  Returns dict(f, grad, logdet_p,
+    logdet_c, log_lik, quad, iterations, halvings, status, x, [var])."""
+    th = (C.c_double * 4)(*[float(v) for v in np.asarray(theta, dtype=np.float64)])
+    x = torch.zeros(model.n, dtype=torch.float64, device="cuda")
+    if x0 is not None:
+        x.copy_(x0)
+    var = torch.empty(model.n, dtype=torch.float64, device="cuda") if want_var else None
+    o = NewtonOpts(int(max_iter), 1 if x0 is not None else 0, float(tol))
+    res = NewtonResult()
+    _check(lib().inla_eval_f_grad_poisson(model.handle, th, C.byref(o), C.byref(res), _ptr(x),
+                                          _ptr(var), _stream()))
+    out = dict(f=res.f, grad=np.array(res.grad[:]), logdet_p=res.logdet_p, logdet_c=res.logdet_c,
+               log_lik=res.log_lik, quad=res.quad, iterations=res.iterations,
+               halvings=res.halvings, status=res.status, x=x)
+    if want_var:
+        out["var"] = var
     return out
 
 

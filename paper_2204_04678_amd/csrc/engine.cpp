@@ -665,7 +665,18 @@ struct inla_model {
   int device = 0;
   long long n = 0, m = 0;
   uint64_t id = 0;    // unique over the process lifetime (captured graphs key on it)
+  bool counts = false;       // every y_i is a non-negative integer (a count likelihood may use it)
+  double log_y_fact = 0.0;   // sum_i log(y_i!) when counts
 };
+
+namespace inla {
+const ModelDev *model_device(const inla_model *m) { return m->dev; }
+const ModelDev &model_host_desc(const inla_model *m) { return m->host; }
+bool model_counts(const inla_model *m, double *log_y_fact) {
+  if (log_y_fact) *log_y_fact = m->log_y_fact;
+  return m->counts;
+}
+}  // namespace inla
 
 namespace {
 
@@ -887,6 +898,58 @@ inla_status inla_model_create(const inla_model_desc *desc, void *hip_stream, inl
   L.add(&A_col, (size_t)nnzA);
   L.add(&A_val, (size_t)nnzA);
   L.add(&y, (size_t)d.m);
+  // A by columns and the dense fixed-effect columns
+  std::vector<long long> cptr((size_t)n + 1, 0);
+  for (long long e = 0; e < nnzA; ++e) ++cptr[(size_t)d.A_col[e] + 1];
+  for (long long j = 0; j < n; ++j) cptr[j + 1] += cptr[j];
+  std::vector<int> crow((size_t)nnzA);
+  std::vector<double> cval((size_t)nnzA);
+  std::vector<long long> cfill(cptr.begin(), cptr.end() - 1);
+  std::vector<double> Zd((size_t)d.m * a, 0.0);
+  for (long long i = 0; i < d.m; ++i)
+    for (long long e = d.A_rowptr[i]; e < d.A_rowptr[i + 1]; ++e) {
+      const int c = d.A_col[e];
+      long long &q = cfill[c];
+      if (q > cptr[c] && crow[q - 1] == (int)i) {
+        cval[q - 1] += d.A_val[e];   // a repeated column within the row
+      } else {
+        crow[q] = (int)i;
+        cval[q] = d.A_val[e];
+        ++q;
+      }
+      if (c >= (long long)b * nt) Zd[(size_t)i * a + (c - (long long)b * nt)] += d.A_val[e];
+    }
+  // compact the columns (repeats leave gaps)
+  {
+    long long w = 0;
+    for (long long j = 0; j < n; ++j) {
+      const long long r0 = cptr[j], r1 = cfill[j];
+      cptr[j] = w;
+      for (long long q = r0; q < r1; ++q, ++w) {
+        crow[w] = crow[q];
+        cval[w] = cval[q];
+      }
+    }
+    cptr[n] = w;
+  }
+  const long long nnzC = cptr[n];
+  long long *Ac_ptr;
+  int *Ac_row;
+  double *Ac_val, *Zdd;
+  L.add(&Ac_ptr, (size_t)n + 1);
+  L.add(&Ac_row, (size_t)std::max<long long>(nnzC, 1));
+  L.add(&Ac_val, (size_t)std::max<long long>(nnzC, 1));
+  L.add(&Zdd, std::max<size_t>(Zd.size(), 1));
+  M->counts = true;
+  for (long long i = 0; i < d.m; ++i) {
+    const double yi = d.y[i];
+    if (!(std::isfinite(yi) && yi >= 0.0 && yi == std::floor(yi))) {
+      M->counts = false;
+      break;
+    }
+    M->log_y_fact += std::lgamma(yi + 1.0);
+  }
+  if (!M->counts) M->log_y_fact = 0.0;
   if (hipMalloc(&M->mem, L.total) != hipSuccess) {
     (void)hipGetLastError();
     delete M;
@@ -904,6 +967,7 @@ inla_status inla_model_create(const inla_model_desc *desc, void *hip_stream, inl
   h.colptr = colptr; h.rowidx = rowidx; h.colidx = colidx; h.pdelta = pdelta; h.pg1 = pg1;
   h.pg2 = pg2; h.AtA = AtA; h.ZtA = ZtA; h.ZtZ = ZtZ; h.Aty = Aty; h.A_rowptr = A_rowptr;
   h.A_col = A_col; h.A_val = A_val; h.y = y;
+  h.Ac_ptr = Ac_ptr; h.Ac_row = Ac_row; h.Ac_val = Ac_val; h.Zd = Zdd;
   hipError_t e = hipSuccess;
   if (!e) e = put(colptr, hm.colptr.data(), hm.colptr.size() * sizeof(int));
   if (!e) e = put(rowidx, hm.rowidx.data(), hm.rowidx.size() * sizeof(int));
@@ -919,6 +983,10 @@ inla_status inla_model_create(const inla_model_desc *desc, void *hip_stream, inl
   if (!e) e = put(A_col, d.A_col, (size_t)nnzA * sizeof(int));
   if (!e) e = put(A_val, d.A_val, (size_t)nnzA * sizeof(double));
   if (!e) e = put(y, d.y, (size_t)d.m * sizeof(double));
+  if (!e) e = put(Ac_ptr, cptr.data(), cptr.size() * sizeof(long long));
+  if (!e) e = put(Ac_row, crow.data(), (size_t)nnzC * sizeof(int));
+  if (!e) e = put(Ac_val, cval.data(), (size_t)nnzC * sizeof(double));
+  if (!e) e = put(Zdd, Zd.data(), Zd.size() * sizeof(double));
   if (!e) e = put(mdev, &h, sizeof(ModelDev));
   if (!e) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {

@@ -38,6 +38,13 @@ struct ModelDev {
   const int *A_col;              // nnz(A)
   const double *A_val;
   const double *y;               // m
+  // A by columns (row indices ascending within a column, duplicates summed)
+  // and its fixed-effect columns dense: for likelihoods whose A^T diag(d) A
+  // is assembled anew for every d
+  const long long *Ac_ptr;       // n + 1
+  const int *Ac_row;             // nnz of the CSC form
+  const double *Ac_val;
+  const double *Zd;              // m x a, row-major
 };
 
 // Device descriptor of one BTA matrix in flight through factor / selinv.
@@ -325,6 +332,36 @@ struct TwistPair {
   int a, b, m;             // arrow width, block size, middle block
   int pad_;
 };
+// Accessors of a model (engine.cpp): its device descriptor, the host copy of
+// that descriptor (device pointers inside), and whether every y_i is a count
+// (with sum_i log y_i!).
+const ModelDev *model_device(const inla_model *m);
+const ModelDev &model_host_desc(const inla_model *m);
+bool model_counts(const inla_model *m, double *log_y_fact);
+
+// Poisson likelihood (the inner Newton loop), kNgBlocks partial sums each:
+//   ng_obs:   eta = A x, e = exp(eta) (e_out), w = y + e (eta - 1) (w_out; both
+//             may be null), part[k] = partial sums of y_i eta_i - e_i;
+//   ng_atv:   out = A^T v (n);
+//   ng_add_obs: D[t] += (A^T diag(e) A) on the pattern, R[t] += its fixed-effect
+//             rows, T += Z^T diag(e) Z (BTA storage of the model's shape);
+//   ng_obs_var: c_i = 1/2 e_i (A Sigma A^T)_ii from Sigma's D, R, T blocks;
+//   ng_quad:  part[4k..] = u^T Q_st v, u^T dQ_st/dtheta_2 v, u^T dQ_st/dtheta_3 v,
+//             u_beta^T v_beta;
+//   ng_step:  cand = x + step (xn - x), part[2k..] = max |cand - x|, max |x|.
+constexpr int kNgBlocks = 256;
+hipError_t launch_ng_obs(const ModelDev *M, long long m, const double *x, double *e_out, double *w_out,
+                         double *part, hipStream_t s);
+hipError_t launch_ng_atv(const ModelDev *M, long long n, const double *v, double *out, hipStream_t s);
+hipError_t launch_ng_add_obs(const ModelDev *M, int b, int nt, int a, int nnz, const double *e, double *D,
+                             double *R, double *T, hipStream_t s);
+hipError_t launch_ng_obs_var(const ModelDev *M, long long m, const double *SD, const double *SR,
+                             const double *ST, const double *e, double *c_out, hipStream_t s);
+hipError_t launch_ng_quad(const ModelDev *M, const double *theta, const double *u, const double *v,
+                          double *part, hipStream_t s);
+hipError_t launch_ng_step(const double *x, const double *xn, double step, double *cand, long long n,
+                          double *part, hipStream_t s);
+
 // Mixture of K Gaussians N(mu^k, v^k) with weights w (device, K doubles; mu, var:
 // K x n point-major).  With d = mu^k - shift: acc_m (+)= sum_k w_k d,
 // acc_s (+)= sum_k w_k (v^k + d^2) (init = 1 starts from zero).  The finish

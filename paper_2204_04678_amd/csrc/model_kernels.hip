@@ -629,6 +629,238 @@ hipError_t launch_mixture_finish(const double *shift, const double *acc_m, const
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Poisson likelihood: the pieces of the inner Newton loop and of the implicit
+// gradient term (every sum in a fixed order: fixed grids, tree reductions,
+// partials summed by the host in block order)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void ng_obs_kernel(const ModelDev *__restrict__ Mp, const double *x,
+                                                     double *e_out, double *w_out, double *part) {
+  const ModelDev &M = *Mp;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < M.m; i += (long long)gridDim.x * 256) {
+    double eta = 0.0;
+    for (long long k = M.A_rowptr[i]; k < M.A_rowptr[i + 1]; ++k) eta = fma(M.A_val[k], x[M.A_col[k]], eta);
+    const double ex = exp(eta), y = M.y[i];
+    if (e_out) e_out[i] = ex;
+    if (w_out) w_out[i] = fma(ex, eta - 1.0, y);
+    v[0] += y * eta - ex;
+  }
+  __shared__ double red[4 * 256];
+  block_reduce<256>(v, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void ng_atv_kernel(const ModelDev *__restrict__ Mp, const double *v, double *out) {
+  const ModelDev &M = *Mp;
+  for (long long j = blockIdx.x * 256LL + threadIdx.x; j < M.n; j += (long long)gridDim.x * 256) {
+    double acc = 0.0;
+    for (long long k = M.Ac_ptr[j]; k < M.Ac_ptr[j + 1]; ++k) acc = fma(M.Ac_val[k], v[M.Ac_row[k]], acc);
+    out[j] = acc;
+  }
+}
+
+// D entries: the observations common to the columns of nodes r and s of block
+// t (both lists ascending); R rows: the observations of node s times Z.
+__global__ void ng_add_obs_kernel(const ModelDev *__restrict__ Mp, const double *e, double *D, double *R) {
+  const ModelDev &M = *Mp;
+  const int b = M.b, a = M.a, nnz = M.nnz;
+  const long long nD = (long long)M.nt * nnz, nR = (long long)M.nt * b * a;
+  for (long long idx = blockIdx.x * 256LL + threadIdx.x; idx < nD + nR; idx += (long long)gridDim.x * 256) {
+    if (idx < nD) {
+      const int t = (int)(idx / nnz), q = (int)(idx % nnz);
+      const int r = M.rowidx[q], c = M.colidx[q];
+      const long long j1 = (long long)t * b + r, j2 = (long long)t * b + c;
+      long long p1 = M.Ac_ptr[j1], p2 = M.Ac_ptr[j2];
+      const long long q1 = M.Ac_ptr[j1 + 1], q2 = M.Ac_ptr[j2 + 1];
+      double acc = 0.0;
+      while (p1 < q1 && p2 < q2) {
+        const int i1 = M.Ac_row[p1], i2 = M.Ac_row[p2];
+        if (i1 == i2) {
+          acc = fma(e[i1] * M.Ac_val[p1], M.Ac_val[p2], acc);
+          ++p1;
+          ++p2;
+        } else if (i1 < i2) {
+          ++p1;
+        } else {
+          ++p2;
+        }
+      }
+      D[(long long)t * b * b + r + (long long)c * b] += acc;
+    } else {
+      const long long q = idx - nD;
+      const int t = (int)(q / ((long long)b * a));
+      const int rem = (int)(q - (long long)t * b * a);
+      const int c = rem / a, al = rem % a;
+      const long long j = (long long)t * b + c;
+      double acc = 0.0;
+      for (long long k = M.Ac_ptr[j]; k < M.Ac_ptr[j + 1]; ++k) {
+        const int i = M.Ac_row[k];
+        acc = fma(e[i] * M.Ac_val[k], M.Zd[(long long)i * a + al], acc);
+      }
+      R[(long long)t * a * b + al + (long long)c * a] += acc;
+    }
+  }
+}
+
+// T += Z^T diag(e) Z: one workgroup per entry, a tree over the observations.
+__global__ __launch_bounds__(256) void ng_add_T_kernel(const ModelDev *__restrict__ Mp, const double *e,
+                                                       double *T) {
+  const ModelDev &M = *Mp;
+  const int a = M.a, al = blockIdx.x % a, be = blockIdx.x / a;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long long i = threadIdx.x; i < M.m; i += 256)
+    v[0] = fma(e[i] * M.Zd[i * a + al], M.Zd[i * a + be], v[0]);
+  __shared__ double red[4 * 256];
+  block_reduce<256>(v, red);
+  if (threadIdx.x == 0) T[al + (long long)be * a] += red[0];
+}
+
+__global__ void ng_obs_var_kernel(const ModelDev *__restrict__ Mp, const double *SD, const double *SR,
+                                  const double *ST, const double *e, double *c_out) {
+  const ModelDev &M = *Mp;
+  const int b = M.b, a = M.a;
+  const long long nst = (long long)b * M.nt;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < M.m; i += (long long)gridDim.x * 256) {
+    const long long k0 = M.A_rowptr[i], k1 = M.A_rowptr[i + 1];
+    double q = 0.0;
+    for (long long k = k0; k < k1; ++k) {
+      const long long ck = M.A_col[k];
+      const double ak = M.A_val[k];
+      if (ck < nst) {
+        const long long t = ck / b;
+        const int r = (int)(ck - t * b);
+        for (long long l = k0; l < k1; ++l) {
+          const long long cl = M.A_col[l];
+          if (cl < nst) {
+            const int c = (int)(cl - t * b);   // same time block (checked at model creation)
+            q = fma(ak * M.A_val[l], SD[t * b * b + r + (long long)c * b], q);
+          } else {
+            const int al = (int)(cl - nst);
+            q = fma(2.0 * ak * M.A_val[l], SR[t * a * b + al + (long long)r * a], q);
+          }
+        }
+      } else {
+        const int al = (int)(ck - nst);
+        for (long long l = k0; l < k1; ++l) {
+          const long long cl = M.A_col[l];
+          if (cl >= nst) q = fma(ak * M.A_val[l], ST[al + (cl - nst) * a], q);
+        }
+      }
+    }
+    c_out[i] = 0.5 * e[i] * q;
+  }
+}
+
+__global__ __launch_bounds__(256) void ng_quad_kernel(const ModelDev *__restrict__ Mp, const double *theta,
+                                                      const double *u, const double *v, double *part) {
+  const ModelDev &M = *Mp;
+  const int b = M.b, nt = M.nt;
+  const Coef c = make_coef(M, theta);
+  const double cS = ar1_off(c), dcS = ar1_doff(c);
+  const long long nst = (long long)nt * b;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < nst; idx += stride) {
+    const int t = (int)(idx / b), s = (int)(idx % b);
+    const bool nx = t < nt - 1;
+    const double *ut1 = u + (long long)(t + 1) * b, *vt = v + (long long)t * b, *vt1 = vt + b;
+    double qv0 = 0.0, dv0 = 0.0, qv1 = 0.0, dv1 = 0.0, qu1 = 0.0, du1 = 0.0;
+    for (int e = M.colptr[s]; e < M.colptr[s + 1]; ++e) {
+      const int i = M.rowidx[e];
+      const double q = qs_entry(M, c, e), dq = dqs_entry(M, c, e);
+      qv0 += q * vt[i];
+      dv0 += dq * vt[i];
+      if (nx) {
+        qv1 += q * vt1[i];
+        dv1 += dq * vt1[i];
+        qu1 += q * ut1[i];
+        du1 += dq * ut1[i];
+      }
+    }
+    const double us = u[idx], vs = v[idx];
+    const double cD = ar1_diag(c, t, nt), dcD = ar1_ddiag(c, t, nt);
+    // u_t^T Q_s v_t cD + (u_t^T Q_s v_{t+1} + u_{t+1}^T Q_s v_t) cS, term by term
+    acc[0] += us * (cD * qv0 + cS * qv1) + vs * cS * qu1;
+    acc[1] += us * (cD * dv0 + cS * dv1) + vs * cS * du1;
+    acc[2] += us * (dcD * qv0 + dcS * qv1) + vs * dcS * qu1;
+  }
+  for (long long j = nst + blockIdx.x * (long long)blockDim.x + threadIdx.x; j < M.n; j += stride)
+    acc[3] += u[j] * v[j];
+  __shared__ double red[4 * 256];
+  block_reduce<256>(acc, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) part[(long long)blockIdx.x * 4 + k] = red[k * 256];
+  }
+}
+
+__global__ __launch_bounds__(256) void ng_step_kernel(const double *x, const double *xn, double step,
+                                                      double *cand, long long n, double *part) {
+  double dmax = 0.0, xmax = 0.0;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    const double xi = x[i];
+    const double ci = fma(step, xn[i] - xi, xi);
+    cand[i] = ci;
+    dmax = fmax(dmax, fabs(ci - xi));
+    xmax = fmax(xmax, fabs(xi));
+  }
+  __shared__ double r0[256], r1[256];
+  r0[threadIdx.x] = dmax;
+  r1[threadIdx.x] = xmax;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      r0[threadIdx.x] = fmax(r0[threadIdx.x], r0[threadIdx.x + off]);
+      r1[threadIdx.x] = fmax(r1[threadIdx.x], r1[threadIdx.x + off]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[blockIdx.x * 2] = r0[0];
+    part[blockIdx.x * 2 + 1] = r1[0];
+  }
+}
+
+hipError_t launch_ng_obs(const ModelDev *M, long long m, const double *x, double *e_out, double *w_out,
+                         double *part, hipStream_t s) {
+  (void)m;
+  hipLaunchKernelGGL(ng_obs_kernel, dim3(kNgBlocks), dim3(256), 0, s, M, x, e_out, w_out, part);
+  return hipGetLastError();
+}
+hipError_t launch_ng_atv(const ModelDev *M, long long n, const double *v, double *out, hipStream_t s) {
+  const int gx = (int)std::max<long long>(1, std::min<long long>((n + 255) / 256, 4096));
+  hipLaunchKernelGGL(ng_atv_kernel, dim3(gx), dim3(256), 0, s, M, v, out);
+  return hipGetLastError();
+}
+hipError_t launch_ng_add_obs(const ModelDev *M, int b, int nt, int a, int nnz, const double *e, double *D,
+                             double *R, double *T, hipStream_t s) {
+  const long long tot = (long long)nt * nnz + (long long)nt * b * a;
+  const int gx = (int)std::max<long long>(1, std::min<long long>((tot + 255) / 256, 8192));
+  hipLaunchKernelGGL(ng_add_obs_kernel, dim3(gx), dim3(256), 0, s, M, e, D, R);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess || a == 0) return err;
+  hipLaunchKernelGGL(ng_add_T_kernel, dim3(a * a), dim3(256), 0, s, M, e, T);
+  return hipGetLastError();
+}
+hipError_t launch_ng_obs_var(const ModelDev *M, long long m, const double *SD, const double *SR,
+                             const double *ST, const double *e, double *c_out, hipStream_t s) {
+  const int gx = (int)std::max<long long>(1, std::min<long long>((m + 255) / 256, 4096));
+  hipLaunchKernelGGL(ng_obs_var_kernel, dim3(gx), dim3(256), 0, s, M, SD, SR, ST, e, c_out);
+  return hipGetLastError();
+}
+hipError_t launch_ng_quad(const ModelDev *M, const double *theta, const double *u, const double *v,
+                          double *part, hipStream_t s) {
+  hipLaunchKernelGGL(ng_quad_kernel, dim3(kNgBlocks), dim3(256), 0, s, M, theta, u, v, part);
+  return hipGetLastError();
+}
+hipError_t launch_ng_step(const double *x, const double *xn, double step, double *cand, long long n,
+                          double *part, hipStream_t s) {
+  hipLaunchKernelGGL(ng_step_kernel, dim3(kNgBlocks), dim3(256), 0, s, x, xn, step, cand, n, part);
+  return hipGetLastError();
+}
+
 hipError_t launch_combine(const CombineItem *items_dev, int n_items, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   hipLaunchKernelGGL(combine_kernel, dim3(n_items), dim3(256), 0, s, items_dev);

@@ -133,3 +133,16 @@ def test_integrate_argument_errors(libpath):
     assert L.inla_integrate(dummy, th, ctypes.byref(o), ctypes.byref(res), None, 0, None, None,
                             None) == -1
     assert b"max_steps" in L.inla_last_error()
+
+
+def test_poisson_argument_errors(libpath):
+    """inla_eval_f_grad_poisson rejects bad arguments on the host."""
+    L = binding.lib(libpath)
+    res = binding.NewtonResult()
+    th = (ctypes.c_double * 4)(0.0, 0.0, 0.0, 0.0)
+    assert L.inla_eval_f_grad_poisson(None, th, None, ctypes.byref(res), None, None, None) == -1
+    assert b"need model" in L.inla_last_error()
+    dummy = ctypes.c_void_p(64)
+    bad = (ctypes.c_double * 4)(0.0, 0.0, float("inf"), 0.0)
+    assert L.inla_eval_f_grad_poisson(dummy, bad, None, ctypes.byref(res), None, None, None) == -1
+    assert b"not finite" in L.inla_last_error()

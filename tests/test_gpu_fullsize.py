@@ -129,3 +129,34 @@ def test_invalid_theta_is_reported_per_item(P):
     assert list(st) == [0, 3, 0]
     f = out["f"].cpu().numpy()
     assert math.isnan(f[1]) and f[0] == f[2]
+
+
+def test_poisson_at_32x32x50(P):
+    """The Poisson likelihood on the 32x32x50 design (n = 51204, m = 102400
+    count responses): the mode is stationary (the oracle's sparse matrices
+    evaluate the gradient of the inner objective at the GPU's x*), and the
+    exact gradient with the implicit term agrees with central differences of
+    the GPU's own f."""
+    import scipy.sparse as sp
+    from inla_synth import poisson_counts
+    from oracle import inla_oracle as O
+    md = poisson_counts(config_model("c2"), seed=2)
+    print(f"poisson 32x32x50: n={md.n}, total count {int(md.y.sum())}", flush=True)
+    M = P.Model.from_data(md)
+    theta = np.array([0.1, 0.9, 0.6, 1.5])
+    r = P.eval_f_grad_poisson(M, theta)
+    assert r["status"] == 0 and r["iterations"] < 30, r
+    x = r["x"].cpu().numpy()
+    Qp = O.prior_precision(md, theta)
+    A = O.obs_matrix(md)
+    res = -(Qp @ x) + A.T @ (md.y - np.exp(A @ x))
+    assert np.abs(res).max() < 1e-8 * np.abs(A.T @ md.y).max()
+    h = 1e-4
+    g = r["grad"]
+    for k in range(3):
+        e = np.zeros(4)
+        e[k] = h
+        fp = P.eval_f_grad_poisson(M, theta + e, x0=r["x"])["f"]
+        fm = P.eval_f_grad_poisson(M, theta - e, x0=r["x"])["f"]
+        fd = (fp - fm) / (2 * h)
+        assert abs(fd - g[k]) < 1e-5 * np.abs(g).max(), (k, fd, g[k])

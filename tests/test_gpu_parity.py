@@ -761,3 +761,37 @@ def test_band_aware_products_match_dense(P, monkeypatch, N, nt, nb, tile):
     assert np.abs(gb - g_ref).max() < 1e-9 * np.abs(g_ref).max()
     v_ref = O.marginal_variances_dense(md, theta)
     np.testing.assert_allclose(bd["var"].cpu().numpy(), v_ref, rtol=1e-9)
+
+
+@pytest.mark.parametrize("N,nt,nb,seed", [(4, 3, 2, 5), (9, 4, 3, 31), (5, 3, 0, 8), (1, 1, 0, 3)])
+def test_poisson_f_grad_matches_oracle(P, N, nt, nb, seed):
+    """A Poisson likelihood (the inner Newton loop of a non-Gaussian
+    likelihood, one factorization of Q_c(x) per iteration) against the
+    oracle: f, the exact gradient with the implicit term, the mode and the
+    marginal variances at the mode; a warm start at the mode converges at once
+    to the same f; Gaussian responses are refused."""
+    from inla_synth import poisson_counts
+    from oracle import nongauss as NG
+    print(f"poisson N={N} nt={nt} nb={nb}", flush=True)
+    base = make_model(N, nt, nb, seed, obs_per_node=30 if N == 1 else 2)
+    md = poisson_counts(base, seed=seed, level=2.0 if N == 1 else 0.5)
+    M = P.Model.from_data(md)
+    theta = np.array([0.1, 0.9, 0.6, 1.5])
+    r = P.eval_f_grad_poisson(M, theta, want_var=True)
+    assert r["status"] == 0, r
+    ref = NG.eval_f(md, theta)
+    g_ref = NG.gradient(md, theta)
+    assert rel(r["f"], ref["f"]) < 1e-10
+    assert np.abs(r["grad"] - g_ref).max() < 1e-8 * np.abs(g_ref).max()
+    x = r["x"].cpu().numpy()
+    assert np.abs(x - ref["x"]).max() < 1e-9 * max(1.0, np.abs(ref["x"]).max())
+    _, Qc = NG.conditional_precision_at(md, theta, ref["x"])
+    v_ref = np.diag(np.linalg.inv(Qc.toarray()))
+    np.testing.assert_allclose(r["var"].cpu().numpy(), v_ref, rtol=1e-9)
+    assert abs(r["iterations"] - ref["iterations"]) <= 1
+    w = P.eval_f_grad_poisson(M, theta, x0=r["x"])
+    assert w["status"] == 0 and w["iterations"] == 1
+    assert rel(w["f"], r["f"]) < 1e-12
+    G = P.Model.from_data(base)
+    with pytest.raises(P.InlaError, match="counts"):
+        P.eval_f_grad_poisson(G, theta)
