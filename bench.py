@@ -87,6 +87,20 @@ def flops_selinv(b, nt, a, w=None):
     return nt * (2.0 / 3.0) * b ** 3 + (nt - 1) * (vv + 3 * b ** 3) + nt * (4 * a * b * b + 2 * a * a * b)
 
 
+def product_alg_bytes(b, nt, a):
+    """Compulsory HBM bytes of the b x b product phases of one f + grad
+    evaluation of one item (both matrices): every operand block read once and
+    every output block written once, dense blocks.  Per matrix and time step
+    below the last: X = S inv(L)^T (S, inv(L) read, X written: 3 b^2), the
+    Schur update (X read, the lower half of D[t+1] read and written: 2 b^2),
+    V = X inv(L) (3 b^2), Sigma_S = -Sigma_D[t+1] V (3 b^2); per step
+    Sigma_D (inv(L)^T inv(L) read as its stored lower half, Sigma_S and V read,
+    Sigma_D written: 3.5 b^2) and inv(L)^T inv(L) itself (inv(L) read, its
+    lower half written: 1.5 b^2).  The arrow rows (a << b) are left out."""
+    per_matrix = (nt - 1) * 11 * b * b + nt * 5 * b * b
+    return 2 * 8.0 * per_matrix
+
+
 def band_of(md):
     """The half-bandwidth the library uses for this model (None with INLA_BAND=0)."""
     if os.environ.get("INLA_BAND", "1").startswith("0"):
@@ -303,10 +317,20 @@ def measure(P, config, model, theta, mds, steps, warmup, timing_steps):
     dom = max(tile_kernels, key=lambda k: tile_kernels[k]["ms"])
     pk = tile_kernels[dom]
     achieved = pk["flops"] / (pk["ms"] * 1e-3) / 1e12 if pk["ms"] > 0 else 0.0
+    traffic = hbm_traffic(config, "inla::" + dom)
+    # compulsory bytes per launch of the product kernel: the b x b product
+    # phases' operand and output blocks once each, over its launches
+    alg_bytes_launch = None
+    if dom == "tile_product_kernel" and pk["launches"]:
+        alg_bytes_launch = round(sum(product_alg_bytes(m.ns, m.nt, m.nb) for m in mds)
+                                 * calls / pk["launches"], 1)
     roofline = {"bound": "mfma", "kernel": dom,
                 "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                "traffic": hbm_traffic(config, "inla::" + dom),
+                "traffic": traffic,
+                "alg_bytes_per_launch": alg_bytes_launch,
+                "traffic_over_alg_bytes": (round(traffic / alg_bytes_launch, 3)
+                                           if traffic and alg_bytes_launch else None),
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
                 "launches_per_step": pk["launches"] / calls,
                 "avg_launch_us": round(pk["ms"] * 1e3 / max(pk["launches"], 1), 3),

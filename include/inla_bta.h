@@ -312,13 +312,15 @@ inla_status inla_robust_quadratic_fit(const double *x, const double *y, int32_t 
 
 /*
  * Options of inla_bfgs_minimize (NULL = defaults; a field <= 0 = its default).
- *   max_iter  : BFGS iterations (100)
+ *   max_iter  : BFGS iterations (300)
  *   n_points  : candidate points on the search interval per iteration (6);
  *               two stabilising points are added on the other side of theta
  *   gamma     : upper bound of the step length along -p (1: the quasi-Newton step)
  *   gtol      : stop when max_k |df/dtheta_k| <= gtol (1e-6)
  *   ftol      : stop when an iteration lowers f by <= ftol max(1, |f|) (1e-13)
  *   eval_opts : options of the evaluations (NULL = defaults)
+ *   max_step  : an iteration's interval is shortened so that no theta_k moves
+ *               by more than max_step (2.0)
  */
 typedef struct {
   int32_t max_iter;
@@ -327,6 +329,7 @@ typedef struct {
   double gtol;
   double ftol;
   const inla_opts *eval_opts;
+  double max_step;
 } inla_bfgs_opts;
 
 /* reason: 0 gradient below gtol, 1 decrease of f below ftol, 2 max_iter,
@@ -341,7 +344,8 @@ typedef struct {
  * (eq. bfgs_update) with the exact adjoint gradient at every accepted iterate,
  * and the parallel line search of Sec. "Parallel Line Search" (Fig.
  * parallel_linsearch): with p = H grad f (H the inverse-Hessian approximation,
- * the first direction of unit length) the n_points candidates
+ * the first direction of unit length) and gamma shortened to max_step / max |p_k|
+ * where it would move some theta_k farther, the n_points candidates
  * theta - alpha p, alpha = gamma i / n_points, and the two stabilising points
  * alpha = -gamma/8, -gamma/4 are evaluated in ONE batched inla_eval_f call; a
  * robust quadratic (inla_robust_quadratic_fit) through them and f(theta) is

@@ -47,7 +47,8 @@ class Opts(C.Structure):
 
 class BfgsOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("n_points", C.c_int32), ("gamma", C.c_double),
-                ("gtol", C.c_double), ("ftol", C.c_double), ("eval_opts", C.POINTER(Opts))]
+                ("gtol", C.c_double), ("ftol", C.c_double), ("eval_opts", C.POINTER(Opts)),
+                ("max_step", C.c_double)]
 
 
 class BfgsResult(C.Structure):
@@ -507,15 +508,15 @@ BFGS_REASONS = {0: "gradient below gtol", 1: "decrease of f below ftol", 2: "max
                 3: "no point of the search interval lowered f"}
 
 
-def minimize(model: Model, theta0, max_iter=100, n_points=6, gamma=1.0, gtol=1e-6, ftol=1e-13,
-             **eval_opts):
+def minimize(model: Model, theta0, max_iter=300, n_points=6, gamma=1.0, gtol=1e-6, ftol=1e-13,
+             max_step=2.0, **eval_opts):
     """BFGS with the parallel line search (inla_bfgs_minimize) from theta0 (4 values).
     Returns dict(theta, f, grad, iterations, f_evals, grad_evals, reason, history)
     with history one row (f, max |grad|, alpha, theta[4], f evaluations) per iteration."""
     th0 = (C.c_double * 4)(*[float(v) for v in np.asarray(theta0, dtype=np.float64)])
     eo = _opts(**eval_opts) if eval_opts else None
     o = BfgsOpts(int(max_iter), int(n_points), float(gamma), float(gtol), float(ftol),
-                 C.pointer(eo) if eo is not None else None)
+                 C.pointer(eo) if eo is not None else None, float(max_step))
     res = BfgsResult()
     hist = (C.c_double * ((max_iter + 1) * 8))()
     _check(lib().inla_bfgs_minimize(model.handle, th0, C.byref(o), C.byref(res), hist, _stream()))

@@ -150,12 +150,13 @@ inla_status inla_bfgs_minimize(const inla_model *model, const double *theta0, co
   if (!model || !theta0 || !res) return set_last_error(INLA_ERR_ARG, "need model, theta0 and res");
   for (int k = 0; k < kDim; ++k)
     if (!std::isfinite(theta0[k])) return set_last_error(INLA_ERR_ARG, "theta0 is not finite");
-  const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 100;
+  const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 300;
   const int npts = (opts && opts->n_points > 0) ? opts->n_points : 6;
   const double gamma0 = (opts && opts->gamma > 0.0) ? opts->gamma : 1.0;
   const double gtol = (opts && opts->gtol > 0.0) ? opts->gtol : 1e-6;
   const double ftol = (opts && opts->ftol > 0.0) ? opts->ftol : 1e-13;
   const inla_opts *eo = opts ? opts->eval_opts : nullptr;
+  const double max_step = (opts && opts->max_step > 0.0) ? opts->max_step : 2.0;
   if (npts > 62) return set_last_error(INLA_ERR_ARG, "n_points above 62");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   std::memset(res, 0, sizeof(*res));
@@ -295,12 +296,18 @@ inla_status inla_bfgs_minimize(const inla_model *model, const double *theta0, co
         for (int b = 0; b < kDim; ++b) H[a][b] = a == b ? 1.0 / std::max(gnorm(g), 1e-300) : 0.0;
       continue;
     }
+    // the interval of this iteration: gamma, shortened so that no hyperparameter
+    // moves by more than max_step
+    double pmax = 0.0;
+    for (int k = 0; k < kDim; ++k) pmax = std::max(pmax, std::fabs(p[k]));
+    double gam = gamma;
+    if (gam * pmax > max_step) gam = max_step / pmax;
     // candidate step lengths: npts on the interval, two stabilising ones on
     // the other side of theta, close to it
     bool moved = false;
     for (int attempt = 0; attempt < 8 && !moved && rc == INLA_OK; ++attempt) {
-      std::vector<double> alphas{-gamma / 4.0, -gamma / 8.0};
-      for (int i = 1; i <= npts; ++i) alphas.push_back(gamma * i / npts);
+      std::vector<double> alphas{-gam / 4.0, -gam / 8.0};
+      for (int i = 1; i <= npts; ++i) alphas.push_back(gam * i / npts);
       std::vector<double> pts;
       for (double al : alphas)
         for (int k = 0; k < kDim; ++k) pts.push_back(th[k] - al * p[k]);
@@ -320,13 +327,13 @@ inla_status inla_bfgs_minimize(const inla_model *model, const double *theta0, co
             best_alpha = alphas[i];
           }
         }
-      // the minimiser of the robust quadratic on the interval (0, gamma]
+      // the minimiser of the robust quadratic on the interval (0, gam]
       double alpha_q = 0.0;
       double c[3];
       if (xa.size() >= 4 &&
           inla_robust_quadratic_fit(xa.data(), ya.data(), (int)xa.size(), c, nullptr) == INLA_OK) {
-        if (c[2] > 0.0) alpha_q = std::min(std::max(-c[1] / (2.0 * c[2]), 0.0), gamma);
-        else alpha_q = (c[1] * gamma + c[2] * gamma * gamma < 0.0) ? gamma : 0.0;
+        if (c[2] > 0.0) alpha_q = std::min(std::max(-c[1] / (2.0 * c[2]), 0.0), gam);
+        else alpha_q = (c[1] * gam + c[2] * gam * gam < 0.0) ? gam : 0.0;
       }
       // the fit's minimiser, unless an evaluated candidate is lower; then that one
       std::vector<double> tries;
@@ -345,7 +352,7 @@ inla_status inla_bfgs_minimize(const inla_model *model, const double *theta0, co
         moved = true;
       }
       // nothing on the interval decreased f: a shorter interval
-      if (!moved) gamma *= 0.25;
+      if (!moved) gam *= 0.25;
     }
     if (rc != INLA_OK) break;
     if (!moved) {
