@@ -206,9 +206,15 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
     case PH_STEPF: {
       SIDE_ONLY(SIDE == kFatOnly || SIDE == kLeanOnly)
       // Tiles p-1 and p are full wherever they are used here (they precede a tile).
+      // The batched step (PH_STEP with PH_DIAGC beside it) is left-looking:
+      // column p+1 and its diagonal tile take every earlier panel in one
+      // product here, and no trailing tile is touched before its column's
+      // turn.  The fused step (few tiles) keeps the right-looking order with
+      // the rest of panel p-1's update deferred to this launch.
+      const bool left = phase != PH_STEPF;
       const int npan = nP - 1 - p;
       const int ncol = max(nP - 2 - p, 0);
-      const int ndef = (p >= 1) ? ncol * (ncol + 1) / 2 : min(ncol, 1);
+      const int ndef = left ? 0 : (p >= 1) ? ncol * (ncol + 1) / 2 : min(ncol, 1);
       int i = -1, jc = p + 1;   // chained task for tile (i, jc)
       if (phase == PH_STEPF && p < nP - 1) {   // task 0 is the diagonal tile
         if (q == 0) i = p + 1;
@@ -277,9 +283,10 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
         tk.nseg = 1;
         return;
       }
-      // column p+1 (and the diagonal tile of column p+2):
-      // A_{i,jc} -= L_{i,p-1} L_{jc,p-1}^T + L_{i,p} L_{jc,p}^T; the diagonal
-      // tile factored in this step took its column p-1 term in the previous one.
+      // column p+1 (and, right-looking, the diagonal tile of column p+2):
+      // right-looking, A_{i,jc} -= L_{i,p-1} L_{jc,p-1}^T + L_{i,p} L_{jc,p}^T
+      // (the diagonal tile factored in this step took its column p-1 term in
+      // the previous one); left-looking, A_{i,jc} -= sum_{m <= p} L_{i,m} L_{jc,m}^T.
       // The fused step forms L_{i,p} = A_ip X_pp^T and L_{jc,p} in the task
       // (X_pp = inv(L_pp) is in place in D[t]); the batched one takes
       // (A_ip M_p) A_{jc,p}^T with M_p = X_pp^T X_pp = inv(A_pp), which the
@@ -296,7 +303,11 @@ __device__ __forceinline__ void decode(const ItemDev &it, int phase, int t, int 
                 kTile, 1, 0, kTile, 1.0);
         set_seg(tk.seg[1], Dt + toff(b, jc, p), 1, b, nullptr, 0, 0, 0, kTile, -1.0);
       }
-      if (p >= 1 && !fac)
+      if (left && p >= 1)
+        // panels 0..p-1 of L_tt (in W2) in one product of k = 64 p
+        set_seg(tk.seg[2], it.W2 + (long long)i * kTile, 1, b, it.W2 + (long long)jc * kTile, 1, b, 0,
+                p * kTile, -1.0);
+      else if (p >= 1 && !fac)
         set_seg(tk.seg[2], it.W2 + toff(b, i, p - 1), 1, b, it.W2 + toff(b, jc, p - 1), 1, b, 0,
                 kTile, -1.0);
       else

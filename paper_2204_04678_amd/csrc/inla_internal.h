@@ -175,7 +175,8 @@ __host__ __device__ inline StepSplit step_split(int nP, int phase, int t, int p,
   if (t >= nrun || p >= nP) return z;
   z.npan = nP - 1 - p;
   z.ncol = (nP - 2 - p > 0) ? nP - 2 - p : 0;
-  z.ndef = (p >= 1) ? z.ncol * (z.ncol + 1) / 2 : (z.ncol > 0 ? 1 : 0);
+  // the batched step is left-looking: no deferred trailing tiles
+  z.ndef = (phase == PH_STEP) ? 0 : (p >= 1) ? z.ncol * (z.ncol + 1) / 2 : (z.ncol > 0 ? 1 : 0);
   z.nrow = p;
   z.nsum = (phase == PH_STEPF) ? (nP - 1 - p) * p : 0;
   z.ndiag = (phase == PH_STEPF && p < nP - 1) ? 1 : 0;
@@ -215,12 +216,14 @@ __host__ __device__ inline int phase_tasks(const ItemDev &it, int phase, int t, 
   const bool last = (t == it.nt - 1);
   switch (phase) {
     case PH_DIAG0: return 1;
-    case PH_STEP:     // panels, column p+1, deferred trailing tiles, row p of inv(L_tt)
-    case PH_STEPF: {  // the same plus the diagonal tile of column p+1 and the running
+    case PH_STEP:     // panels, column p+1 (left-looking: every earlier panel), row p of inv(L_tt)
+    case PH_STEPF: {  // panels, column p+1, the deferred trailing tiles (right-looking),
+                      // row p of inv(L_tt), the diagonal tile of column p+1 and the running
                       // sums of the later rows of inv(L_tt)
       if (p >= nP) return 0;
       const int ncol = (nP - 2 - p > 0) ? nP - 2 - p : 0;
-      return (nP - 1 - p) + ncol + (p >= 1 ? ncol * (ncol + 1) / 2 : (ncol > 0 ? 1 : 0)) + p +
+      const int ndef = (phase == PH_STEP) ? 0 : (p >= 1 ? ncol * (ncol + 1) / 2 : (ncol > 0 ? 1 : 0));
+      return (nP - 1 - p) + ncol + ndef + p +
              ((phase == PH_STEPF) ? (nP - 1 - p) * p : 0) +
              ((phase == PH_STEPF && p < nP - 1) ? 1 : 0);
     }
