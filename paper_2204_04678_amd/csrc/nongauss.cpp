@@ -225,7 +225,7 @@ inla_status inla_eval_f_grad_poisson(const inla_model *model, const double *thet
   // traces tr(Sigma dQ_k) of both selected inverses through the library's
   // trace kernel (an item whose Sigma blocks are the caller-layout ones)
   std::vector<double> trp((size_t)(nt + 1) * inla::kTraceBlocks * 4);
-  double *trd, *var_tmp = nullptr;
+  double *trd;
   inla::ItemDev *itd;
   if (!B.get(&trd, trp.size()) || !B.get(&itd, 1)) return set_last_error(INLA_ERR_NOMEM, "trace buffers");
   auto traces = [&](inla_bta &L, double *diag, double tr[4]) -> inla_status {
@@ -250,7 +250,7 @@ inla_status inla_eval_f_grad_poisson(const inla_model *model, const double *thet
   };
   double trP[4], trC[4];
   NG_TRY(traces(Qp, nullptr, trP));
-  NG_TRY(traces(Qc, var_dev ? var_dev : var_tmp, trC));
+  NG_TRY(traces(Qc, var_dev, trC));
   // the implicit term: c_i = 1/2 e_i (A Sigma_c A^T)_ii, z = Q_c^{-1} A^T c
   NG_HIP(inla::launch_ng_obs_var(Md, m, Sg.D, Sg.R, Sg.T, e, c, s), "observation variances");
   NG_HIP(inla::launch_ng_atv(Md, n, c, rhs, s), "A^T c");
