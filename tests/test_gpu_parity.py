@@ -797,3 +797,23 @@ def test_poisson_f_grad_matches_oracle(P, N, nt, nb, seed):
     G = P.Model.from_data(base)
     with pytest.raises(P.InlaError, match="counts"):
         P.eval_f_grad_poisson(G, theta)
+
+
+def test_integrate_and_poisson_status_paths(P):
+    """The drivers' failure paths: a Hessian that is not positive definite
+    (a difference step so small that theta +- h e_k round to theta, so H = 0)
+    is refused with INLA_ERR_NOT_SPD; Newton's method stopped after one
+    iteration reports status 4 with NaN f and gradient, and the library stays
+    usable (the next call with the default budget converges)."""
+    from inla_synth import poisson_counts
+    md = make_model(4, 3, 2, 5)
+    M = P.Model.from_data(md)
+    with pytest.raises(P.InlaError, match="positive definite"):
+        P.integrate(M, THETA0, h=1e-300, latent=False)
+    C = P.Model.from_data(poisson_counts(md, seed=5))
+    theta = np.array([0.1, 0.9, 0.6, 1.5])
+    r = P.eval_f_grad_poisson(C, theta, max_iter=1)
+    assert r["status"] == 4 and r["iterations"] == 1
+    assert math.isnan(r["f"]) and np.all(np.isnan(r["grad"]))
+    ok = P.eval_f_grad_poisson(C, theta)
+    assert ok["status"] == 0 and math.isfinite(ok["f"])
