@@ -345,7 +345,8 @@ bool model_counts(const inla_model *m, double *log_y_fact);
 // Poisson likelihood (the inner Newton loop), kNgBlocks partial sums each:
 //   ng_obs:   eta = A x, e = exp(eta) (e_out), w = y + e (eta - 1) (w_out; both
 //             may be null), part[k] = partial sums of y_i eta_i - e_i;
-//   ng_atv:   out = A^T v (n);
+//   ng_atv:   out = A^T v (n = nst + a: the space-time columns, then the a
+//             fixed-effect columns, each reduced by a workgroup);
 //   ng_add_obs: D[t] += (A^T diag(e) A) on the pattern, R[t] += its fixed-effect
 //             rows, T += Z^T diag(e) Z (BTA storage of the model's shape);
 //   ng_obs_var: c_i = 1/2 e_i (A Sigma A^T)_ii from Sigma's D, R, T blocks;
@@ -355,7 +356,8 @@ bool model_counts(const inla_model *m, double *log_y_fact);
 constexpr int kNgBlocks = 256;
 hipError_t launch_ng_obs(const ModelDev *M, long long m, const double *x, double *e_out, double *w_out,
                          double *part, hipStream_t s);
-hipError_t launch_ng_atv(const ModelDev *M, long long n, const double *v, double *out, hipStream_t s);
+hipError_t launch_ng_atv(const ModelDev *M, long long nst, int a, const double *v, double *out,
+                         hipStream_t s);
 hipError_t launch_ng_add_obs(const ModelDev *M, int b, int nt, int a, int nnz, const double *e, double *D,
                              double *R, double *T, hipStream_t s);
 hipError_t launch_ng_obs_var(const ModelDev *M, long long m, const double *SD, const double *SR,

@@ -652,13 +652,28 @@ __global__ __launch_bounds__(256) void ng_obs_kernel(const ModelDev *__restrict_
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-__global__ void ng_atv_kernel(const ModelDev *__restrict__ Mp, const double *v, double *out) {
+// The first gsp workgroups take the space-time columns (a few observations
+// each) one per lane; each further workgroup takes one fixed-effect column
+// (every observation) with a tree over its entries.
+__global__ __launch_bounds__(256) void ng_atv_kernel(const ModelDev *__restrict__ Mp, const double *v,
+                                                     double *out, int gsp) {
   const ModelDev &M = *Mp;
-  for (long long j = blockIdx.x * 256LL + threadIdx.x; j < M.n; j += (long long)gridDim.x * 256) {
-    double acc = 0.0;
-    for (long long k = M.Ac_ptr[j]; k < M.Ac_ptr[j + 1]; ++k) acc = fma(M.Ac_val[k], v[M.Ac_row[k]], acc);
-    out[j] = acc;
+  const long long nst = (long long)M.b * M.nt;
+  if ((int)blockIdx.x < gsp) {
+    for (long long j = blockIdx.x * 256LL + threadIdx.x; j < nst; j += (long long)gsp * 256) {
+      double acc = 0.0;
+      for (long long k = M.Ac_ptr[j]; k < M.Ac_ptr[j + 1]; ++k) acc = fma(M.Ac_val[k], v[M.Ac_row[k]], acc);
+      out[j] = acc;
+    }
+    return;
   }
+  const long long j = nst + (blockIdx.x - gsp);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long long k = M.Ac_ptr[j] + threadIdx.x; k < M.Ac_ptr[j + 1]; k += 256)
+    acc[0] = fma(M.Ac_val[k], v[M.Ac_row[k]], acc[0]);
+  __shared__ double red[4 * 256];
+  block_reduce<256>(acc, red);
+  if (threadIdx.x == 0) out[j] = red[0];
 }
 
 // D entries: the observations common to the columns of nodes r and s of block
@@ -829,9 +844,10 @@ hipError_t launch_ng_obs(const ModelDev *M, long long m, const double *x, double
   hipLaunchKernelGGL(ng_obs_kernel, dim3(kNgBlocks), dim3(256), 0, s, M, x, e_out, w_out, part);
   return hipGetLastError();
 }
-hipError_t launch_ng_atv(const ModelDev *M, long long n, const double *v, double *out, hipStream_t s) {
-  const int gx = (int)std::max<long long>(1, std::min<long long>((n + 255) / 256, 4096));
-  hipLaunchKernelGGL(ng_atv_kernel, dim3(gx), dim3(256), 0, s, M, v, out);
+hipError_t launch_ng_atv(const ModelDev *M, long long nst, int a, const double *v, double *out,
+                         hipStream_t s) {
+  const int gsp = (int)std::max<long long>(1, std::min<long long>((nst + 255) / 256, 4096));
+  hipLaunchKernelGGL(ng_atv_kernel, dim3(gsp + a), dim3(256), 0, s, M, v, out, gsp);
   return hipGetLastError();
 }
 hipError_t launch_ng_add_obs(const ModelDev *M, int b, int nt, int a, int nnz, const double *e, double *D,

@@ -171,7 +171,7 @@ inla_status inla_eval_f_grad_poisson(const inla_model *model, const double *thet
       res->iterations = it;
       return INLA_OK;
     }
-    NG_HIP(inla::launch_ng_atv(Md, n, w, rhs, s), "A^T w");
+    NG_HIP(inla::launch_ng_atv(Md, (long long)b * nt, a, w, rhs, s), "A^T w");
     NG_TRY(inla_solve(&Qc, rhs, xn, 1, s));
     double step = 1.0, gc = 0.0, mx[2] = {0.0, 0.0};
     for (int h = 0;; ++h) {
@@ -253,7 +253,7 @@ inla_status inla_eval_f_grad_poisson(const inla_model *model, const double *thet
   NG_TRY(traces(Qc, var_dev, trC));
   // the implicit term: c_i = 1/2 e_i (A Sigma_c A^T)_ii, z = Q_c^{-1} A^T c
   NG_HIP(inla::launch_ng_obs_var(Md, m, Sg.D, Sg.R, Sg.T, e, c, s), "observation variances");
-  NG_HIP(inla::launch_ng_atv(Md, n, c, rhs, s), "A^T c");
+  NG_HIP(inla::launch_ng_atv(Md, (long long)b * nt, a, c, rhs, s), "A^T c");
   NG_TRY(inla_solve(&Qc, rhs, z, 1, s));
   double qzx[4];
   NG_HIP(quad(z, x, qzx) ? hipSuccess : hipErrorUnknown, "quadratic forms");
