@@ -444,7 +444,8 @@ typedef struct {
 } inla_newton_opts;
 
 /* status: 0 ok; 1 Q_prior, 2 Q_c(x) not positive definite; 4 Newton's method
- * did not converge in max_iter iterations (f and grad are NaN unless 0).
+ * did not converge in max_iter iterations, or 60 halvings of a step did not
+ * keep the objective (f and grad are NaN unless 0).
  * log_lik = log pi(y | x*) with its log y! terms; quad = x*^T Q_prior x*. */
 typedef struct {
   double f, grad[4];
@@ -462,8 +463,9 @@ typedef struct {
  * the mode x* from x = 0 (or from x_mode_dev with opts->warm): per iteration
  * Q_c(x) = Q_prior + A^T diag(exp(A x)) A is assembled and factored
  * (inla_assemble, the observation terms, inla_factor_logdet) and
- * Q_c(x) x_new = A^T (y + e (eta - 1)) solved; the step is halved (at most 60
- * times) until log pi(x | theta) + log pi(y | x) does not decrease.  Then
+ * Q_c(x) x_new = A^T (y + e (eta - 1)) solved; the step is halved until
+ * log pi(x | theta) + log pi(y | x) does not decrease (status 4 if 60 halvings
+ * do not get there).  Then
  *   f = -log pi(theta) - 1/2 log|Q_prior| + 1/2 x*^T Q_prior x* - log pi(y | x*)
  *       + 1/2 log|Q_c(x*)|
  *   df/dtheta_k = p_k (theta_k - m_k) - 1/2 tr(Q_prior^{-1} dQ_k) + 1/2 x*^T dQ_k x*

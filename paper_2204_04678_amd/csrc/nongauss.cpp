@@ -184,7 +184,15 @@ inla_status inla_eval_f_grad_poisson(const inla_model *model, const double *thet
         mx[1] = std::max(mx[1], hp[2 * blk + 1]);
       }
       NG_HIP(objective(cand, gc) ? hipSuccess : hipErrorUnknown, "objective");
-      if (gc >= gx || h >= 60) break;
+      if (gc >= gx) break;
+      if (h >= 60) {
+        // no step along the Newton direction keeps the objective (a NaN from
+        // an overflowing exp(eta), say): no mode, rather than a tiny step
+        // taken for convergence
+        res->status = 4;
+        res->iterations = it;
+        return INLA_OK;
+      }
       step *= 0.5;
       ++res->halvings;
     }
