@@ -368,8 +368,8 @@ def main():
     ap.add_argument("--no-fd", action="store_true", help="skip the finite-difference baseline")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
-              f"batched items would shard across GPUs by theta point, which is not built.",
+        print(f"bench.py: the library runs on one GPU (asked for --gpus {args.gpus}); the "
+              f"batched items would shard across GPUs by theta point, which is not implemented.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -1,4 +1,4 @@
-// Host driver of the integration step after the mode search (paper, Sec.
+// Host side of the integration step after the mode search (paper, Sec.
 // "Latent Gaussian Models", Sec. "Approximating pi(x_i | y)" with eq.
 // LatParam, Sec. "Parallelization of Function Evaluations"): the Hessian at
 // the mode from differences of the adjoint gradient, the standardised grid

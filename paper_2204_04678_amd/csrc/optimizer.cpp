@@ -1,4 +1,4 @@
-// Host driver of the hyperparameter optimisation (paper, Sec. "Parallel
+// Host side of the hyperparameter optimisation (paper, Sec. "Parallel
 // Optimization" and Sec. "Parallel Line Search"): BFGS on f(theta) with the
 // exact adjoint gradient, and in every iteration a parallel line search -- the
 // candidate points of the search interval and two stabilising points on the
