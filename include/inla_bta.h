@@ -137,9 +137,11 @@ typedef struct {
  *   autotune_cache   : path of a JSON file (or NULL).  On the first call with
  *                      a new signature (the multiset of item shapes and the
  *                      outputs asked for) every candidate (the tile edge and
- *                      the product kernel's layout) is timed once on the
- *                      caller's stream, synchronously, and the fastest is
- *                      stored; later calls and processes read it back.
+ *                      the product kernel's layout, then the fused and the
+ *                      batched Cholesky step with the best of those) is timed
+ *                      once on the caller's stream, synchronously, and the
+ *                      fastest is stored; later calls and processes read it
+ *                      back.
  * Results with different tile layouts agree to rounding (about 1e-15
  * relative), not bitwise.
  *

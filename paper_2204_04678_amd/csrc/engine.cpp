@@ -258,10 +258,12 @@ constexpr long long kVBatchTiles = 4096;
 // b = 2025 with 2, 4 and 8 matrices (2048, 4096, 8192 tiles): fused 23%, 11%
 // faster and 1% slower per evaluation; b = 1600 with 2 matrices: 13% faster.
 constexpr long long kStepFusedTiles = 6144;
-// INLA_STEP_FUSED=1 (0) in the environment makes every Cholesky step fused (batched).
+// INLA_STEP_FUSED=1 (0) in the environment makes every Cholesky step fused
+// (batched); else the autotuner's choice (g_step_pref), else the tile-count rule.
+int g_step_pref = -1;
 int step_fused_override() {
   const char *e = getenv("INLA_STEP_FUSED");
-  return (e && (e[0] == '0' || e[0] == '1')) ? e[0] - '0' : -1;
+  return (e && (e[0] == '0' || e[0] == '1')) ? e[0] - '0' : g_step_pref;
 }
 // INLA_SI_BATCH=0 keeps the selected inversion's V_t, U_t step by step; 1 (or
 // unset) forms them up front where the built-in rule wants it.
@@ -1885,6 +1887,7 @@ struct TileChoice {
   int tile = 0;      // 64 or 128 (0: built-in rule)
   int variant = kDefaultBigVariant;   // layout of the 128-wide kernel
   int small = kDefaultSmallVariant;   // form of the 64-wide product phases
+  int step = -1;     // Cholesky step: 1 fused, 0 batched, -1 the tile-count rule
   double ms = 0.0;
 };
 std::unordered_map<std::string, TileChoice> g_tune;
@@ -1917,10 +1920,12 @@ void tune_load(const std::string &path) {
   while (fgets(line, sizeof(line), fp)) {
     char key[256];
     TileChoice c;
-    if (sscanf(line, " \"%255[^\"]\": {\"tile\": %d, \"variant\": %d, \"small\": %d, \"ms\": %lf",
-               key, &c.tile, &c.variant, &c.small, &c.ms) == 5 &&
-        (c.tile == 64 || c.tile == 128) && c.variant >= 0 && c.variant < kBigVariants &&
-        c.small >= 0 && c.small < kSmallVariants)
+    const int got = sscanf(line,
+                           " \"%255[^\"]\": {\"tile\": %d, \"variant\": %d, \"small\": %d, "
+                           "\"step\": %d, \"ms\": %lf",
+                           key, &c.tile, &c.variant, &c.small, &c.step, &c.ms);
+    if (got == 6 && (c.tile == 64 || c.tile == 128) && c.variant >= 0 && c.variant < kBigVariants &&
+        c.small >= 0 && c.small < kSmallVariants && c.step >= -1 && c.step <= 1)
       g_tune[key] = c;
   }
   fclose(fp);
@@ -1936,8 +1941,8 @@ void tune_save(const std::string &path) {
   fprintf(fp, "{\n");
   for (size_t i = 0; i < keys.size(); ++i) {
     const TileChoice &c = g_tune[keys[i]];
-    fprintf(fp, "  \"%s\": {\"tile\": %d, \"variant\": %d, \"small\": %d, \"ms\": %.4f}%s\n",
-            keys[i].c_str(), c.tile, c.variant, c.small, c.ms, i + 1 < keys.size() ? "," : "");
+    fprintf(fp, "  \"%s\": {\"tile\": %d, \"variant\": %d, \"small\": %d, \"step\": %d, \"ms\": %.4f}%s\n",
+            keys[i].c_str(), c.tile, c.variant, c.small, c.step, c.ms, i + 1 < keys.size() ? "," : "");
   }
   fprintf(fp, "}\n");
   fclose(fp);
@@ -1993,11 +1998,13 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
     g_tile_pref = c.tile;
     set_big_variant(c.variant);
     set_small_variant(c.small);
+    g_step_pref = c.step;
     const inla_status st = eval_run(models, n_items, theta_dev, f_dev, grad_dev, mu_out, var_out,
                                     status_dev, sigma, budget, seq_mode, allow_graph, s);
     g_tile_pref = 0;
     set_big_variant(kDefaultBigVariant);
     set_small_variant(kDefaultSmallVariant);
+    g_step_pref = -1;
     return st;
   };
   TileChoice choice;
@@ -2026,28 +2033,35 @@ inla_status eval_impl(const inla_model *const *models, int32_t n_items, const do
       HIP_TRY(hipEventCreate(&e0));
       HIP_TRY(hipEventCreate(&e1));
       bool have = false;
-      for (const TileChoice &c0 : cands) {
-        TileChoice c = c0;
+      auto trial = [&](TileChoice c) -> inla_status {
         inla_status st = run(c, false);
         if (st == INLA_OK) {
           HIP_TRY(hipEventRecord(e0, s));
           st = run(c, false);
           HIP_TRY(hipEventRecord(e1, s));
         }
-        if (st != INLA_OK) {
-          (void)hipEventDestroy(e0);
-          (void)hipEventDestroy(e1);
-          return st;
-        }
+        if (st != INLA_OK) return st;
         HIP_TRY(hipEventSynchronize(e1));
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
         c.ms = ms;
         if (!have || c.ms < choice.ms) choice = c;
         have = true;
+        return INLA_OK;
+      };
+      // the product layouts under the tile-count rule for the step form, then
+      // both step forms with the best layout
+      inla_status st = INLA_OK;
+      for (const TileChoice &c0 : cands)
+        if (st == INLA_OK) st = trial(c0);
+      for (int form = 0; form <= 1 && st == INLA_OK; ++form) {
+        TileChoice c = choice;
+        c.step = form;
+        st = trial(c);
       }
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
+      if (st != INLA_OK) return st;
       g_tune[key] = choice;
       tune_save(path);
     }

@@ -420,7 +420,8 @@ def test_shared_storage_mode_matches_two_matrix_mode(P):
 
 
 def test_autotune_cache(P, tmp_path):
-    """The autotuner times the tile layouts once, stores the winner, and reuses it."""
+    """The autotuner times the tile layouts and the two Cholesky step forms
+    once, stores the winner, and reuses it."""
     import json
     md = config_model("c4small")
     M = P.Model.from_data(md)
@@ -431,6 +432,7 @@ def test_autotune_cache(P, tmp_path):
     assert len(entries) == 1
     (key, val), = entries.items()
     assert key.startswith("grad:n2:") and val["tile"] in (64, 128) and val["ms"] > 0
+    assert val["step"] in (-1, 0, 1)
     again = P.eval_f_grad([M, M], np.stack([THETA0, THETA0 + 0.05]), autotune_cache=path)
     torch.cuda.synchronize()
     assert len(json.loads(path.read_text())) == 1
