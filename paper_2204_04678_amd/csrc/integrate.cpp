@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <vector>
@@ -224,7 +225,13 @@ inla_status inla_integrate(const inla_model *model, const double *theta_mode,
 
   // 6. latent marginals: the mixture over the kept points, chunk by chunk
   if (!x_mean_dev && !x_var_dev) return INLA_OK;
-  const int chunk = (int)std::max<long long>(1, std::min<long long>(K, (long long)(kLatentBytes / (16ull * n))));
+  int chunk = (int)std::max<long long>(1, std::min<long long>(K, (long long)(kLatentBytes / (16ull * n))));
+  // INLA_LATENT_CHUNK=c in the environment caps the points per chunk (the
+  // chunks continue one sequential sum, so the results do not depend on it)
+  if (const char *e = getenv("INLA_LATENT_CHUNK")) {
+    const int c = atoi(e);
+    if (c >= 1) chunk = std::min(chunk, c);
+  }
   double *d_mu = nullptr, *d_var = nullptr, *d_shift = nullptr, *d_am = nullptr, *d_as = nullptr, *d_w = nullptr,
          *d_th2 = nullptr, *d_f2 = nullptr;
   int *d_st2 = nullptr;

@@ -819,3 +819,20 @@ def test_integrate_and_poisson_status_paths(P):
     assert math.isnan(r["f"]) and np.all(np.isnan(r["grad"]))
     ok = P.eval_f_grad_poisson(C, theta)
     assert ok["status"] == 0 and math.isfinite(ok["f"])
+
+
+def test_integrate_latent_chunks_continue_one_sum(P, monkeypatch):
+    """The latent mixture over the kept points is accumulated chunk by chunk
+    (at most about 1 GiB of mu and variances at a time); the chunks continue
+    one sequential sum, so chunks of 3 points give the one-chunk result bit for
+    bit."""
+    md = make_model(4, 3, 2, 5)
+    M = P.Model.from_data(md)
+    theta = np.array([-3.87344165, 2.44666108, 0.05611112, 4.58238323])   # near the mode
+    monkeypatch.delenv("INLA_LATENT_CHUNK", raising=False)
+    one = P.integrate(M, theta)
+    monkeypatch.setenv("INLA_LATENT_CHUNK", "3")
+    many = P.integrate(M, theta)
+    assert one["n_points"] > 6
+    assert torch.equal(one["x_mean"], many["x_mean"]) and torch.equal(one["x_var"], many["x_var"])
+    assert np.array_equal(one["points"], many["points"])
