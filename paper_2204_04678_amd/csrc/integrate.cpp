@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "../../include/inla_bta.h"
+#include "call_buffers.h"
 #include "inla_internal.h"
 #include "integrate_host.h"
 
@@ -27,26 +28,6 @@ namespace {
 constexpr int kD = G::kD;
 constexpr int kBatch = 256;                 // items per batched f call
 constexpr size_t kLatentBytes = 1ull << 30; // mu and variances of one latent chunk
-
-// Device buffers freed on every return path.
-struct DevBufs {
-  std::vector<void *> p;
-  ~DevBufs() {
-    for (void *q : p)
-      if (q) (void)hipFree(q);
-  }
-  template <class T>
-  bool alloc(T **out, size_t count) {
-    void *q = nullptr;
-    if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) {
-      (void)hipGetLastError();
-      return false;
-    }
-    p.push_back(q);
-    *out = static_cast<T *>(q);
-    return true;
-  }
-};
 
 }  // namespace
 
@@ -77,12 +58,12 @@ inla_status inla_integrate(const inla_model *model, const double *theta_mode,
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   std::memset(res, 0, sizeof(*res));
 
-  DevBufs bufs;
+  inla::CallBuffers bufs;
   const int cap = std::max(kBatch, 2 * kD * max_steps);
   double *d_th = nullptr, *d_f = nullptr, *d_g = nullptr;
   int *d_st = nullptr;
-  if (!bufs.alloc(&d_th, (size_t)cap * kD) || !bufs.alloc(&d_f, cap) ||
-      !bufs.alloc(&d_g, (size_t)(2 * kD + 1) * kD) || !bufs.alloc(&d_st, cap))
+  if (!bufs.get(&d_th, (size_t)cap * kD) || !bufs.get(&d_f, cap) ||
+      !bufs.get(&d_g, (size_t)(2 * kD + 1) * kD) || !bufs.get(&d_st, cap))
     return set_last_error(INLA_ERR_NOMEM, "integration buffers");
   std::vector<const inla_model *> ms(cap, model);
 
@@ -235,9 +216,9 @@ inla_status inla_integrate(const inla_model *model, const double *theta_mode,
   double *d_mu = nullptr, *d_var = nullptr, *d_shift = nullptr, *d_am = nullptr, *d_as = nullptr, *d_w = nullptr,
          *d_th2 = nullptr, *d_f2 = nullptr;
   int *d_st2 = nullptr;
-  if (!bufs.alloc(&d_mu, (size_t)chunk * n) || !bufs.alloc(&d_var, (size_t)chunk * n) ||
-      !bufs.alloc(&d_shift, n) || !bufs.alloc(&d_am, n) || !bufs.alloc(&d_as, n) || !bufs.alloc(&d_w, chunk) ||
-      !bufs.alloc(&d_th2, (size_t)chunk * kD) || !bufs.alloc(&d_f2, chunk) || !bufs.alloc(&d_st2, chunk))
+  if (!bufs.get(&d_mu, (size_t)chunk * n) || !bufs.get(&d_var, (size_t)chunk * n) ||
+      !bufs.get(&d_shift, n) || !bufs.get(&d_am, n) || !bufs.get(&d_as, n) || !bufs.get(&d_w, chunk) ||
+      !bufs.get(&d_th2, (size_t)chunk * kD) || !bufs.get(&d_f2, chunk) || !bufs.get(&d_st2, chunk))
     return set_last_error(INLA_ERR_NOMEM, "latent mixture buffers");
   std::vector<const inla_model *> mk(chunk, model);
   std::vector<int> st2(chunk);

@@ -25,38 +25,22 @@
 #include <vector>
 
 #include "../../include/inla_bta.h"
+#include "call_buffers.h"
 #include "inla_internal.h"
 
 using inla::set_last_error;
 
 namespace {
 
-struct Bufs {
-  std::vector<void *> p;
-  ~Bufs() {
-    for (void *q : p)
-      if (q) (void)hipFree(q);
-  }
-  template <class T>
-  bool get(T **out, size_t count) {
-    void *q = nullptr;
-    if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) {
-      (void)hipGetLastError();
-      return false;
-    }
-    p.push_back(q);
-    *out = static_cast<T *>(q);
-    return true;
-  }
-  bool bta(inla_bta &q, int b, int nt, int a) {
-    q.b = b; q.nt = nt; q.a = a;
-    q.S = nullptr; q.R = nullptr; q.T = nullptr;
-    if (!get(&q.D, (size_t)nt * b * b)) return false;
-    if (nt > 1 && !get(&q.S, (size_t)(nt - 1) * b * b)) return false;
-    if (a > 0 && (!get(&q.R, (size_t)nt * a * b) || !get(&q.T, (size_t)a * a))) return false;
-    return true;
-  }
-};
+// the storage of one BTA matrix of the model's shape
+bool bta_buffers(inla::CallBuffers &B, inla_bta &q, int b, int nt, int a) {
+  q.b = b; q.nt = nt; q.a = a;
+  q.S = nullptr; q.R = nullptr; q.T = nullptr;
+  if (!B.get(&q.D, (size_t)nt * b * b)) return false;
+  if (nt > 1 && !B.get(&q.S, (size_t)(nt - 1) * b * b)) return false;
+  if (a > 0 && (!B.get(&q.R, (size_t)nt * a * b) || !B.get(&q.T, (size_t)a * a))) return false;
+  return true;
+}
 
 }  // namespace
 
@@ -86,11 +70,11 @@ inla_status inla_eval_f_grad_poisson(const inla_model *model, const double *thet
   res->f = NAN;
   for (double &g : res->grad) g = NAN;
 
-  Bufs B;
+  inla::CallBuffers B;
   inla_bta Qp, Qc, Sg;
   double *th, *x, *xn, *cand, *e, *w, *rhs, *c, *z, *part, *ld;
   int *info;
-  if (!B.bta(Qp, b, nt, a) || !B.bta(Qc, b, nt, a) || !B.bta(Sg, b, nt, a) || !B.get(&th, 4) ||
+  if (!bta_buffers(B, Qp, b, nt, a) || !bta_buffers(B, Qc, b, nt, a) || !bta_buffers(B, Sg, b, nt, a) || !B.get(&th, 4) ||
       !B.get(&x, n) || !B.get(&xn, n) || !B.get(&cand, n) || !B.get(&e, m) || !B.get(&w, m) ||
       !B.get(&rhs, n) || !B.get(&c, m) || !B.get(&z, n) || !B.get(&part, 4 * inla::kNgBlocks) ||
       !B.get(&ld, 2) || !B.get(&info, 2))
