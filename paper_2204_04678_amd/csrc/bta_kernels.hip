@@ -72,6 +72,11 @@ template <> struct BigCfg<8> {   // 64: 4 waves of 32 x 32, direct loads, k-chun
   static constexpr bool DMA = true;
   static constexpr int STAGES = 4;
 };
+template <> struct BigCfg<9> {   // 64: 8 waves of 32 x 16, direct loads, k-chunk 16
+  static constexpr int TS = 64, WR = 2, WC = 4, KC = 16, DEPTH = 1, OCC = 4;
+  static constexpr bool DMA = true;
+  static constexpr int STAGES = 2;
+};
 // Row length of a [k][row] LDS panel of a TS-row tile: 128 rows are padded by
 // two; 64 rows stay unpadded so that one 1 KiB direct load fills two k-columns.
 template <int TS> constexpr int pld() { return TS == 128 ? TS + 2 : TS; }
@@ -1969,8 +1974,8 @@ __global__ __launch_bounds__(big_threads<V>(), BigCfg<V>::OCC) void tile_product
 // Layout of the 64-wide product phases: 0 the 64-tile kernel with the side
 // phase in the same launch, 1 / 2 / 3 the product kernel with direct loads
 // (layouts 6 / 7 / 8) and the side phase in the same launch, 4 layout 6 or 7
-// by the size of the launch; INLA_SMALL_VARIANT=0..4 in the environment
-// overrides the engine's choice.
+// by the size of the launch, 5 layout 9; INLA_SMALL_VARIANT=0..5 in the
+// environment overrides the engine's choice.
 static int g_small_variant = kDefaultSmallVariant;
 void set_small_variant(int v) {
   g_small_variant = (v >= 0 && v < kSmallVariants) ? v : kDefaultSmallVariant;
@@ -2082,7 +2087,8 @@ hipError_t launch_tile_phase(const ItemDev *items_dev, int n_items, int total, i
         }
         sv = (grid > 2LL * cus) ? 2 : 1;
       }
-      if (sv == 3) launch_big_dma<8>(phase, ph2, ns, grid, s, items_dev, n_items, t, 1);
+      if (sv == 5) launch_big_dma<9>(phase, ph2, ns, grid, s, items_dev, n_items, t, 1);
+      else if (sv == 3) launch_big_dma<8>(phase, ph2, ns, grid, s, items_dev, n_items, t, 1);
       else if (sv == 2) launch_big_dma<7>(phase, ph2, ns, grid, s, items_dev, n_items, t, 1);
       else launch_big_dma<6>(phase, ph2, ns, grid, s, items_dev, n_items, t, 1);
       return hipGetLastError();

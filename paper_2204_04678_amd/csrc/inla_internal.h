@@ -273,9 +273,10 @@ constexpr int kDefaultBigVariant = 4;
 // Form of the 64-wide product phases (0: 64-tile kernel, the side phase in the
 // same launch; 1, 2, 3: product kernel with direct loads, k-chunk 32 / 16 /
 // 16 with four LDS stages; 4: 1, or 2 when a launch has more workgroups than
-// two per compute unit).
-constexpr int kSmallVariants = 5;
-constexpr int kDefaultSmallVariant = 4;
+// two per compute unit; 5: as 2 on eight waves of 32 x 16, the same sums in
+// the same order).
+constexpr int kSmallVariants = 6;
+constexpr int kDefaultSmallVariant = 5;
 void set_small_variant(int v);
 int small_variant();
 void set_big_variant(int v);

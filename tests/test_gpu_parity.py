@@ -19,14 +19,16 @@ torch = pytest.importorskip("torch")
 
 
 @pytest.fixture(params=[("64", "0"), ("64", "1"), ("64", "2"), ("64", "3"), ("64", "4"),
+                        ("64", "5"),
                         ("128", "0"), ("128", "3"), ("128", "4"), ("128", "5")],
                 ids=["tile64", "tile64dma32", "tile64dma16", "tile64dma16s4", "tile64auto",
+                     "tile64dma16w8",
                      "tile128", "tile128dma32", "tile128dma16", "tile128dma16w4"])
 def tile(request, monkeypatch):
     """Run the b x b product phases on 64- or 128-wide tiles: 64 in the 64-tile
     kernel (form 0) or in the product kernel with direct-to-LDS staging (forms
     1, 2, 3: k-chunks of 32 and 16, and 16 with four LDS stages; form 4
-    picks 1 or 2 by launch size); 128 with
+    picks 1 or 2 by launch size; form 5: k-chunk 16 on eight waves); 128 with
     register staging (layout 0) or
     direct-to-LDS staging (layouts 3-5: 8 waves with k-chunks of 32 and 16,
     4 waves with k-chunk 16)."""
@@ -490,6 +492,24 @@ def test_eval_f_grad_multi_tile(P, tile, N, nt, nb):
     out = P.eval_f_grad(M, theta, want_mu=True, want_var=True)
     torch.cuda.synchronize()
     check_against_dense_oracle(out, 0, md, theta)
+
+
+def test_eight_wave_products_equal_four_wave_bitwise(P, monkeypatch):
+    """The 64-wide products on eight waves of 32 x 16 (form 5) take every sum
+    in the order the four waves of 32 x 32 (form 2) do: f, gradient, mean and
+    variances agree bit for bit, on a batch of uneven multi-tile models."""
+    print("eight-wave vs four-wave 64-wide products", flush=True)
+    mds = [make_model(12, 3, 3, 71), make_model(9, 4, 0, 72), make_model(5, 3, 2, 73)]
+    Ms = [P.Model.from_data(m) for m in mds]
+    th = np.array([[0.3, 0.9, 1.1, 3.5], [-0.2, 0.6, 0.2, 2.5], [0.1, 0.8, 0.5, 2.0]])
+    monkeypatch.setenv("INLA_TILE", "64")
+    out = {}
+    for form in ("2", "5"):
+        monkeypatch.setenv("INLA_SMALL_VARIANT", form)
+        out[form] = P.eval_f_grad(Ms, th, want_mu=True, want_var=True)
+        torch.cuda.synchronize()
+    for key in ("f", "grad", "mu", "var", "status"):
+        assert torch.equal(out["2"][key], out["5"][key]), key
 
 
 @pytest.mark.parametrize("fused", ["0", "1"], ids=["batched_step", "fused_step"])
