@@ -9,6 +9,13 @@ Each workload writes tests/golden/<name>.json with f, both log-determinants,
 the posterior mode at sampled indices and the marginal variances at sampled
 indices (all of the fixed effects, the first and last time block's first 16
 nodes, and seeded random others).
+
+    python tests/golden/make_golden.py --grad c2
+
+adds to an existing file the gradient of f by central differences of the
+oracle's f, Richardson-extrapolated from the steps 2h and h:
+g_k = (4 D_k(h) - D_k(2h)) / 3, D_k(s) = (f(theta + s e_k) - f(theta - s e_k)) / 2s,
+whose truncation error is O(h^4).
 """
 import json
 import os
@@ -53,6 +60,37 @@ def golden_for(md, theta, variances=True):
     return rec
 
 
+def fd_gradient_richardson(md, theta, h=1e-3):
+    theta = np.asarray(theta, dtype=float)
+    d = {}
+    for s in (2 * h, h):
+        g = np.zeros(theta.size)
+        for k in range(theta.size):
+            e = np.zeros(theta.size)
+            e[k] = s
+            fp = oracle.eval_f_banded(md, theta + e)["f"]
+            fm = oracle.eval_f_banded(md, theta - e)["f"]
+            g[k] = (fp - fm) / (2 * s)
+        d[s] = g
+    return (4 * d[h] - d[2 * h]) / 3, d
+
+
+def add_gradient(name, h=1e-3):
+    path = os.path.join(HERE, f"{name}.json")
+    with open(path) as fh:
+        data = json.load(fh)
+    md = config_model(name)
+    t0 = time.time()
+    g, d = fd_gradient_richardson(md, THETA0, h)
+    data["grad_fd"] = g.tolist()
+    data["grad_fd_steps"] = [2 * h, h]
+    data["grad_fd_central"] = {str(s): v.tolist() for s, v in d.items()}
+    data["grad_fd_seconds"] = time.time() - t0
+    with open(path, "w") as fh:
+        json.dump(data, fh)
+    print(name, "grad_fd", g.tolist(), f"{data['grad_fd_seconds']:.1f}s", flush=True)
+
+
 def main(names):
     for name in names:
         if name == "c3":
@@ -74,4 +112,8 @@ def main(names):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["c2", "c4", "c5", "c3"])
+    if sys.argv[1:2] == ["--grad"]:
+        for name in sys.argv[2:] or ["c2"]:
+            add_gradient(name)
+    else:
+        main(sys.argv[1:] or ["c2", "c4", "c5", "c3"])

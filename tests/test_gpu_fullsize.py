@@ -78,8 +78,20 @@ def check_against_golden(P, name, tol_f=1e-10):
     return M, md
 
 
+def check_gradient_against_golden(P, M, name):
+    """The adjoint gradient at full size against the oracle's f differentiated
+    numerically (central differences at steps 2e-3 and 1e-3, Richardson-
+    extrapolated: truncation O(h^4); the rounding of f, ~1e-13 relative, over
+    2h leaves ~1e-10 relative in a component).  The bar is 1e-8."""
+    g_ref = np.array(golden(name)["grad_fd"])
+    g = P.eval_f_grad(M, THETA0)["grad"].cpu().numpy()[0]
+    scale = np.maximum(np.abs(g_ref), 1e-3 * np.abs(g_ref).max())
+    assert np.max(np.abs(g - g_ref) / scale) < 1e-8, (g, g_ref)
+
+
 def test_workload_32x32x50_against_oracle(P):
-    check_against_golden(P, "c2")
+    M, md = check_against_golden(P, "c2")
+    check_gradient_against_golden(P, M, "c2")
 
 
 def test_workload_40x40x100_against_oracle_and_fd(P):
@@ -91,12 +103,16 @@ def test_workload_40x40x100_against_oracle_and_fd(P):
     g = P.eval_f_grad(M, THETA0)["grad"].cpu().numpy()[0]
     scale = np.abs(fd).max()
     assert np.all(np.abs(g - fd) <= 1e-5 * np.maximum(np.abs(fd), 1e-3 * scale)), (g, fd)
+    if "grad_fd" in golden("c4"):
+        check_gradient_against_golden(P, M, "c4")
 
 
 def test_workload_45x45x200_against_oracle(P):
     if not os.path.exists(os.path.join(GOLDEN, "c5.json")):
         pytest.skip("stored oracle values for the 45x45x200 workload not generated")
-    check_against_golden(P, "c5")
+    M, md = check_against_golden(P, "c5")
+    if "grad_fd" in golden("c5"):
+        check_gradient_against_golden(P, M, "c5")
 
 
 def test_uneven_batch_of_64_models(P):
